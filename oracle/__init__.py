@@ -1,0 +1,217 @@
+"""ctypes wrapper around the plain FP64 CPU oracle (``hyb_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, by the smoke check and
+by the CPU-baseline leg of the benchmark.  The product package never imports
+it, and it imports nothing from the product package.
+
+Geometry convention (shared by the whole project, stated in the paper's
+terms): the outer box has ``n[d]`` cells of size ``h`` per axis (``n[d]+1``
+nodes, x fastest); the FEM box covers cells ``[o, o+C)`` per axis; faces are
+ordered x-, x+, y-, y+, z-, z+; the backscattered trace is recorded on z+.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+from .build import build, lib_path
+
+ABC, NEUMANN, SOURCE = 0, 1, 2
+
+
+class _Geom(ct.Structure):
+    _fields_ = [("n", ct.c_int32 * 3), ("h", ct.c_double), ("bc", ct.c_int32 * 6),
+                ("fem_o", ct.c_int32 * 3), ("fem_c", ct.c_int32 * 3)]
+
+
+class _Source(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("omega", ct.c_double),
+                ("flux", ct.POINTER(ct.c_double)), ("k_on", ct.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path()):
+            build()
+        lib = ct.CDLL(lib_path())
+        dp = ct.POINTER(ct.c_double)
+        lib.orc_sizes.argtypes = [ct.POINTER(_Geom), ct.POINTER(ct.c_int64)]
+        lib.orc_forward.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
+                                    ct.c_double, dp, dp, dp, dp, dp]
+        lib.orc_adjoint.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
+                                    ct.c_double, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_misfit.argtypes = [ct.POINTER(_Geom), ct.c_int, ct.c_double, dp, dp, dp]
+        lib.orc_misfit.restype = ct.c_double
+        lib.orc_gradient.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
+                                     ct.c_double, dp, ct.c_double, dp, dp, dp]
+        lib.orc_cg.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
+                               ct.c_double, dp, ct.c_double, ct.c_double, ct.c_int, dp]
+        _lib = lib
+    return _lib
+
+
+class Geometry:
+    """Outer grid, face boundary conditions and FEM box (cells)."""
+
+    def __init__(self, n, h=None, bc=(ABC, ABC, ABC, ABC, ABC, SOURCE), fem_o=(0, 0, 0),
+                 fem_c=(0, 0, 0)):
+        n = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+        self.n = n
+        self.h = float(h if h is not None else 1.0 / n[2])
+        self.bc = tuple(int(b) for b in bc)
+        self.fem_o = (fem_o,) * 3 if np.isscalar(fem_o) else tuple(int(v) for v in fem_o)
+        self.fem_c = (fem_c,) * 3 if np.isscalar(fem_c) else tuple(int(v) for v in fem_c)
+
+    def _c(self):
+        g = _Geom()
+        g.n[:] = self.n
+        g.h = self.h
+        g.bc[:] = self.bc
+        g.fem_o[:] = self.fem_o
+        g.fem_c[:] = self.fem_c
+        return g
+
+    @property
+    def nodes(self):
+        return tuple(v + 1 for v in self.n)
+
+    @property
+    def nface(self):
+        return (self.n[0] + 1) * (self.n[1] + 1)
+
+    @property
+    def ncube(self):
+        return int(np.prod(self.fem_c))
+
+    def sizes(self):
+        out = (ct.c_int64 * 8)()
+        if _load().orc_sizes(ct.byref(self._c()), out):
+            raise ValueError("invalid geometry")
+        keys = ("grid_nodes", "face_nodes", "fem_nodes", "fem_cubes", "fem_updated",
+                "fdm_updated", "omega_o", "omega_diamond")
+        return dict(zip(keys, list(out)))
+
+
+def _src(kind=0, omega=40.0, flux=None, k_on=0):
+    s = _Source()
+    s.kind = kind
+    s.omega = omega
+    s.k_on = k_on
+    if flux is not None:
+        s.flux = flux.ctypes.data_as(ct.POINTER(ct.c_double))
+    return s
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=None,
+            want_vhist=False, want_ufinal=False):
+    """Forward sweep of Algorithm 2.  Returns obs [nt+1, ny+1, nx+1] and,
+    optionally, the FEM history [nt+1, fz, fy, fx] and the final grid level."""
+    lib = _load()
+    g = geom._c()
+    sz = geom.sizes()
+    sigma = _f64(sigma)
+    flux = _f64(flux)
+    u0, um1 = _f64(u0), _f64(um1)
+    obs = np.zeros((nt + 1, geom.n[1] + 1, geom.n[0] + 1))
+    vh = np.zeros((nt + 1, sz["fem_nodes"])) if want_vhist and sz["fem_nodes"] else None
+    uf = np.zeros(sz["grid_nodes"]) if want_ufinal else None
+    s = _src(1 if flux is not None else 0, omega, flux, k_on)
+    rc = lib.orc_forward(ct.byref(g), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
+                         _p(obs), _p(vh), _p(uf))
+    if rc:
+        raise RuntimeError(f"orc_forward failed ({rc})")
+    out = [obs]
+    if want_vhist:
+        out.append(vh)
+    if want_ufinal:
+        out.append(uf)
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def adjoint(geom, sigma, nt, dt, seed, omega=40.0, flux=None, k_on=0, u0=None, um1=None,
+            want_dflux=False, want_dinit=False):
+    """Exact discrete adjoint: seed [nt+1, face] is the cotangent of the
+    trace.  Returns dJ/dsigma per cube (Euclidean) and optionally the source
+    cotangent [nt, face] and the cotangents of u^0, u^{-1}."""
+    lib = _load()
+    g = geom._c()
+    sz = geom.sizes()
+    sigma = _f64(sigma)
+    flux = _f64(flux)
+    seed = _f64(seed)
+    u0, um1 = _f64(u0), _f64(um1)
+    dsig = np.zeros(max(sz["fem_cubes"], 1))
+    dflux = np.zeros((nt, geom.nface)) if want_dflux else None
+    du0 = np.zeros(sz["grid_nodes"]) if want_dinit else None
+    dum1 = np.zeros(sz["grid_nodes"]) if want_dinit else None
+    s = _src(1 if flux is not None else 0, omega, flux, k_on)
+    rc = lib.orc_adjoint(ct.byref(g), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
+                         _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1))
+    if rc:
+        raise RuntimeError(f"orc_adjoint failed ({rc})")
+    out = [dsig[:sz["fem_cubes"]]]
+    if want_dflux:
+        out.append(dflux)
+    if want_dinit:
+        out += [du0, dum1]
+    return out[0] if len(out) == 1 else tuple(out)
+
+
+def misfit(geom, nt, dt, obs, data):
+    """J_misfit and its trace cotangent seed (eq. (functional))."""
+    lib = _load()
+    obs, data = _f64(obs), _f64(data)
+    seed = np.zeros_like(obs)
+    J = lib.orc_misfit(ct.byref(geom._c()), nt, dt, _p(obs), _p(data), _p(seed))
+    return J, seed
+
+
+def gradient(geom, sigma, nt, dt, data, gamma=0.01, omega=40.0, want_obs=False):
+    """L2 gradient g_c (eq. (gradient1), discrete) and J at sigma."""
+    lib = _load()
+    sz = geom.sizes()
+    sigma = _f64(sigma)
+    data = _f64(data)
+    grad = np.zeros(sz["fem_cubes"])
+    J = ct.c_double()
+    obs = np.zeros_like(data) if want_obs else None
+    s = _src(0, omega)
+    rc = lib.orc_gradient(ct.byref(geom._c()), _p(sigma), ct.byref(s), nt, dt, _p(data),
+                          gamma, _p(grad), ct.byref(J), _p(obs))
+    if rc:
+        raise RuntimeError(f"orc_gradient failed ({rc})")
+    return (grad, J.value, obs) if want_obs else (grad, J.value)
+
+
+def cg(geom, sigma, nt, dt, data, iters, gamma=0.01, alpha_rel=0.25, omega=40.0):
+    """Algorithm 3: returns (sigma after `iters` iterations, log [iters, 5]
+    with columns J, |g|_L2, beta, alpha, max|d|)."""
+    lib = _load()
+    sig = np.array(sigma, dtype=np.float64, copy=True)
+    data = _f64(data)
+    log = np.zeros((iters, 5))
+    s = _src(0, omega)
+    rc = lib.orc_cg(ct.byref(geom._c()), _p(sig), ct.byref(s), nt, dt, _p(data), gamma,
+                    alpha_rel, iters, _p(log))
+    if rc:
+        raise RuntimeError(f"orc_cg failed ({rc})")
+    return sig, log

@@ -1,0 +1,389 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test names the passage of the paper it rests on (sections, equations
+and algorithms of arXiv 1509.01399) and the kind of pin: closed form,
+invariant, brute force on tiny inputs, or an independent second formulation.
+Together they are chosen so that a plausible slip anywhere in the oracle (a
+dropped term, a wrong sign or index, a transposed operand, a wrong weight)
+fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+from tests.assembled_ref import Merged, kuhn_cube_stiffness
+
+ABC, NEUMANN, SOURCE = 0, 1, 2
+
+
+def _eligible(C):
+    e = np.zeros((C, C, C), bool)
+    e[2:C - 2, 2:C - 2, 2:C - 2] = True
+    return e.ravel()
+
+
+def _rand_sigma(C, rng, lo=0.0, hi=2.0):
+    s = np.zeros(C ** 3)
+    el = _eligible(C)
+    s[el] = rng.uniform(lo, hi, el.sum())
+    return s
+
+
+# --------------------------------------------------------------- structure
+
+def test_kuhn_cube_couples_axis_edges_only():
+    """Sec. 7.2 element matrices on the 6 Kuhn tetrahedra of a cube: brute
+    force from vertex coordinates.  The cube stiffness has no face- or
+    body-diagonal coupling; axis-edge weights are h/3 on the 6 edges that
+    touch the (0,0,0) or (1,1,1) corner and h/6 on the other 6; summed over
+    the 4 cubes around an interior edge this gives h (seven-point stencil,
+    the coincidence of the FEM and FDM schemes claimed in the abstract)."""
+    h = 0.37
+    K = kuhn_cube_stiffness(h)
+    for i in range(8):
+        for j in range(8):
+            if i == j:
+                continue
+            diff = bin(i ^ j).count("1")
+            if diff != 1:
+                assert abs(K[i, j]) < 1e-14
+            else:
+                touches = 0 in (i, j) or 7 in (i, j)
+                assert abs(-K[i, j] - (h / 3 if touches else h / 6)) < 1e-14
+    assert np.allclose(K.sum(1), 0, atol=1e-14)
+
+
+def test_sizes_match_node_sets(orc):
+    """Sec. 3 node sets for the 40^3 grid with a central 16^3 FEM box."""
+    g = orc.Geometry(40, fem_o=12, fem_c=16)
+    s = g.sizes()
+    assert s["grid_nodes"] == 41 ** 3
+    assert s["fdm_updated"] == 41 ** 3 - 13 ** 3
+    assert s["fem_updated"] == 15 ** 3
+    assert s["omega_o"] == 17 ** 3 - 15 ** 3
+    assert s["omega_diamond"] == 13 ** 3 - 11 ** 3
+
+
+# ---------------------------------------------------------- FEM = FDM rows
+
+def test_fem_rows_equal_seven_point_when_a_is_one(orc):
+    """Abstract / Sec. 1: the explicit FEM and FDM schemes coincide on the
+    structured overlap.  One step from random levels u^0, u^{-1} with a = 1:
+    every FEM-updated node must equal the seven-point leapfrog of eq.
+    (fdmschemeforward) computed here directly."""
+    rng = np.random.default_rng(1)
+    n, o, C, h = 14, 3, 8, 1.0 / 14
+    dt = 0.3 * h
+    g = orc.Geometry(n, h=h, bc=(NEUMANN,) * 6, fem_o=o, fem_c=C)
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = rng.standard_normal((n + 1,) * 3)
+    _, vh = orc.forward(g, None, 1, dt, u0=u0, um1=um1, want_vhist=True)
+    v1 = vh[1].reshape((C + 1,) * 3)
+    lap = np.zeros_like(u0)
+    c = u0[1:-1, 1:-1, 1:-1]
+    lap[1:-1, 1:-1, 1:-1] = (u0[2:, 1:-1, 1:-1] + u0[:-2, 1:-1, 1:-1] + u0[1:-1, 2:, 1:-1]
+                             + u0[1:-1, :-2, 1:-1] + u0[1:-1, 1:-1, 2:] + u0[1:-1, 1:-1, :-2]
+                             - 6 * c) / h ** 2
+    ref = dt * dt * lap + 2 * u0 - um1
+    sl = slice(o + 1, o + C)
+    got = v1[1:-1, 1:-1, 1:-1]
+    want = ref[sl, sl, sl]
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_fem_rows_variable_coefficient(orc):
+    """Sec. 7.2 eq. (fem) with per-cube a: one FEM step equals the
+    edge-conductance stencil of the independent merged formulation."""
+    rng = np.random.default_rng(2)
+    n, o, C, h = 14, 3, 8, 1.0 / 14
+    dt = 0.2 * h
+    sig = _rand_sigma(C, rng, 0, 4)
+    g = orc.Geometry(n, h=h, bc=(NEUMANN,) * 6, fem_o=o, fem_c=C)
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = rng.standard_normal((n + 1,) * 3)
+    _, vh = orc.forward(g, sig, 1, dt, u0=u0, um1=um1, want_vhist=True)
+    M = Merged((n,) * 3, h, (NEUMANN,) * 6, (o,) * 3, (C,) * 3, sig)
+    ref = 2 * u0 - um1 - dt * dt * M.stiff(u0) / M.W
+    sl = slice(o + 1, o + C)
+    got = vh[1].reshape((C + 1,) * 3)[1:-1, 1:-1, 1:-1]
+    assert np.max(np.abs(got - ref[sl, sl, sl])) <= 1e-12 * np.max(np.abs(ref))
+
+
+# --------------------------------------------------- hybrid identities
+
+def test_hybrid_equals_pure_fdm_sigma_zero(orc):
+    """Algorithm 2 with a = 1: the hybrid trace equals the pure FDM trace."""
+    n, dt, nt = 24, 0.4 / 24, 120
+    a = orc.forward(orc.Geometry(n, fem_o=6, fem_c=12), None, nt, dt, omega=20.0)
+    b = orc.forward(orc.Geometry(n), None, nt, dt, omega=20.0)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_hybrid_invariant_to_fem_box_size(orc):
+    """Sec. 1: the hybrid is a pure FE scheme in disguise, so enlarging the
+    FEM box around the same inclusion does not change the trace."""
+    rng = np.random.default_rng(3)
+    n, dt, nt = 24, 0.25 / 24, 120
+    C1, o1 = 10, 7
+    s1 = _rand_sigma(C1, rng, 0, 3)
+    C2, o2 = 14, 5
+    s2 = np.zeros((C2,) * 3)
+    s2[2:12, 2:12, 2:12] = s1.reshape((C1,) * 3)  # same cells of the grid
+    a = orc.forward(orc.Geometry(n, fem_o=o1, fem_c=C1), s1, nt, dt, omega=20.0)
+    b = orc.forward(orc.Geometry(n, fem_o=o2, fem_c=C2), s2.ravel(), nt, dt, omega=20.0)
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("bc", [(ABC, ABC, ABC, ABC, ABC, SOURCE),
+                                (NEUMANN, ABC, NEUMANN, ABC, ABC, SOURCE),
+                                (NEUMANN, NEUMANN, NEUMANN, NEUMANN, ABC, SOURCE)])
+def test_hybrid_equals_merged_reference(orc, bc):
+    """Independent second formulation (tests/assembled_ref.py): the hybrid
+    FEM/FDM sweep equals a whole-grid edge-conductance leapfrog with the same
+    absorbing rows (eq. (eq:abs2)) and Neumann source (eq. (f))."""
+    rng = np.random.default_rng(4)
+    n, o, C = 16, 4, 8
+    h = 1.0 / n
+    dt, nt, om = 0.25 * h, 90, 30.0
+    sig = _rand_sigma(C, rng, 0, 4)
+    g = orc.Geometry(n, bc=bc, fem_o=o, fem_c=C)
+    a = orc.forward(g, sig, nt, dt, omega=om)
+    M = Merged((n,) * 3, h, bc, (o,) * 3, (C,) * 3, sig)
+    t1 = 2 * np.pi / om
+    k_on = max(k + 1 for k in range(nt) if k * dt < t1)
+    b = M.run(nt, dt, lambda k: np.sin(om * k * dt), k_on)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+
+
+# --------------------------------------------------------------- energy
+
+@pytest.mark.parametrize("with_sigma", [False, True])
+def test_energy_conserved_reflecting_walls(orc, with_sigma):
+    """Sec. 4 energy estimate with g = 0 and no absorbing flux: the discrete
+    energy of the leapfrog is constant.  Gaussian initial data as in eq.
+    (initcond) (read with x3^2), all faces reflecting."""
+    rng = np.random.default_rng(5)
+    n, o, C = 16, 4, 8
+    h = 1.0 / n
+    dt = 0.25 * h
+    sig = _rand_sigma(C, rng, 0, 4) if with_sigma else None
+    g = orc.Geometry(n, bc=(NEUMANN,) * 6, fem_o=o, fem_c=C)
+    x = np.arange(n + 1) * h - 0.5
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    u0 = np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / 0.02)
+    M = Merged((n,) * 3, h, (NEUMANN,) * 6, (o,) * 3, (C,) * 3, sig)
+
+    def merged(nt):
+        _, vh, uf = orc.forward(g, sig, nt, dt, u0=u0, um1=u0, want_vhist=True,
+                                want_ufinal=True)
+        u = uf.reshape((n + 1,) * 3).copy()
+        v = vh[nt].reshape((C + 1,) * 3)
+        u[o + 1:o + C, o + 1:o + C, o + 1:o + C] = v[1:-1, 1:-1, 1:-1]
+        return u
+
+    E = []
+    for k in (0, 37, 150):
+        E.append(M.energy(merged(k + 1), merged(k), dt))
+    assert E[0] > 0
+    assert max(abs(e - E[0]) for e in E) <= 1e-12 * E[0]
+
+
+# ------------------------------------------------------ plane wave closed form
+
+def _plane_wave_obs(orc, nz, om, T, frac=0.4):
+    h = 1.0 / nz
+    dt = frac * h
+    nt = int(round(T / dt))
+    g = orc.Geometry((2, 2, nz), h=h, bc=(NEUMANN, NEUMANN, NEUMANN, NEUMANN, ABC, SOURCE))
+    obs = orc.forward(g, None, nt, dt, omega=om)
+    return obs, dt, nt
+
+
+def _F(s, om):
+    """u(z,t) = F(t + z - 1), F(s) = integral_0^s p (eq. (f)): the exact
+    plane wave in the waveguide of Model Problem 2 with a = 1."""
+    s = np.asarray(s)
+    t1 = 2 * np.pi / om
+    return np.where((s > 0) & (s < t1), (1 - np.cos(om * s)) / om, 0.0)
+
+
+def test_plane_wave_closed_form(orc):
+    """Model Problem 2 with a = 1 in a waveguide (Neumann lateral faces S_3,
+    source on the front face, absorbing back face): the trace converges to
+    the closed form F(t) at second order, and is uniform across the face."""
+    om, T = 10.0, 1.5
+    errs = []
+    for nz in (40, 80):
+        obs, dt, nt = _plane_wave_obs(orc, nz, om, T)
+        assert np.max(np.abs(obs - obs[:, :1, :1])) <= 1e-13 * np.max(np.abs(obs))
+        t = np.arange(nt + 1) * dt
+        errs.append(np.max(np.abs(obs[:, 1, 1] - _F(t, om))) / np.max(_F(t, om)))
+    assert errs[0] < 0.03
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_plane_wave_absorbed_at_back_face(orc):
+    """eq. (eq:abs2) is exact for normal incidence in the continuum: after the
+    pulse has crossed the unit box and left through the absorbing back face,
+    almost nothing comes back to the observed face (a wrong sign of r would
+    reflect it)."""
+    om = 10.0
+    obs, dt, nt = _plane_wave_obs(orc, 80, om, 3.5)
+    t = np.arange(nt + 1) * dt
+    late = t > 2 * np.pi / om + 2.05  # after the round trip front->back->front
+    assert np.max(np.abs(obs[late, 1, 1])) < 2e-3 * np.max(np.abs(obs))
+
+
+def test_second_order_convergence_smooth_pulse(orc):
+    """Leapfrog + ghost-node source + absorbing rows are second order for a
+    smooth (C^2) pulse: flux p = sin^3(omega t) on (0, pi/omega), fed as a
+    per-step flux table; the final field is compared with the closed form."""
+    om, T = 20.0, 0.8
+    errs = []
+    for nz in (80, 160, 320):
+        h = 1.0 / nz
+        dt = 0.4 * h
+        nt = int(round(T / dt))
+        t1 = np.pi / om
+        k_on = max(k + 1 for k in range(nt) if k * dt < t1)
+        flux = np.zeros((nt, 9))
+        for k in range(k_on):
+            flux[k] = np.sin(om * k * dt) ** 3
+        g = orc.Geometry((2, 2, nz), h=h, bc=(NEUMANN,) * 4 + (ABC, SOURCE))
+        _, uf = orc.forward(g, None, nt, dt, flux=flux, k_on=k_on, want_ufinal=True)
+        u = uf.reshape(nz + 1, 3, 3)[:, 1, 1]
+        z = np.arange(nz + 1) * h
+        s = nt * dt + z - 1.0
+        # F(s) = int_0^s sin^3(om t) dt on (0, pi/om), constant after
+        ss = np.clip(s, 0, t1)
+        F = (2 / 3 - np.cos(om * ss) + np.cos(om * ss) ** 3 / 3) / om
+        F = np.where(s > 0, F, 0.0)
+        errs.append(np.sqrt(np.mean((u - F) ** 2)) / np.sqrt(np.mean(F ** 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > 1.85, (errs, orders)
+
+
+def test_plane_wave_source_table_matches_closed_source(orc):
+    """The per-step flux table path reproduces the built-in pulse of eq. (f)."""
+    n, dt, nt, om = 12, 0.4 / 12, 60, 40.0
+    g = orc.Geometry(n, fem_o=2, fem_c=8)
+    a = orc.forward(g, None, nt, dt, omega=om)
+    t1 = 2 * np.pi / om
+    k_on = max(k + 1 for k in range(nt) if k * dt < t1)
+    flux = np.zeros((nt, g.nface))
+    for k in range(k_on):
+        flux[k] = np.sin(om * k * dt)
+    b = orc.forward(g, None, nt, dt, flux=flux, k_on=k_on)
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------- adjoint
+
+@pytest.mark.parametrize("bc", [(ABC, ABC, ABC, ABC, ABC, SOURCE),
+                                (NEUMANN, ABC, NEUMANN, NEUMANN, ABC, SOURCE)])
+def test_adjoint_dot_test_source(orc, bc):
+    """The reverse sweep is the exact transpose of the forward sweep
+    (Sec. 6 Lagrangian, discretised first): <A f, r> = <f, A^T r> for the
+    linear map from the source flux table to the recorded trace."""
+    rng = np.random.default_rng(6)
+    n, o, C = 12, 2, 8
+    h = 1.0 / n
+    dt, nt, k_on = 0.25 * h, 50, 30
+    g = orc.Geometry(n, bc=bc, fem_o=o, fem_c=C)
+    sig = _rand_sigma(C, rng, 0, 4)
+    flux = rng.standard_normal((nt, g.nface))
+    obs = orc.forward(g, sig, nt, dt, flux=flux, k_on=k_on)
+    r = rng.standard_normal(obs.shape)
+    _, dflux = orc.adjoint(g, sig, nt, dt, r, flux=flux, k_on=k_on, want_dflux=True)
+    lhs, rhs = np.sum(obs * r), np.sum(flux[:k_on] * dflux[:k_on])
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+    assert np.all(dflux[k_on:] == 0)
+
+
+def test_adjoint_dot_test_initial_levels(orc):
+    """Dot test for the map (u^0, u^{-1}) -> trace (Model Problem 1 data):
+    exercises the FEM copies of the initial levels and the full interior."""
+    rng = np.random.default_rng(7)
+    n, o, C = 12, 2, 8
+    h = 1.0 / n
+    dt, nt = 0.25 * h, 40
+    g = orc.Geometry(n, bc=(ABC, NEUMANN, ABC, ABC, NEUMANN, SOURCE), fem_o=o, fem_c=C)
+    sig = _rand_sigma(C, rng, 0, 4)
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = rng.standard_normal((n + 1,) * 3)
+    zero_flux = np.zeros((nt, g.nface))
+    obs = orc.forward(g, sig, nt, dt, flux=zero_flux, k_on=0, u0=u0, um1=um1)
+    r = rng.standard_normal(obs.shape)
+    _, du0, dum1 = orc.adjoint(g, sig, nt, dt, r, flux=zero_flux, k_on=0, want_dinit=True)
+    lhs = np.sum(obs * r)
+    rhs = np.sum(u0.ravel() * du0) + np.sum(um1.ravel() * dum1)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_gradient_matches_central_differences(orc):
+    """eq. (grad1new)/(gradient1) in discrete form: the returned L2 gradient
+    times h^3 is the derivative of the discrete Tikhonov functional,
+    eq. (functional); central differences on every free cube of a tiny grid."""
+    rng = np.random.default_rng(8)
+    n, o, C = 12, 2, 8
+    h = 1.0 / n
+    dt, nt, om, gamma = 0.25 * h, 60, 40.0, 0.01
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    el = _eligible(C)
+    data = orc.forward(g, np.where(el, 1.5, 0.0), nt, dt, omega=om)
+    sig = _rand_sigma(C, rng, 0, 2)
+    gr, J = orc.gradient(g, sig, nt, dt, data, gamma=gamma, omega=om)
+    assert np.all(gr[~el] == 0)
+    eps = 1e-5
+    worst = 0.0
+    for c in np.flatnonzero(el):
+        sp, sm = sig.copy(), sig.copy()
+        sp[c] += eps
+        sm[c] -= eps
+        fd = (orc.gradient(g, sp, nt, dt, data, gamma=gamma, omega=om)[1]
+              - orc.gradient(g, sm, nt, dt, data, gamma=gamma, omega=om)[1]) / (2 * eps) / h ** 3
+        worst = max(worst, abs(fd - gr[c]) / np.max(np.abs(gr)))
+    assert worst < 1e-6
+
+
+def test_misfit_quadrature_closed_form(orc):
+    """eq. (functional) misfit with trapezoid weights in space and the
+    rectangle rule in time: a constant mismatch d over the unit face for nt
+    steps gives J = 1/2 * nt * tau * d^2 exactly (face area 1)."""
+    n, nt, dt, d = 10, 7, 0.03, 0.6
+    g = orc.Geometry(n)
+    obs = np.zeros((nt + 1, n + 1, n + 1))
+    data = obs - d
+    J, seed = orc.misfit(g, nt, dt, obs, data)
+    assert abs(J - 0.5 * nt * dt * d * d) < 1e-14
+    assert np.all(seed[0] == 0)
+    assert abs(seed[1].sum() - dt * d) < 1e-14
+
+
+# ------------------------------------------------------------------- CG
+
+def test_cg_invariants(orc):
+    """Algorithm 3: the first direction is -g^0, steps are bounded by
+    alpha_rel in the max norm, a stays in the admissible set [1,5]
+    (eq. (admpar)), the functional decreases and the iterate moves towards
+    the true conductivity (noise-free data from the same grid)."""
+    # omega = 10 keeps about 7 cells per wavelength on this 12-cell grid; at
+    # omega = 40 the wave is aliased and a relative step of 0.25 overshoots.
+    n, o, C = 12, 2, 8
+    h = 1.0 / n
+    dt, nt, om = 0.25 * h, 120, 10.0
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    el = _eligible(C)
+    true = np.zeros((C,) * 3)
+    true[3:5, 3:5, 3:5] = 2.0
+    true = true.ravel()
+    data = orc.forward(g, true, nt, dt, omega=om)
+    s0 = np.zeros(C ** 3)
+    g0, J0 = orc.gradient(g, s0, nt, dt, data, omega=om)
+    s1, log1 = orc.cg(g, s0, nt, dt, data, 1, omega=om)
+    alpha = 0.25 / np.max(np.abs(g0))
+    assert np.allclose(s1, np.clip(s0 - alpha * g0, 0, 4), rtol=0, atol=1e-15)
+    s3, log = orc.cg(g, s0, nt, dt, data, 4, omega=om)
+    assert np.all(log[:, 0][1:] < log[:, 0][:-1])
+    assert np.all((s3 >= 0) & (s3 <= 4))
+    assert np.all(s3[~el] == 0)
+    assert np.linalg.norm(s3 - true) < np.linalg.norm(s0 - true)
