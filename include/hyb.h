@@ -1,0 +1,231 @@
+/*
+ * hyb.h -- C ABI of the MI355X domain-decomposition FEM/FDM wave solver
+ * (L. Beilina, "Domain decomposition finite element/finite difference method
+ * for the conductivity reconstruction in a hyperbolic equation",
+ * arXiv 1509.01399).
+ *
+ * One context (hyb_ctx) owns all device state of one problem on one GPU:
+ * the wavefields of the structured outer grid (finite differences) and of
+ * the inner tetrahedral box (finite elements), the forward history or
+ * checkpoints needed by the adjoint, the FP64 gradient accumulator and the
+ * conjugate-gradient direction.  Every compute step runs in hand-written HIP
+ * kernels for gfx950 on the context's stream.
+ *
+ * Conventions used by every call
+ *  - Grid: n_cells[d] cells of size h per axis, (n_cells[d]+1) nodes, x
+ *    fastest.  Faces are ordered x-, x+, y-, y+, z-, z+.  The backscattered
+ *    trace (S_T of Sec. 5) is recorded on the z+ face, which is also the
+ *    only face that may carry the plane-wave source.
+ *  - FEM box: the tetrahedral mesh passed to hyb_create must be the split of
+ *    a box of whole grid cells [o, o+C] into 6 tetrahedra per cube sharing
+ *    the cube diagonal (a structured P1 mesh conforming to the grid, so that
+ *    the FEM and FDM schemes coincide on the overlap, Sec. 1 and Sec. 3).
+ *    The box must keep >= 1 cell to the outer boundary and be >= 5 cells
+ *    wide.  General unstructured meshes return HYB_E_UNSUPPORTED.
+ *  - Conductivity: a = 1 + sigma, sigma piecewise constant per FEM cube
+ *    (a subspace of C_h, eq. (p0)), laid out [C_z][C_y][C_x] (x fastest),
+ *    FP64.  Cubes within two cells of the FEM boundary are the overlap layer
+ *    where a = 1 (condition (2.3)); their sigma is ignored and their gradient
+ *    is 0.  Admissible values 0 <= sigma <= 4 (eq. (admpar)).
+ *  - Traces: obs / residual / data are FP64 device arrays
+ *    [nt+1][(n_x+1)(n_y+1)] (level k = time k*dt; level 0 included).
+ *  - Pointers named *_dev are device pointers owned by the caller; they must
+ *    stay valid until the call's work has completed on the stream.  Pointers
+ *    named *_host are host pointers.  Mesh arrays are host pointers that are
+ *    copied during hyb_create.
+ *  - Asynchrony: calls enqueue work on opts.hip_stream and return.  Calls
+ *    that return a host scalar (J, gnorm) synchronise that stream.
+ *  - Errors: argument, mesh, CFL and state errors are detected on the host
+ *    before any work is enqueued and leave the context unchanged.  Device
+ *    errors are reported as HYB_E_DEVICE by the call that observes them.
+ *    hyb_last_error returns a text description of the last error.
+ */
+#ifndef HYB_H
+#define HYB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hyb_ctx hyb_ctx;
+
+typedef enum {
+    HYB_OK = 0,
+    HYB_E_ARG = -1,          /* invalid argument (null, size, range)           */
+    HYB_E_MESH = -2,         /* FEM mesh does not conform to the grid          */
+    HYB_E_CFL = -3,          /* dt above the CFL bound tau <= h / sqrt(3 a)    */
+    HYB_E_STATE = -4,        /* call out of order (e.g. adjoint before forward)*/
+    HYB_E_OOM = -5,          /* device allocation failed                       */
+    HYB_E_DEVICE = -6,       /* HIP runtime error                              */
+    HYB_E_NONFINITE = -7,    /* NaN/Inf in an input                            */
+    HYB_E_UNSUPPORTED = -8   /* valid but not supported by this build          */
+} hyb_status;
+
+/* Face conditions of the outer boundary.
+ * ABC: first-order absorbing condition d_n u = -d_t u, discretised as in
+ *      eq. (eq:abs2) (Sec. 7.4).
+ * NEUMANN: d_n u = 0 (the lateral faces S_3 of Model Problems 1-2, Sec. 5).
+ * SOURCE: z+ only; d_n u = p(t) while the pulse is on (S_{1,1}), absorbing
+ *      afterwards (S_{1,2}), Model Problem 2 eq. (model2). */
+typedef enum { HYB_BC_ABC = 0, HYB_BC_NEUMANN = 1, HYB_BC_SOURCE = 2 } hyb_bc;
+
+typedef struct {
+    int32_t n_cells[3];   /* cells per axis (>= 2)                                  */
+    double h;             /* cell size, equal on all axes (> 0)                     */
+    double origin[3];     /* coordinates of grid node (0,0,0)                       */
+    int32_t face[6];      /* hyb_bc per face x-,x+,y-,y+,z-,z+                      */
+} hyb_fd_grid;
+
+typedef struct {
+    int64_t n_nodes;      /* (C_x+1)(C_y+1)(C_z+1)                                  */
+    const double *xyz;    /* host [n_nodes][3] node coordinates                     */
+    int64_t n_tets;       /* 6 C_x C_y C_z                                          */
+    const int32_t *tet4;  /* host [n_tets][4] node ids (0-based)                    */
+} hyb_fem_mesh;
+
+typedef struct {
+    int32_t width_cells;  /* overlap thickness; the method uses 2 (Sec. 3)          */
+} hyb_overlap;
+
+typedef struct {
+    int32_t field_f32;    /* 0: FP64 wavefields; 1: FP32 wavefields (the gradient
+                             integral, CG reductions and sigma stay FP64)           */
+    int32_t store_mode;   /* forward states kept for the adjoint:
+                             0: FEM-box history of every level;
+                             1: sqrt(nt) checkpoints of the full state (field
+                                precision) with segment recompute;
+                             2: as 1, checkpoint increments in BF16             */
+    double gamma;         /* Tikhonov regularisation parameter (eq. (functional))*/
+    double alpha_rel;     /* CG step: alpha^m = alpha_rel / max|d^m|            */
+    void *hip_stream;     /* hipStream_t for all work; NULL = default stream      */
+} hyb_opts;
+
+typedef struct {
+    int32_t kind;         /* 0: plane wave p(t) = sin(omega t) for
+                                t < 2 pi / omega, then 0 (eq. (f));
+                             1: flux table                                       */
+    double omega;         /* kind 0: angular frequency (> 0)                     */
+    const double *flux_dev; /* kind 1: device [nt][(n_x+1)(n_y+1)] flux d_n u   */
+    int32_t k_on;         /* kind 1: steps k < k_on use the flux; afterwards the
+                             z+ face is absorbing                                */
+} hyb_source;
+
+typedef struct {
+    int32_t iter;         /* CG iterations done (0 before the first)             */
+    double gnorm2_prev;   /* |g^{m-1}|^2_{L2} (host copy, informational)         */
+} hyb_cg_state;
+
+/* Create a context.  Validates the grid, the FEM mesh (must be the 6-tet
+ * split of a box of grid cells) and the overlap width (must be 2), computes
+ * the P1 element stiffness of the mesh from its vertex coordinates and
+ * allocates the wavefields.  opts may be NULL (FP64, history, gamma = 0.01,
+ * alpha_rel = 0.25, default stream).  fem may be NULL for a pure
+ * finite-difference grid (no FEM box, no conductivity).  On success *out
+ * owns the device state until hyb_destroy.
+ * Errors: HYB_E_ARG, HYB_E_MESH, HYB_E_UNSUPPORTED, HYB_E_OOM, HYB_E_DEVICE. */
+hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem,
+                      const hyb_overlap *overlap, const hyb_opts *opts, hyb_ctx **out);
+
+/* Release all device memory of the context (synchronises its stream). */
+void hyb_destroy(hyb_ctx *ctx);
+
+/* Forward solve (Algorithm 2, Sec. 7.5) for nt steps of size dt:
+ * each step updates the FDM nodes with eq. (fdmschemeforward), the FEM nodes
+ * with the lumped-mass scheme eq. (fem), the outer boundary with eq.
+ * (eq:abs2) and the source of eq. (f), then copies the FEM values to the
+ * FDM inner boundary omega_diamond and the FDM values to the FEM boundary
+ * omega_o (Algorithm 1).  Zero initial data (Model Problem 2).
+ * sigma_dev: device FP64 [C^3] (NULL = a = 1; must be NULL without FEM box).
+ * obs_dev:   device FP64 [nt+1][face] receives the z+ trace (may be NULL).
+ * Keeps what the adjoint needs according to opts.store_mode.
+ * Errors: HYB_E_ARG (nt < 1, dt <= 0, source), HYB_E_CFL (dt above
+ * h/sqrt(3 max a)), HYB_E_NONFINITE (sigma not finite), HYB_E_OOM. */
+hyb_status hyb_forward(hyb_ctx *ctx, const double *sigma_dev, const hyb_source *src,
+                       int32_t nt, double dt, double *obs_dev);
+
+/* Model Problem 1 initial data for the next hyb_forward (and only that one):
+ * u0_dev, um1_dev are device FP64 [(n_z+1)(n_y+1)(n_x+1)] levels u^0 and
+ * u^{-1} (NULL = zero).  Copied on the stream. */
+hyb_status hyb_set_initial(hyb_ctx *ctx, const double *u0_dev, const double *um1_dev);
+
+/* Adjoint solve: the exact transpose of the last forward sweep, run backward
+ * in time (in the interior it is eq. (fdmschemeadjoint) and the second line
+ * of eq. (fem); boundary, source and exchange rows are transposed exactly).
+ * residual_dev: device FP64 [nt+1][face].
+ *   mode 0: residual = obs - data; the trace cotangent is
+ *           tau * w_i * residual (trapezoid weights w_i on the z+ face,
+ *           rectangle rule in time, z_delta = 1), i.e. the misfit part of
+ *           eq. (functional);
+ *   mode 1: residual is the raw cotangent dL/dobs (autograd).
+ * Accumulates, fused with the FEM adjoint update, the FP64 time integral of
+ * eq. (gradient1) per cube.  Requires a preceding hyb_forward (HYB_E_STATE).
+ * Errors: HYB_E_ARG, HYB_E_STATE, HYB_E_OOM. */
+hyb_status hyb_adjoint(hyb_ctx *ctx, const double *residual_dev, int32_t mode);
+
+/* Finalise the gradient of the last adjoint into grad_dev (device FP64
+ * [C^3]; 0 on overlap cubes):
+ *   mode 0: g_c = (1/h^3) dJ/dsigma_c + gamma * sigma_c, the L2 density of
+ *           eq. (gradient1) for J of eq. (functional) (a_0 = 1);
+ *   mode 1: g_c = dL/dsigma_c (Euclidean, no regularisation).
+ * J_host (nullable, mode 0 only): J = misfit + regularisation (synchronises).
+ * Errors: HYB_E_ARG, HYB_E_STATE. */
+hyb_status hyb_gradient(hyb_ctx *ctx, double *grad_dev, double *J_host);
+
+/* One iteration of Algorithm 3 (Sec. 8) at sigma_dev (device FP64 [C^3],
+ * updated in place): forward, residual obs - data, adjoint, gradient g^m,
+ * beta^m = |g^m|^2 / |g^{m-1}|^2 (beta^0 = 0), d^m = -g^m + beta^m d^{m-1},
+ * alpha^m = alpha_rel / max|d^m|, sigma <- clip(sigma + alpha^m d^m, 0, 4)
+ * on the free cubes.  All of it in FP64 on the device; the direction d lives
+ * in the context.  state (in/out) counts iterations; *gnorm_host (nullable)
+ * receives |g^m|_{L2} for the stopping test (synchronises), *J_host the
+ * functional at sigma^m.
+ * Errors: as hyb_forward/hyb_adjoint. */
+hyb_status hyb_cg_step(hyb_ctx *ctx, const double *data_dev, double *sigma_dev,
+                       const hyb_source *src, int32_t nt, double dt, hyb_cg_state *state,
+                       double *gnorm_host, double *J_host);
+
+/* Device bytes a context with these arguments needs for nt steps (fields,
+ * history or checkpoints, accumulators), without allocating anything.
+ * Errors: HYB_E_ARG, HYB_E_MESH, HYB_E_UNSUPPORTED. */
+hyb_status hyb_footprint(const hyb_fd_grid *grid, const hyb_fem_mesh *fem,
+                         const hyb_overlap *overlap, const hyb_opts *opts, int32_t nt,
+                         size_t *bytes);
+
+/* Wait for all work of the context; returns the first pending device error. */
+hyb_status hyb_sync(hyb_ctx *ctx);
+
+/* Text of the last error of ctx (or of the last failed hyb_create when ctx
+ * is NULL).  The string is owned by the library. */
+const char *hyb_last_error(const hyb_ctx *ctx);
+
+/* Node counts used by the throughput metric: *fdm = nodes updated by the
+ * finite-difference scheme or the outer boundary rows per step, *fem = FEM
+ * nodes updated per step. */
+hyb_status hyb_counts(const hyb_ctx *ctx, int64_t *fdm, int64_t *fem);
+
+/* Average device time (ms) of one launch of the dominant kernel (the fused
+ * FDM/FEM interior update of the forward sweep) over `reps` launches on the
+ * context's stream, measured with HIP events around the launches, after the
+ * given forward set-up (sigma_dev, dt).  The wavefield content is arbitrary
+ * (the kernel's cost does not depend on values).  Synchronises.
+ * Errors: HYB_E_ARG, HYB_E_STATE, HYB_E_DEVICE. */
+hyb_status hyb_time_interior(hyb_ctx *ctx, const double *sigma_dev, double dt, int32_t reps,
+                             double *ms_host);
+
+/* Copy the newest level of the last sweep to caller buffers (FP64, unpadded):
+ *   which 0: u^{nt} of the last forward sweep;
+ *   which 1: the multipliers of level 0 of the last adjoint sweep, i.e. the
+ *            cotangent of u^0 (grid part; the FEM part is the cotangent of the
+ *            FEM copy of u^0, to be added on the FEM box nodes).
+ * u_dev: device [(n_z+1)(n_y+1)(n_x+1)] grid part (nullable);
+ * v_dev: device [(C+1)^3] FEM part (nullable; ignored without FEM box).
+ * Errors: HYB_E_ARG, HYB_E_STATE (no such sweep yet). */
+hyb_status hyb_get_wavefield(hyb_ctx *ctx, int32_t which, double *u_dev, double *v_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYB_H */

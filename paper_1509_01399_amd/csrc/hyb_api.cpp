@@ -1,0 +1,803 @@
+// Host side of libhyb: the C ABI of include/hyb.h.  Validates inputs, turns
+// the tetrahedral FEM mesh into per-cube P1 element weights, owns the device
+// memory of one problem and drives the time loops of Algorithm 2 (forward and
+// exact adjoint) and the conjugate-gradient iteration of Algorithm 3.  All
+// arithmetic on fields runs in the kernels of hyb_kernels.hip.
+#include "../../include/hyb.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hyb_internal.h"
+
+using namespace hyb;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct Mesh {
+    int o[3] = {0, 0, 0}, C[3] = {0, 0, 0};
+    double w[12] = {0};  // cube edge weights / h
+};
+
+}  // namespace
+
+struct hyb_ctx {
+    Geo g{};
+    int n[3]{};
+    double h = 0;
+    int bc[6]{};
+    int f32 = 0, store_mode = 0;
+    double gamma = 0.01, alpha_rel = 0.25;
+    hipStream_t stream = nullptr;
+    Mesh mesh;
+    size_t esz = 8;  // field element size
+    // device memory
+    void *U[3]{}, *V[3]{}, *P[3]{}, *Q[3]{};
+    void *acube = nullptr;
+    void *hist = nullptr;
+    size_t hist_levels = 0;
+    double *sig = nullptr, *G = nullptr, *dir = nullptr, *grad = nullptr;
+    double *obsbuf = nullptr, *resbuf = nullptr;
+    size_t tracebuf_levels = 0;
+    double *partials = nullptr, *scal = nullptr;
+    const double *ic_u0 = nullptr, *ic_um1 = nullptr;
+    bool ic_set = false;
+    // state of the last forward / adjoint
+    bool have_forward = false, have_adjoint = false;
+    int nt = 0, k_on = 0, adj_mode = 0;
+    int last_u = 1, last_p = 1;  // buffer index of the newest level
+    double dt = 0;
+    std::string err;
+};
+
+namespace {
+
+hyb_status fail(hyb_ctx *c, hyb_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    else g_create_err = msg;
+    return s;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, HYB_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+// Gradients of the barycentric coordinates of a tetrahedron (P1 element,
+// Sec. 7.2) and its volume from the vertex coordinates.
+double tet_grads(const double X[4][3], double Gr[4][3])
+{
+    double E[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) E[r][c] = X[c + 1][r] - X[0][r];
+    const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                       E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                       E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+    double I[3][3];  // rows: gradients of barycentric coordinates 1..3
+    I[0][0] = (E[1][1] * E[2][2] - E[1][2] * E[2][1]) / det;
+    I[0][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) / det;
+    I[0][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) / det;
+    I[1][0] = (E[1][2] * E[2][0] - E[1][0] * E[2][2]) / det;
+    I[1][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) / det;
+    I[1][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) / det;
+    I[2][0] = (E[1][0] * E[2][1] - E[1][1] * E[2][0]) / det;
+    I[2][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) / det;
+    I[2][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) / det;
+    for (int c = 0; c < 3; ++c) {
+        Gr[0][c] = -(I[0][c] + I[1][c] + I[2][c]);
+        for (int r = 0; r < 3; ++r) Gr[r + 1][c] = I[r][c];
+    }
+    return std::fabs(det) / 6.0;
+}
+
+// Check that the mesh is the 6-tetrahedra split of a box of grid cells and
+// extract the box and the per-cube P1 stiffness (a = 1), which must be the
+// same for every cube and couple only along the 12 axis edges (then the FEM
+// update is exactly an edge-conductance stencil, which the kernels use).
+hyb_status analyse_mesh(const hyb_fd_grid *gr, const hyb_fem_mesh *m, Mesh *out, hyb_ctx *c)
+{
+    const double h = gr->h;
+    if (m->n_nodes < 8 || m->n_tets < 6 || !m->xyz || !m->tet4)
+        return fail(c, HYB_E_ARG, "fem mesh: empty or null arrays");
+    double lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) { lo[d] = 1e300; hi[d] = -1e300; }
+    for (int64_t i = 0; i < m->n_nodes; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double v = m->xyz[3 * i + d];
+            if (!std::isfinite(v)) return fail(c, HYB_E_NONFINITE, "fem mesh: non-finite coordinate");
+            lo[d] = std::min(lo[d], v);
+            hi[d] = std::max(hi[d], v);
+        }
+    const double tol = 1e-7 * h;
+    for (int d = 0; d < 3; ++d) {
+        const double fo = (lo[d] - gr->origin[d]) / h, fc = (hi[d] - lo[d]) / h;
+        out->o[d] = (int)std::lround(fo);
+        out->C[d] = (int)std::lround(fc);
+        if (std::fabs(fo - out->o[d]) * h > tol || std::fabs(fc - out->C[d]) * h > tol)
+            return fail(c, HYB_E_MESH, "fem mesh: box corners are not grid nodes");
+        if (out->C[d] < 5) return fail(c, HYB_E_MESH, "fem mesh: box must be at least 5 cells wide");
+        if (out->o[d] < 1 || out->o[d] + out->C[d] > gr->n_cells[d] - 1)
+            return fail(c, HYB_E_MESH, "fem mesh: box must keep at least one cell to the outer boundary");
+    }
+    if (out->C[0] != out->C[1] || out->C[1] != out->C[2])
+        return fail(c, HYB_E_UNSUPPORTED, "fem mesh: only cubic FEM boxes are supported");
+    const long long fx = out->C[0] + 1, fy = out->C[1] + 1, fz = out->C[2] + 1;
+    const long long ncube = (long long)out->C[0] * out->C[1] * out->C[2];
+    if (m->n_nodes != fx * fy * fz || m->n_tets != 6 * ncube)
+        return fail(c, HYB_E_UNSUPPORTED, "fem mesh: not a 6-tetrahedra split of its box (node/tet count)");
+    // lattice position of every node, must be a bijection onto the box nodes
+    std::vector<int64_t> lat(m->n_nodes);
+    std::vector<int64_t> owner(m->n_nodes, -1);
+    for (int64_t i = 0; i < m->n_nodes; ++i) {
+        long long q[3];
+        for (int d = 0; d < 3; ++d) {
+            const double f = (m->xyz[3 * i + d] - lo[d]) / h;
+            q[d] = std::llround(f);
+            if (std::fabs(f - q[d]) * h > tol) return fail(c, HYB_E_MESH, "fem mesh: node off the grid");
+        }
+        const int64_t L = q[0] + fx * (q[1] + fy * q[2]);
+        if (owner[L] >= 0) return fail(c, HYB_E_MESH, "fem mesh: duplicate node");
+        owner[L] = i;
+        lat[i] = L;
+    }
+    // every tetrahedron: one of the 6 diagonal tetrahedra of one cube
+    std::vector<uint8_t> seen(ncube, 0);
+    std::vector<int64_t> tet_of(6 * ncube, -1);
+    for (int64_t t = 0; t < m->n_tets; ++t) {
+        long long v[4][3], s[4];
+        for (int q = 0; q < 4; ++q) {
+            const int32_t id = m->tet4[4 * t + q];
+            if (id < 0 || id >= m->n_nodes) return fail(c, HYB_E_ARG, "fem mesh: node id out of range");
+            const int64_t L = lat[id];
+            v[q][0] = L % fx;
+            v[q][1] = (L / fx) % fy;
+            v[q][2] = L / (fx * fy);
+            s[q] = v[q][0] + v[q][1] + v[q][2];
+        }
+        int ord[4] = {0, 1, 2, 3};
+        std::sort(ord, ord + 4, [&](int a, int b) { return s[a] < s[b]; });
+        int perm_code = 0, used = 0;
+        bool ok = true;
+        for (int q = 1; q < 4 && ok; ++q) {
+            int ax = -1, nd = 0;
+            for (int d = 0; d < 3; ++d) {
+                const long long df = v[ord[q]][d] - v[ord[q - 1]][d];
+                if (df == 1) { ax = d; ++nd; }
+                else if (df != 0) ok = false;
+            }
+            if (nd != 1 || (used >> ax & 1)) ok = false;
+            else { used |= 1 << ax; perm_code = perm_code * 3 + ax; }
+        }
+        if (!ok) return fail(c, HYB_E_UNSUPPORTED, "fem mesh: tetrahedron is not a cube-diagonal tetrahedron");
+        static const int codes[6] = {0 * 9 + 1 * 3 + 2, 0 * 9 + 2 * 3 + 1, 1 * 9 + 0 * 3 + 2,
+                                     1 * 9 + 2 * 3 + 0, 2 * 9 + 0 * 3 + 1, 2 * 9 + 1 * 3 + 0};
+        int p = -1;
+        for (int q = 0; q < 6; ++q)
+            if (codes[q] == perm_code) p = q;
+        const long long *b = v[ord[0]];
+        if (b[0] >= out->C[0] || b[1] >= out->C[1] || b[2] >= out->C[2])
+            return fail(c, HYB_E_MESH, "fem mesh: tetrahedron outside the box");
+        const long long cube = b[0] + out->C[0] * (b[1] + (long long)out->C[1] * b[2]);
+        if (seen[cube] >> p & 1) return fail(c, HYB_E_MESH, "fem mesh: duplicate tetrahedron");
+        seen[cube] |= (uint8_t)(1 << p);
+        tet_of[6 * cube + p] = t;
+    }
+    // per-cube stiffness from the element matrices; all cubes must agree
+    double Kref[8][8];
+    std::vector<double> mass(m->n_nodes, 0.0);
+    for (long long cube = 0; cube < ncube; ++cube) {
+        if (seen[cube] != 63) return fail(c, HYB_E_MESH, "fem mesh: cube not covered by its 6 tetrahedra");
+        const long long ci = cube % out->C[0], cj = (cube / out->C[0]) % out->C[1],
+                        ck = cube / ((long long)out->C[0] * out->C[1]);
+        double K[8][8];
+        std::memset(K, 0, sizeof K);
+        for (int p = 0; p < 6; ++p) {
+            const int64_t t = tet_of[6 * cube + p];
+            double X[4][3], Gr[4][3];
+            int loc[4];
+            for (int q = 0; q < 4; ++q) {
+                const int32_t id = m->tet4[4 * t + q];
+                for (int d = 0; d < 3; ++d) X[q][d] = m->xyz[3 * id + d];
+                const int64_t L = lat[id];
+                const long long a = L % fx - ci, b = (L / fx) % fy - cj, cc = L / (fx * fy) - ck;
+                loc[q] = (int)(a + 2 * b + 4 * cc);
+            }
+            const double vol = tet_grads(X, Gr);
+            for (int q = 0; q < 4; ++q) {
+                mass[m->tet4[4 * t + q]] += vol / 4.0;
+                for (int r = 0; r < 4; ++r)
+                    K[loc[q]][loc[r]] += vol * (Gr[q][0] * Gr[r][0] + Gr[q][1] * Gr[r][1] + Gr[q][2] * Gr[r][2]);
+            }
+        }
+        if (cube == 0) std::memcpy(Kref, K, sizeof K);
+        else
+            for (int a = 0; a < 8; ++a)
+                for (int b = 0; b < 8; ++b)
+                    if (std::fabs(K[a][b] - Kref[a][b]) > 1e-9 * h)
+                        return fail(c, HYB_E_UNSUPPORTED, "fem mesh: cubes with different element matrices");
+    }
+    for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b)
+            if (a != b && __builtin_popcount(a ^ b) != 1 && std::fabs(Kref[a][b]) > 1e-9 * h)
+                return fail(c, HYB_E_UNSUPPORTED, "fem mesh: element matrices couple across cube diagonals");
+    // lumped mass of the FEM interior nodes must be h^3 (uniform cells)
+    const double h3 = h * h * h;
+    for (int64_t i = 0; i < m->n_nodes; ++i) {
+        const int64_t L = lat[i];
+        const long long a = L % fx, b = (L / fx) % fy, cc = L / (fx * fy);
+        if (a > 0 && a < fx - 1 && b > 0 && b < fy - 1 && cc > 0 && cc < fz - 1 &&
+            std::fabs(mass[i] - h3) > 1e-9 * h3)
+            return fail(c, HYB_E_UNSUPPORTED, "fem mesh: non-uniform lumped mass");
+    }
+    for (int s1 = 0; s1 < 2; ++s1)
+        for (int s0 = 0; s0 < 2; ++s0) {
+            const int e = s0 + 2 * s1;
+            out->w[e] = -Kref[2 * s0 + 4 * s1][1 + 2 * s0 + 4 * s1] / h;      // x-edge (y=s0, z=s1)
+            out->w[4 + e] = -Kref[s0 + 4 * s1][s0 + 2 + 4 * s1] / h;          // y-edge (x=s0, z=s1)
+            out->w[8 + e] = -Kref[s0 + 2 * s1][s0 + 2 * s1 + 4] / h;          // z-edge (x=s0, y=s1)
+        }
+    return HYB_OK;
+}
+
+hyb_status check_grid(const hyb_fd_grid *gr, hyb_ctx *c)
+{
+    if (!gr) return fail(c, HYB_E_ARG, "grid is null");
+    if (!(gr->h > 0) || !std::isfinite(gr->h)) return fail(c, HYB_E_ARG, "grid: h must be positive");
+    for (int d = 0; d < 3; ++d)
+        if (gr->n_cells[d] < 2) return fail(c, HYB_E_ARG, "grid: need at least 2 cells per axis");
+    for (int f = 0; f < 6; ++f) {
+        if (gr->face[f] < 0 || gr->face[f] > 2) return fail(c, HYB_E_ARG, "grid: bad face condition");
+        if (gr->face[f] == HYB_BC_SOURCE && f != 5)
+            return fail(c, HYB_E_UNSUPPORTED, "grid: the source must be on the z+ face");
+    }
+    const double nodes = (double)(gr->n_cells[0] + 1) * (gr->n_cells[1] + 1) * (gr->n_cells[2] + 1);
+    if (nodes > 4.0e9) return fail(c, HYB_E_UNSUPPORTED, "grid: too many nodes");
+    return HYB_OK;
+}
+
+void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
+{
+    g.nx = n[0] + 1;
+    g.ny = n[1] + 1;
+    g.nz = n[2] + 1;
+    const long long align = 128 / (long long)esz;  // rows start on 128-byte lines
+    g.px = ceil_div(g.nx, align) * align;
+    g.plane = g.px * g.ny;
+    g.has_fem = has_fem ? 1 : 0;
+    for (int d = 0; d < 3; ++d) {
+        g.o[d] = has_fem ? m.o[d] : 0;
+        g.C[d] = has_fem ? m.C[d] : 0;
+        g.hlo[d] = g.o[d] + 2;
+        g.hhi[d] = g.o[d] + g.C[d] - 2;
+        g.hn[d] = has_fem ? g.C[d] - 3 : 0;
+    }
+    g.fpx = g.C[0] + 1;
+    g.fplane = g.fpx * (g.C[1] + 1);
+    g.hlevel = (long long)g.hn[0] * g.hn[1] * g.hn[2];
+    g.nbnd = (long long)g.nx * g.ny * g.nz - (long long)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+    if (has_fem) {
+        const long long L1 = g.C[0] - 4 + 1, L2 = g.C[0] + 1;
+        g.nwd = L1 * L1 * L1 - (L1 - 2) * (L1 - 2) * (L1 - 2);
+        g.nwo = L2 * L2 * L2 - (L2 - 2) * (L2 - 2) * (L2 - 2);
+    } else {
+        g.nwd = g.nwo = 0;
+    }
+    g.fdm_tiles[0] = (int)ceil_div(g.nx - 2, TX_FDM);
+    g.fdm_tiles[1] = (int)ceil_div(g.ny - 2, TY_FDM);
+    const long long txy = (long long)g.fdm_tiles[0] * g.fdm_tiles[1];
+    int zc = 64;
+    while (zc > 4 && txy * ceil_div(g.nz - 2, zc) < 1024) zc /= 2;
+    g.zc_fdm = zc;
+    g.fdm_tiles[2] = (int)ceil_div(g.nz - 2, zc);
+    g.n_fdm_blocks = (int)(txy * g.fdm_tiles[2]);
+    if (has_fem) {
+        g.fem_tiles[0] = (int)ceil_div(g.C[0] - 1, TX_FEM);
+        g.fem_tiles[1] = (int)ceil_div(g.C[1] - 1, TY_FEM);
+        const long long fxy = (long long)g.fem_tiles[0] * g.fem_tiles[1];
+        int zf = 32;
+        while (zf > 4 && fxy * ceil_div(g.C[2] - 1, zf) < 256) zf /= 2;
+        g.zc_fem = zf;
+        g.fem_tiles[2] = (int)ceil_div(g.C[2] - 1, zf);
+        g.n_fem_blocks = (int)(fxy * g.fem_tiles[2]);
+    } else {
+        g.fem_tiles[0] = g.fem_tiles[1] = g.fem_tiles[2] = 0;
+        g.zc_fem = 1;
+        g.n_fem_blocks = 0;
+    }
+    g.bnd_blocks = (int)ceil_div(g.nbnd + g.nwd + g.nwo, BLOCK);
+}
+
+size_t field_bytes(const Geo &g, size_t esz) { return (size_t)g.plane * g.nz * esz; }
+size_t fem_bytes(const Geo &g, size_t esz) { return g.has_fem ? (size_t)g.fplane * (g.C[2] + 1) * esz : 0; }
+size_t cube_count(const Geo &g) { return (size_t)g.C[0] * g.C[1] * g.C[2]; }
+
+int face_types(const hyb_ctx *c, int step)
+{
+    int t = 0;
+    for (int f = 0; f < 6; ++f) {
+        int v;
+        if (c->bc[f] == HYB_BC_NEUMANN) v = F_NEUMANN;
+        else if (c->bc[f] == HYB_BC_SOURCE) v = (step >= 0 && step < c->k_on) ? F_SOURCE : F_ABC;
+        else v = F_ABC;
+        t |= v << (2 * f);
+    }
+    return t;
+}
+
+hyb_status dmalloc(hyb_ctx *c, void **p, size_t bytes)
+{
+    if (*p) return HYB_OK;
+    if (hipMalloc(p, bytes ? bytes : 8) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, HYB_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    return HYB_OK;
+}
+
+void dfree(void *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+template <typename T>
+Step<T> make_step(const hyb_ctx *c)
+{
+    Step<T> s;
+    std::memset(&s, 0, sizeof s);
+    s.g = c->g;
+    s.acube = (const T *)c->acube;
+    s.c2 = (T)((c->dt / c->h) * (c->dt / c->h));
+    s.r = (T)((c->h - c->dt) / (c->h + c->dt));
+    for (int q = 0; q < 12; ++q) s.w[q] = (T)c->mesh.w[q];
+    s.dt = c->dt;
+    s.h2 = c->h * c->h;
+    return s;
+}
+
+template <typename T>
+hyb_status run_forward(hyb_ctx *c, const hyb_source *src, double *obs)
+{
+    const Geo &g = c->g;
+    const hipStream_t st = c->stream;
+    const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
+    for (int q = 0; q < 3; ++q) {
+        HIPCHK(c, hipMemsetAsync(c->U[q], 0, fb, st));
+        if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->V[q], 0, vb, st));
+    }
+    if (c->ic_set) {
+        if (c->ic_u0) launch_load_level<T>(g, c->ic_u0, (T *)c->U[1], (T *)c->V[1], st);
+        if (c->ic_um1) launch_load_level<T>(g, c->ic_um1, (T *)c->U[0], (T *)c->V[0], st);
+        c->ic_set = false;
+        c->ic_u0 = c->ic_um1 = nullptr;
+    }
+    const long long nface = (long long)g.nx * g.ny;
+    if (obs) launch_record_face<T>(g, (const T *)c->U[1], obs, st);
+    if (g.has_fem) launch_hist_level<T>(g, (const T *)c->V[1], (T *)c->hist, st);
+    Step<T> s = make_step<T>(c);
+    const double fluxscale = 2.0 * c->dt * c->dt / c->h;
+    int ia = 0, ib = 1, ic = 2;
+    for (int k = 0; k < c->nt; ++k) {
+        s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
+        s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
+        s.types1 = face_types(c, k);
+        if (src->kind == 0) {
+            s.flux = nullptr;
+            s.srcterm = (T)(fluxscale * std::sin(src->omega * ((double)k * c->dt)));
+        } else {
+            s.flux = k < c->k_on ? src->flux_dev + (long long)k * nface : nullptr;
+            s.fluxscale = fluxscale;
+            s.srcterm = 0;
+        }
+        s.obs = obs ? obs + (long long)(k + 1) * nface : nullptr;
+        s.hist = g.has_fem ? (T *)c->hist + (long long)(k + 1) * g.hlevel : nullptr;
+        launch_interior<T>(s, false, st);
+        launch_bnd_fwd<T>(s, st);
+        const int t = ia; ia = ib; ib = ic; ic = t;
+    }
+    c->last_u = ib;
+    HIPCHK(c, hipGetLastError());
+    return HYB_OK;
+}
+
+template <typename T>
+hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
+{
+    const Geo &g = c->g;
+    const hipStream_t st = c->stream;
+    const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
+    for (int q = 0; q < 3; ++q) {
+        HIPCHK(c, hipMemsetAsync(c->P[q], 0, fb, st));
+        if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->Q[q], 0, vb, st));
+    }
+    if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
+    if (mode == 0) launch_misfit(g, res, c->nt, c->dt, c->h, c->partials, c->scal, S_JMIS, st);
+    else HIPCHK(c, hipMemsetAsync(c->scal + S_JMIS, 0, sizeof(double), st));
+    const long long nface = (long long)g.nx * g.ny;
+    Step<T> s = make_step<T>(c);
+    s.seed_mode = mode;
+    s.G = c->G;
+    int ia = 0, ib = 1, ic = 2;
+    for (int k = c->nt; k >= 0; --k) {
+        s.Ua = (const T *)c->P[ia]; s.Ub = (const T *)c->P[ib]; s.Uc = (T *)c->P[ic];
+        s.Va = (const T *)c->Q[ia]; s.Vb = (const T *)c->Q[ib]; s.Vc = (T *)c->Q[ic];
+        s.types0 = face_types(c, k - 1);
+        s.types1 = face_types(c, k);
+        s.types2 = face_types(c, k + 1);
+        s.level_rows = k >= 1;
+        s.res = (mode == 0 && k == 0) ? nullptr : res + (long long)k * nface;
+        s.hist = g.has_fem ? (T *)c->hist + (long long)k * g.hlevel : nullptr;
+        for (int f = 0; f < 6; ++f) {
+            const int t1 = (s.types1 >> (2 * f)) & 3, t0 = (s.types0 >> (2 * f)) & 3;
+            s.wB1[f] = t1 == F_ABC ? (T)1 : (T)2 * s.c2;
+            s.wB0[f] = (k >= 1 && t0 == F_ABC) ? -s.r : (T)0;
+        }
+        launch_bnd_adj<T>(s, st);
+        launch_interior<T>(s, true, st);
+        const int t = ia; ia = ib; ib = ic; ic = t;
+    }
+    c->last_p = ib;
+    HIPCHK(c, hipGetLastError());
+    return HYB_OK;
+}
+
+hyb_status ensure_trace_bufs(hyb_ctx *c, int nt)
+{
+    if ((size_t)nt + 1 > c->tracebuf_levels) {
+        dfree((void *&)c->obsbuf);
+        dfree((void *&)c->resbuf);
+        c->tracebuf_levels = 0;
+        const size_t b = (size_t)(nt + 1) * c->g.nx * c->g.ny * sizeof(double);
+        hyb_status s = dmalloc(c, (void **)&c->obsbuf, b);
+        if (s) return s;
+        s = dmalloc(c, (void **)&c->resbuf, b);
+        if (s) return s;
+        c->tracebuf_levels = (size_t)nt + 1;
+    }
+    return HYB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hyb_overlap *overlap,
+                      const hyb_opts *opts, hyb_ctx **out)
+{
+    if (!out) return fail(nullptr, HYB_E_ARG, "out is null");
+    *out = nullptr;
+    hyb_status s = check_grid(grid, nullptr);
+    if (s) return s;
+    Mesh mesh;
+    if (fem) {
+        if (!overlap || overlap->width_cells != 2)
+            return fail(nullptr, HYB_E_UNSUPPORTED, "overlap: the method uses a two-element overlap");
+        s = analyse_mesh(grid, fem, &mesh, nullptr);
+        if (s) return s;
+    }
+    hyb_ctx *c = new hyb_ctx();
+    for (int d = 0; d < 3; ++d) c->n[d] = grid->n_cells[d];
+    c->h = grid->h;
+    for (int f = 0; f < 6; ++f) c->bc[f] = grid->face[f];
+    if (opts) {
+        if (opts->field_f32 < 0 || opts->field_f32 > 1 || opts->store_mode != 0 ||
+            !std::isfinite(opts->gamma) || opts->gamma < 0 || !(opts->alpha_rel > 0)) {
+            delete c;
+            return fail(nullptr, opts->store_mode != 0 ? HYB_E_UNSUPPORTED : HYB_E_ARG, "opts: invalid options");
+        }
+        c->f32 = opts->field_f32;
+        c->store_mode = opts->store_mode;
+        c->gamma = opts->gamma;
+        c->alpha_rel = opts->alpha_rel;
+        c->stream = (hipStream_t)opts->hip_stream;
+    }
+    c->esz = c->f32 ? 4 : 8;
+    c->mesh = mesh;
+    setup_geo(c->g, c->n, mesh, fem != nullptr, c->esz);
+    const size_t fb = field_bytes(c->g, c->esz), vb = fem_bytes(c->g, c->esz);
+    const size_t nc = cube_count(c->g);
+    s = HYB_OK;
+    for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->U[q], fb);
+    if (!s && c->g.has_fem)
+        for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->V[q], vb);
+    if (!s && c->g.has_fem) s = dmalloc(c, &c->acube, nc * c->esz);
+    if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->sig, nc * sizeof(double));
+    if (!s) s = dmalloc(c, (void **)&c->partials, MAX_PARTIALS * sizeof(double));
+    if (!s) s = dmalloc(c, (void **)&c->scal, S_NSCAL * sizeof(double));
+    if (s) {
+        g_create_err = c->err;
+        hyb_destroy(c);
+        return s;
+    }
+    if (hipMemset(c->scal, 0, S_NSCAL * sizeof(double)) != hipSuccess) {
+        hyb_destroy(c);
+        return fail(nullptr, HYB_E_DEVICE, "hipMemset failed");
+    }
+    *out = c;
+    return HYB_OK;
+}
+
+void hyb_destroy(hyb_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int q = 0; q < 3; ++q) { dfree(c->U[q]); dfree(c->V[q]); dfree(c->P[q]); dfree(c->Q[q]); }
+    dfree(c->acube);
+    dfree(c->hist);
+    dfree((void *&)c->sig);
+    dfree((void *&)c->G);
+    dfree((void *&)c->dir);
+    dfree((void *&)c->grad);
+    dfree((void *&)c->obsbuf);
+    dfree((void *&)c->resbuf);
+    dfree((void *&)c->partials);
+    dfree((void *&)c->scal);
+    delete c;
+}
+
+hyb_status hyb_set_initial(hyb_ctx *c, const double *u0, const double *um1)
+{
+    if (!c) return HYB_E_ARG;
+    c->ic_u0 = u0;
+    c->ic_um1 = um1;
+    c->ic_set = u0 || um1;
+    return HYB_OK;
+}
+
+hyb_status hyb_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, int32_t nt, double dt,
+                       double *obs)
+{
+    if (!c) return HYB_E_ARG;
+    if (!src) return fail(c, HYB_E_ARG, "source is null");
+    if (nt < 1 || !(dt > 0) || !std::isfinite(dt)) return fail(c, HYB_E_ARG, "need nt >= 1 and dt > 0");
+    if (src->kind == 0) {
+        if (!(src->omega > 0) || !std::isfinite(src->omega)) return fail(c, HYB_E_ARG, "source: omega must be > 0");
+    } else if (src->kind == 1) {
+        if (src->k_on < 0 || (src->k_on > 0 && !src->flux_dev)) return fail(c, HYB_E_ARG, "source: flux table");
+    } else {
+        return fail(c, HYB_E_ARG, "source: unknown kind");
+    }
+    if (!c->g.has_fem && sigma) return fail(c, HYB_E_ARG, "sigma given without a FEM box");
+    const hipStream_t st = c->stream;
+    double smax = 0.0;
+    if (c->g.has_fem) {
+        if (c->f32) launch_acube<float>(c->g, sigma, (float *)c->acube, c->partials, c->scal, st);
+        else launch_acube<double>(c->g, sigma, (double *)c->acube, c->partials, c->scal, st);
+        double hs[2];
+        HIPCHK(c, hipMemcpyAsync(hs, c->scal + S_SMAX, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (hs[1] != 0.0) return fail(c, HYB_E_NONFINITE, "sigma has non-finite entries");
+        smax = hs[0];
+    }
+    // CFL condition, eq. (CFL): tau <= h / sqrt(3 a) with the largest a
+    const double amax = 1.0 + std::max(0.0, smax);
+    if (dt > c->h / std::sqrt(3.0 * amax) * (1.0 + 1e-12))
+        return fail(c, HYB_E_CFL, "dt violates the CFL bound h/sqrt(3 a_max)");
+    if (c->g.has_fem) {
+        const size_t need = (size_t)nt + 1;
+        if (need > c->hist_levels) {
+            dfree(c->hist);
+            c->hist_levels = 0;
+            hyb_status s = dmalloc(c, &c->hist, need * (size_t)c->g.hlevel * c->esz);
+            if (s) return s;
+            c->hist_levels = need;
+        }
+        if (sigma) HIPCHK(c, hipMemcpyAsync(c->sig, sigma, cube_count(c->g) * sizeof(double),
+                                           hipMemcpyDeviceToDevice, st));
+        else HIPCHK(c, hipMemsetAsync(c->sig, 0, cube_count(c->g) * sizeof(double), st));
+    }
+    c->nt = nt;
+    c->dt = dt;
+    if (src->kind == 0) {
+        const double t1 = 2.0 * M_PI / src->omega;
+        int kon = 0;
+        for (int k = 0; k < nt; ++k)
+            if ((double)k * dt < t1) kon = k + 1;
+        c->k_on = kon;
+    } else {
+        c->k_on = std::min(src->k_on, nt);
+    }
+    c->have_forward = false;
+    c->have_adjoint = false;
+    hyb_status s = c->f32 ? run_forward<float>(c, src, obs) : run_forward<double>(c, src, obs);
+    if (s) return s;
+    c->have_forward = true;
+    return HYB_OK;
+}
+
+hyb_status hyb_adjoint(hyb_ctx *c, const double *res, int32_t mode)
+{
+    if (!c) return HYB_E_ARG;
+    if (!res || (mode != 0 && mode != 1)) return fail(c, HYB_E_ARG, "adjoint: residual and mode 0/1");
+    if (!c->have_forward) return fail(c, HYB_E_STATE, "adjoint before forward");
+    const size_t fb = field_bytes(c->g, c->esz), vb = fem_bytes(c->g, c->esz);
+    hyb_status s = HYB_OK;
+    for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->P[q], fb);
+    if (!s && c->g.has_fem)
+        for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->Q[q], vb);
+    if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->G, cube_count(c->g) * sizeof(double));
+    if (s) return s;
+    s = c->f32 ? run_adjoint<float>(c, res, mode) : run_adjoint<double>(c, res, mode);
+    if (s) return s;
+    c->have_adjoint = true;
+    c->adj_mode = mode;
+    return HYB_OK;
+}
+
+hyb_status hyb_gradient(hyb_ctx *c, double *grad, double *J)
+{
+    if (!c) return HYB_E_ARG;
+    if (!grad) return fail(c, HYB_E_ARG, "grad is null");
+    if (!c->g.has_fem) return fail(c, HYB_E_STATE, "gradient needs a FEM box");
+    if (!c->have_adjoint) return fail(c, HYB_E_STATE, "gradient before adjoint");
+    const double h = c->h, h3 = h * h * h;
+    // dJ/dsigma_c = -(dt^2/h^2) G_c (G = sum_k sum_e w_e D_e lambda^{k+1} D_e u^k)
+    const double dJ = -(c->dt * c->dt) / (h * h);
+    const int mode = c->adj_mode;
+    launch_grad_final(c->g, c->G, c->sig, mode == 0 ? dJ / h3 : dJ, c->gamma, mode, h3, grad, c->partials,
+                      c->scal, S_JREG, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (J) {
+        double hs[2];
+        HIPCHK(c, hipMemcpyAsync(hs, c->scal + S_JMIS, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *J = mode == 0 ? hs[0] + hs[1] : 0.0;
+    }
+    return HYB_OK;
+}
+
+hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_source *src, int32_t nt,
+                       double dt, hyb_cg_state *state, double *gnorm, double *J)
+{
+    if (!c) return HYB_E_ARG;
+    if (!data || !sigma || !state) return fail(c, HYB_E_ARG, "cg_step: null argument");
+    if (!c->g.has_fem) return fail(c, HYB_E_STATE, "cg_step needs a FEM box");
+    hyb_status s = ensure_trace_bufs(c, nt);
+    if (!s) s = dmalloc(c, (void **)&c->dir, cube_count(c->g) * sizeof(double));
+    if (!s) s = dmalloc(c, (void **)&c->grad, cube_count(c->g) * sizeof(double));
+    if (s) return s;
+    s = hyb_forward(c, sigma, src, nt, dt, c->obsbuf);
+    if (s) return s;
+    const long long ntr = (long long)(nt + 1) * c->g.nx * c->g.ny;
+    launch_residual(c->obsbuf, data, c->resbuf, ntr, c->stream);
+    s = hyb_adjoint(c, c->resbuf, 0);
+    if (s) return s;
+    s = hyb_gradient(c, c->grad, nullptr);
+    if (s) return s;
+    const double h3 = c->h * c->h * c->h;
+    launch_norm2(c->g, c->grad, h3, c->partials, c->scal, S_GN2, c->stream);
+    launch_cg_dir(c->g, c->grad, c->dir, state->iter == 0, c->partials, c->scal, c->stream);
+    launch_cg_update(c->g, c->dir, sigma, c->alpha_rel, c->scal, c->stream);
+    HIPCHK(c, hipGetLastError());
+    state->iter += 1;
+    if (gnorm || J) {
+        double hs[S_NSCAL];
+        HIPCHK(c, hipMemcpyAsync(hs, c->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        state->gnorm2_prev = hs[S_GN2];
+        if (gnorm) *gnorm = std::sqrt(hs[S_GN2]);
+        if (J) *J = hs[S_JMIS] + hs[S_JREG];
+    }
+    return HYB_OK;
+}
+
+hyb_status hyb_footprint(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hyb_overlap *overlap,
+                         const hyb_opts *opts, int32_t nt, size_t *bytes)
+{
+    if (!bytes || nt < 1) return fail(nullptr, HYB_E_ARG, "footprint: bytes null or nt < 1");
+    hyb_status s = check_grid(grid, nullptr);
+    if (s) return s;
+    Mesh mesh;
+    if (fem) {
+        if (!overlap || overlap->width_cells != 2)
+            return fail(nullptr, HYB_E_UNSUPPORTED, "overlap: the method uses a two-element overlap");
+        s = analyse_mesh(grid, fem, &mesh, nullptr);
+        if (s) return s;
+    }
+    const size_t esz = (opts && opts->field_f32) ? 4 : 8;
+    Geo g{};
+    int n[3] = {grid->n_cells[0], grid->n_cells[1], grid->n_cells[2]};
+    setup_geo(g, n, mesh, fem != nullptr, esz);
+    const size_t nc = cube_count(g), ntr = (size_t)(nt + 1) * g.nx * g.ny * sizeof(double);
+    size_t b = 6 * field_bytes(g, esz) + 6 * fem_bytes(g, esz) + nc * (esz + 4 * sizeof(double));
+    b += (size_t)(nt + 1) * g.hlevel * esz + 2 * ntr + (MAX_PARTIALS + S_NSCAL) * sizeof(double);
+    *bytes = b;
+    return HYB_OK;
+}
+
+hyb_status hyb_sync(hyb_ctx *c)
+{
+    if (!c) return HYB_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGetLastError());
+    return HYB_OK;
+}
+
+const char *hyb_last_error(const hyb_ctx *c)
+{
+    return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+hyb_status hyb_counts(const hyb_ctx *c, int64_t *fdm, int64_t *fem)
+{
+    if (!c || !fdm || !fem) return HYB_E_ARG;
+    const Geo &g = c->g;
+    const long long nn = (long long)g.nx * g.ny * g.nz;
+    const long long hole = g.has_fem ? (long long)(g.C[0] - 3) * (g.C[1] - 3) * (g.C[2] - 3) : 0;
+    *fdm = nn - hole;
+    *fem = g.has_fem ? (long long)(g.C[0] - 1) * (g.C[1] - 1) * (g.C[2] - 1) : 0;
+    return HYB_OK;
+}
+
+hyb_status hyb_get_wavefield(hyb_ctx *c, int32_t which, double *u, double *v)
+{
+    if (!c || (which != 0 && which != 1)) return HYB_E_ARG;
+    if ((which == 0 && !c->have_forward) || (which == 1 && !c->have_adjoint))
+        return fail(c, HYB_E_STATE, "get_wavefield: no such sweep yet");
+    void *const *A = which == 0 ? c->U : c->P;
+    void *const *B = which == 0 ? c->V : c->Q;
+    const int q = which == 0 ? c->last_u : c->last_p;
+    if (c->f32) launch_export_level<float>(c->g, (const float *)A[q], (const float *)B[q], u, v, c->stream);
+    else launch_export_level<double>(c->g, (const double *)A[q], (const double *)B[q], u, v, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return HYB_OK;
+}
+
+hyb_status hyb_time_interior(hyb_ctx *c, const double *sigma, double dt, int32_t reps, double *ms)
+{
+    if (!c || !ms || reps < 1 || !(dt > 0)) return HYB_E_ARG;
+    const hipStream_t st = c->stream;
+    if (c->g.has_fem) {
+        if (c->f32) launch_acube<float>(c->g, sigma, (float *)c->acube, c->partials, c->scal, st);
+        else launch_acube<double>(c->g, sigma, (double *)c->acube, c->partials, c->scal, st);
+        if (!c->hist) return fail(c, HYB_E_STATE, "time_interior needs a previous forward (history)");
+    }
+    // the launches overwrite the wavefields and the first history level
+    c->have_forward = false;
+    c->have_adjoint = false;
+    const double save_dt = c->dt;
+    c->dt = dt;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    auto body = [&](auto tag) -> hyb_status {
+        using T = decltype(tag);
+        Step<T> s = make_step<T>(c);
+        s.types1 = face_types(c, -1);
+        int ia = 0, ib = 1, ic = 2;
+        HIPCHK(c, hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) {
+            s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
+            s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
+            s.hist = c->g.has_fem ? (T *)c->hist : nullptr;
+            launch_interior<T>(s, false, st);
+            const int t = ia; ia = ib; ib = ic; ic = t;
+        }
+        HIPCHK(c, hipEventRecord(e1, st));
+        return HYB_OK;
+    };
+    hyb_status s = c->f32 ? body(0.0f) : body(0.0);
+    c->dt = save_dt;
+    if (s) return s;
+    HIPCHK(c, hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / reps;
+    return HYB_OK;
+}
+
+}  // extern "C"

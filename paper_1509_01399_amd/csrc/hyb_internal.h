@@ -1,0 +1,114 @@
+// Internal declarations shared by the host library (hyb_api.cpp) and the
+// kernels (hyb_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace hyb {
+
+// Block shapes (64-wide wavefronts): the FDM tile is 64 x TY_FDM columns, the
+// FEM tile 32 x TY_FEM columns; both stream along z.
+constexpr int TX_FDM = 64, TY_FDM = 4;
+constexpr int TX_FEM = 32, TY_FEM = 8;
+constexpr int BLOCK = 256;
+
+// Face condition of one face at one step, 2 bits per face in a packed int.
+enum : int { F_ABC = 0, F_NEUMANN = 1, F_SOURCE = 2 };
+
+struct Geo {
+    int nx, ny, nz;           // grid nodes per axis
+    long long px, plane;      // row pitch and plane pitch (elements)
+    int has_fem;
+    int o[3], C[3];           // FEM box: cells [o, o+C)
+    long long fpx, fplane;    // FEM node array pitches ((C+1) per axis)
+    int hlo[3], hhi[3];       // closed hole [o+2, o+C-2] (grid coords)
+    int hn[3];                // history sub-box node counts (C-3 per axis)
+    long long hlevel;         // history elements per level
+    long long nbnd;           // outer boundary nodes
+    long long nwd, nwo;       // |omega_diamond|, |omega_o|
+    int fdm_tiles[3], fem_tiles[3];
+    int zc_fdm, zc_fem;       // z chunk per block
+    int n_fdm_blocks, n_fem_blocks;
+    int bnd_blocks;           // blocks of the boundary kernels
+};
+
+// Arguments of one time step.  In the forward sweep the U/V fields are the
+// wavefields (a = level k-1, b = level k, c = level k+1).  In the adjoint
+// sweep they are the multipliers of the U/V rows (a = level k+2, b = level
+// k+1, c = level k, computed).
+template <typename T>
+struct Step {
+    Geo g;
+    const T *Ua, *Ub;
+    T *Uc;
+    const T *Va, *Vb;
+    T *Vc;
+    const T *acube;          // conductivity a per FEM cube [C^3]
+    T c2;                    // (dt/h)^2
+    T r;                     // (h - dt)/(h + dt), eq. (eq:abs2)
+    T w[12];                 // cube edge weights / h: x-edges [y+2z], y [x+2z], z [x+2y]
+    int types0, types1, types2;  // face conditions of steps k-1, k, k+1
+    // forward
+    T srcterm;               // 2 dt^2 p(t_k) / h (plane wave)
+    const double *flux;      // flux row of step k (table source) or null
+    double fluxscale;        // 2 dt^2 / h
+    double *obs;             // trace row k+1 (or null)
+    T *hist;                 // forward: history level k+1; adjoint: level k
+    // adjoint
+    int level_rows;          // level k has rows (k >= 1)
+    const double *res;       // residual row of level k (or null)
+    int seed_mode;           // 0: tau * w_i * res; 1: res
+    double dt, h2;
+    double *G;               // FP64 gradient accumulator [C^3]
+    T wB1[6], wB0[6];        // weights of boundary neighbours (adjoint interior)
+};
+
+// ---- launchers (hyb_kernels.hip) ----
+template <typename T> void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st);
+template <typename T> void launch_bnd_fwd(const Step<T> &s, hipStream_t st);
+template <typename T> void launch_bnd_adj(const Step<T> &s, hipStream_t st);
+
+// a = 1 + sigma on free cubes (1 elsewhere); scal[0] = max sigma over free
+// cubes, scal[1] = 1 if sigma has a non-finite entry.
+template <typename T>
+void launch_acube(const Geo &g, const double *sigma, T *acube, double *partials, double *scal,
+                  hipStream_t st);
+// copy a full grid level (unpadded FP64) into a padded field, and its FEM part
+template <typename T>
+void launch_load_level(const Geo &g, const double *src, T *U, T *V, hipStream_t st);
+template <typename T>
+void launch_hist_level(const Geo &g, const T *V, T *hist, hipStream_t st);
+template <typename T>
+void launch_record_face(const Geo &g, const T *U, double *obs_row, hipStream_t st);
+
+template <typename T>
+void launch_export_level(const Geo &g, const T *U, const T *V, double *u, double *v, hipStream_t st);
+
+// J_misfit = 1/2 sum_{k=1..nt} dt sum_i w_i res^2 -> scal[slot]
+void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h, double *partials,
+                   double *scal, int slot, hipStream_t st);
+// gradient finalisation (see hyb_gradient); reg -> scal[slot] (0.5 gamma h^3 sum sigma^2)
+void launch_grad_final(const Geo &g, const double *G, const double *sigma, double coefG,
+                       double gamma, int mode, double h3, double *grad, double *partials,
+                       double *scal, int slot, hipStream_t st);
+// CG: scal[gn2] = h^3 sum g^2; direction update d = -g + beta d with
+// beta = scal[gn2]/scal[gn2_prev] (0 on the first iteration); scal[dmax];
+// sigma update with alpha = alpha_rel / scal[dmax]; then gn2_prev <- gn2.
+void launch_norm2(const Geo &g, const double *v, double h3, double *partials, double *scal, int slot,
+                  hipStream_t st);
+void launch_cg_dir(const Geo &g, const double *grad, double *dir, int first, double *partials,
+                   double *scal, hipStream_t st);
+void launch_cg_update(const Geo &g, const double *dir, double *sigma, double alpha_rel, double *scal,
+                      hipStream_t st);
+void launch_residual(const double *obs, const double *data, double *res, long long n,
+                     hipStream_t st);
+
+// device scalar slots
+enum : int { S_SMAX = 0, S_BAD = 1, S_JMIS = 2, S_JREG = 3, S_GN2 = 4, S_GN2P = 5, S_BETA = 6,
+             S_DMAX = 7, S_ALPHA = 8, S_NSCAL = 16 };
+constexpr int MAX_PARTIALS = 4096;
+
+}  // namespace hyb

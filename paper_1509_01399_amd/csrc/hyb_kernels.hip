@@ -1,0 +1,816 @@
+// HIP kernels (gfx950) of the domain-decomposition FEM/FDM time stepping of
+// arXiv 1509.01399 (Algorithm 2, Sec. 7.5) and its exact discrete adjoint.
+//
+// Per forward step k -> k+1 two launches:
+//   k_interior<T,false>: the seven-point leapfrog of eq. (fdmschemeforward)
+//     on every FDM-owned interior node (blocks of 64 x 4 columns streaming
+//     along z with a register queue; the hole [o+2, o+C-2]^3 is skipped) and,
+//     in the same launch, the lumped-mass P1 update of eq. (fem) on the open
+//     FEM box (32 x 8 columns).  On the 6-tetrahedra cube split the P1
+//     stiffness couples only along the 12 axis edges of each cube, so the
+//     element gather over the 8 cubes around a node reduces to six edge
+//     conductances kappa_e = sum over the 4 cubes of the edge of a_c * w_{c,e}
+//     (w from the element matrices computed on the host); no atomics.
+//   k_bnd_fwd: the outer boundary rows (absorbing eq. (eq:abs2) or the
+//     ghost-node Neumann/source rows of eq. (f)), the two overlap copies of
+//     Algorithm 2 steps 3-4, the trace of the z+ face and nothing else.  Each
+//     boundary thread recomputes the values of lower-codimension boundary
+//     neighbours it depends on, so faces, edges and corners need no ordering
+//     between threads (three rotating buffers keep level k-1 intact).
+// Per adjoint step (computing the multipliers of level k) the reverse:
+//   k_bnd_adj: multipliers of the boundary rows, including the trace seed;
+//   k_interior<T,true>: the same FDM/FEM stencils applied to the multipliers
+//     plus the transposed boundary, exchange and absorbing couplings, and the
+//     FP64 gradient time-integral of eq. (gradient1) per cube.
+#include "hyb_internal.h"
+
+#include <cmath>
+
+namespace hyb {
+
+__device__ __forceinline__ long long gidx(const Geo &g, int x, int y, int z)
+{
+    return (long long)x + (long long)y * g.px + (long long)z * g.plane;
+}
+
+__device__ __forceinline__ long long fidx(const Geo &g, int i, int j, int k)
+{
+    return (long long)i + (long long)j * g.fpx + (long long)k * g.fplane;
+}
+
+__device__ __forceinline__ int ftype(int types, int f) { return (types >> (2 * f)) & 3; }
+
+__device__ __forceinline__ bool on_bnd(const Geo &g, int x, int y, int z)
+{
+    return x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
+}
+
+// Boundary axes of a node and the condition of each at one step.
+struct BInfo {
+    int nb, nabc;
+    int ax[3], dir[3], kind[3];
+};
+
+__device__ __forceinline__ BInfo classify(const Geo &g, int x, int y, int z, int types)
+{
+    BInfo B;
+    B.nb = 0;
+    B.nabc = 0;
+    const int c[3] = {x, y, z};
+    const int m[3] = {g.nx - 1, g.ny - 1, g.nz - 1};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int f, dir;
+        if (c[d] == 0) { f = 2 * d; dir = 1; }
+        else if (c[d] == m[d]) { f = 2 * d + 1; dir = -1; }
+        else continue;
+        int kd = ftype(types, f);
+        B.ax[B.nb] = d;
+        B.dir[B.nb] = dir;
+        B.kind[B.nb] = kd;
+        B.nb++;
+        if (kd == F_ABC) B.nabc++;
+    }
+    return B;
+}
+
+__device__ __forceinline__ int axis_slot(const BInfo &B, int d)
+{
+    for (int q = 0; q < B.nb; ++q)
+        if (B.ax[q] == d) return q;
+    return -1;
+}
+
+// ---------------------------------------------------------------- forward
+
+// Level k+1 value of boundary node (x,y,z).  Ghost-node leapfrog when every
+// boundary axis reflects (Neumann, or the source face while the pulse is on:
+// each such axis contributes 2(u_in - u)/h^2, the source adds 2 p/h); else
+// the absorbing row of eq. (eq:abs2) averaged over the absorbing axes, which
+// needs the new value of the inward neighbour (recomputed if it is itself on
+// the boundary; D bounds the recursion depth).
+template <typename T, int D>
+__device__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
+{
+    const Geo &g = s.g;
+    const BInfo B = classify(g, x, y, z, s.types1);
+    const long long id = gidx(g, x, y, z);
+    const long long st[3] = {1, g.px, g.plane};
+    const T u = s.Ub[id];
+    if (B.nabc == 0) {
+        T lap = 0;
+        bool src = false;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int q = axis_slot(B, d);
+            if (q < 0) {
+                lap += (s.Ub[id + st[d]] - u) + (s.Ub[id - st[d]] - u);
+            } else {
+                lap += (T)2 * (s.Ub[id + B.dir[q] * st[d]] - u);
+                if (B.kind[q] == F_SOURCE) src = true;
+            }
+        }
+        T v = (T)2 * u - s.Ua[id] + s.c2 * lap;
+        if (src) v += s.flux ? (T)(s.fluxscale * s.flux[x + (long long)g.nx * y]) : s.srcterm;
+        return v;
+    }
+    T acc = 0;
+    for (int q = 0; q < B.nb; ++q) {
+        if (B.kind[q] != F_ABC) continue;
+        int c[3] = {x, y, z};
+        c[B.ax[q]] += B.dir[q];
+        const long long in = gidx(g, c[0], c[1], c[2]);
+        T up;
+        if (on_bnd(g, c[0], c[1], c[2])) {
+            if constexpr (D > 1) up = bnd_fwd<T, D - 1>(s, c[0], c[1], c[2]);
+            else up = 0;  // unreachable: the inward chain ends in the interior
+        } else {
+            up = s.Uc[in];
+        }
+        acc += s.Ub[in] + s.r * (u - up);
+    }
+    return acc / (T)B.nabc;
+}
+
+// Position of thread t among the boundary nodes: z faces whole, then y faces
+// without z edges, then x faces without y/z edges.
+__device__ __forceinline__ void bnd_coord(const Geo &g, long long t, int &x, int &y, int &z)
+{
+    const long long nxy = (long long)g.nx * g.ny;
+    if (t < 2 * nxy) {
+        z = t < nxy ? 0 : g.nz - 1;
+        const long long r = t % nxy;
+        x = (int)(r % g.nx);
+        y = (int)(r / g.nx);
+        return;
+    }
+    t -= 2 * nxy;
+    const long long nxz = (long long)g.nx * (g.nz - 2);
+    if (t < 2 * nxz) {
+        y = t < nxz ? 0 : g.ny - 1;
+        const long long r = t % nxz;
+        x = (int)(r % g.nx);
+        z = 1 + (int)(r / g.nx);
+        return;
+    }
+    t -= 2 * nxz;
+    const long long nyz = (long long)(g.ny - 2) * (g.nz - 2);
+    x = t < nyz ? 0 : g.nx - 1;
+    const long long r = t % nyz;
+    y = 1 + (int)(r % (g.ny - 2));
+    z = 1 + (int)(r / (g.ny - 2));
+}
+
+// Surface node t of a box with L+1 nodes per axis (L >= 2): local coords.
+__device__ __forceinline__ void box_surface(long long t, int L, int &a, int &b, int &c)
+{
+    const long long n1 = L + 1, f = n1 * n1;
+    if (t < 2 * f) {
+        c = t < f ? 0 : L;
+        const long long r = t % f;
+        a = (int)(r % n1);
+        b = (int)(r / n1);
+        return;
+    }
+    t -= 2 * f;
+    const long long fy = n1 * (L - 1);
+    if (t < 2 * fy) {
+        b = t < fy ? 0 : L;
+        const long long r = t % fy;
+        a = (int)(r % n1);
+        c = 1 + (int)(r / n1);
+        return;
+    }
+    t -= 2 * fy;
+    const long long fx = (long long)(L - 1) * (L - 1);
+    a = t < fx ? 0 : L;
+    const long long r = t % fx;
+    b = 1 + (int)(r % (L - 1));
+    c = 1 + (int)(r / (L - 1));
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_fwd(Step<T> s)
+{
+    const Geo &g = s.g;
+    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (t < g.nbnd) {
+        int x, y, z;
+        bnd_coord(g, t, x, y, z);
+        const T v = bnd_fwd<T, 3>(s, x, y, z);
+        s.Uc[gidx(g, x, y, z)] = v;
+        if (s.obs && z == g.nz - 1) s.obs[x + (long long)g.nx * y] = (double)v;
+        return;
+    }
+    t -= g.nbnd;
+    if (t < g.nwd) {  // Algorithm 2 step 3: FEM values to the FDM inner boundary
+        int a, b, c;
+        box_surface(t, g.C[0] - 4, a, b, c);
+        s.Uc[gidx(g, g.o[0] + 2 + a, g.o[1] + 2 + b, g.o[2] + 2 + c)] = s.Vc[fidx(g, 2 + a, 2 + b, 2 + c)];
+        return;
+    }
+    t -= g.nwd;
+    if (t < g.nwo) {  // Algorithm 2 step 4: FDM values to the FEM boundary
+        int a, b, c;
+        box_surface(t, g.C[0], a, b, c);
+        s.Vc[fidx(g, a, b, c)] = s.Uc[gidx(g, g.o[0] + a, g.o[1] + b, g.o[2] + c)];
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+
+// Multiplier of boundary node b at level k: the sum, over every row that
+// reads u^k_b, of (its coefficient) x (its multiplier):
+//   own row at level k+1 (ghost: 2 - 6 c2, absorbing: r) and at level k+2
+//   (ghost: -1); the interior FDM row of the inward neighbour (c2); ghost
+//   rows of boundary neighbours at level k+1 (c2, or 2 c2 when b is their
+//   inward neighbour); absorbing rows at level k+1 whose inward neighbour is
+//   b (1/|S|) and absorbing rows of the same level k whose inward neighbour
+//   is b (-r/|S|, recomputed recursively); the trace seed on the z+ face.
+template <typename T, int D>
+__device__ T bnd_adj(const Step<T> &s, int x, int y, int z)
+{
+    const Geo &g = s.g;
+    const long long id = gidx(g, x, y, z);
+    const T c2 = s.c2;
+    const BInfo B1 = classify(g, x, y, z, s.types1);
+    T mu = (B1.nabc == 0 ? ((T)2 - (T)6 * c2) : s.r) * s.Ub[id];
+    const BInfo B2 = classify(g, x, y, z, s.types2);
+    if (B2.nabc == 0) mu -= s.Ua[id];
+    for (int d = 0; d < 3; ++d) {
+        for (int sg = -1; sg <= 1; sg += 2) {
+            int c[3] = {x, y, z};
+            c[d] += sg;
+            const int m = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+            if (c[d] < 0 || c[d] >= m) continue;
+            const long long nid = gidx(g, c[0], c[1], c[2]);
+            if (!on_bnd(g, c[0], c[1], c[2])) {
+                mu += c2 * s.Ub[nid];
+                continue;
+            }
+            const BInfo N1 = classify(g, c[0], c[1], c[2], s.types1);
+            const int q1 = axis_slot(N1, d);
+            if (N1.nabc == 0) {
+                mu += (q1 >= 0 ? (T)2 * c2 : c2) * s.Ub[nid];
+            } else if (q1 >= 0 && N1.kind[q1] == F_ABC) {
+                mu += s.Ub[nid] / (T)N1.nabc;
+            }
+            if (s.level_rows) {
+                const BInfo N0 = classify(g, c[0], c[1], c[2], s.types0);
+                const int q0 = axis_slot(N0, d);
+                if (N0.nabc > 0 && q0 >= 0 && N0.kind[q0] == F_ABC) {
+                    T mun = 0;
+                    if constexpr (D > 1) mun = bnd_adj<T, D - 1>(s, c[0], c[1], c[2]);
+                    mu -= s.r * mun / (T)N0.nabc;
+                }
+            }
+        }
+    }
+    if (s.res && z == g.nz - 1) {
+        double rv = s.res[x + (long long)g.nx * y];
+        if (s.seed_mode == 0) {
+            double w = s.h2;
+            if (x == 0 || x == g.nx - 1) w *= 0.5;
+            if (y == 0 || y == g.ny - 1) w *= 0.5;
+            rv *= s.dt * w;
+        }
+        mu += (T)rv;
+    }
+    return mu;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj(Step<T> s)
+{
+    const Geo &g = s.g;
+    const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (t < g.nbnd) {
+        int x, y, z;
+        bnd_coord(g, t, x, y, z);
+        s.Uc[gidx(g, x, y, z)] = bnd_adj<T, 3>(s, x, y, z);
+    }
+}
+
+// ---------------------------------------------------------------- interior
+
+// kappa_e / h of the FEM-local x/y/z edge starting at node (i,j,k): sum over
+// the 4 cubes of the edge of a_c * w.
+template <typename T>
+__device__ __forceinline__ T acub(const Step<T> &s, int i, int j, int k)
+{
+    return s.acube[i + (long long)s.g.C[0] * (j + (long long)s.g.C[1] * k)];
+}
+
+template <typename T>
+__device__ T kappa_edge(const Step<T> &s, int d, int i, int j, int k)
+{
+    T kap = 0;
+#pragma unroll
+    for (int s1 = 0; s1 < 2; ++s1)
+#pragma unroll
+        for (int s0 = 0; s0 < 2; ++s0) {
+            T a;
+            if (d == 0) a = acub(s, i, j - s0, k - s1);
+            else if (d == 1) a = acub(s, i - s0, j, k - s1);
+            else a = acub(s, i - s0, j - s1, k);
+            kap += a * s.w[4 * d + s0 + 2 * s1];
+        }
+    return kap;
+}
+
+template <typename T, bool ADJ>
+__device__ void fdm_tile(const Step<T> &s, int bid)
+{
+    const Geo &g = s.g;
+    const int bx = bid % g.fdm_tiles[0];
+    const int t = bid / g.fdm_tiles[0];
+    const int by = t % g.fdm_tiles[1];
+    const int bz = t / g.fdm_tiles[1];
+    const int x = 1 + bx * TX_FDM + (int)(threadIdx.x % TX_FDM);
+    const int y = 1 + by * TY_FDM + (int)(threadIdx.x / TX_FDM);
+    if (x > g.nx - 2 || y > g.ny - 2) return;
+    const int z0 = 1 + bz * g.zc_fdm;
+    const int z1 = min(z0 + g.zc_fdm, g.nz - 1);
+    const bool hcol = g.has_fem && x >= g.hlo[0] && x <= g.hhi[0] && y >= g.hlo[1] && y <= g.hhi[1];
+    if (hcol && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
+    const long long py = g.px, pz = g.plane;
+    long long id = gidx(g, x, y, z0);
+    const T c2 = s.c2;
+    T cm = s.Ub[id - pz], c0 = s.Ub[id];
+    for (int z = z0; z < z1; ++z, id += pz) {
+        const T cp = s.Ub[id + pz];
+        if (!(hcol && z >= g.hlo[2] && z <= g.hhi[2])) {
+            const T xm = s.Ub[id - 1], xp = s.Ub[id + 1], ym = s.Ub[id - py], yp = s.Ub[id + py];
+            T v;
+            if constexpr (!ADJ) {
+                v = (T)2 * c0 - s.Ua[id] + c2 * (((xm + xp) + (ym + yp)) + (cm + cp) - (T)6 * c0);
+            } else {
+                // transposed rows that read this node: its own FDM row (levels
+                // k+1, k+2), the FDM rows of its neighbours, the boundary rows
+                // of boundary neighbours (weights wB1 at level k+1, wB0 for the
+                // absorbing rows of level k), and on omega_o the FEM rows that
+                // read the copied value.
+                T acc = (T)2 * c0 - s.Ua[id] - (T)6 * c2 * c0;
+                acc += (x == 1 ? s.wB1[0] : c2) * xm + (x == g.nx - 2 ? s.wB1[1] : c2) * xp;
+                acc += (y == 1 ? s.wB1[2] : c2) * ym + (y == g.ny - 2 ? s.wB1[3] : c2) * yp;
+                acc += (z == 1 ? s.wB1[4] : c2) * cm + (z == g.nz - 2 ? s.wB1[5] : c2) * cp;
+                if (x == 1) acc += s.wB0[0] * s.Uc[id - 1];
+                if (x == g.nx - 2) acc += s.wB0[1] * s.Uc[id + 1];
+                if (y == 1) acc += s.wB0[2] * s.Uc[id - py];
+                if (y == g.ny - 2) acc += s.wB0[3] * s.Uc[id + py];
+                if (z == 1) acc += s.wB0[4] * s.Uc[id - pz];
+                if (z == g.nz - 2) acc += s.wB0[5] * s.Uc[id + pz];
+                if (g.has_fem) {
+                    const int i = x - g.o[0], j = y - g.o[1], k = z - g.o[2];
+                    const int Cx = g.C[0], Cy = g.C[1], Cz = g.C[2];
+                    const bool in_i = i > 0 && i < Cx, in_j = j > 0 && j < Cy, in_k = k > 0 && k < Cz;
+                    if (in_j && in_k && (i == 0 || i == Cx)) {
+                        const int ie = i == 0 ? 0 : Cx - 1, im = i == 0 ? 1 : Cx - 1;
+                        acc += c2 * kappa_edge(s, 0, ie, j, k) * s.Vb[fidx(g, im, j, k)];
+                    } else if (in_i && in_k && (j == 0 || j == Cy)) {
+                        const int je = j == 0 ? 0 : Cy - 1, jm = j == 0 ? 1 : Cy - 1;
+                        acc += c2 * kappa_edge(s, 1, i, je, k) * s.Vb[fidx(g, i, jm, k)];
+                    } else if (in_i && in_j && (k == 0 || k == Cz)) {
+                        const int ke = k == 0 ? 0 : Cz - 1, km = k == 0 ? 1 : Cz - 1;
+                        acc += c2 * kappa_edge(s, 2, i, j, ke) * s.Vb[fidx(g, i, j, km)];
+                    }
+                }
+                v = acc;
+            }
+            s.Uc[id] = v;
+        }
+        cm = c0;
+        c0 = cp;
+    }
+}
+
+template <typename T, bool ADJ>
+__device__ void fem_tile(const Step<T> &s, int bid)
+{
+    const Geo &g = s.g;
+    const int Cx = g.C[0], Cy = g.C[1], Cz = g.C[2];
+    const int bx = bid % g.fem_tiles[0];
+    const int t = bid / g.fem_tiles[0];
+    const int by = t % g.fem_tiles[1];
+    const int bz = t / g.fem_tiles[1];
+    const int i = 1 + bx * TX_FEM + (int)(threadIdx.x % TX_FEM);
+    const int j = 1 + by * TY_FEM + (int)(threadIdx.x / TX_FEM);
+    if (i > Cx - 1 || j > Cy - 1) return;
+    const int k0 = 1 + bz * g.zc_fem;
+    const int k1 = min(k0 + g.zc_fem, Cz);
+    const long long cpy = Cx, cpz = (long long)Cx * Cy;
+    const long long cb = (i - 1) + (long long)(j - 1) * cpy;
+    const T *A = s.acube;
+    // a of the 8 cubes around the node: index dx + 2 dy, lo = dz 0, hi = dz 1
+    T alo[4], ahi[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) alo[q] = A[cb + (q & 1) + (q >> 1) * cpy + (long long)(k0 - 1) * cpz];
+    const T *w = s.w;
+    const T c2 = s.c2;
+    const long long fy = g.fpx, fz = g.fplane;
+    long long id = fidx(g, i, j, k0);
+    T vm = s.Vb[id - fz], v0 = s.Vb[id];
+    // adjoint gradient: multipliers and history on the 4 corners (x,y)+{0,1}
+    const bool gcol = ADJ && i >= 2 && i <= Cx - 3 && j >= 2 && j <= Cy - 3;
+    const bool hcol = i >= 2 && i <= Cx - 2 && j >= 2 && j <= Cy - 2;
+    const int hn0 = g.hn[0], hn1 = g.hn[1];
+    const long long hpz = (long long)hn0 * hn1;
+    for (int k = k0; k < k1; ++k, id += fz) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ahi[q] = A[cb + (q & 1) + (q >> 1) * cpy + (long long)k * cpz];
+        const T vp = s.Vb[id + fz];
+        const T xm = s.Vb[id - 1], xp = s.Vb[id + 1], ym = s.Vb[id - fy], yp = s.Vb[id + fy];
+        // a(dx,dy,dz): dz = 0 -> alo, 1 -> ahi
+#define AC(dx, dy, dz) ((dz) ? ahi[(dx) + 2 * (dy)] : alo[(dx) + 2 * (dy)])
+        const T kxp = w[0] * AC(1, 1, 1) + w[1] * AC(1, 0, 1) + w[2] * AC(1, 1, 0) + w[3] * AC(1, 0, 0);
+        const T kxm = w[0] * AC(0, 1, 1) + w[1] * AC(0, 0, 1) + w[2] * AC(0, 1, 0) + w[3] * AC(0, 0, 0);
+        const T kyp = w[4] * AC(1, 1, 1) + w[5] * AC(0, 1, 1) + w[6] * AC(1, 1, 0) + w[7] * AC(0, 1, 0);
+        const T kym = w[4] * AC(1, 0, 1) + w[5] * AC(0, 0, 1) + w[6] * AC(1, 0, 0) + w[7] * AC(0, 0, 0);
+        const T kzp = w[8] * AC(1, 1, 1) + w[9] * AC(0, 1, 1) + w[10] * AC(1, 0, 1) + w[11] * AC(0, 0, 1);
+        const T kzm = w[8] * AC(1, 1, 0) + w[9] * AC(0, 1, 0) + w[10] * AC(1, 0, 0) + w[11] * AC(0, 0, 0);
+#undef AC
+        const T Ku = kxp * (v0 - xp) + kxm * (v0 - xm) + kyp * (v0 - yp) + kym * (v0 - ym) +
+                     kzp * (v0 - vp) + kzm * (v0 - vm);
+        T v = (T)2 * v0 - s.Va[id] - c2 * Ku;
+        const bool hin = hcol && k >= 2 && k <= Cz - 2;
+        if constexpr (ADJ) {
+            // omega_diamond: the FDM rows around read the copied value
+            if (hin && (i == 2 || i == Cx - 2 || j == 2 || j == Cy - 2 || k == 2 || k == Cz - 2)) {
+                const long long gg = gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k);
+                v += c2 * (((s.Ub[gg - 1] + s.Ub[gg + 1]) + (s.Ub[gg - g.px] + s.Ub[gg + g.px])) +
+                           (s.Ub[gg - g.plane] + s.Ub[gg + g.plane]));
+            }
+            // gradient of eq. (gradient1): cube with lower corner (i,j,k),
+            // sum over its 12 edges of w_e (D_e lambda^{k+1}) (D_e u^k) in FP64
+            if (gcol && k >= 2 && k <= Cz - 3) {
+                double q[8], hv[8];
+                const T *H = s.hist;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+                    q[c] = (double)s.Vb[id + dx + dy * fy + dz * fz];
+                    hv[c] = (double)H[(i - 2 + dx) + (long long)(j - 2 + dy) * hn0 + (long long)(k - 2 + dz) * hpz];
+                }
+                double acc = 0.0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int s0 = e & 1, s1 = e >> 1;
+                    const int ax0 = 0 + 2 * s0 + 4 * s1, ax1 = ax0 + 1;          // x-edge (y=s0,z=s1)
+                    const int ay0 = s0 + 4 * s1, ay1 = ay0 + 2;                  // y-edge (x=s0,z=s1)
+                    const int az0 = s0 + 2 * s1, az1 = az0 + 4;                  // z-edge (x=s0,y=s1)
+                    acc += (double)w[e] * (q[ax1] - q[ax0]) * (hv[ax1] - hv[ax0]);
+                    acc += (double)w[4 + e] * (q[ay1] - q[ay0]) * (hv[ay1] - hv[ay0]);
+                    acc += (double)w[8 + e] * (q[az1] - q[az0]) * (hv[az1] - hv[az0]);
+                }
+                s.G[i + cpy * j + cpz * k] += acc;
+            }
+        } else {
+            if (hin && s.hist)
+                s.hist[(i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz] = v;
+        }
+        s.Vc[id] = v;
+        vm = v0;
+        v0 = vp;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) alo[q] = ahi[q];
+    }
+}
+
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(BLOCK) void k_interior(Step<T> s)
+{
+    const int b = blockIdx.x;
+    if (b < s.g.n_fem_blocks) fem_tile<T, ADJ>(s, b);
+    else fdm_tile<T, ADJ>(s, b - s.g.n_fem_blocks);
+}
+
+template <typename T>
+void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st)
+{
+    const int nb = s.g.n_fem_blocks + s.g.n_fdm_blocks;
+    if (adjoint) hipLaunchKernelGGL((k_interior<T, true>), dim3(nb), dim3(BLOCK), 0, st, s);
+    else hipLaunchKernelGGL((k_interior<T, false>), dim3(nb), dim3(BLOCK), 0, st, s);
+}
+
+template <typename T>
+void launch_bnd_fwd(const Step<T> &s, hipStream_t st)
+{
+    const long long n = s.g.nbnd + s.g.nwd + s.g.nwo;
+    hipLaunchKernelGGL((k_bnd_fwd<T>), dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
+}
+
+template <typename T>
+void launch_bnd_adj(const Step<T> &s, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_bnd_adj<T>), dim3((unsigned)((s.g.nbnd + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       st, s);
+}
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ bool cube_free(const Geo &g, long long c)
+{
+    const int i = (int)(c % g.C[0]);
+    const int j = (int)((c / g.C[0]) % g.C[1]);
+    const int k = (int)(c / ((long long)g.C[0] * g.C[1]));
+    return i >= 2 && i < g.C[0] - 2 && j >= 2 && j < g.C[1] - 2 && k >= 2 && k < g.C[2] - 2;
+}
+
+// block-wide sum / max of a double (wave64 shuffles + LDS), thread 0 gets it
+__device__ double block_reduce(double v, bool is_max)
+{
+    __shared__ double sh[BLOCK / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(v, off, 64);
+        v = is_max ? fmax(v, o) : v + o;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v = sh[0];
+        for (int q = 1; q < BLOCK / 64; ++q) v = is_max ? fmax(v, sh[q]) : v + sh[q];
+    }
+    return v;
+}
+
+// Second pass of a deterministic reduction: one block folds the partials in
+// a fixed order; result scaled by `scale` into scal[slot].
+__global__ __launch_bounds__(BLOCK) void k_final(const double *part, int n, int is_max, double scale,
+                                                 double *scal, int slot)
+{
+    double v = is_max ? 0.0 : 0.0;
+    for (int q = threadIdx.x; q < n; q += BLOCK) v = is_max ? fmax(v, part[q]) : v + part[q];
+    v = block_reduce(v, is_max != 0);
+    if (threadIdx.x == 0) scal[slot] = v * scale;
+}
+
+static int nparts(long long n) { return (int)std::min<long long>(MAX_PARTIALS, (n + BLOCK - 1) / BLOCK); }
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_acube(Geo g, const double *sigma, T *acube, double *part_max,
+                                                 double *part_bad)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    double mx = 0.0, bad = 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK) {
+        double sv = 0.0;
+        if (sigma && cube_free(g, c)) {
+            sv = sigma[c];
+            if (!isfinite(sv)) { bad = 1.0; sv = 0.0; }
+            mx = fmax(mx, sv);
+        }
+        acube[c] = (T)(1.0 + sv);
+    }
+    mx = block_reduce(mx, true);
+    __syncthreads();
+    bad = block_reduce(bad, true);
+    if (threadIdx.x == 0) { part_max[blockIdx.x] = mx; part_bad[blockIdx.x] = bad; }
+}
+
+template <typename T>
+void launch_acube(const Geo &g, const double *sigma, T *acube, double *partials, double *scal,
+                  hipStream_t st)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    const int nb = std::min(nparts(n), MAX_PARTIALS / 2);
+    hipLaunchKernelGGL((k_acube<T>), dim3(nb), dim3(BLOCK), 0, st, g, sigma, acube, partials,
+                       partials + MAX_PARTIALS / 2);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 1, 1.0, scal, (int)S_SMAX);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials + MAX_PARTIALS / 2, nb, 1, 1.0,
+                       scal, (int)S_BAD);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_load_level(Geo g, const double *src, T *U, T *V)
+{
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), z = (int)(t / ((long long)g.nx * g.ny));
+        const T v = src ? (T)src[t] : (T)0;
+        U[gidx(g, x, y, z)] = v;
+        if (g.has_fem) {
+            const int i = x - g.o[0], j = y - g.o[1], k = z - g.o[2];
+            if (i >= 0 && i <= g.C[0] && j >= 0 && j <= g.C[1] && k >= 0 && k <= g.C[2]) V[fidx(g, i, j, k)] = v;
+        }
+    }
+}
+
+template <typename T>
+void launch_load_level(const Geo &g, const double *src, T *U, T *V, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_load_level<T>), dim3(2048), dim3(BLOCK), 0, st, g, src, U, V);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_hist_level(Geo g, const T *V, T *hist)
+{
+    const long long n = g.hlevel;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const int a = (int)(t % g.hn[0]), b = (int)((t / g.hn[0]) % g.hn[1]),
+                  c = (int)(t / ((long long)g.hn[0] * g.hn[1]));
+        hist[t] = V[fidx(g, 2 + a, 2 + b, 2 + c)];
+    }
+}
+
+template <typename T>
+void launch_hist_level(const Geo &g, const T *V, T *hist, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_hist_level<T>), dim3(1024), dim3(BLOCK), 0, st, g, V, hist);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_record_face(Geo g, const T *U, double *row)
+{
+    const long long n = (long long)g.nx * g.ny;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK)
+        row[t] = (double)U[gidx(g, (int)(t % g.nx), (int)(t / g.nx), g.nz - 1)];
+}
+
+template <typename T>
+void launch_record_face(const Geo &g, const T *U, double *obs_row, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_record_face<T>), dim3(256), dim3(BLOCK), 0, st, g, U, obs_row);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const T *V, double *u, double *v)
+{
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), z = (int)(t / ((long long)g.nx * g.ny));
+        if (u) u[t] = (double)U[gidx(g, x, y, z)];
+    }
+    if (!v || !g.has_fem) return;
+    const long long nf = (long long)(g.C[0] + 1) * (g.C[1] + 1) * (g.C[2] + 1);
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nf; t += (long long)gridDim.x * BLOCK)
+        v[t] = (double)V[t];
+}
+
+template <typename T>
+void launch_export_level(const Geo &g, const T *U, const T *V, double *u, double *v, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_export_level<T>), dim3(1024), dim3(BLOCK), 0, st, g, U, V, u, v);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_misfit(Geo g, const double *res, int nt, double wscale,
+                                                  double *part)
+{
+    const long long nf = (long long)g.nx * g.ny, n = nf * nt;
+    double acc = 0.0;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const long long q = t % nf;
+        const int x = (int)(q % g.nx), y = (int)(q / g.nx);
+        double w = 1.0;
+        if (x == 0 || x == g.nx - 1) w *= 0.5;
+        if (y == 0 || y == g.ny - 1) w *= 0.5;
+        const double r = res[nf + t];  // levels 1..nt
+        acc += w * r * r;
+    }
+    acc = block_reduce(acc, false);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc * wscale;
+}
+
+void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h, double *partials,
+                   double *scal, int slot, hipStream_t st)
+{
+    const long long n = (long long)g.nx * g.ny * nt;
+    const int nb = nparts(n);
+    hipLaunchKernelGGL(k_misfit, dim3(nb), dim3(BLOCK), 0, st, g, res, nt, 0.5 * dt * h * h, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 1.0, scal, slot);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_grad_final(Geo g, const double *G, const double *sigma, double coefG,
+                                                      double gamma, int mode, double *grad, double *part)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    double reg = 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK) {
+        double v = 0.0;
+        if (cube_free(g, c)) {
+            const double sv = sigma ? sigma[c] : 0.0;
+            v = coefG * G[c];
+            if (mode == 0) {
+                v += gamma * sv;
+                reg += sv * sv;
+            }
+        }
+        grad[c] = v;
+    }
+    reg = block_reduce(reg, false);
+    if (threadIdx.x == 0) part[blockIdx.x] = reg;
+}
+
+void launch_grad_final(const Geo &g, const double *G, const double *sigma, double coefG, double gamma,
+                       int mode, double h3, double *grad, double *partials, double *scal, int slot,
+                       hipStream_t st)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    const int nb = nparts(n);
+    hipLaunchKernelGGL(k_grad_final, dim3(nb), dim3(BLOCK), 0, st, g, G, sigma, coefG, gamma, mode, grad,
+                       partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 0.5 * gamma * h3, scal, slot);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_sumsq(long long n, const double *v, double *part)
+{
+    double acc = 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK)
+        acc += v[c] * v[c];
+    acc = block_reduce(acc, false);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+void launch_norm2(const Geo &g, const double *v, double h3, double *partials, double *scal, int slot,
+                  hipStream_t st)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    const int nb = nparts(n);
+    hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(BLOCK), 0, st, n, v, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, h3, scal, slot);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cg_dir(Geo g, const double *grad, double *dir, int first,
+                                                  const double *scal, double *part)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    const double beta = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
+    double mx = 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK) {
+        double d = 0.0;
+        if (cube_free(g, c)) d = first ? -grad[c] : -grad[c] + beta * dir[c];
+        dir[c] = d;
+        mx = fmax(mx, fabs(d));
+    }
+    mx = block_reduce(mx, true);
+    if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+__global__ void k_store_beta(double *scal, int first)
+{
+    if (threadIdx.x == 0) scal[S_BETA] = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
+}
+
+void launch_cg_dir(const Geo &g, const double *grad, double *dir, int first, double *partials,
+                   double *scal, hipStream_t st)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    const int nb = nparts(n);
+    hipLaunchKernelGGL(k_store_beta, dim3(1), dim3(64), 0, st, scal, first);
+    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(BLOCK), 0, st, g, grad, dir, first, scal, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 1, 1.0, scal, (int)S_DMAX);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cg_update(Geo g, const double *dir, double *sigma, double alpha_rel,
+                                                     double *scal)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    const double dmax = scal[S_DMAX];
+    const double alpha = dmax > 0.0 ? alpha_rel / dmax : 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK) {
+        if (!cube_free(g, c)) continue;
+        const double sv = sigma[c] + alpha * dir[c];
+        sigma[c] = sv < 0.0 ? 0.0 : (sv > 4.0 ? 4.0 : sv);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
+}
+
+__global__ void k_roll_gn2(double *scal)
+{
+    if (threadIdx.x == 0) scal[S_GN2P] = scal[S_GN2];
+}
+
+void launch_cg_update(const Geo &g, const double *dir, double *sigma, double alpha_rel, double *scal,
+                      hipStream_t st)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    hipLaunchKernelGGL(k_cg_update, dim3(nparts(n)), dim3(BLOCK), 0, st, g, dir, sigma, alpha_rel, scal);
+    hipLaunchKernelGGL(k_roll_gn2, dim3(1), dim3(64), 0, st, scal);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_residual(const double *obs, const double *data, double *res,
+                                                    long long n)
+{
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK)
+        res[t] = obs[t] - data[t];
+}
+
+void launch_residual(const double *obs, const double *data, double *res, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_residual, dim3(nparts(n)), dim3(BLOCK), 0, st, obs, data, res, n);
+}
+
+// explicit instantiations
+#define HYB_INST(T)                                                                               \
+    template void launch_interior<T>(const Step<T> &, bool, hipStream_t);                          \
+    template void launch_bnd_fwd<T>(const Step<T> &, hipStream_t);                                \
+    template void launch_bnd_adj<T>(const Step<T> &, hipStream_t);                                \
+    template void launch_acube<T>(const Geo &, const double *, T *, double *, double *, hipStream_t); \
+    template void launch_load_level<T>(const Geo &, const double *, T *, T *, hipStream_t);        \
+    template void launch_hist_level<T>(const Geo &, const T *, T *, hipStream_t);                  \
+    template void launch_record_face<T>(const Geo &, const T *, double *, hipStream_t);            \
+    template void launch_export_level<T>(const Geo &, const T *, const T *, double *, double *, hipStream_t);
+HYB_INST(double)
+HYB_INST(float)
+
+}  // namespace hyb

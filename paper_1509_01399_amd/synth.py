@@ -76,7 +76,7 @@ def symmetric_pair(C, seed, edge=3, value=2.0):
     s = np.zeros((C, C, C))
     lo, hi = 2, C - 2
     half = C // 2
-    x0 = int(rng.integers(lo, max(lo + 1, half - edge + 1)))
+    x0 = int(rng.integers(lo, max(lo + 1, half - edge)))  # gap >= 1 cell
     y0 = int(rng.integers(lo, hi - edge + 1))
     z0 = int(rng.integers(lo, hi - edge + 1))
     x1 = C - x0 - edge

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  FP64 bar: relative L2 <= 1e-12 on traces, fields and
+gradients (the scheme is linear and stable, so summation-order differences of
+~1e-16 per step stay far below it).  FP32 wavefields: traces <= 1e-5 and
+gradients <= 1e-4 relative L2."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1509_01399_amd import hyb
+    assert torch.cuda.is_available()
+    hyb.load()
+    return torch
+
+
+def _solver(n, C, o=None, f32=False, bc=(0, 0, 0, 0, 0, 2), h=None):
+    from paper_1509_01399_amd.hyb import Solver
+    return Solver(n, C=C, o=o, f32=f32, bc=bc, h=h)
+
+
+def _t(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _tiny40(seed=0):
+    from paper_1509_01399_amd import synth
+    wl = synth.WORKLOADS["tiny40"]
+    sig = synth.sigma_for(wl, seed)
+    return wl, sig, synth.dt_rule(wl.h, sig.max())
+
+
+# ------------------------------------------------------------------ forward
+
+def test_forward_tiny40_fp64(env, orc):
+    torch = env
+    wl, sig, dt = _tiny40()
+    print(f"tiny40 forward n={wl.n} C={wl.C} nt={wl.nt} dt={dt}", flush=True)
+    s = _solver(wl.n, wl.C)
+    obs = s.forward(_t(torch, sig), wl.nt, dt, omega=wl.omega).cpu().numpy()
+    ref = orc.forward(orc.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C), sig.ravel(), wl.nt, dt, omega=wl.omega)
+    assert np.abs(ref).max() > 1e-3
+    assert rel(obs, ref) <= TOL64
+
+
+@pytest.mark.parametrize("case", ["fdm_abc", "fdm_waveguide", "hyb_ragged", "hyb_neumann_mix", "hyb_o1"])
+def test_forward_shapes_and_bcs(env, orc, case):
+    torch = env
+    from paper_1509_01399_amd import synth
+    N, A, S = 1, 0, 2
+    if case == "fdm_abc":
+        n, C, o, bc = (37, 37, 37), 0, None, (A, A, A, A, A, S)
+    elif case == "fdm_waveguide":
+        n, C, o, bc = (3, 2, 70), 0, None, (N, N, N, N, A, S)
+    elif case == "hyb_ragged":
+        n, C, o, bc = (67, 45, 29), 9, (40, 17, 11), (A, A, A, A, A, S)
+    elif case == "hyb_neumann_mix":
+        n, C, o, bc = (30, 26, 33), 11, (7, 8, 12), (N, A, A, N, N, S)
+    else:
+        n, C, o, bc = (20, 20, 20), 18, (1, 1, 1), (A, A, A, A, A, S)
+    h = 1.0 / n[2]
+    print(f"case {case} n={n} C={C} o={o}", flush=True)
+    rng = np.random.default_rng(11)
+    sig = None
+    if C:
+        s3 = np.zeros((C, C, C))
+        s3[2:C - 2, 2:C - 2, 2:C - 2] = rng.uniform(0, 4, (C - 4,) * 3)
+        sig = s3.ravel()
+    dt = 0.25 * h
+    nt = 150
+    s = _solver(n, C, o=o, bc=bc, h=h)
+    obs = s.forward(_t(torch, sig) if C else None, nt, dt, omega=30.0).cpu().numpy()
+    g = orc.Geometry(n, h=h, bc=bc, fem_o=o if C else 0, fem_c=C)
+    ref = orc.forward(g, sig, nt, dt, omega=30.0)
+    assert rel(obs, ref) <= TOL64
+
+
+def test_forward_initial_levels_and_fields(env, orc):
+    """Model Problem 1 style initial levels; compares the final grid and FEM
+    fields, and the adjoint's cotangent of u^0 (exact transposition)."""
+    torch = env
+    from paper_1509_01399_amd import synth
+    n, C, o = 24, 10, 7
+    h = 1.0 / n
+    bc = (0, 1, 0, 0, 1, 2)
+    rng = np.random.default_rng(3)
+    sig = np.zeros((C, C, C))
+    sig[2:C - 2, 2:C - 2, 2:C - 2] = rng.uniform(0, 3, (C - 4,) * 3)
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = u0 + 0.1 * rng.standard_normal((n + 1,) * 3)
+    dt, nt = 0.25 * h, 40
+    s = _solver(n, C, o=o, bc=bc)
+    s.set_initial(_t(torch, u0), _t(torch, um1))
+    obs = s.forward(_t(torch, sig), nt, dt, omega=25.0).cpu().numpy()
+    u, v = s.wavefield(0)
+    g = orc.Geometry(n, bc=bc, fem_o=o, fem_c=C)
+    ref, vh, uf = orc.forward(g, sig.ravel(), nt, dt, omega=25.0, u0=u0, um1=um1, want_vhist=True,
+                              want_ufinal=True)
+    assert rel(obs, ref) <= TOL64
+    assert rel(u.cpu().numpy().ravel(), uf) <= TOL64
+    assert rel(v.cpu().numpy().ravel(), vh[nt]) <= TOL64
+    # adjoint with a raw trace cotangent: cotangent of u^0
+    r = rng.standard_normal(ref.shape)
+    s.adjoint(_t(torch, r), mode=1)
+    gsig, _ = s.gradient(want_J=False)
+    mu, muv = s.wavefield(1)
+    du0 = mu.cpu().numpy().copy()
+    du0[o:o + C + 1, o:o + C + 1, o:o + C + 1] += muv.cpu().numpy()
+    dsig, du0_ref, _ = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=25.0, u0=u0, um1=um1,
+                                   want_dinit=True)
+    assert rel(du0.ravel(), du0_ref) <= TOL64
+    assert rel(gsig.cpu().numpy().ravel(), dsig) <= TOL64
+
+
+# ------------------------------------------------------------------ adjoint
+
+def test_gradient_and_J_tiny40(env, orc):
+    torch = env
+    from paper_1509_01399_amd import synth
+    wl, sig_true, dt = _tiny40()
+    g = orc.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
+    data = orc.forward(g, sig_true.ravel(), wl.nt, dt, omega=wl.omega)
+    data = synth.add_noise(data, 0.03, 5)
+    sig = 0.5 * sig_true
+    s = _solver(wl.n, wl.C)
+    obs = s.forward(_t(torch, sig), wl.nt, dt, omega=wl.omega)
+    s.adjoint(obs - _t(torch, data), mode=0)
+    grad, J = s.gradient()
+    gref, Jref = orc.gradient(g, sig.ravel(), wl.nt, dt, data, gamma=0.01, omega=wl.omega)
+    print("J", J, Jref, "rel grad err", rel(grad.cpu().numpy().ravel(), gref), flush=True)
+    assert abs(J - Jref) <= TOL64 * abs(Jref)
+    assert rel(grad.cpu().numpy().ravel(), gref) <= TOL64
+
+
+def test_adjoint_mode1_random_cotangent(env, orc):
+    torch = env
+    wl, sig, dt = _tiny40(1)
+    g = orc.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
+    rng = np.random.default_rng(9)
+    nt = 200
+    r = rng.standard_normal((nt + 1, wl.n + 1, wl.n + 1))
+    s = _solver(wl.n, wl.C)
+    s.forward(_t(torch, sig), nt, dt, omega=wl.omega)
+    s.adjoint(_t(torch, r), mode=1)
+    grad, _ = s.gradient(want_J=False)
+    ref = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=wl.omega)
+    assert rel(grad.cpu().numpy().ravel(), ref) <= TOL64
+
+
+def test_cg_three_iterations_tiny40(env, orc):
+    """The tiny workload: 3 iterations of Algorithm 3 from sigma = 0."""
+    torch = env
+    from paper_1509_01399_amd import hyb
+    wl, sig_true, dt = _tiny40()
+    g = orc.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
+    data = orc.forward(g, sig_true.ravel(), wl.nt, dt, omega=wl.omega)
+    sig_ref, log = orc.cg(g, np.zeros(wl.C ** 3), wl.nt, dt, data, 3, omega=wl.omega)
+    s = _solver(wl.n, wl.C)
+    sig = torch.zeros((wl.C,) * 3, dtype=torch.float64, device="cuda")
+    st = hyb.hyb_cg_state()
+    d = _t(torch, data)
+    for m in range(3):
+        gn, J = s.cg_step(d, sig, wl.nt, dt, st, omega=wl.omega)
+        print(m, gn, log[m, 1], J, log[m, 0], flush=True)
+        assert abs(gn - log[m, 1]) <= 1e-11 * log[m, 1]
+        assert abs(J - log[m, 0]) <= 1e-11 * log[m, 0]
+    assert rel(sig.cpu().numpy().ravel(), sig_ref) <= 1e-11
+
+
+# ----------------------------------------------------------------- precision
+
+def test_fp32_form_error_bounds(env, orc):
+    torch = env
+    from paper_1509_01399_amd import synth
+    wl, sig_true, dt = _tiny40()
+    g = orc.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
+    data = synth.add_noise(orc.forward(g, sig_true.ravel(), wl.nt, dt, omega=wl.omega), 0.03, 5)
+    sig = 0.5 * sig_true
+    s = _solver(wl.n, wl.C, f32=True)
+    obs = s.forward(_t(torch, sig), wl.nt, dt, omega=wl.omega)
+    s.adjoint(obs - _t(torch, data), mode=0)
+    grad, J = s.gradient()
+    gref, Jref, oref = orc.gradient(g, sig.ravel(), wl.nt, dt, data, gamma=0.01, omega=wl.omega,
+                                    want_obs=True)
+    e_obs = rel(obs.cpu().numpy(), oref)
+    e_g = rel(grad.cpu().numpy().ravel(), gref)
+    print("fp32 trace err", e_obs, "grad err", e_g, flush=True)
+    assert e_obs <= 1e-5
+    assert e_g <= 1e-4
+
+
+# ------------------------------------------------------------- determinism
+
+def test_bitwise_deterministic(env):
+    torch = env
+    wl, sig, dt = _tiny40()
+    s = _solver(wl.n, wl.C)
+    out = []
+    for _ in range(2):
+        obs = s.forward(_t(torch, sig), 120, dt, omega=wl.omega)
+        s.adjoint(obs.clone(), mode=1)
+        grad, _ = s.gradient(want_J=False)
+        out.append((obs.cpu().numpy(), grad.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+# ------------------------------------------------------------- error paths
+
+def test_error_paths(env):
+    torch = env
+    from paper_1509_01399_amd import hyb
+    n, C = 20, 8
+    s = _solver(n, C)
+    h = 1.0 / n
+    grad = torch.zeros((C,) * 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(hyb.HybError) as e:
+        s.adjoint(torch.zeros((11, n + 1, n + 1), dtype=torch.float64, device="cuda"))
+    assert e.value.status == hyb.HYB_E_STATE
+    with pytest.raises(hyb.HybError) as e:
+        s.gradient(grad)
+    assert e.value.status == hyb.HYB_E_STATE
+    sig = torch.zeros((C,) * 3, dtype=torch.float64, device="cuda")
+    sig[4, 4, 4] = 4.0
+    with pytest.raises(hyb.HybError) as e:
+        s.forward(sig, 10, 0.4 * h)
+    assert e.value.status == hyb.HYB_E_CFL
+    sig[4, 4, 4] = float("nan")
+    with pytest.raises(hyb.HybError) as e:
+        s.forward(sig, 10, 0.25 * h)
+    assert e.value.status == hyb.HYB_E_NONFINITE
+    with pytest.raises(hyb.HybError) as e:
+        s.forward(None, 0, 0.25 * h)
+    assert e.value.status == hyb.HYB_E_ARG
+    # a valid call still works after the errors
+    sig[4, 4, 4] = 1.0
+    s.forward(sig, 10, 0.25 * h)
+    s.sync()
