@@ -1,0 +1,253 @@
+"""Benchmark: forward+adjoint grid-point updates per second of the hybrid
+FEM/FDM solver on one MI355X, on the 256^3 reconstruction workload (FEM box
+96^3 cells x 6 tetrahedra, 1200 steps, 1-4 cubic inclusions, 3% noise).
+
+One timed step = one iteration of Algorithm 3: forward sweep (1200 steps),
+residual, adjoint sweep with the fused FP64 gradient integral, gradient
+finalisation and the CG update of sigma, all on the device with inputs
+resident in HBM.  value = 2 * (FDM-updated + FEM-updated nodes) * nt * steps /
+wall time.  The line also carries the roofline of the dominant kernel (the
+fused FDM/FEM interior update), timed with HIP events on the solver's
+stream, and the CPU oracle timed on a bounded window of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--workload cg256] [--probe {interior,copy}]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def interior_bytes(n, C, s):
+    """Algorithmic bytes of one forward interior launch (fused FDM + FEM):
+    FDM nodes: read u^k, read u^{k-1}, write u^{k+1} (3 s each);
+    FEM nodes: the same 3 s plus one coefficient per cube (s) and one history
+    write per stored node (s)."""
+    fdm_int = (n - 1) ** 3 - (C - 3) ** 3 if C else (n - 1) ** 3
+    fem = (C - 1) ** 3 if C else 0
+    return 3 * s * fdm_int + 3 * s * fem + s * C ** 3 + s * (C - 3) ** 3 if C else 3 * s * fdm_int
+
+
+def setup(wl_name, f32, seed=0):
+    import numpy as np
+    import torch
+
+    from paper_1509_01399_amd import hyb, synth
+    wl = synth.WORKLOADS[wl_name]
+    sig_true = synth.sigma_for(wl, seed)
+    dt = synth.dt_rule(wl.h, sig_true.max())
+    solver = hyb.Solver(wl.n, C=wl.C, f32=f32)
+    st = torch.as_tensor(sig_true, dtype=torch.float64, device="cuda")
+    obs = solver.forward(st, wl.nt, dt, omega=wl.omega)
+    data = synth.add_noise(obs.cpu().numpy(), wl.noise, seed + 1)
+    data = torch.as_tensor(data, dtype=torch.float64, device="cuda")
+    del obs
+    return wl, dt, solver, data, sig_true
+
+
+def run_cg(wl, dt, solver, data, steps, warmup):
+    import torch
+
+    from paper_1509_01399_amd import hyb
+    sig = torch.zeros((wl.C,) * 3, dtype=torch.float64, device="cuda")
+    state = hyb.hyb_cg_state()
+    log = []
+    for _ in range(warmup):
+        log.append(solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        log.append(solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0), log, sig
+
+
+def cpu_baseline(wl, dt, window):
+    """The CPU oracle (plain FP64 C, one thread) on windows of the same
+    workload: full grid and FEM box, w forward steps then w adjoint steps (one
+    oracle gradient evaluation) for w = 2 and w = window; the rate is the
+    marginal one between the two windows, so the oracle's mesh set-up is not
+    charged to it."""
+    import numpy as np
+
+    import oracle
+    from oracle.build import build, lib_path
+    from paper_1509_01399_amd import synth
+    if not os.path.exists(lib_path()):
+        build()
+    g = oracle.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
+    sz = g.sizes()
+    sig = synth.sigma_for(wl, 0).ravel()
+    ts = []
+    for w in (2, window):
+        data = np.zeros((w + 1, wl.n + 1, wl.n + 1))
+        t0 = time.perf_counter()
+        oracle.gradient(g, sig, w, dt, data, omega=wl.omega)
+        ts.append(time.perf_counter() - t0)
+    upd = 2 * (sz["fdm_updated"] + sz["fem_updated"]) * (window - 2)
+    t = ts[1] - ts[0]
+    return {"value": round(upd / t / 1e9, 5), "unit": "Gpt-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{wl.name} full grid ({wl.n}^3 cells, FEM {wl.C}^3): one oracle forward+adjoint "
+                      f"of 2 and of {window} steps ({ts[0]:.1f} s, {ts[1]:.1f} s); marginal rate over "
+                      f"the {window - 2} extra step pairs, single thread"}
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hyb_kernels.hip", "hyb_internal.h"):
+        with open(os.path.join(ROOT, "paper_1509_01399_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(wl_name, f32):
+    """HBM bytes per launch of the interior kernel from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE passes, calibrated on a plain copy), or
+    None when the summary is missing or was taken on other kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_interior_{wl_name}_{'f32' if f32 else 'f64'}_counters.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith(" ") and "|" not in line:
+            k, _, v = line.strip().partition("=")
+            kv[k] = v
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return int(float(kv["read_bytes"]) + float(kv["write_bytes"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(wl, dt, solver, f32, reps=50):
+    import torch
+    from paper_1509_01399_amd import hyb
+    s = 4 if f32 else 8
+    sig = torch.as_tensor(__import__("paper_1509_01399_amd.synth", fromlist=["x"]).sigma_for(wl, 0),
+                          dtype=torch.float64, device="cuda")
+    hyb.hyb_time_interior(solver.ctx, sig, dt, 5)  # warm
+    ms = hyb.hyb_time_interior(solver.ctx, sig, dt, reps)
+    b = interior_bytes(wl.n, wl.C, s)
+    achieved = b / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(wl.name, f32),
+            "kernel": "k_interior<%s,false>" % ("float" if f32 else "double"),
+            "bytes_per_launch": b, "avg_launch_ms": round(ms, 5)}
+
+
+def probe(kind, wl_name, f32, reps):
+    """Single-kernel runs for the counter passes (rocprofv3 --pmc)."""
+    import torch
+
+    from paper_1509_01399_amd import hyb, synth
+    wl = synth.WORKLOADS[wl_name]
+    if kind == "copy":
+        nbytes = 512 * 2 ** 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(reps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "reps": reps}))
+        return
+    sig_true = synth.sigma_for(wl, 0)
+    dt = synth.dt_rule(wl.h, sig_true.max())
+    solver = hyb.Solver(wl.n, C=wl.C, f32=f32)
+    st = torch.as_tensor(sig_true, dtype=torch.float64, device="cuda")
+    solver.forward(st, 2, dt, omega=wl.omega)
+    ms = hyb.hyb_time_interior(solver.ctx, st, dt, reps)
+    print(json.dumps({"probe": "interior", "workload": wl_name, "f32": f32, "reps": reps, "avg_ms": ms,
+                      "bytes_per_launch": interior_bytes(wl.n, wl.C, 4 if f32 else 8)}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cg256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-window", type=int, default=10)
+    ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--probe", choices=["interior", "copy"])
+    ap.add_argument("--probe-f32", action="store_true")
+    ap.add_argument("--probe-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus must be 1 (a multi-GPU split of the "
+              "grid is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(2)
+    from paper_1509_01399_amd import hyb
+    if not os.path.exists(hyb.LIB_PATH):
+        from paper_1509_01399_amd.build import build
+        build()
+    if args.probe:
+        probe(args.probe, args.workload, args.probe_f32, args.probe_reps)
+        return
+
+    wl, dt, solver, data, _ = setup(args.workload, False)
+    nfdm, nfem = solver.counts()
+    print(f"[bench] {wl.name}: n={wl.n} C={wl.C} nt={wl.nt} dt={dt:.6g} fdm={nfdm} fem={nfem}",
+          file=sys.stderr, flush=True)
+    t, log, _ = run_cg(wl, dt, solver, data, args.steps, args.warmup)
+    upd = 2.0 * (nfdm + nfem) * wl.nt * args.steps
+    value = upd / t / 1e9
+    print(f"[bench] f64: {t / args.steps * 1e3:.1f} ms/CG-iteration, {value:.1f} Gupd/s; "
+          f"|g| {log[-1][0]:.3e} J {log[-1][1]:.4e}", file=sys.stderr, flush=True)
+    rl = roofline(wl, dt, solver, False)
+    print(f"[bench] roofline f64 interior: {rl}", file=sys.stderr, flush=True)
+    solver.close()
+    del data
+    torch.cuda.empty_cache()
+
+    f32 = None
+    if not args.no_f32:
+        wl2, dt2, s2, d2, _ = setup(args.workload, True)
+        t2, log2, _ = run_cg(wl2, dt2, s2, d2, args.steps, args.warmup)
+        v2 = upd / t2 / 1e9
+        rl2 = roofline(wl2, dt2, s2, True)
+        print(f"[bench] f32: {t2 / args.steps * 1e3:.1f} ms/CG-iteration, {v2:.1f} Gupd/s; {rl2}",
+              file=sys.stderr, flush=True)
+        f32 = {"value": round(v2, 2), "ms_per_step": round(t2 / args.steps * 1e3, 3), "dtype": "f32",
+               "roofline": rl2}
+        s2.close()
+        del d2
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, dt, args.cpu_window)
+        print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "forward+adjoint Gpt-updates/s", "value": round(value, 2), "unit": "Gpt-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": wl.name, "grid_cells": wl.n, "fem_cells": wl.C, "nt": wl.nt,
+                   "dt_over_h": round(dt / wl.h, 4), "omega": wl.omega, "noise": wl.noise,
+                   "step": "one CG iteration (forward + adjoint + gradient + update)",
+                   "parallelism": "single GPU"},
+        "roofline": rl, "cpu_baseline": cpu, "f32_form": f32,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -38,7 +38,7 @@ struct hyb_ctx {
     Mesh mesh;
     size_t esz = 8;  // field element size
     // device memory
-    void *U[3]{}, *V[3]{}, *P[3]{}, *Q[3]{};
+    void *U[3]{}, *V[3]{}, *P[3]{}, *Q[3]{}, *F[3]{};
     void *acube = nullptr;
     void *hist = nullptr;
     size_t hist_levels = 0;
@@ -286,6 +286,17 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     g.fplane = g.fpx * (g.C[1] + 1);
     g.hlevel = (long long)g.hn[0] * g.hn[1] * g.hn[2];
     g.nbnd = (long long)g.nx * g.ny * g.nz - (long long)(g.nx - 2) * (g.ny - 2) * (g.nz - 2);
+    g.n_fi = 2 * ((long long)(g.nx - 2) * (g.ny - 2) + (long long)(g.nx - 2) * (g.nz - 2) +
+                  (long long)(g.ny - 2) * (g.nz - 2));
+    g.n_ec = g.nbnd - g.n_fi;
+    const long long fxx = (long long)g.ny * g.nz, fyy = (long long)g.nx * g.nz, fzz = (long long)g.nx * g.ny;
+    g.foff[0] = 0;
+    g.foff[1] = fxx;
+    g.foff[2] = 2 * fxx;
+    g.foff[3] = 2 * fxx + fyy;
+    g.foff[4] = 2 * fxx + 2 * fyy;
+    g.foff[5] = 2 * fxx + 2 * fyy + fzz;
+    g.ftot = 2 * (fxx + fyy + fzz);
     if (has_fem) {
         const long long L1 = g.C[0] - 4 + 1, L2 = g.C[0] + 1;
         g.nwd = L1 * L1 * L1 - (L1 - 2) * (L1 - 2) * (L1 - 2);
@@ -296,8 +307,10 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     g.fdm_tiles[0] = (int)ceil_div(g.nx - 2, TX_FDM);
     g.fdm_tiles[1] = (int)ceil_div(g.ny - 2, TY_FDM);
     const long long txy = (long long)g.fdm_tiles[0] * g.fdm_tiles[1];
-    int zc = 64;
-    while (zc > 4 && txy * ceil_div(g.nz - 2, zc) < 1024) zc /= 2;
+    // z chunk: at most 16 planes (enough workgroups to fill 256 CUs at 8
+    // waves/SIMD), fewer on small grids
+    int zc = 16;
+    while (zc > 4 && txy * ceil_div(g.nz - 2, zc) < 2048) zc /= 2;
     g.zc_fdm = zc;
     g.fdm_tiles[2] = (int)ceil_div(g.nz - 2, zc);
     g.n_fdm_blocks = (int)(txy * g.fdm_tiles[2]);
@@ -315,7 +328,7 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
         g.zc_fem = 1;
         g.n_fem_blocks = 0;
     }
-    g.bnd_blocks = (int)ceil_div(g.nbnd + g.nwd + g.nwo, BLOCK);
+    g.bnd_blocks = (int)ceil_div(g.nbnd + g.nwd + g.nwo, BLOCK);  // informational
 }
 
 size_t field_bytes(const Geo &g, size_t esz) { return (size_t)g.plane * g.nz * esz; }
@@ -420,6 +433,7 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
     const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
     for (int q = 0; q < 3; ++q) {
         HIPCHK(c, hipMemsetAsync(c->P[q], 0, fb, st));
+        HIPCHK(c, hipMemsetAsync(c->F[q], 0, (size_t)g.ftot * sizeof(T), st));
         if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->Q[q], 0, vb, st));
     }
     if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
@@ -433,6 +447,8 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
     for (int k = c->nt; k >= 0; --k) {
         s.Ua = (const T *)c->P[ia]; s.Ub = (const T *)c->P[ib]; s.Uc = (T *)c->P[ic];
         s.Va = (const T *)c->Q[ia]; s.Vb = (const T *)c->Q[ib]; s.Vc = (T *)c->Q[ic];
+        s.Fa = (const T *)c->F[ia]; s.Fb = (const T *)c->F[ib]; s.Fc = (T *)c->F[ic];
+        s.Pw = (T *)c->P[ib];
         s.types0 = face_types(c, k - 1);
         s.types1 = face_types(c, k);
         s.types2 = face_types(c, k + 1);
@@ -533,7 +549,9 @@ void hyb_destroy(hyb_ctx *c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    for (int q = 0; q < 3; ++q) { dfree(c->U[q]); dfree(c->V[q]); dfree(c->P[q]); dfree(c->Q[q]); }
+    for (int q = 0; q < 3; ++q) {
+        dfree(c->U[q]); dfree(c->V[q]); dfree(c->P[q]); dfree(c->Q[q]); dfree(c->F[q]);
+    }
     dfree(c->acube);
     dfree(c->hist);
     dfree((void *&)c->sig);
@@ -625,6 +643,7 @@ hyb_status hyb_adjoint(hyb_ctx *c, const double *res, int32_t mode)
     const size_t fb = field_bytes(c->g, c->esz), vb = fem_bytes(c->g, c->esz);
     hyb_status s = HYB_OK;
     for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->P[q], fb);
+    for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->F[q], (size_t)c->g.ftot * c->esz);
     if (!s && c->g.has_fem)
         for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->Q[q], vb);
     if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->G, cube_count(c->g) * sizeof(double));
@@ -713,6 +732,7 @@ hyb_status hyb_footprint(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const
     const size_t nc = cube_count(g), ntr = (size_t)(nt + 1) * g.nx * g.ny * sizeof(double);
     size_t b = 6 * field_bytes(g, esz) + 6 * fem_bytes(g, esz) + nc * (esz + 4 * sizeof(double));
     b += (size_t)(nt + 1) * g.hlevel * esz + 2 * ntr + (MAX_PARTIALS + S_NSCAL) * sizeof(double);
+    b += 3 * (size_t)g.ftot * esz;
     *bytes = b;
     return HYB_OK;
 }
@@ -749,8 +769,13 @@ hyb_status hyb_get_wavefield(hyb_ctx *c, int32_t which, double *u, double *v)
     void *const *A = which == 0 ? c->U : c->P;
     void *const *B = which == 0 ? c->V : c->Q;
     const int q = which == 0 ? c->last_u : c->last_p;
-    if (c->f32) launch_export_level<float>(c->g, (const float *)A[q], (const float *)B[q], u, v, c->stream);
-    else launch_export_level<double>(c->g, (const double *)A[q], (const double *)B[q], u, v, c->stream);
+    const void *Fq = which == 1 ? c->F[q] : nullptr;  // true boundary multipliers
+    if (c->f32)
+        launch_export_level<float>(c->g, (const float *)A[q], (const float *)B[q], (const float *)Fq, u, v,
+                                   c->stream);
+    else
+        launch_export_level<double>(c->g, (const double *)A[q], (const double *)B[q], (const double *)Fq, u,
+                                    v, c->stream);
     HIPCHK(c, hipGetLastError());
     return HYB_OK;
 }

@@ -27,7 +27,9 @@ struct Geo {
     int hlo[3], hhi[3];       // closed hole [o+2, o+C-2] (grid coords)
     int hn[3];                // history sub-box node counts (C-3 per axis)
     long long hlevel;         // history elements per level
-    long long nbnd;           // outer boundary nodes
+    long long nbnd;           // outer boundary nodes (= n_fi + n_ec)
+    long long n_fi, n_ec;     // face-interior nodes; edge and corner nodes
+    long long foff[6], ftot;  // compact per-face arrays of boundary values
     long long nwd, nwo;       // |omega_diamond|, |omega_o|
     int fdm_tiles[3], fem_tiles[3];
     int zc_fdm, zc_fem;       // z chunk per block
@@ -63,7 +65,10 @@ struct Step {
     int seed_mode;           // 0: tau * w_i * res; 1: res
     double dt, h2;
     double *G;               // FP64 gradient accumulator [C^3]
-    T wB1[6], wB0[6];        // weights of boundary neighbours (adjoint interior)
+    const T *Fa, *Fb;        // boundary multipliers of levels k+2, k+1 (face arrays)
+    T *Fc;                   // boundary multipliers of level k
+    T *Pw;                   // level k+1 grid array: receives the boundary proxies
+    T wB1[6], wB0[6];        // proxy weights per face
 };
 
 // ---- launchers (hyb_kernels.hip) ----
@@ -85,7 +90,8 @@ template <typename T>
 void launch_record_face(const Geo &g, const T *U, double *obs_row, hipStream_t st);
 
 template <typename T>
-void launch_export_level(const Geo &g, const T *U, const T *V, double *u, double *v, hipStream_t st);
+void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, double *u, double *v,
+                         hipStream_t st);
 
 // J_misfit = 1/2 sum_{k=1..nt} dt sum_i w_i res^2 -> scal[slot]
 void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h, double *partials,

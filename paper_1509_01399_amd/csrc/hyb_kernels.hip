@@ -45,50 +45,108 @@ __device__ __forceinline__ bool on_bnd(const Geo &g, int x, int y, int z)
     return x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
 }
 
-// Boundary axes of a node and the condition of each at one step.
+// Boundary axes of a node and the condition of each at one step; kind[d] is
+// -1 when d is not a boundary axis, dir[d] the inward direction.  Fixed-size
+// per-axis arrays indexed by unrolled loop constants stay in registers.
 struct BInfo {
-    int nb, nabc;
-    int ax[3], dir[3], kind[3];
+    int kind[3], dir[3];
+    int nabc;
 };
 
 __device__ __forceinline__ BInfo classify(const Geo &g, int x, int y, int z, int types)
 {
     BInfo B;
-    B.nb = 0;
     B.nabc = 0;
     const int c[3] = {x, y, z};
     const int m[3] = {g.nx - 1, g.ny - 1, g.nz - 1};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        int f, dir;
-        if (c[d] == 0) { f = 2 * d; dir = 1; }
-        else if (c[d] == m[d]) { f = 2 * d + 1; dir = -1; }
-        else continue;
-        int kd = ftype(types, f);
-        B.ax[B.nb] = d;
-        B.dir[B.nb] = dir;
-        B.kind[B.nb] = kd;
-        B.nb++;
-        if (kd == F_ABC) B.nabc++;
+        B.kind[d] = -1;
+        B.dir[d] = 0;
+        if (c[d] == 0) { B.kind[d] = ftype(types, 2 * d); B.dir[d] = 1; }
+        else if (c[d] == m[d]) { B.kind[d] = ftype(types, 2 * d + 1); B.dir[d] = -1; }
+        if (B.kind[d] == F_ABC) B.nabc++;
     }
     return B;
 }
 
-__device__ __forceinline__ int axis_slot(const BInfo &B, int d)
+// Index of a boundary node in the compact per-face arrays (the node is
+// stored once, on its first boundary face in the order x, y, z).
+__device__ __forceinline__ long long cidx(const Geo &g, int x, int y, int z)
 {
-    for (int q = 0; q < B.nb; ++q)
-        if (B.ax[q] == d) return q;
-    return -1;
+    if (x == 0) return g.foff[0] + y + (long long)g.ny * z;
+    if (x == g.nx - 1) return g.foff[1] + y + (long long)g.ny * z;
+    if (y == 0) return g.foff[2] + x + (long long)g.nx * z;
+    if (y == g.ny - 1) return g.foff[3] + x + (long long)g.nx * z;
+    if (z == 0) return g.foff[4] + x + (long long)g.nx * y;
+    return g.foff[5] + x + (long long)g.nx * y;
+}
+
+// Boundary threads: face-interior nodes first (z faces, then y, then x; f is
+// the face), then the 12 edges, then the 8 corners.
+__device__ __forceinline__ void face_node(const Geo &g, long long t, int &x, int &y, int &z, int &f)
+{
+    const long long ax = g.nx - 2, ay = g.ny - 2, az = g.nz - 2;
+    const long long A45 = ax * ay, A23 = ax * az;
+    if (t < 2 * A45) {
+        f = t < A45 ? 4 : 5;
+        const long long r = t % A45;
+        x = 1 + (int)(r % ax); y = 1 + (int)(r / ax); z = f == 4 ? 0 : g.nz - 1;
+        return;
+    }
+    t -= 2 * A45;
+    if (t < 2 * A23) {
+        f = t < A23 ? 2 : 3;
+        const long long r = t % A23;
+        x = 1 + (int)(r % ax); z = 1 + (int)(r / ax); y = f == 2 ? 0 : g.ny - 1;
+        return;
+    }
+    t -= 2 * A23;
+    const long long A01 = ay * az;
+    f = t < A01 ? 0 : 1;
+    const long long r = t % A01;
+    y = 1 + (int)(r % ay); z = 1 + (int)(r / ay); x = f == 0 ? 0 : g.nx - 1;
+}
+
+__device__ __forceinline__ void edge_corner_node(const Geo &g, long long t, int &x, int &y, int &z)
+{
+    const long long ex = g.nx - 2, ey = g.ny - 2, ez = g.nz - 2;
+    if (t < 4 * ex) {
+        const int e = (int)(t / ex);
+        x = 1 + (int)(t % ex); y = (e & 1) ? g.ny - 1 : 0; z = (e & 2) ? g.nz - 1 : 0;
+        return;
+    }
+    t -= 4 * ex;
+    if (t < 4 * ey) {
+        const int e = (int)(t / ey);
+        y = 1 + (int)(t % ey); x = (e & 1) ? g.nx - 1 : 0; z = (e & 2) ? g.nz - 1 : 0;
+        return;
+    }
+    t -= 4 * ey;
+    if (t < 4 * ez) {
+        const int e = (int)(t / ez);
+        z = 1 + (int)(t % ez); x = (e & 1) ? g.nx - 1 : 0; y = (e & 2) ? g.ny - 1 : 0;
+        return;
+    }
+    t -= 4 * ez;
+    x = (t & 1) ? g.nx - 1 : 0; y = (t & 2) ? g.ny - 1 : 0; z = (t & 4) ? g.nz - 1 : 0;
 }
 
 // ---------------------------------------------------------------- forward
 
-// Level k+1 value of boundary node (x,y,z).  Ghost-node leapfrog when every
-// boundary axis reflects (Neumann, or the source face while the pulse is on:
-// each such axis contributes 2(u_in - u)/h^2, the source adds 2 p/h); else
-// the absorbing row of eq. (eq:abs2) averaged over the absorbing axes, which
-// needs the new value of the inward neighbour (recomputed if it is itself on
-// the boundary; D bounds the recursion depth).
+template <typename T>
+__device__ __forceinline__ T src_flux(const Step<T> &s, int x, int y)
+{
+    return s.flux ? (T)(s.fluxscale * s.flux[x + (long long)s.g.nx * y]) : s.srcterm;
+}
+
+// Level k+1 value of boundary node (x,y,z), any codimension.  Ghost-node
+// leapfrog when every boundary axis reflects (Neumann, or the source face
+// while the pulse is on: each such axis contributes 2(u_in - u)/h^2, the
+// source adds 2 p/h); otherwise the absorbing row of eq. (eq:abs2) averaged
+// over the absorbing axes.  The absorbing row needs the new value of the
+// inward neighbour, recomputed here when that neighbour is itself a boundary
+// node (D bounds the depth: corner -> edge -> face -> interior).
 template <typename T, int D>
 __device__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
 {
@@ -102,66 +160,30 @@ __device__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
         bool src = false;
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const int q = axis_slot(B, d);
-            if (q < 0) {
-                lap += (s.Ub[id + st[d]] - u) + (s.Ub[id - st[d]] - u);
-            } else {
-                lap += (T)2 * (s.Ub[id + B.dir[q] * st[d]] - u);
-                if (B.kind[q] == F_SOURCE) src = true;
-            }
+            if (B.kind[d] < 0) lap += (s.Ub[id + st[d]] - u) + (s.Ub[id - st[d]] - u);
+            else lap += (T)2 * (s.Ub[id + B.dir[d] * st[d]] - u);
+            if (B.kind[d] == F_SOURCE) src = true;
         }
         T v = (T)2 * u - s.Ua[id] + s.c2 * lap;
-        if (src) v += s.flux ? (T)(s.fluxscale * s.flux[x + (long long)g.nx * y]) : s.srcterm;
+        if (src) v += src_flux(s, x, y);
         return v;
     }
     T acc = 0;
-    for (int q = 0; q < B.nb; ++q) {
-        if (B.kind[q] != F_ABC) continue;
-        int c[3] = {x, y, z};
-        c[B.ax[q]] += B.dir[q];
-        const long long in = gidx(g, c[0], c[1], c[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (B.kind[d] != F_ABC) continue;
+        const int cx = x + (d == 0 ? B.dir[d] : 0), cy = y + (d == 1 ? B.dir[d] : 0),
+                  cz = z + (d == 2 ? B.dir[d] : 0);
+        const long long in = gidx(g, cx, cy, cz);
         T up;
-        if (on_bnd(g, c[0], c[1], c[2])) {
-            if constexpr (D > 1) up = bnd_fwd<T, D - 1>(s, c[0], c[1], c[2]);
-            else up = 0;  // unreachable: the inward chain ends in the interior
-        } else {
-            up = s.Uc[in];
-        }
+        if constexpr (D > 1) up = on_bnd(g, cx, cy, cz) ? bnd_fwd<T, D - 1>(s, cx, cy, cz) : s.Uc[in];
+        else up = s.Uc[in];
         acc += s.Ub[in] + s.r * (u - up);
     }
     return acc / (T)B.nabc;
 }
 
-// Position of thread t among the boundary nodes: z faces whole, then y faces
-// without z edges, then x faces without y/z edges.
-__device__ __forceinline__ void bnd_coord(const Geo &g, long long t, int &x, int &y, int &z)
-{
-    const long long nxy = (long long)g.nx * g.ny;
-    if (t < 2 * nxy) {
-        z = t < nxy ? 0 : g.nz - 1;
-        const long long r = t % nxy;
-        x = (int)(r % g.nx);
-        y = (int)(r / g.nx);
-        return;
-    }
-    t -= 2 * nxy;
-    const long long nxz = (long long)g.nx * (g.nz - 2);
-    if (t < 2 * nxz) {
-        y = t < nxz ? 0 : g.ny - 1;
-        const long long r = t % nxz;
-        x = (int)(r % g.nx);
-        z = 1 + (int)(r / g.nx);
-        return;
-    }
-    t -= 2 * nxz;
-    const long long nyz = (long long)(g.ny - 2) * (g.nz - 2);
-    x = t < nyz ? 0 : g.nx - 1;
-    const long long r = t % nyz;
-    y = 1 + (int)(r % (g.ny - 2));
-    z = 1 + (int)(r / (g.ny - 2));
-}
-
-// Surface node t of a box with L+1 nodes per axis (L >= 2): local coords.
+// Surface node t of a box with L+1 nodes per axis (L >= 1): local coords.
 __device__ __forceinline__ void box_surface(long long t, int L, int &a, int &b, int &c)
 {
     const long long n1 = L + 1, f = n1 * n1;
@@ -194,15 +216,39 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_fwd(Step<T> s)
 {
     const Geo &g = s.g;
     long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (t < g.nbnd) {
+    if (t < g.n_fi) {
+        // face-interior node: one boundary axis, never needs recursion
+        int x, y, z, f;
+        face_node(g, t, x, y, z, f);
+        const int d = f >> 1, dir = (f & 1) ? -1 : 1;
+        const long long sd = d == 0 ? 1 : (d == 1 ? g.px : g.plane);     // inward axis stride
+        const long long sa = d == 0 ? g.px : 1, sb = d == 2 ? g.px : g.plane;  // tangential strides
+        const long long id = gidx(g, x, y, z), in = id + dir * sd;
+        const int kind = ftype(s.types1, f);
+        const T u = s.Ub[id];
+        T v;
+        if (kind == F_ABC) {
+            v = s.Ub[in] + s.r * (u - s.Uc[in]);
+        } else {
+            const T lap = (T)2 * (s.Ub[in] - u) + ((s.Ub[id + sa] - u) + (s.Ub[id - sa] - u)) +
+                          ((s.Ub[id + sb] - u) + (s.Ub[id - sb] - u));
+            v = (T)2 * u - s.Ua[id] + s.c2 * lap;
+            if (kind == F_SOURCE) v += src_flux(s, x, y);
+        }
+        s.Uc[id] = v;
+        if (s.obs && f == 5) s.obs[x + (long long)g.nx * y] = (double)v;
+        return;
+    }
+    t -= g.n_fi;
+    if (t < g.n_ec) {
         int x, y, z;
-        bnd_coord(g, t, x, y, z);
+        edge_corner_node(g, t, x, y, z);
         const T v = bnd_fwd<T, 3>(s, x, y, z);
         s.Uc[gidx(g, x, y, z)] = v;
         if (s.obs && z == g.nz - 1) s.obs[x + (long long)g.nx * y] = (double)v;
         return;
     }
-    t -= g.nbnd;
+    t -= g.n_ec;
     if (t < g.nwd) {  // Algorithm 2 step 3: FEM values to the FDM inner boundary
         int a, b, c;
         box_surface(t, g.C[0] - 4, a, b, c);
@@ -218,6 +264,26 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_fwd(Step<T> s)
 }
 
 // ---------------------------------------------------------------- adjoint
+//
+// Multipliers of the boundary rows live in compact per-face arrays (Fa, Fb,
+// Fc = levels k+2, k+1, k).  The grid array of level k+1 carries, at each
+// face node, the value the seven-point stencil of the interior neighbour has
+// to see ("proxy": (wB1 mu^{k+1}_b + wB0 mu^k_b) / c2), so the interior
+// adjoint update is the plain stencil.
+
+template <typename T>
+__device__ __forceinline__ T seed_at(const Step<T> &s, int x, int y)
+{
+    const Geo &g = s.g;
+    double rv = s.res[x + (long long)g.nx * y];
+    if (s.seed_mode == 0) {
+        double w = s.h2;
+        if (x == 0 || x == g.nx - 1) w *= 0.5;
+        if (y == 0 || y == g.ny - 1) w *= 0.5;
+        rv *= s.dt * w;
+    }
+    return (T)rv;
+}
 
 // Multiplier of boundary node b at level k: the sum, over every row that
 // reads u^k_b, of (its coefficient) x (its multiplier):
@@ -226,75 +292,143 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_fwd(Step<T> s)
 //   rows of boundary neighbours at level k+1 (c2, or 2 c2 when b is their
 //   inward neighbour); absorbing rows at level k+1 whose inward neighbour is
 //   b (1/|S|) and absorbing rows of the same level k whose inward neighbour
-//   is b (-r/|S|, recomputed recursively); the trace seed on the z+ face.
-template <typename T, int D>
+//   is b (-r/|S|); the trace seed on z+.  The last kind comes from nodes of
+//   higher codimension, whose level-k multipliers are already in Fc:
+//   corners are computed first, then edges, then faces.
+template <typename T>
 __device__ T bnd_adj(const Step<T> &s, int x, int y, int z)
 {
     const Geo &g = s.g;
-    const long long id = gidx(g, x, y, z);
     const T c2 = s.c2;
+    const long long cb = cidx(g, x, y, z);
     const BInfo B1 = classify(g, x, y, z, s.types1);
-    T mu = (B1.nabc == 0 ? ((T)2 - (T)6 * c2) : s.r) * s.Ub[id];
     const BInfo B2 = classify(g, x, y, z, s.types2);
-    if (B2.nabc == 0) mu -= s.Ua[id];
+    T mu = (B1.nabc == 0 ? ((T)2 - (T)6 * c2) : s.r) * s.Fb[cb];
+    if (B2.nabc == 0) mu -= s.Fa[cb];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        for (int sg = -1; sg <= 1; sg += 2) {
-            int c[3] = {x, y, z};
-            c[d] += sg;
-            const int m = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
-            if (c[d] < 0 || c[d] >= m) continue;
-            const long long nid = gidx(g, c[0], c[1], c[2]);
-            if (!on_bnd(g, c[0], c[1], c[2])) {
-                mu += c2 * s.Ub[nid];
-                continue;
-            }
-            const BInfo N1 = classify(g, c[0], c[1], c[2], s.types1);
-            const int q1 = axis_slot(N1, d);
-            if (N1.nabc == 0) {
-                mu += (q1 >= 0 ? (T)2 * c2 : c2) * s.Ub[nid];
-            } else if (q1 >= 0 && N1.kind[q1] == F_ABC) {
-                mu += s.Ub[nid] / (T)N1.nabc;
-            }
-            if (s.level_rows) {
-                const BInfo N0 = classify(g, c[0], c[1], c[2], s.types0);
-                const int q0 = axis_slot(N0, d);
-                if (N0.nabc > 0 && q0 >= 0 && N0.kind[q0] == F_ABC) {
-                    T mun = 0;
-                    if constexpr (D > 1) mun = bnd_adj<T, D - 1>(s, c[0], c[1], c[2]);
-                    mu -= s.r * mun / (T)N0.nabc;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int sg = 2 * q - 1;
+            const int cx = x + (d == 0 ? sg : 0), cy = y + (d == 1 ? sg : 0), cz = z + (d == 2 ? sg : 0);
+            const int cd = d == 0 ? cx : (d == 1 ? cy : cz);
+            const int md = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+            if (cd >= 0 && cd < md) {
+                if (!on_bnd(g, cx, cy, cz)) {
+                    mu += c2 * s.Ub[gidx(g, cx, cy, cz)];
+                } else {
+                    const long long cn = cidx(g, cx, cy, cz);
+                    const BInfo N1 = classify(g, cx, cy, cz, s.types1);
+                    if (N1.nabc == 0) mu += (N1.kind[d] >= 0 ? (T)2 * c2 : c2) * s.Fb[cn];
+                    else if (N1.kind[d] == F_ABC) mu += s.Fb[cn] / (T)N1.nabc;
+                    if (s.level_rows) {
+                        const BInfo N0 = classify(g, cx, cy, cz, s.types0);
+                        if (N0.nabc > 0 && N0.kind[d] == F_ABC) mu -= s.r * s.Fc[cn] / (T)N0.nabc;
+                    }
                 }
             }
         }
     }
-    if (s.res && z == g.nz - 1) {
-        double rv = s.res[x + (long long)g.nx * y];
-        if (s.seed_mode == 0) {
-            double w = s.h2;
-            if (x == 0 || x == g.nx - 1) w *= 0.5;
-            if (y == 0 || y == g.ny - 1) w *= 0.5;
-            rv *= s.dt * w;
-        }
-        mu += (T)rv;
-    }
+    if (s.res && z == g.nz - 1) mu += seed_at(s, x, y);
     return mu;
 }
 
+// Edge node number p (1..L) of edge e (0-3 along x, 4-7 along y, 8-11 along z;
+// bit 0 / bit 1 of e pick the low or high side of the other two axes).
+__device__ __forceinline__ void edge_node(const Geo &g, int e, int p, int &x, int &y, int &z)
+{
+    const int a = e >> 2, b0 = e & 1, b1 = (e >> 1) & 1;
+    if (a == 0) { x = p; y = b0 ? g.ny - 1 : 0; z = b1 ? g.nz - 1 : 0; }
+    else if (a == 1) { y = p; x = b0 ? g.nx - 1 : 0; z = b1 ? g.nz - 1 : 0; }
+    else { z = p; x = b0 ? g.nx - 1 : 0; y = b1 ? g.ny - 1 : 0; }
+}
+
+// Corners and edges of level k.  Only the two end nodes of each edge read a
+// corner of the same level: block 0 computes the 8 corners, then (after a
+// barrier) the 24 end nodes; all other edge nodes are independent.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec(Step<T> s)
+{
+    const Geo &g = s.g;
+    const int L[3] = {g.nx - 2, g.ny - 2, g.nz - 2};
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < 8) {
+            const int t = threadIdx.x;
+            const int x = (t & 1) ? g.nx - 1 : 0, y = (t & 2) ? g.ny - 1 : 0, z = (t & 4) ? g.nz - 1 : 0;
+            s.Fc[cidx(g, x, y, z)] = bnd_adj(s, x, y, z);
+        }
+        __syncthreads();
+        if (threadIdx.x < 24) {
+            const int e = threadIdx.x >> 1, end = threadIdx.x & 1;
+            const int Le = L[e >> 2];
+            int x, y, z;
+            edge_node(g, e, end ? Le : 1, x, y, z);
+            const T mu = bnd_adj(s, x, y, z);
+            if (!(end && Le == 1)) s.Fc[cidx(g, x, y, z)] = mu;  // a 1-node edge is written once
+        }
+        return;
+    }
+    // inner edge nodes (positions 2..L-1)
+    long long t = (long long)(blockIdx.x - 1) * BLOCK + threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long long m = L[a] > 2 ? L[a] - 2 : 0;
+        if (t < 4 * m) {
+            int x, y, z;
+            edge_node(g, 4 * a + (int)(t / m), 2 + (int)(t % m), x, y, z);
+            s.Fc[cidx(g, x, y, z)] = bnd_adj(s, x, y, z);
+            return;
+        }
+        t -= 4 * m;
+    }
+}
+
+template <typename T, bool ADJ>
+__device__ void fem_tile(const Step<T> &s, int bid);
+
+// Face nodes (after k_bnd_adj_ec), and in the same launch the FEM rows of the
+// adjoint with the gradient integral (they need nothing of level k).
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_bnd_adj(Step<T> s)
 {
     const Geo &g = s.g;
-    const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
-    if (t < g.nbnd) {
-        int x, y, z;
-        bnd_coord(g, t, x, y, z);
-        s.Uc[gidx(g, x, y, z)] = bnd_adj<T, 3>(s, x, y, z);
+    if ((int)blockIdx.x < g.n_fem_blocks) {
+        fem_tile<T, true>(s, blockIdx.x);
+        return;
     }
+    const long long t = (long long)(blockIdx.x - g.n_fem_blocks) * BLOCK + threadIdx.x;
+    if (t >= g.n_fi) return;
+    int x, y, z, f;
+    face_node(g, t, x, y, z, f);
+    const int d = f >> 1, dir = (f & 1) ? -1 : 1;
+    const long long sd = d == 0 ? 1 : (d == 1 ? g.px : g.plane);
+    const long long id = gidx(g, x, y, z), in = id + dir * sd;
+    const long long cb = cidx(g, x, y, z);
+    // position on the face along its two tangential axes
+    const int pa = d == 0 ? y : x, pb = d == 2 ? y : z;
+    const int na = d == 0 ? g.ny : g.nx, nb = d == 2 ? g.ny : g.nz;
+    const T fb = s.Fb[cb];
+    T mu;
+    if (pa >= 2 && pa <= na - 3 && pb >= 2 && pb <= nb - 3) {
+        // away from edges: the neighbours on the face are face nodes of the
+        // same kind; the only other neighbour is the interior one
+        const int k1 = ftype(s.types1, f), k2 = ftype(s.types2, f);
+        const long long sb = d == 0 ? g.ny : g.nx;  // strides in the face array: 1 and sb
+        mu = (k1 != F_ABC ? ((T)2 - (T)6 * s.c2) : s.r) * fb + s.c2 * s.Ub[in];
+        if (k2 != F_ABC) mu -= s.Fa[cb];
+        if (k1 != F_ABC) mu += s.c2 * ((s.Fb[cb - 1] + s.Fb[cb + 1]) + (s.Fb[cb - sb] + s.Fb[cb + sb]));
+        if (s.res && f == 5) mu += seed_at(s, x, y);
+    } else {
+        mu = bnd_adj(s, x, y, z);
+    }
+    s.Fc[cb] = mu;
+    s.Pw[id] = (s.wB1[f] * fb + s.wB0[f] * mu) / s.c2;  // what the interior stencil reads
 }
 
 // ---------------------------------------------------------------- interior
 
-// kappa_e / h of the FEM-local x/y/z edge starting at node (i,j,k): sum over
-// the 4 cubes of the edge of a_c * w.
+// a of FEM-local cube (i,j,k) and kappa_e / h of the FEM-local x/y/z edge
+// starting at node (i,j,k): the sum over the 4 cubes of the edge of a_c * w.
 template <typename T>
 __device__ __forceinline__ T acub(const Step<T> &s, int i, int j, int k)
 {
@@ -318,70 +452,91 @@ __device__ T kappa_edge(const Step<T> &s, int d, int i, int j, int k)
     return kap;
 }
 
-template <typename T, bool ADJ>
-__device__ void fdm_tile(const Step<T> &s, int bid)
+// Adjoint only, on omega_o (the FEM boundary, FDM interior): the FEM rows
+// that read the copied value V[omega_o] = U[omega_o] contribute
+// c2 kappa_e lambda_V^{k+1} of the FEM node next to it.  Only face-interior
+// nodes of the FEM box surface have such a neighbour.  ax: 0/1/2 for a node
+// on an x/y/z face of the surface; (i,j,k) FEM-local coordinates.
+template <typename T>
+__device__ __forceinline__ T omega_o_term(const Step<T> &s, int ax, int i, int j, int k)
 {
     const Geo &g = s.g;
-    const int bx = bid % g.fdm_tiles[0];
-    const int t = bid / g.fdm_tiles[0];
-    const int by = t % g.fdm_tiles[1];
-    const int bz = t / g.fdm_tiles[1];
-    const int x = 1 + bx * TX_FDM + (int)(threadIdx.x % TX_FDM);
-    const int y = 1 + by * TY_FDM + (int)(threadIdx.x / TX_FDM);
-    if (x > g.nx - 2 || y > g.ny - 2) return;
-    const int z0 = 1 + bz * g.zc_fdm;
-    const int z1 = min(z0 + g.zc_fdm, g.nz - 1);
-    const bool hcol = g.has_fem && x >= g.hlo[0] && x <= g.hhi[0] && y >= g.hlo[1] && y <= g.hhi[1];
-    if (hcol && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
+    if (ax == 0) {
+        const int ie = i == 0 ? 0 : g.C[0] - 1, im = i == 0 ? 1 : g.C[0] - 1;
+        return s.c2 * kappa_edge(s, 0, ie, j, k) * s.Vb[fidx(g, im, j, k)];
+    }
+    if (ax == 1) {
+        const int je = j == 0 ? 0 : g.C[1] - 1, jm = j == 0 ? 1 : g.C[1] - 1;
+        return s.c2 * kappa_edge(s, 1, i, je, k) * s.Vb[fidx(g, i, jm, k)];
+    }
+    const int ke = k == 0 ? 0 : g.C[2] - 1, km = k == 0 ? 1 : g.C[2] - 1;
+    return s.c2 * kappa_edge(s, 2, i, j, ke) * s.Vb[fidx(g, i, j, km)];
+}
+
+// Seven-point leapfrog, eq. (fdmschemeforward), on one column (x,y) for
+// z in [z0, z1), skipping the closed hole [o+2, o+C-2]^3.  The same stencil
+// is the adjoint update of the FDM rows (ADJ adds the omega_o term).
+template <typename T, bool ADJ>
+__device__ __forceinline__ void fdm_column(const Step<T> &s, int x, int y, int z0, int z1, bool hcol)
+{
+    const Geo &g = s.g;
     const long long py = g.px, pz = g.plane;
     long long id = gidx(g, x, y, z0);
     const T c2 = s.c2;
+    // omega_o column flags (adjoint): x/y faces of the FEM box surface need
+    // the term for o < z < o+C, the z faces at z = o and z = o+C
+    const int i = x - g.o[0], j = y - g.o[1];
+    const bool ii = i > 0 && i < g.C[0], jj = j > 0 && j < g.C[1];
+    const bool colx = ADJ && g.has_fem && jj && (i == 0 || i == g.C[0]);
+    const bool coly = ADJ && g.has_fem && ii && (j == 0 || j == g.C[1]);
+    const bool colz = ADJ && g.has_fem && ii && jj;
     T cm = s.Ub[id - pz], c0 = s.Ub[id];
     for (int z = z0; z < z1; ++z, id += pz) {
         const T cp = s.Ub[id + pz];
         if (!(hcol && z >= g.hlo[2] && z <= g.hhi[2])) {
             const T xm = s.Ub[id - 1], xp = s.Ub[id + 1], ym = s.Ub[id - py], yp = s.Ub[id + py];
-            T v;
-            if constexpr (!ADJ) {
-                v = (T)2 * c0 - s.Ua[id] + c2 * (((xm + xp) + (ym + yp)) + (cm + cp) - (T)6 * c0);
-            } else {
-                // transposed rows that read this node: its own FDM row (levels
-                // k+1, k+2), the FDM rows of its neighbours, the boundary rows
-                // of boundary neighbours (weights wB1 at level k+1, wB0 for the
-                // absorbing rows of level k), and on omega_o the FEM rows that
-                // read the copied value.
-                T acc = (T)2 * c0 - s.Ua[id] - (T)6 * c2 * c0;
-                acc += (x == 1 ? s.wB1[0] : c2) * xm + (x == g.nx - 2 ? s.wB1[1] : c2) * xp;
-                acc += (y == 1 ? s.wB1[2] : c2) * ym + (y == g.ny - 2 ? s.wB1[3] : c2) * yp;
-                acc += (z == 1 ? s.wB1[4] : c2) * cm + (z == g.nz - 2 ? s.wB1[5] : c2) * cp;
-                if (x == 1) acc += s.wB0[0] * s.Uc[id - 1];
-                if (x == g.nx - 2) acc += s.wB0[1] * s.Uc[id + 1];
-                if (y == 1) acc += s.wB0[2] * s.Uc[id - py];
-                if (y == g.ny - 2) acc += s.wB0[3] * s.Uc[id + py];
-                if (z == 1) acc += s.wB0[4] * s.Uc[id - pz];
-                if (z == g.nz - 2) acc += s.wB0[5] * s.Uc[id + pz];
-                if (g.has_fem) {
-                    const int i = x - g.o[0], j = y - g.o[1], k = z - g.o[2];
-                    const int Cx = g.C[0], Cy = g.C[1], Cz = g.C[2];
-                    const bool in_i = i > 0 && i < Cx, in_j = j > 0 && j < Cy, in_k = k > 0 && k < Cz;
-                    if (in_j && in_k && (i == 0 || i == Cx)) {
-                        const int ie = i == 0 ? 0 : Cx - 1, im = i == 0 ? 1 : Cx - 1;
-                        acc += c2 * kappa_edge(s, 0, ie, j, k) * s.Vb[fidx(g, im, j, k)];
-                    } else if (in_i && in_k && (j == 0 || j == Cy)) {
-                        const int je = j == 0 ? 0 : Cy - 1, jm = j == 0 ? 1 : Cy - 1;
-                        acc += c2 * kappa_edge(s, 1, i, je, k) * s.Vb[fidx(g, i, jm, k)];
-                    } else if (in_i && in_j && (k == 0 || k == Cz)) {
-                        const int ke = k == 0 ? 0 : Cz - 1, km = k == 0 ? 1 : Cz - 1;
-                        acc += c2 * kappa_edge(s, 2, i, j, ke) * s.Vb[fidx(g, i, j, km)];
-                    }
-                }
-                v = acc;
+            T v = (T)2 * c0 - s.Ua[id] + c2 * (((xm + xp) + (ym + yp)) + (cm + cp) - (T)6 * c0);
+            if constexpr (ADJ) {
+                const int k = z - g.o[2];
+                const bool kk = k > 0 && k < g.C[2];
+                if ((colx || coly) && kk) v += omega_o_term(s, colx ? 0 : 1, i, j, k);
+                else if (colz && (k == 0 || k == g.C[2])) v += omega_o_term(s, 2, i, j, k);
             }
             s.Uc[id] = v;
         }
         cm = c0;
         c0 = cp;
     }
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
+// Remap so that every XCD gets a contiguous range of tiles: neighbouring
+// tiles (which read each other's rows as halo) then share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblk)
+{
+    const int per = (nblk + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
+template <typename T, bool ADJ>
+__device__ void fdm_tile(const Step<T> &s, int bid)
+{
+    const Geo &g = s.g;
+    bid = xcd_remap(bid, g.n_fdm_blocks);
+    if (bid >= g.n_fdm_blocks) return;
+    const int bx = bid % g.fdm_tiles[0];
+    const int t = bid / g.fdm_tiles[0];
+    const int by = t % g.fdm_tiles[1];
+    const int bz = t / g.fdm_tiles[1];
+    const int x0 = 1 + bx * TX_FDM, y0 = 1 + by * TY_FDM;
+    const int x = x0 + (int)(threadIdx.x % TX_FDM);
+    const int y = y0 + (int)(threadIdx.x / TX_FDM);
+    if (x > g.nx - 2 || y > g.ny - 2) return;
+    const int z0 = 1 + bz * g.zc_fdm;
+    const int z1 = min(z0 + g.zc_fdm, g.nz - 1);
+    const bool hcol = g.has_fem && x >= g.hlo[0] && x <= g.hhi[0] && y >= g.hlo[1] && y <= g.hhi[1];
+    if (hcol && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
+    fdm_column<T, ADJ>(s, x, y, z0, z1, hcol);
 }
 
 template <typename T, bool ADJ>
@@ -476,34 +631,43 @@ __device__ void fem_tile(const Step<T> &s, int bid)
     }
 }
 
+// FDM blocks first (their count rounded up to a multiple of 8 for the XCD
+// remap), then, in the forward sweep, the FEM blocks.  The FEM rows of the
+// adjoint run in the boundary launch.
 template <typename T, bool ADJ>
 __global__ __launch_bounds__(BLOCK) void k_interior(Step<T> s)
 {
     const int b = blockIdx.x;
-    if (b < s.g.n_fem_blocks) fem_tile<T, ADJ>(s, b);
-    else fdm_tile<T, ADJ>(s, b - s.g.n_fem_blocks);
+    const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
+    if (b < nf) fdm_tile<T, ADJ>(s, b);
+    else if constexpr (!ADJ) fem_tile<T, false>(s, b - nf);
 }
 
 template <typename T>
 void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st)
 {
-    const int nb = s.g.n_fem_blocks + s.g.n_fdm_blocks;
-    if (adjoint) hipLaunchKernelGGL((k_interior<T, true>), dim3(nb), dim3(BLOCK), 0, st, s);
-    else hipLaunchKernelGGL((k_interior<T, false>), dim3(nb), dim3(BLOCK), 0, st, s);
+    const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
+    if (adjoint)
+        hipLaunchKernelGGL((k_interior<T, true>), dim3(nf), dim3(BLOCK), 0, st, s);
+    else
+        hipLaunchKernelGGL((k_interior<T, false>), dim3(nf + s.g.n_fem_blocks), dim3(BLOCK), 0, st, s);
 }
 
 template <typename T>
 void launch_bnd_fwd(const Step<T> &s, hipStream_t st)
 {
-    const long long n = s.g.nbnd + s.g.nwd + s.g.nwo;
+    const long long n = s.g.n_fi + s.g.n_ec + s.g.nwd + s.g.nwo;
     hipLaunchKernelGGL((k_bnd_fwd<T>), dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
 }
 
 template <typename T>
 void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_bnd_adj<T>), dim3((unsigned)((s.g.nbnd + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
-                       st, s);
+    long long inner = 0;
+    for (int n : {s.g.nx, s.g.ny, s.g.nz}) inner += 4 * (long long)(n - 2 > 2 ? n - 4 : 0);
+    hipLaunchKernelGGL((k_bnd_adj_ec<T>), dim3((unsigned)(1 + (inner + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
+    const long long nb = s.g.n_fem_blocks + (s.g.n_fi + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL((k_bnd_adj<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, s);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -634,12 +798,13 @@ void launch_record_face(const Geo &g, const T *U, double *obs_row, hipStream_t s
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const T *V, double *u, double *v)
+__global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const T *V, const T *F, double *u,
+                                                       double *v)
 {
     const long long n = (long long)g.nx * g.ny * g.nz;
     for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
         const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), z = (int)(t / ((long long)g.nx * g.ny));
-        if (u) u[t] = (double)U[gidx(g, x, y, z)];
+        if (u) u[t] = (double)((F && on_bnd(g, x, y, z)) ? F[cidx(g, x, y, z)] : U[gidx(g, x, y, z)]);
     }
     if (!v || !g.has_fem) return;
     const long long nf = (long long)(g.C[0] + 1) * (g.C[1] + 1) * (g.C[2] + 1);
@@ -648,9 +813,10 @@ __global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const
 }
 
 template <typename T>
-void launch_export_level(const Geo &g, const T *U, const T *V, double *u, double *v, hipStream_t st)
+void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, double *u, double *v,
+                         hipStream_t st)
 {
-    hipLaunchKernelGGL((k_export_level<T>), dim3(1024), dim3(BLOCK), 0, st, g, U, V, u, v);
+    hipLaunchKernelGGL((k_export_level<T>), dim3(1024), dim3(BLOCK), 0, st, g, U, V, F, u, v);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_misfit(Geo g, const double *res, int nt, double wscale,
@@ -809,7 +975,8 @@ void launch_residual(const double *obs, const double *data, double *res, long lo
     template void launch_load_level<T>(const Geo &, const double *, T *, T *, hipStream_t);        \
     template void launch_hist_level<T>(const Geo &, const T *, T *, hipStream_t);                  \
     template void launch_record_face<T>(const Geo &, const T *, double *, hipStream_t);            \
-    template void launch_export_level<T>(const Geo &, const T *, const T *, double *, double *, hipStream_t);
+    template void launch_export_level<T>(const Geo &, const T *, const T *, const T *, double *, double *,     \
+                                         hipStream_t);
 HYB_INST(double)
 HYB_INST(float)
 
