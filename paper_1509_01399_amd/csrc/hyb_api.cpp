@@ -52,6 +52,11 @@ struct hyb_ctx {
     bool have_forward = false, have_adjoint = false;
     int nt = 0, k_on = 0, adj_mode = 0;
     int last_u = 1, last_p = 1;  // buffer index of the newest level
+    bool u_valid = false;        // U buffers still hold the last forward level
+    hyb_source src{};            // source of the last forward (recompute)
+    void *ckpt = nullptr;        // checkpoints (store modes 1, 2)
+    size_t ckpt_bytes = 0;
+    int ckK = 1, cur_seg = 0;    // segment length and the segment in the history
     double dt = 0;
     std::string err;
 };
@@ -380,8 +385,107 @@ Step<T> make_step(const hyb_ctx *c)
     return s;
 }
 
+// History pointer of FEM level L (null when not kept).  Store mode 0 keeps
+// every level; the checkpoint modes keep the levels of one segment
+// [seg*K, seg*K + K - 1] of the sqrt(nt) segmentation.
 template <typename T>
-hyb_status run_forward(hyb_ctx *c, const hyb_source *src, double *obs)
+T *hist_ptr(hyb_ctx *c, int L)
+{
+    if (!c->g.has_fem) return nullptr;
+    if (c->store_mode == 0) return (T *)c->hist + (long long)L * c->g.hlevel;
+    const int lo = c->cur_seg * c->ckK;
+    if (L < lo || L >= lo + c->ckK) return nullptr;
+    return (T *)c->hist + (long long)(L - lo) * c->g.hlevel;
+}
+
+size_t ckpt_slot_bytes(const Geo &g, size_t esz, int mode)
+{
+    const size_t fb = field_bytes(g, esz), vb = fem_bytes(g, esz);
+    return mode == 2 ? (fb + vb) + (fb + vb) / 2 : 2 * (fb + vb);
+}
+
+// Save the state (levels L, L-1 in buffers ib, ia) as checkpoint number q.
+template <typename T>
+hyb_status save_ckpt(hyb_ctx *c, int q, int ia, int ib)
+{
+    const Geo &g = c->g;
+    const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
+    char *base = (char *)c->ckpt + (size_t)q * ckpt_slot_bytes(g, sizeof(T), c->store_mode);
+    const hipStream_t st = c->stream;
+    HIPCHK(c, hipMemcpyAsync(base, c->U[ib], fb, hipMemcpyDeviceToDevice, st));
+    if (vb) HIPCHK(c, hipMemcpyAsync(base + fb, c->V[ib], vb, hipMemcpyDeviceToDevice, st));
+    if (c->store_mode == 1) {
+        HIPCHK(c, hipMemcpyAsync(base + fb + vb, c->U[ia], fb, hipMemcpyDeviceToDevice, st));
+        if (vb) HIPCHK(c, hipMemcpyAsync(base + 2 * fb + vb, c->V[ia], vb, hipMemcpyDeviceToDevice, st));
+    } else {
+        uint16_t *half = (uint16_t *)(base + fb + vb);
+        launch_pack_bf16(c->U[ib], c->U[ia], half, (long long)(fb / sizeof(float)), st);
+        if (vb)
+            launch_pack_bf16(c->V[ib], c->V[ia], half + fb / sizeof(float), (long long)(vb / sizeof(float)), st);
+    }
+    return HYB_OK;
+}
+
+// Restore checkpoint q into buffers 1 (level L) and 0 (level L-1).
+template <typename T>
+hyb_status load_ckpt(hyb_ctx *c, int q)
+{
+    const Geo &g = c->g;
+    const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
+    const char *base = (const char *)c->ckpt + (size_t)q * ckpt_slot_bytes(g, sizeof(T), c->store_mode);
+    const hipStream_t st = c->stream;
+    HIPCHK(c, hipMemcpyAsync(c->U[1], base, fb, hipMemcpyDeviceToDevice, st));
+    if (vb) HIPCHK(c, hipMemcpyAsync(c->V[1], base + fb, vb, hipMemcpyDeviceToDevice, st));
+    if (c->store_mode == 1) {
+        HIPCHK(c, hipMemcpyAsync(c->U[0], base + fb + vb, fb, hipMemcpyDeviceToDevice, st));
+        if (vb) HIPCHK(c, hipMemcpyAsync(c->V[0], base + 2 * fb + vb, vb, hipMemcpyDeviceToDevice, st));
+    } else {
+        const uint16_t *half = (const uint16_t *)(base + fb + vb);
+        launch_unpack_bf16(c->U[1], half, c->U[0], (long long)(fb / sizeof(float)), st);
+        if (vb)
+            launch_unpack_bf16(c->V[1], half + fb / sizeof(float), c->V[0], (long long)(vb / sizeof(float)), st);
+    }
+    return HYB_OK;
+}
+
+// Forward steps k in [k0, k1) on buffers (ia, ib, ic) (levels k-1, k, k+1);
+// records the trace when obs is given and the FEM history where kept; saves
+// a checkpoint at every multiple of K when `save` is set.
+template <typename T>
+hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, double *obs, bool save)
+{
+    const Geo &g = c->g;
+    const hipStream_t st = c->stream;
+    const long long nface = (long long)g.nx * g.ny;
+    Step<T> s = make_step<T>(c);
+    const double fluxscale = 2.0 * c->dt * c->dt / c->h;
+    for (int k = k0; k < k1; ++k) {
+        s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
+        s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
+        s.types1 = face_types(c, k);
+        if (c->src.kind == 0) {
+            s.flux = nullptr;
+            s.srcterm = (T)(fluxscale * std::sin(c->src.omega * ((double)k * c->dt)));
+        } else {
+            s.flux = k < c->k_on ? c->src.flux_dev + (long long)k * nface : nullptr;
+            s.fluxscale = fluxscale;
+            s.srcterm = 0;
+        }
+        s.obs = obs ? obs + (long long)(k + 1) * nface : nullptr;
+        s.hist = hist_ptr<T>(c, k + 1);
+        launch_interior<T>(s, false, st);
+        launch_bnd_fwd<T>(s, st);
+        const int t = ia; ia = ib; ib = ic; ic = t;
+        if (save && (k + 1) % c->ckK == 0) {
+            hyb_status r = save_ckpt<T>(c, (k + 1) / c->ckK, ia, ib);
+            if (r) return r;
+        }
+    }
+    return HYB_OK;
+}
+
+template <typename T>
+hyb_status run_forward(hyb_ctx *c, double *obs)
 {
     const Geo &g = c->g;
     const hipStream_t st = c->stream;
@@ -396,33 +500,39 @@ hyb_status run_forward(hyb_ctx *c, const hyb_source *src, double *obs)
         c->ic_set = false;
         c->ic_u0 = c->ic_um1 = nullptr;
     }
-    const long long nface = (long long)g.nx * g.ny;
+    const bool ck = c->store_mode != 0;
+    // the forward sweep ends in the last segment, whose history it keeps
+    c->cur_seg = ck ? c->nt / c->ckK : 0;
     if (obs) launch_record_face<T>(g, (const T *)c->U[1], obs, st);
-    if (g.has_fem) launch_hist_level<T>(g, (const T *)c->V[1], (T *)c->hist, st);
-    Step<T> s = make_step<T>(c);
-    const double fluxscale = 2.0 * c->dt * c->dt / c->h;
+    if (T *h0 = hist_ptr<T>(c, 0)) launch_hist_level<T>(g, (const T *)c->V[1], h0, st);
     int ia = 0, ib = 1, ic = 2;
-    for (int k = 0; k < c->nt; ++k) {
-        s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
-        s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
-        s.types1 = face_types(c, k);
-        if (src->kind == 0) {
-            s.flux = nullptr;
-            s.srcterm = (T)(fluxscale * std::sin(src->omega * ((double)k * c->dt)));
-        } else {
-            s.flux = k < c->k_on ? src->flux_dev + (long long)k * nface : nullptr;
-            s.fluxscale = fluxscale;
-            s.srcterm = 0;
-        }
-        s.obs = obs ? obs + (long long)(k + 1) * nface : nullptr;
-        s.hist = g.has_fem ? (T *)c->hist + (long long)(k + 1) * g.hlevel : nullptr;
-        launch_interior<T>(s, false, st);
-        launch_bnd_fwd<T>(s, st);
-        const int t = ia; ia = ib; ib = ic; ic = t;
+    if (ck) {
+        hyb_status r = save_ckpt<T>(c, 0, ia, ib);
+        if (r) return r;
     }
+    hyb_status r = fwd_steps<T>(c, 0, c->nt, ia, ib, ic, obs, ck);
+    if (r) return r;
     c->last_u = ib;
+    c->u_valid = true;
     HIPCHK(c, hipGetLastError());
     return HYB_OK;
+}
+
+// Make the history hold the segment of level L (checkpoint modes): restore
+// its checkpoint and recompute its levels.
+template <typename T>
+hyb_status load_segment(hyb_ctx *c, int L)
+{
+    const int seg = L / c->ckK;
+    if (seg == c->cur_seg) return HYB_OK;
+    hyb_status r = load_ckpt<T>(c, seg);
+    if (r) return r;
+    c->cur_seg = seg;
+    c->u_valid = false;
+    const int lo = seg * c->ckK, hi = std::min(lo + c->ckK - 1, c->nt);
+    if (T *h0 = hist_ptr<T>(c, lo)) launch_hist_level<T>(c->g, (const T *)c->V[1], h0, c->stream);
+    int ia = 0, ib = 1, ic = 2;
+    return fwd_steps<T>(c, lo, hi, ia, ib, ic, nullptr, false);
 }
 
 template <typename T>
@@ -445,6 +555,10 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
     s.G = c->G;
     int ia = 0, ib = 1, ic = 2;
     for (int k = c->nt; k >= 0; --k) {
+        if (c->store_mode != 0 && g.has_fem) {
+            hyb_status r = load_segment<T>(c, k);
+            if (r) return r;
+        }
         s.Ua = (const T *)c->P[ia]; s.Ub = (const T *)c->P[ib]; s.Uc = (T *)c->P[ic];
         s.Va = (const T *)c->Q[ia]; s.Vb = (const T *)c->Q[ib]; s.Vc = (T *)c->Q[ic];
         s.Fa = (const T *)c->F[ia]; s.Fb = (const T *)c->F[ib]; s.Fc = (T *)c->F[ic];
@@ -454,7 +568,7 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
         s.types2 = face_types(c, k + 1);
         s.level_rows = k >= 1;
         s.res = (mode == 0 && k == 0) ? nullptr : res + (long long)k * nface;
-        s.hist = g.has_fem ? (T *)c->hist + (long long)k * g.hlevel : nullptr;
+        s.hist = hist_ptr<T>(c, k);
         for (int f = 0; f < 6; ++f) {
             const int t1 = (s.types1 >> (2 * f)) & 3, t0 = (s.types0 >> (2 * f)) & 3;
             s.wB1[f] = t1 == F_ABC ? (T)1 : (T)2 * s.c2;
@@ -508,10 +622,14 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
     c->h = grid->h;
     for (int f = 0; f < 6; ++f) c->bc[f] = grid->face[f];
     if (opts) {
-        if (opts->field_f32 < 0 || opts->field_f32 > 1 || opts->store_mode != 0 ||
+        if (opts->field_f32 < 0 || opts->field_f32 > 1 || opts->store_mode < 0 || opts->store_mode > 2 ||
             !std::isfinite(opts->gamma) || opts->gamma < 0 || !(opts->alpha_rel > 0)) {
             delete c;
-            return fail(nullptr, opts->store_mode != 0 ? HYB_E_UNSUPPORTED : HYB_E_ARG, "opts: invalid options");
+            return fail(nullptr, HYB_E_ARG, "opts: invalid options");
+        }
+        if (opts->store_mode == 2 && !opts->field_f32) {
+            delete c;
+            return fail(nullptr, HYB_E_UNSUPPORTED, "opts: BF16 checkpoints need FP32 wavefields");
         }
         c->f32 = opts->field_f32;
         c->store_mode = opts->store_mode;
@@ -554,6 +672,7 @@ void hyb_destroy(hyb_ctx *c)
     }
     dfree(c->acube);
     dfree(c->hist);
+    dfree(c->ckpt);
     dfree((void *&)c->sig);
     dfree((void *&)c->G);
     dfree((void *&)c->dir);
@@ -603,8 +722,21 @@ hyb_status hyb_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, i
     const double amax = 1.0 + std::max(0.0, smax);
     if (dt > c->h / std::sqrt(3.0 * amax) * (1.0 + 1e-12))
         return fail(c, HYB_E_CFL, "dt violates the CFL bound h/sqrt(3 a_max)");
+    // sqrt(nt) segmentation of the levels 0..nt (checkpoint modes)
+    c->ckK = c->store_mode ? (int)std::ceil(std::sqrt((double)nt + 1.0)) : nt + 1;
+    if (c->store_mode) {
+        const size_t nck = (size_t)(nt / c->ckK + 1);
+        const size_t need = nck * ckpt_slot_bytes(c->g, c->esz, c->store_mode);
+        if (need > c->ckpt_bytes) {
+            dfree(c->ckpt);
+            c->ckpt_bytes = 0;
+            hyb_status s = dmalloc(c, &c->ckpt, need);
+            if (s) return s;
+            c->ckpt_bytes = need;
+        }
+    }
     if (c->g.has_fem) {
-        const size_t need = (size_t)nt + 1;
+        const size_t need = (size_t)(c->store_mode ? c->ckK : nt + 1);
         if (need > c->hist_levels) {
             dfree(c->hist);
             c->hist_levels = 0;
@@ -629,7 +761,8 @@ hyb_status hyb_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, i
     }
     c->have_forward = false;
     c->have_adjoint = false;
-    hyb_status s = c->f32 ? run_forward<float>(c, src, obs) : run_forward<double>(c, src, obs);
+    c->src = *src;
+    hyb_status s = c->f32 ? run_forward<float>(c, obs) : run_forward<double>(c, obs);
     if (s) return s;
     c->have_forward = true;
     return HYB_OK;
@@ -733,6 +866,12 @@ hyb_status hyb_footprint(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const
     size_t b = 6 * field_bytes(g, esz) + 6 * fem_bytes(g, esz) + nc * (esz + 4 * sizeof(double));
     b += (size_t)(nt + 1) * g.hlevel * esz + 2 * ntr + (MAX_PARTIALS + S_NSCAL) * sizeof(double);
     b += 3 * (size_t)g.ftot * esz;
+    const int sm = opts ? opts->store_mode : 0;
+    if (sm) {
+        const int K = (int)std::ceil(std::sqrt((double)nt + 1.0));
+        b -= (size_t)(nt + 1 - K) * g.hlevel * esz;
+        b += (size_t)(nt / K + 1) * ckpt_slot_bytes(g, esz, sm);
+    }
     *bytes = b;
     return HYB_OK;
 }
@@ -764,8 +903,8 @@ hyb_status hyb_counts(const hyb_ctx *c, int64_t *fdm, int64_t *fem)
 hyb_status hyb_get_wavefield(hyb_ctx *c, int32_t which, double *u, double *v)
 {
     if (!c || (which != 0 && which != 1)) return HYB_E_ARG;
-    if ((which == 0 && !c->have_forward) || (which == 1 && !c->have_adjoint))
-        return fail(c, HYB_E_STATE, "get_wavefield: no such sweep yet");
+    if ((which == 0 && !(c->have_forward && c->u_valid)) || (which == 1 && !c->have_adjoint))
+        return fail(c, HYB_E_STATE, "get_wavefield: no such sweep yet (or overwritten by a recompute)");
     void *const *A = which == 0 ? c->U : c->P;
     void *const *B = which == 0 ? c->V : c->Q;
     const int q = which == 0 ? c->last_u : c->last_p;
@@ -791,6 +930,7 @@ hyb_status hyb_time_interior(hyb_ctx *c, const double *sigma, double dt, int32_t
     }
     // the launches overwrite the wavefields and the first history level
     c->have_forward = false;
+    c->u_valid = false;
     c->have_adjoint = false;
     const double save_dt = c->dt;
     c->dt = dt;

@@ -93,6 +93,11 @@ template <typename T>
 void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, double *u, double *v,
                          hipStream_t st);
 
+// BF16 checkpoint increments: half[i] = bf16(a[i] - b[i]) (round to nearest
+// even); unpack: b[i] = a[i] - float(half[i]).  a, b are FP32 arrays.
+void launch_pack_bf16(const void *a, const void *b, uint16_t *half, long long n, hipStream_t st);
+void launch_unpack_bf16(const void *a, const uint16_t *half, void *b, long long n, hipStream_t st);
+
 // J_misfit = 1/2 sum_{k=1..nt} dt sum_i w_i res^2 -> scal[slot]
 void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h, double *partials,
                    double *scal, int slot, hipStream_t st);

@@ -819,6 +819,36 @@ void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, doubl
     hipLaunchKernelGGL((k_export_level<T>), dim3(1024), dim3(BLOCK), 0, st, g, U, V, F, u, v);
 }
 
+__device__ __forceinline__ uint16_t f32_to_bf16(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);  // round to nearest even
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__global__ __launch_bounds__(BLOCK) void k_pack_bf16(const float *a, const float *b, uint16_t *half, long long n)
+{
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK)
+        half[i] = f32_to_bf16(a[i] - b[i]);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_unpack_bf16(const float *a, const uint16_t *half, float *b, long long n)
+{
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK)
+        b[i] = a[i] - bf16_to_f32(half[i]);
+}
+
+void launch_pack_bf16(const void *a, const void *b, uint16_t *half, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_bf16, dim3(4096), dim3(BLOCK), 0, st, (const float *)a, (const float *)b, half, n);
+}
+
+void launch_unpack_bf16(const void *a, const uint16_t *half, void *b, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unpack_bf16, dim3(4096), dim3(BLOCK), 0, st, (const float *)a, half, (float *)b, n);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_misfit(Geo g, const double *res, int nt, double wscale,
                                                   double *part)
 {

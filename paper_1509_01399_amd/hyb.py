@@ -259,6 +259,7 @@ class Solver:
         self.ctx = hyb_create(self.grid, self.mesh, 2, self.opts)
         self.nface = (self.n[0] + 1) * (self.n[1] + 1)
         self.nt = None
+        self.generation = 0  # counts forward sweeps (the adjoint uses the last one)
 
     def close(self):
         if self.ctx is not None:
@@ -283,6 +284,7 @@ class Solver:
             obs = self.trace_buffer(nt)
         hyb_forward(self.ctx, sigma, make_source(omega, flux, k_on), nt, dt, obs)
         self.nt = nt
+        self.generation += 1
         return obs
 
     def set_initial(self, u0=None, um1=None):
@@ -300,6 +302,7 @@ class Solver:
         return grad, J
 
     def cg_step(self, data, sigma, nt, dt, state, omega=40.0):
+        self.generation += 1  # runs a forward sweep
         return hyb_cg_step(self.ctx, data, sigma, make_source(omega), nt, dt, state)
 
     def wavefield(self, which=0):
