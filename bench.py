@@ -147,6 +147,50 @@ def roofline(wl, dt, solver, f32, reps=50):
             "bytes_per_launch": b, "avg_launch_ms": round(ms, 5)}
 
 
+def serving(n_req=256, seed=0, budget=200e9):
+    """Serving workload: n_req forward+adjoint+gradient requests, grid sizes
+    uniform over {64,96,128,192,256}^3, FP32 fields, Poisson arrivals at
+    twice the rate the unbatched path sustains (2 / mean unbatched service
+    time, measured on one request per size), 200 GB HBM budget."""
+    import numpy as np
+    import torch
+
+    from paper_1509_01399_amd import serve, synth
+    sizes = synth.SERVE_SIZES
+    data = serve.background_data(sizes)
+    pool = serve.Pool(budget, True)
+    # calibration: one request per size, alone
+    cal = serve.make_requests(len(sizes) * 3, seed + 100, rate=1e9, sizes=sizes)
+    seen, calib = set(), []
+    for r in cal:
+        if r.n not in seen:
+            seen.add(r.n)
+            r.arrival = 0.0
+            calib.append(r)
+    serve.run_unbatched(calib, data, pool=pool)          # warm (allocations, code)
+    res, _ = serve.run_unbatched(calib, data, pool=pool)
+    mean_service = float(np.mean([x.finished - x.admitted for x in res]))
+    # offered load: twice what the unbatched path sustains, so that both
+    # paths run at their capacity and the throughputs compare the servers
+    rate = 2.0 / mean_service
+    reqs = serve.make_requests(n_req, seed, rate, sizes)
+    rb, wb = serve.run_batched(reqs, data, budget=budget, pool=pool)
+    ru, wu = serve.run_unbatched(reqs, data, pool=pool)
+    peak = pool.used
+    pool.close()
+    del data
+    torch.cuda.empty_cache()
+    sb, su = serve.summarize(rb, wb, reqs), serve.summarize(ru, wu, reqs)
+    jd = max(abs(a.J - b.J) / abs(b.J) for a, b in zip(rb, ru))
+    return {"workload": f"{n_req} requests, n in {list(sizes)}, C = 3n/8, nt = 5n, fp32 fields",
+            "arrival_rate_per_s": round(rate, 2), "budget_gb": budget / 1e9,
+            "caps": {str(k): v for k, v in serve.DEFAULT_CAPS.items()},
+            "steps_per_call": serve.DEFAULT_STEPS_PER_CALL,
+            "resident_gb": round(peak / 1e9, 1), "batched": sb, "unbatched": su,
+            "throughput_ratio": round(sb["throughput_req_s"] / su["throughput_req_s"], 3),
+            "max_rel_J_diff_batched_vs_alone": jd}
+
+
 def probe(kind, wl_name, f32, reps):
     """Single-kernel runs for the counter passes (rocprofv3 --pmc)."""
     import torch
@@ -181,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-window", type=int, default=10)
     ap.add_argument("--no-f32", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--probe", choices=["interior", "copy"])
     ap.add_argument("--probe-f32", action="store_true")
     ap.add_argument("--probe-reps", type=int, default=20)
@@ -230,6 +276,11 @@ def main():
         del d2
         torch.cuda.empty_cache()
 
+    srv = None
+    if not args.no_serve:
+        srv = serving(args.serve_requests)
+        print(f"[bench] serving: {srv}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, dt, args.cpu_window)
@@ -245,6 +296,9 @@ def main():
                    "step": "one CG iteration (forward + adjoint + gradient + update)",
                    "parallelism": "single GPU"},
         "roofline": rl, "cpu_baseline": cpu, "f32_form": f32,
+        "p50_ms": srv["batched"]["p50_ms"] if srv else None,
+        "p99_ms": srv["batched"]["p99_ms"] if srv else None,
+        "serving": srv,
     }
     print(json.dumps(line), flush=True)
 

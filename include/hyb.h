@@ -225,6 +225,65 @@ hyb_status hyb_time_interior(hyb_ctx *ctx, const double *sigma_dev, double dt, i
  * Errors: HYB_E_ARG, HYB_E_STATE (no such sweep yet). */
 hyb_status hyb_get_wavefield(hyb_ctx *ctx, int32_t which, double *u_dev, double *v_dev);
 
+/* ---------------------------------------------------------------------
+ * Batched solves for request serving.  A batch advances many contexts at
+ * once: every hyb_batch_tick performs one time step of every running slot,
+ * and slots whose contexts have the same geometry (grid, FEM box, dt,
+ * precision) run in the same kernel launches, each at its own step and
+ * phase.  A slot runs one forward+adjoint+gradient solve: the forward sweep,
+ * the residual obs - data, the adjoint sweep (mode 0) and the gradient of
+ * hyb_gradient mode 0; results land in the caller's obs and grad buffers.
+ * Each slot's arithmetic follows hyb_forward/hyb_adjoint/hyb_gradient step
+ * for step; the batched kernels are separately compiled, so results agree
+ * with those calls (and alone vs in a mix) to rounding, not bit for bit.
+ */
+typedef struct hyb_batch hyb_batch;
+
+/* Create a batch of up to max_slots slots.  Each slot's work goes to the
+ * stream of its context; slots on different streams run concurrently on the
+ * device (a typical server gives each grid size its own stream), slots on
+ * the same stream and geometry share launches.  hip_stream names the first
+ * stream; pinned staging rings are allocated per stream.
+ * Errors: HYB_E_ARG, HYB_E_OOM. */
+hyb_status hyb_batch_create(int32_t max_slots, void *hip_stream, hyb_batch **out);
+
+/* Release the batch (synchronises its stream; contexts stay with the caller). */
+void hyb_batch_destroy(hyb_batch *b);
+
+/* Start a solve on context ctx (FEM box required, full-history store mode)
+ * in a free slot.  sigma_dev as in hyb_forward; sigma_max: the caller's
+ * value of max(sigma) over the free cubes, used for the CFL check without a
+ * device round trip; data_dev, obs_dev [nt+1][face] and grad_dev [C^3] are
+ * device FP64 buffers owned by the caller and kept valid until the slot is
+ * released.  *slot receives the slot number.
+ * Errors: HYB_E_ARG, HYB_E_STATE (no free slot / context busy), HYB_E_CFL,
+ * HYB_E_UNSUPPORTED (checkpoint store modes), HYB_E_OOM. */
+hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *ctx, const double *sigma_dev, double sigma_max,
+                            const hyb_source *src, int32_t nt, double dt, const double *data_dev,
+                            double *obs_dev, double *grad_dev, int32_t *slot);
+
+/* Up to `steps` ticks; each tick enqueues one time step of every running
+ * slot (asynchronous).  Stops early when no slot is running.  *n_active
+ * (nullable) receives the number of slots that stepped in the first tick.
+ * The host plans up to 32 ticks at a time and ships their step arguments in
+ * one copy per stream; it blocks only when it runs more than 16 such plans
+ * ahead of the device. */
+hyb_status hyb_batch_tick(hyb_batch *b, int32_t steps, int32_t *n_active);
+
+/* State of a slot: -1 free, 0 running, 1 all work enqueued, 2 finished
+ * (results valid; *J_host, nullable, receives J = misfit + regularisation),
+ * 3 failed.  Does not block. */
+hyb_status hyb_batch_poll(hyb_batch *b, int32_t slot, int32_t *state, double *J_host);
+
+/* hyb_batch_poll for every slot: state[max_slots], J[max_slots] (nullable). */
+hyb_status hyb_batch_poll_all(hyb_batch *b, int32_t *state, double *J_host);
+
+/* Free a slot whose work has been enqueued (waits for it to finish). */
+hyb_status hyb_batch_release(hyb_batch *b, int32_t slot);
+
+/* Text of the last batch error. */
+const char *hyb_batch_last_error(const hyb_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,7 @@ struct hyb_ctx {
     void *ckpt = nullptr;        // checkpoints (store modes 1, 2)
     size_t ckpt_bytes = 0;
     int ckK = 1, cur_seg = 0;    // segment length and the segment in the history
+    bool in_batch = false;       // owned by a batch slot (single calls refused)
     double dt = 0;
     std::string err;
 };
@@ -448,44 +449,72 @@ hyb_status load_ckpt(hyb_ctx *c, int q)
     return HYB_OK;
 }
 
-// Forward steps k in [k0, k1) on buffers (ia, ib, ic) (levels k-1, k, k+1);
-// records the trace when obs is given and the FEM history where kept; saves
-// a checkpoint at every multiple of K when `save` is set.
+// Arguments of forward step k (levels k-1, k, k+1 in buffers ia, ib, ic).
 template <typename T>
-hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, double *obs, bool save)
+Step<T> fwd_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, double *obs)
+{
+    const long long nface = (long long)c->g.nx * c->g.ny;
+    Step<T> s = make_step<T>(c);
+    s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
+    s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
+    s.types1 = face_types(c, k);
+    const double fluxscale = 2.0 * c->dt * c->dt / c->h;
+    if (c->src.kind == 0) {
+        s.flux = nullptr;
+        s.srcterm = (T)(fluxscale * std::sin(c->src.omega * ((double)k * c->dt)));
+    } else {
+        s.flux = k < c->k_on ? c->src.flux_dev + (long long)k * nface : nullptr;
+        s.fluxscale = fluxscale;
+        s.srcterm = 0;
+    }
+    s.obs = obs ? obs + (long long)(k + 1) * nface : nullptr;
+    s.hist = hist_ptr<T>(c, k + 1);
+    return s;
+}
+
+// Arguments of the adjoint step that computes level k (multipliers of levels
+// k+2, k+1, k in buffers ia, ib, ic).
+template <typename T>
+Step<T> adj_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, const double *res, int mode)
+{
+    const long long nface = (long long)c->g.nx * c->g.ny;
+    Step<T> s = make_step<T>(c);
+    s.seed_mode = mode;
+    s.G = c->G;
+    s.Ua = (const T *)c->P[ia]; s.Ub = (const T *)c->P[ib]; s.Uc = (T *)c->P[ic];
+    s.Va = (const T *)c->Q[ia]; s.Vb = (const T *)c->Q[ib]; s.Vc = (T *)c->Q[ic];
+    s.Fa = (const T *)c->F[ia]; s.Fb = (const T *)c->F[ib]; s.Fc = (T *)c->F[ic];
+    s.Pw = (T *)c->P[ib];
+    s.types0 = face_types(c, k - 1);
+    s.types1 = face_types(c, k);
+    s.types2 = face_types(c, k + 1);
+    s.level_rows = k >= 1;
+    s.res = (mode == 0 && k == 0) ? nullptr : res + (long long)k * nface;
+    s.hist = hist_ptr<T>(c, k);
+    return s;
+}
+
+// Zero the multipliers and the gradient accumulator; the misfit J of mode 0.
+template <typename T>
+hyb_status adj_setup(hyb_ctx *c, const double *res, int mode)
 {
     const Geo &g = c->g;
     const hipStream_t st = c->stream;
-    const long long nface = (long long)g.nx * g.ny;
-    Step<T> s = make_step<T>(c);
-    const double fluxscale = 2.0 * c->dt * c->dt / c->h;
-    for (int k = k0; k < k1; ++k) {
-        s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
-        s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
-        s.types1 = face_types(c, k);
-        if (c->src.kind == 0) {
-            s.flux = nullptr;
-            s.srcterm = (T)(fluxscale * std::sin(c->src.omega * ((double)k * c->dt)));
-        } else {
-            s.flux = k < c->k_on ? c->src.flux_dev + (long long)k * nface : nullptr;
-            s.fluxscale = fluxscale;
-            s.srcterm = 0;
-        }
-        s.obs = obs ? obs + (long long)(k + 1) * nface : nullptr;
-        s.hist = hist_ptr<T>(c, k + 1);
-        launch_interior<T>(s, false, st);
-        launch_bnd_fwd<T>(s, st);
-        const int t = ia; ia = ib; ib = ic; ic = t;
-        if (save && (k + 1) % c->ckK == 0) {
-            hyb_status r = save_ckpt<T>(c, (k + 1) / c->ckK, ia, ib);
-            if (r) return r;
-        }
+    const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
+    for (int q = 0; q < 3; ++q) {
+        HIPCHK(c, hipMemsetAsync(c->P[q], 0, fb, st));
+        HIPCHK(c, hipMemsetAsync(c->F[q], 0, (size_t)g.ftot * sizeof(T), st));
+        if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->Q[q], 0, vb, st));
     }
+    if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
+    if (mode == 0) launch_misfit(g, res, c->nt, c->dt, c->h, c->partials, c->scal, S_JMIS, st);
+    else HIPCHK(c, hipMemsetAsync(c->scal + S_JMIS, 0, sizeof(double), st));
     return HYB_OK;
 }
 
+// Zero the wavefields, load initial levels, record level 0.
 template <typename T>
-hyb_status run_forward(hyb_ctx *c, double *obs)
+hyb_status fwd_setup(hyb_ctx *c, double *obs)
 {
     const Geo &g = c->g;
     const hipStream_t st = c->stream;
@@ -500,11 +529,39 @@ hyb_status run_forward(hyb_ctx *c, double *obs)
         c->ic_set = false;
         c->ic_u0 = c->ic_um1 = nullptr;
     }
-    const bool ck = c->store_mode != 0;
-    // the forward sweep ends in the last segment, whose history it keeps
-    c->cur_seg = ck ? c->nt / c->ckK : 0;
+    c->cur_seg = c->store_mode ? c->nt / c->ckK : 0;
     if (obs) launch_record_face<T>(g, (const T *)c->U[1], obs, st);
     if (T *h0 = hist_ptr<T>(c, 0)) launch_hist_level<T>(g, (const T *)c->V[1], h0, st);
+    return HYB_OK;
+}
+
+// Forward steps k in [k0, k1) on buffers (ia, ib, ic) (levels k-1, k, k+1);
+// records the trace when obs is given and the FEM history where kept; saves
+// a checkpoint at every multiple of K when `save` is set.
+template <typename T>
+hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, double *obs, bool save)
+{
+    const hipStream_t st = c->stream;
+    for (int k = k0; k < k1; ++k) {
+        const Step<T> s = fwd_step_args<T>(c, k, ia, ib, ic, obs);
+        launch_interior<T>(s, false, st);
+        launch_bnd_fwd<T>(s, st);
+        const int t = ia; ia = ib; ib = ic; ic = t;
+        if (save && (k + 1) % c->ckK == 0) {
+            hyb_status r = save_ckpt<T>(c, (k + 1) / c->ckK, ia, ib);
+            if (r) return r;
+        }
+    }
+    return HYB_OK;
+}
+
+template <typename T>
+hyb_status run_forward(hyb_ctx *c, double *obs)
+{
+    // the forward sweep ends in the last segment, whose history it keeps
+    const bool ck = c->store_mode != 0;
+    hyb_status r0 = fwd_setup<T>(c, obs);
+    if (r0) return r0;
     int ia = 0, ib = 1, ic = 2;
     if (ck) {
         hyb_status r = save_ckpt<T>(c, 0, ia, ib);
@@ -540,40 +597,15 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
 {
     const Geo &g = c->g;
     const hipStream_t st = c->stream;
-    const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
-    for (int q = 0; q < 3; ++q) {
-        HIPCHK(c, hipMemsetAsync(c->P[q], 0, fb, st));
-        HIPCHK(c, hipMemsetAsync(c->F[q], 0, (size_t)g.ftot * sizeof(T), st));
-        if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->Q[q], 0, vb, st));
-    }
-    if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
-    if (mode == 0) launch_misfit(g, res, c->nt, c->dt, c->h, c->partials, c->scal, S_JMIS, st);
-    else HIPCHK(c, hipMemsetAsync(c->scal + S_JMIS, 0, sizeof(double), st));
-    const long long nface = (long long)g.nx * g.ny;
-    Step<T> s = make_step<T>(c);
-    s.seed_mode = mode;
-    s.G = c->G;
+    hyb_status r0 = adj_setup<T>(c, res, mode);
+    if (r0) return r0;
     int ia = 0, ib = 1, ic = 2;
     for (int k = c->nt; k >= 0; --k) {
         if (c->store_mode != 0 && g.has_fem) {
             hyb_status r = load_segment<T>(c, k);
             if (r) return r;
         }
-        s.Ua = (const T *)c->P[ia]; s.Ub = (const T *)c->P[ib]; s.Uc = (T *)c->P[ic];
-        s.Va = (const T *)c->Q[ia]; s.Vb = (const T *)c->Q[ib]; s.Vc = (T *)c->Q[ic];
-        s.Fa = (const T *)c->F[ia]; s.Fb = (const T *)c->F[ib]; s.Fc = (T *)c->F[ic];
-        s.Pw = (T *)c->P[ib];
-        s.types0 = face_types(c, k - 1);
-        s.types1 = face_types(c, k);
-        s.types2 = face_types(c, k + 1);
-        s.level_rows = k >= 1;
-        s.res = (mode == 0 && k == 0) ? nullptr : res + (long long)k * nface;
-        s.hist = hist_ptr<T>(c, k);
-        for (int f = 0; f < 6; ++f) {
-            const int t1 = (s.types1 >> (2 * f)) & 3, t0 = (s.types0 >> (2 * f)) & 3;
-            s.wB1[f] = t1 == F_ABC ? (T)1 : (T)2 * s.c2;
-            s.wB0[f] = (k >= 1 && t0 == F_ABC) ? -s.r : (T)0;
-        }
+        const Step<T> s = adj_step_args<T>(c, k, ia, ib, ic, res, mode);
         launch_bnd_adj<T>(s, st);
         launch_interior<T>(s, true, st);
         const int t = ia; ia = ib; ib = ic; ic = t;
@@ -655,7 +687,7 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
         hyb_destroy(c);
         return s;
     }
-    if (hipMemset(c->scal, 0, S_NSCAL * sizeof(double)) != hipSuccess) {
+    if (hipMemsetAsync(c->scal, 0, S_NSCAL * sizeof(double), c->stream) != hipSuccess) {
         hyb_destroy(c);
         return fail(nullptr, HYB_E_DEVICE, "hipMemset failed");
     }
@@ -693,10 +725,16 @@ hyb_status hyb_set_initial(hyb_ctx *c, const double *u0, const double *um1)
     return HYB_OK;
 }
 
-hyb_status hyb_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, int32_t nt, double dt,
-                       double *obs)
+}  // extern "C"
+
+namespace {
+
+// Validation and set-up shared by hyb_forward and the batch submission:
+// source, CFL (with the largest a, from the device unless the caller passes
+// sigma_max), storage for history/checkpoints, sigma copy, step counts.
+hyb_status prepare_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, int32_t nt, double dt,
+                           const double *sigma_max_host)
 {
-    if (!c) return HYB_E_ARG;
     if (!src) return fail(c, HYB_E_ARG, "source is null");
     if (nt < 1 || !(dt > 0) || !std::isfinite(dt)) return fail(c, HYB_E_ARG, "need nt >= 1 and dt > 0");
     if (src->kind == 0) {
@@ -712,11 +750,16 @@ hyb_status hyb_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, i
     if (c->g.has_fem) {
         if (c->f32) launch_acube<float>(c->g, sigma, (float *)c->acube, c->partials, c->scal, st);
         else launch_acube<double>(c->g, sigma, (double *)c->acube, c->partials, c->scal, st);
-        double hs[2];
-        HIPCHK(c, hipMemcpyAsync(hs, c->scal + S_SMAX, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipStreamSynchronize(st));
-        if (hs[1] != 0.0) return fail(c, HYB_E_NONFINITE, "sigma has non-finite entries");
-        smax = hs[0];
+        if (sigma_max_host) {
+            if (!std::isfinite(*sigma_max_host)) return fail(c, HYB_E_NONFINITE, "sigma_max is not finite");
+            smax = *sigma_max_host;
+        } else {
+            double hs[2];
+            HIPCHK(c, hipMemcpyAsync(hs, c->scal + S_SMAX, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(c, hipStreamSynchronize(st));
+            if (hs[1] != 0.0) return fail(c, HYB_E_NONFINITE, "sigma has non-finite entries");
+            smax = hs[0];
+        }
     }
     // CFL condition, eq. (CFL): tau <= h / sqrt(3 a) with the largest a
     const double amax = 1.0 + std::max(0.0, smax);
@@ -762,7 +805,33 @@ hyb_status hyb_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, i
     c->have_forward = false;
     c->have_adjoint = false;
     c->src = *src;
-    hyb_status s = c->f32 ? run_forward<float>(c, obs) : run_forward<double>(c, obs);
+    return HYB_OK;
+}
+
+hyb_status alloc_adjoint(hyb_ctx *c)
+{
+    const size_t fb = field_bytes(c->g, c->esz), vb = fem_bytes(c->g, c->esz);
+    hyb_status s = HYB_OK;
+    for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->P[q], fb);
+    for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->F[q], (size_t)c->g.ftot * c->esz);
+    if (!s && c->g.has_fem)
+        for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->Q[q], vb);
+    if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->G, cube_count(c->g) * sizeof(double));
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+hyb_status hyb_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, int32_t nt, double dt,
+                       double *obs)
+{
+    if (!c) return HYB_E_ARG;
+    if (c->in_batch) return fail(c, HYB_E_STATE, "context is busy in a batch");
+    hyb_status s = prepare_forward(c, sigma, src, nt, dt, nullptr);
+    if (s) return s;
+    s = c->f32 ? run_forward<float>(c, obs) : run_forward<double>(c, obs);
     if (s) return s;
     c->have_forward = true;
     return HYB_OK;
@@ -773,13 +842,8 @@ hyb_status hyb_adjoint(hyb_ctx *c, const double *res, int32_t mode)
     if (!c) return HYB_E_ARG;
     if (!res || (mode != 0 && mode != 1)) return fail(c, HYB_E_ARG, "adjoint: residual and mode 0/1");
     if (!c->have_forward) return fail(c, HYB_E_STATE, "adjoint before forward");
-    const size_t fb = field_bytes(c->g, c->esz), vb = fem_bytes(c->g, c->esz);
-    hyb_status s = HYB_OK;
-    for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->P[q], fb);
-    for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->F[q], (size_t)c->g.ftot * c->esz);
-    if (!s && c->g.has_fem)
-        for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->Q[q], vb);
-    if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->G, cube_count(c->g) * sizeof(double));
+    if (c->in_batch) return fail(c, HYB_E_STATE, "context is busy in a batch");
+    hyb_status s = alloc_adjoint(c);
     if (s) return s;
     s = c->f32 ? run_adjoint<float>(c, res, mode) : run_adjoint<double>(c, res, mode);
     if (s) return s;
@@ -964,5 +1028,384 @@ hyb_status hyb_time_interior(hyb_ctx *c, const double *sigma, double dt, int32_t
     *ms = (double)t / reps;
     return HYB_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch
+
+struct hyb_batch {
+    struct Slot {
+        hyb_ctx *c = nullptr;
+        int state = 0;  // 0 free, 1 forward, 2 adjoint, 3 finished (event pending), 4 failed
+        int k = 0, ia = 0, ib = 1, ic = 2;
+        const double *data = nullptr;
+        double *obs = nullptr, *grad = nullptr;
+        hipEvent_t done = nullptr;
+        double *J_host = nullptr;  // pinned triple: non-finite flag, misfit, regularisation
+        int lane = 0;
+    };
+    // one lane per stream: slots of different lanes run concurrently on the
+    // device; each lane has its own ring of step-argument staging buffers
+    struct Lane {
+        hipStream_t st = nullptr;
+        char *h_stage = nullptr, *d_stage = nullptr;
+        int cur = 0;
+        std::vector<hipEvent_t> ev;
+    };
+    int max_slots = 0;
+    std::vector<Slot> slots;
+    std::vector<Lane> lanes;
+    size_t entry = 0;
+    int ring = 0;
+    double *h_J = nullptr;
+    std::string err;
+};
+
+namespace {
+
+constexpr int STAGE_RING = 16;
+constexpr int TICKS_PER_PLAN = 32;
+
+hyb_status bfail(hyb_batch *b, hyb_status s, const std::string &m)
+{
+    if (b) b->err = m;
+    return s;
+}
+
+void free_lane(hyb_batch::Lane &L)
+{
+    for (auto e : L.ev)
+        if (e) (void)hipEventDestroy(e);
+    L.ev.clear();
+    if (L.h_stage) (void)hipHostFree(L.h_stage);
+    if (L.d_stage) (void)hipFree(L.d_stage);
+    L.h_stage = L.d_stage = nullptr;
+}
+
+// index of the lane of stream st (created on first use)
+int lane_of(hyb_batch *b, hipStream_t st)
+{
+    for (size_t q = 0; q < b->lanes.size(); ++q)
+        if (b->lanes[q].st == st) return (int)q;
+    hyb_batch::Lane L;
+    L.st = st;
+    bool ok = hipHostMalloc((void **)&L.h_stage, b->entry * b->ring) == hipSuccess &&
+              hipMalloc((void **)&L.d_stage, b->entry * b->ring) == hipSuccess;
+    L.ev.resize(b->ring, nullptr);
+    for (int q = 0; ok && q < b->ring; ++q) ok = hipEventCreateWithFlags(&L.ev[q], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        free_lane(L);
+        return -1;
+    }
+    b->lanes.push_back(L);
+    return (int)b->lanes.size() - 1;
+}
+
+// Advance the host-side state of a slot by one step; returns 1 when its
+// forward sweep has just ended, 2 when its adjoint sweep has just ended.
+int advance_slot(hyb_batch::Slot &sl)
+{
+    hyb_ctx *c = sl.c;
+    const int t = sl.ia; sl.ia = sl.ib; sl.ib = sl.ic; sl.ic = t;
+    if (sl.state == 1) {
+        if (++sl.k == c->nt) {
+            c->last_u = sl.ib;
+            sl.state = 2;
+            sl.k = c->nt;
+            sl.ia = 0; sl.ib = 1; sl.ic = 2;
+            return 1;
+        }
+    } else if (sl.state == 2) {
+        if (--sl.k < 0) {
+            c->last_p = sl.ib;
+            sl.state = 3;
+            return 2;
+        }
+    }
+    return 0;
+}
+
+// Work between the sweeps of a slot: residual against the data, adjoint set-up.
+template <typename T>
+void finish_forward(hyb_batch::Slot &sl)
+{
+    hyb_ctx *c = sl.c;
+    c->u_valid = true;
+    c->have_forward = true;
+    const long long ntr = (long long)(c->nt + 1) * c->g.nx * c->g.ny;
+    launch_residual(sl.obs, sl.data, c->resbuf, ntr, c->stream);
+    adj_setup<T>(c, c->resbuf, 0);
+}
+
+// Gradient of the slot, its J and the completion event.
+void finish_adjoint(hyb_batch::Slot &sl)
+{
+    hyb_ctx *c = sl.c;
+    c->have_adjoint = true;
+    c->adj_mode = 0;
+    const double h = c->h, h3 = h * h * h, dJ = -(c->dt * c->dt) / (h * h);
+    launch_grad_final(c->g, c->G, c->sig, dJ / h3, c->gamma, 0, h3, sl.grad, c->partials, c->scal, S_JREG,
+                      c->stream);
+    // non-finite flag of sigma, misfit, regularisation
+    (void)hipMemcpyAsync(sl.J_host, c->scal + S_BAD, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    (void)hipEventRecord(sl.done, c->stream);
+}
+
+// One planned launch group or slot transition, in stream order.
+struct Action {
+    int kind;        // 0 launch group, 1 forward ended, 2 adjoint ended
+    int lane, slot;  // lane of the work; slot for transitions / first slot of a group
+    int adjoint, n, f32;
+    size_t offset;   // byte offset of the group's step array in the lane buffer
+};
+
+bool same_geometry(const hyb_ctx *a, const hyb_ctx *b)
+{
+    return a->f32 == b->f32 && a->stream == b->stream && std::memcmp(&a->g, &b->g, sizeof(Geo)) == 0 &&
+           std::memcmp(a->mesh.w, b->mesh.w, sizeof a->mesh.w) == 0 && a->dt == b->dt && a->h == b->h;
+}
+
+}  // namespace
+
+namespace {
+
+// Plan up to `ticks` ticks: the host advances every running slot one step per
+// tick and records the step arguments of each launch group (per lane, in one
+// buffer) and the slot transitions; then one copy per lane ships all step
+// arguments and the launches and transitions are issued in the planned order.
+hyb_status batch_plan_run(hyb_batch *b, int ticks, int32_t *n_first)
+{
+    std::vector<std::vector<char>> buf(b->lanes.size());
+    std::vector<Action> acts;
+    int first = -1;
+    for (int t = 0; t < ticks; ++t) {
+        std::vector<std::vector<int>> groups;
+        std::vector<int> gphase;
+        for (int i = 0; i < b->max_slots; ++i) {
+            const auto &sl = b->slots[i];
+            if (sl.state != 1 && sl.state != 2) continue;
+            int gi = -1;
+            for (size_t q = 0; q < groups.size(); ++q)
+                if (gphase[q] == sl.state && same_geometry(b->slots[groups[q][0]].c, sl.c)) { gi = (int)q; break; }
+            if (gi < 0) { groups.emplace_back(); gphase.push_back(sl.state); gi = (int)groups.size() - 1; }
+            groups[gi].push_back(i);
+        }
+        if (first < 0) {
+            first = 0;
+            for (auto &gr : groups) first += (int)gr.size();
+        }
+        if (groups.empty()) break;
+        std::vector<Action> trans;
+        for (size_t q = 0; q < groups.size(); ++q) {
+            const auto &ids = groups[q];
+            const hyb_batch::Slot &s0 = b->slots[ids[0]];
+            const bool adj = gphase[q] == 2, f32 = s0.c->f32;
+            std::vector<char> &B = buf[s0.lane];
+            const size_t off = (B.size() + 255) / 256 * 256;
+            const size_t one = f32 ? sizeof(Step<float>) : sizeof(Step<double>);
+            B.resize(off + ids.size() * one);
+            for (size_t j = 0; j < ids.size(); ++j) {
+                hyb_batch::Slot &sl = b->slots[ids[j]];
+                char *dst = B.data() + off + j * one;
+                if (f32) {
+                    const Step<float> st = adj ? adj_step_args<float>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.c->resbuf, 0)
+                                               : fwd_step_args<float>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.obs);
+                    std::memcpy(dst, &st, one);
+                } else {
+                    const Step<double> st = adj ? adj_step_args<double>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.c->resbuf, 0)
+                                                : fwd_step_args<double>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.obs);
+                    std::memcpy(dst, &st, one);
+                }
+            }
+            acts.push_back(Action{0, s0.lane, ids[0], adj ? 1 : 0, (int)ids.size(), f32 ? 1 : 0, off});
+            for (int id : ids) {
+                const int ev = advance_slot(b->slots[id]);
+                if (ev) trans.push_back(Action{ev, b->slots[id].lane, id, 0, 0, b->slots[id].c->f32 ? 1 : 0, 0});
+            }
+        }
+        acts.insert(acts.end(), trans.begin(), trans.end());
+    }
+    // ship the step arguments, one copy per lane
+    std::vector<char *> dbase(b->lanes.size(), nullptr);
+    std::vector<int> used(b->lanes.size(), -1);
+    for (size_t li = 0; li < b->lanes.size(); ++li) {
+        if (buf[li].empty()) continue;
+        hyb_batch::Lane &L = b->lanes[li];
+        if (buf[li].size() > b->entry) return bfail(b, HYB_E_ARG, "batch: staging entry too small");
+        const int e = L.cur;
+        L.cur = (L.cur + 1) % b->ring;
+        if (hipEventSynchronize(L.ev[e]) != hipSuccess) return bfail(b, HYB_E_DEVICE, "staging event");
+        char *h = L.h_stage + (size_t)e * b->entry;
+        dbase[li] = L.d_stage + (size_t)e * b->entry;
+        std::memcpy(h, buf[li].data(), buf[li].size());
+        if (hipMemcpyAsync(dbase[li], h, buf[li].size(), hipMemcpyHostToDevice, L.st) != hipSuccess)
+            return bfail(b, HYB_E_DEVICE, "staging copy failed");
+        used[li] = e;
+    }
+    // launches and transitions in planned order
+    for (const Action &a : acts) {
+        hyb_batch::Slot &sl = b->slots[a.slot];
+        if (a.kind == 0) {
+            const Geo &g = sl.c->g;
+            const hipStream_t st = b->lanes[a.lane].st;
+            if (a.f32) {
+                const Step<float> *d = (const Step<float> *)(dbase[a.lane] + a.offset);
+                if (a.adjoint) launch_batch_adj<float>(g, d, a.n, st); else launch_batch_fwd<float>(g, d, a.n, st);
+            } else {
+                const Step<double> *d = (const Step<double> *)(dbase[a.lane] + a.offset);
+                if (a.adjoint) launch_batch_adj<double>(g, d, a.n, st); else launch_batch_fwd<double>(g, d, a.n, st);
+            }
+        } else if (a.kind == 1) {
+            if (a.f32) finish_forward<float>(sl); else finish_forward<double>(sl);
+        } else {
+            finish_adjoint(sl);
+        }
+    }
+    for (size_t li = 0; li < b->lanes.size(); ++li)
+        if (used[li] >= 0 && hipEventRecord(b->lanes[li].ev[used[li]], b->lanes[li].st) != hipSuccess)
+            return bfail(b, HYB_E_DEVICE, "staging event");
+    if (hipGetLastError() != hipSuccess) return bfail(b, HYB_E_DEVICE, "kernel launch failed");
+    if (n_first) *n_first = first < 0 ? 0 : first;
+    return HYB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hyb_status hyb_batch_create(int32_t max_slots, void *hip_stream, hyb_batch **out)
+{
+    if (!out || max_slots < 1 || max_slots > 4096) return HYB_E_ARG;
+    *out = nullptr;
+    hyb_batch *b = new hyb_batch();
+    b->max_slots = max_slots;
+    b->slots.resize(max_slots);
+    b->ring = STAGE_RING;
+    // per plan and lane: TICKS_PER_PLAN ticks of at most max_slots step
+    // structs in at most max_slots groups, each group aligned to 256 bytes
+    b->entry = (size_t)TICKS_PER_PLAN * (size_t)max_slots * (sizeof(Step<double>) + 256);
+    bool ok = hipHostMalloc((void **)&b->h_J, 3 * sizeof(double) * max_slots) == hipSuccess &&
+              lane_of(b, (hipStream_t)hip_stream) == 0;
+    for (int q = 0; ok && q < max_slots; ++q) {
+        ok = hipEventCreateWithFlags(&b->slots[q].done, hipEventDisableTiming) == hipSuccess;
+        b->slots[q].J_host = b->h_J + 3 * q;
+    }
+    if (!ok) {
+        hyb_batch_destroy(b);
+        return fail(nullptr, HYB_E_OOM, "batch: allocation failed");
+    }
+    *out = b;
+    return HYB_OK;
+}
+
+void hyb_batch_destroy(hyb_batch *b)
+{
+    if (!b) return;
+    for (auto &L : b->lanes) (void)hipStreamSynchronize(L.st);
+    for (auto &sl : b->slots) {
+        if (sl.c) sl.c->in_batch = false;
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    for (auto &L : b->lanes) free_lane(L);
+    if (b->h_J) (void)hipHostFree(b->h_J);
+    delete b;
+}
+
+hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *c, const double *sigma, double sigma_max, const hyb_source *src,
+                            int32_t nt, double dt, const double *data, double *obs, double *grad, int32_t *slot)
+{
+    if (!b || !c || !slot) return HYB_E_ARG;
+    *slot = -1;
+    if (c->in_batch) return bfail(b, HYB_E_STATE, "context already in a batch slot");
+    if (!c->g.has_fem || !data || !obs || !grad) return bfail(b, HYB_E_ARG, "batch: needs a FEM box, data, obs, grad");
+    if (c->store_mode != 0) return bfail(b, HYB_E_UNSUPPORTED, "batch: contexts must keep the full history");
+    int q = -1;
+    for (int i = 0; i < b->max_slots; ++i)
+        if (b->slots[i].state == 0) { q = i; break; }
+    if (q < 0) return bfail(b, HYB_E_STATE, "batch: no free slot");
+    const int lane = lane_of(b, c->stream);
+    if (lane < 0) return bfail(b, HYB_E_OOM, "batch: staging allocation failed");
+    hyb_status s = prepare_forward(c, sigma, src, nt, dt, &sigma_max);
+    if (!s) s = alloc_adjoint(c);
+    if (!s) s = ensure_trace_bufs(c, nt);
+    if (s) return bfail(b, s, c->err);
+    s = c->f32 ? fwd_setup<float>(c, obs) : fwd_setup<double>(c, obs);
+    if (s) return bfail(b, s, c->err);
+    hyb_batch::Slot &sl = b->slots[q];
+    sl.c = c;
+    sl.state = 1;
+    sl.k = 0; sl.ia = 0; sl.ib = 1; sl.ic = 2;
+    sl.data = data; sl.obs = obs; sl.grad = grad;
+    sl.lane = lane;
+    c->in_batch = true;
+    *slot = q;
+    return HYB_OK;
+}
+
+hyb_status hyb_batch_tick(hyb_batch *b, int32_t steps, int32_t *n_active)
+{
+    if (!b || steps < 1) return HYB_E_ARG;
+    int32_t first = -1;
+    while (steps > 0) {
+        const int m = std::min(steps, (int32_t)TICKS_PER_PLAN);
+        int32_t act = 0;
+        hyb_status s = batch_plan_run(b, m, &act);
+        if (s) return s;
+        if (first < 0) first = act;
+        if (act == 0) break;
+        steps -= m;
+    }
+    if (n_active) *n_active = first < 0 ? 0 : first;
+    return HYB_OK;
+}
+
+hyb_status hyb_batch_poll_all(hyb_batch *b, int32_t *state, double *J)
+{
+    if (!b || !state) return HYB_E_ARG;
+    for (int q = 0; q < b->max_slots; ++q) {
+        hyb_status s = hyb_batch_poll(b, q, state + q, J ? J + q : nullptr);
+        if (s) return s;
+    }
+    return HYB_OK;
+}
+
+}  // extern "C"
+
+
+extern "C" {
+
+hyb_status hyb_batch_poll(hyb_batch *b, int32_t slot, int32_t *state, double *J)
+{
+    if (!b || slot < 0 || slot >= b->max_slots || !state) return HYB_E_ARG;
+    hyb_batch::Slot &sl = b->slots[slot];
+    int st = sl.state;
+    if (st == 3) {
+        const hipError_t e = hipEventQuery(sl.done);
+        if (e == hipSuccess) {
+            st = sl.J_host[0] != 0.0 ? 4 : 5;  // failed (non-finite sigma) or finished
+            if (J) *J = sl.J_host[1] + sl.J_host[2];
+        } else if (e != hipErrorNotReady) {
+            return bfail(b, HYB_E_DEVICE, "batch: device error");
+        }
+    }
+    *state = st == 5 ? 2 : (st == 0 ? -1 : (st == 3 ? 1 : (st == 4 ? 3 : 0)));
+    return HYB_OK;
+}
+
+hyb_status hyb_batch_release(hyb_batch *b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->max_slots) return HYB_E_ARG;
+    hyb_batch::Slot &sl = b->slots[slot];
+    if (sl.state == 1 || sl.state == 2) return bfail(b, HYB_E_STATE, "batch: slot still running");
+    if (sl.state == 3 && hipEventSynchronize(sl.done) != hipSuccess) return bfail(b, HYB_E_DEVICE, "batch: device error");
+    if (sl.c) sl.c->in_batch = false;
+    sl.c = nullptr;
+    sl.state = 0;
+    sl.k = 0; sl.ia = 0; sl.ib = 1; sl.ic = 2;
+    sl.data = nullptr; sl.obs = nullptr; sl.grad = nullptr;
+    return HYB_OK;
+}
+
+const char *hyb_batch_last_error(const hyb_batch *b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

@@ -68,13 +68,16 @@ struct Step {
     const T *Fa, *Fb;        // boundary multipliers of levels k+2, k+1 (face arrays)
     T *Fc;                   // boundary multipliers of level k
     T *Pw;                   // level k+1 grid array: receives the boundary proxies
-    T wB1[6], wB0[6];        // proxy weights per face
 };
 
 // ---- launchers (hyb_kernels.hip) ----
 template <typename T> void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st);
 template <typename T> void launch_bnd_fwd(const Step<T> &s, hipStream_t st);
 template <typename T> void launch_bnd_adj(const Step<T> &s, hipStream_t st);
+
+// batched steps: steps_dev[n] device array, all of geometry g
+template <typename T> void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st);
+template <typename T> void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st);
 
 // a = 1 + sigma on free cubes (1 elsewhere); scal[0] = max sigma over free
 // cubes, scal[1] = 1 if sigma has a non-finite entry.

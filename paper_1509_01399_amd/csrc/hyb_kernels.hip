@@ -148,7 +148,7 @@ __device__ __forceinline__ T src_flux(const Step<T> &s, int x, int y)
 // inward neighbour, recomputed here when that neighbour is itself a boundary
 // node (D bounds the depth: corner -> edge -> face -> interior).
 template <typename T, int D>
-__device__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
+__device__ __forceinline__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
 {
     const Geo &g = s.g;
     const BInfo B = classify(g, x, y, z, s.types1);
@@ -212,10 +212,9 @@ __device__ __forceinline__ void box_surface(long long t, int L, int &a, int &b, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_bnd_fwd(Step<T> s)
+__device__ __forceinline__ void bnd_fwd_body(const Step<T> &s, long long t)
 {
     const Geo &g = s.g;
-    long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
     if (t < g.n_fi) {
         // face-interior node: one boundary axis, never needs recursion
         int x, y, z, f;
@@ -263,6 +262,12 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_fwd(Step<T> s)
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_fwd(Step<T> s)
+{
+    bnd_fwd_body<T>(s, (long long)blockIdx.x * BLOCK + threadIdx.x);
+}
+
 // ---------------------------------------------------------------- adjoint
 //
 // Multipliers of the boundary rows live in compact per-face arrays (Fa, Fb,
@@ -296,7 +301,7 @@ __device__ __forceinline__ T seed_at(const Step<T> &s, int x, int y)
 //   higher codimension, whose level-k multipliers are already in Fc:
 //   corners are computed first, then edges, then faces.
 template <typename T>
-__device__ T bnd_adj(const Step<T> &s, int x, int y, int z)
+__device__ __forceinline__ T bnd_adj(const Step<T> &s, int x, int y, int z)
 {
     const Geo &g = s.g;
     const T c2 = s.c2;
@@ -347,7 +352,7 @@ __device__ __forceinline__ void edge_node(const Geo &g, int e, int p, int &x, in
 // corner of the same level: block 0 computes the 8 corners, then (after a
 // barrier) the 24 end nodes; all other edge nodes are independent.
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec(Step<T> s)
+__device__ __forceinline__ void bnd_adj_ec_body(const Step<T> &s)
 {
     const Geo &g = s.g;
     const int L[3] = {g.nx - 2, g.ny - 2, g.nz - 2};
@@ -383,13 +388,19 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec(Step<T> s)
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec(Step<T> s)
+{
+    bnd_adj_ec_body<T>(s);
+}
+
 template <typename T, bool ADJ>
-__device__ void fem_tile(const Step<T> &s, int bid);
+__device__ __forceinline__ void fem_tile(const Step<T> &s, int bid);
 
 // Face nodes (after k_bnd_adj_ec), and in the same launch the FEM rows of the
 // adjoint with the gradient integral (they need nothing of level k).
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_bnd_adj(Step<T> s)
+__device__ __forceinline__ void bnd_adj_body(const Step<T> &s)
 {
     const Geo &g = s.g;
     if ((int)blockIdx.x < g.n_fem_blocks) {
@@ -421,8 +432,20 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_adj(Step<T> s)
     } else {
         mu = bnd_adj(s, x, y, z);
     }
+    // proxy weights of face f: its level-(k+1) row reads the interior
+    // neighbour with 2 c2 (ghost) or 1 (absorbing); an absorbing row of level
+    // k reads it with -r (computed from the packed face conditions: a runtime
+    // index into the by-value argument would force a private copy of it)
+    const T w1 = ftype(s.types1, f) == F_ABC ? (T)1 : (T)2 * s.c2;
+    const T w0 = (s.level_rows && ftype(s.types0, f) == F_ABC) ? -s.r : (T)0;
     s.Fc[cb] = mu;
-    s.Pw[id] = (s.wB1[f] * fb + s.wB0[f] * mu) / s.c2;  // what the interior stencil reads
+    s.Pw[id] = (w1 * fb + w0 * mu) / s.c2;  // what the interior stencil reads
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj(Step<T> s)
+{
+    bnd_adj_body<T>(s);
 }
 
 // ---------------------------------------------------------------- interior
@@ -436,7 +459,7 @@ __device__ __forceinline__ T acub(const Step<T> &s, int i, int j, int k)
 }
 
 template <typename T>
-__device__ T kappa_edge(const Step<T> &s, int d, int i, int j, int k)
+__device__ __forceinline__ T kappa_edge(const Step<T> &s, int d, int i, int j, int k)
 {
     T kap = 0;
 #pragma unroll
@@ -519,7 +542,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk)
 }
 
 template <typename T, bool ADJ>
-__device__ void fdm_tile(const Step<T> &s, int bid)
+__device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
 {
     const Geo &g = s.g;
     bid = xcd_remap(bid, g.n_fdm_blocks);
@@ -540,7 +563,7 @@ __device__ void fdm_tile(const Step<T> &s, int bid)
 }
 
 template <typename T, bool ADJ>
-__device__ void fem_tile(const Step<T> &s, int bid)
+__device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 {
     const Geo &g = s.g;
     const int Cx = g.C[0], Cy = g.C[1], Cz = g.C[2];
@@ -668,6 +691,63 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
     hipLaunchKernelGGL((k_bnd_adj_ec<T>), dim3((unsigned)(1 + (inner + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
     const long long nb = s.g.n_fem_blocks + (s.g.n_fi + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL((k_bnd_adj<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, s);
+}
+
+// ---------------------------------------------------------------- batches
+//
+// Batched launches for the request server: blockIdx.y selects a slot whose
+// step arguments sit in a device array.  Every slot of one launch has the
+// same geometry (same grid and FEM box) but its own fields, time step and
+// phase; the per-slot work is exactly that of the single-context kernels.
+
+template <typename T, bool ADJ>
+__global__ __launch_bounds__(BLOCK) void k_interior_b(const Step<T> *__restrict__ steps)
+{
+    const Step<T> &s = steps[blockIdx.y];
+    const int b = blockIdx.x;
+    const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
+    if (b < nf) fdm_tile<T, ADJ>(s, b);
+    else if constexpr (!ADJ) fem_tile<T, false>(s, b - nf);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_fwd_b(const Step<T> *__restrict__ steps)
+{
+    bnd_fwd_body<T>(steps[blockIdx.y], (long long)blockIdx.x * BLOCK + threadIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec_b(const Step<T> *__restrict__ steps)
+{
+    bnd_adj_ec_body<T>(steps[blockIdx.y]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj_b(const Step<T> *__restrict__ steps)
+{
+    bnd_adj_body<T>(steps[blockIdx.y]);
+}
+
+template <typename T>
+void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st)
+{
+    const int nf = (g.n_fdm_blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_interior_b<T, false>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
+    const long long m = g.n_fi + g.n_ec + g.nwd + g.nwo;
+    hipLaunchKernelGGL((k_bnd_fwd_b<T>), dim3((unsigned)((m + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0, st, steps_dev);
+}
+
+template <typename T>
+void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st)
+{
+    long long inner = 0;
+    for (int q : {g.nx, g.ny, g.nz}) inner += 4 * (long long)(q - 2 > 2 ? q - 4 : 0);
+    hipLaunchKernelGGL((k_bnd_adj_ec_b<T>), dim3((unsigned)(1 + (inner + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0,
+                       st, steps_dev);
+    const long long nb = g.n_fem_blocks + (g.n_fi + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL((k_bnd_adj_b<T>), dim3((unsigned)nb, n), dim3(BLOCK), 0, st, steps_dev);
+    const int nf = (g.n_fdm_blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_interior_b<T, true>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -1001,6 +1081,8 @@ void launch_residual(const double *obs, const double *data, double *res, long lo
     template void launch_interior<T>(const Step<T> &, bool, hipStream_t);                          \
     template void launch_bnd_fwd<T>(const Step<T> &, hipStream_t);                                \
     template void launch_bnd_adj<T>(const Step<T> &, hipStream_t);                                \
+    template void launch_batch_fwd<T>(const Geo &, const Step<T> *, int, hipStream_t);            \
+    template void launch_batch_adj<T>(const Geo &, const Step<T> *, int, hipStream_t);                                \
     template void launch_acube<T>(const Geo &, const double *, T *, double *, double *, hipStream_t); \
     template void launch_load_level<T>(const Geo &, const double *, T *, T *, hipStream_t);        \
     template void launch_hist_level<T>(const Geo &, const T *, T *, hipStream_t);                  \

@@ -25,7 +25,9 @@ BC_ABC, BC_NEUMANN, BC_SOURCE = 0, 1, 2
 
 EXPORTS = ("hyb_create", "hyb_destroy", "hyb_forward", "hyb_set_initial", "hyb_adjoint",
            "hyb_gradient", "hyb_cg_step", "hyb_footprint", "hyb_sync", "hyb_last_error",
-           "hyb_counts", "hyb_time_interior", "hyb_get_wavefield")
+           "hyb_counts", "hyb_time_interior", "hyb_get_wavefield", "hyb_batch_create",
+           "hyb_batch_destroy", "hyb_batch_submit", "hyb_batch_tick", "hyb_batch_poll",
+           "hyb_batch_release", "hyb_batch_last_error", "hyb_batch_poll_all")
 
 
 class hyb_fd_grid(ct.Structure):
@@ -93,8 +95,19 @@ def load():
     lib.hyb_counts.argtypes = [vp, P(ct.c_int64), P(ct.c_int64)]
     lib.hyb_time_interior.argtypes = [vp, vp, dp, ct.c_int32, P(dp)]
     lib.hyb_get_wavefield.argtypes = [vp, ct.c_int32, vp, vp]
+    lib.hyb_batch_create.argtypes = [ct.c_int32, vp, P(vp)]
+    lib.hyb_batch_destroy.argtypes = [vp]
+    lib.hyb_batch_destroy.restype = None
+    lib.hyb_batch_submit.argtypes = [vp, vp, vp, dp, P(hyb_source), ct.c_int32, dp, vp, vp, vp,
+                                     P(ct.c_int32)]
+    lib.hyb_batch_tick.argtypes = [vp, ct.c_int32, P(ct.c_int32)]
+    lib.hyb_batch_poll_all.argtypes = [vp, P(ct.c_int32), P(dp)]
+    lib.hyb_batch_poll.argtypes = [vp, ct.c_int32, P(ct.c_int32), P(dp)]
+    lib.hyb_batch_release.argtypes = [vp, ct.c_int32]
+    lib.hyb_batch_last_error.argtypes = [vp]
+    lib.hyb_batch_last_error.restype = ct.c_char_p
     for name in EXPORTS:
-        if name not in ("hyb_destroy", "hyb_last_error"):
+        if name not in ("hyb_destroy", "hyb_last_error", "hyb_batch_destroy", "hyb_batch_last_error"):
             getattr(lib, name).restype = ct.c_int
     _lib = lib
     return lib
@@ -232,6 +245,57 @@ def hyb_time_interior(ctx, sigma, dt, reps):
 
 def hyb_get_wavefield(ctx, which, u, v=None):
     _check(load().hyb_get_wavefield(ctx, int(which), _ptr(u), _ptr(v)), ctx)
+
+
+def _bcheck(status, b):
+    if status != HYB_OK:
+        msg = load().hyb_batch_last_error(b)
+        raise HybError(status, msg.decode() if msg else "")
+
+
+def hyb_batch_create(max_slots, stream=None):
+    b = ct.c_void_p()
+    _check(load().hyb_batch_create(int(max_slots), stream, ct.byref(b)))
+    return b
+
+
+def hyb_batch_destroy(b):
+    load().hyb_batch_destroy(b)
+
+
+def hyb_batch_submit(b, ctx, sigma, sigma_max, src, nt, dt, data, obs, grad):
+    slot = ct.c_int32(-1)
+    _bcheck(load().hyb_batch_submit(b, ctx, _ptr(sigma), float(sigma_max), ct.byref(src), int(nt),
+                                    float(dt), _ptr(data), _ptr(obs), _ptr(grad), ct.byref(slot)), b)
+    return slot.value
+
+
+def hyb_batch_tick(b, steps=1):
+    n = ct.c_int32(0)
+    _bcheck(load().hyb_batch_tick(b, int(steps), ct.byref(n)), b)
+    return n.value
+
+
+def hyb_batch_poll_all(b, max_slots):
+    st = (ct.c_int32 * max_slots)()
+    J = (ct.c_double * max_slots)()
+    _bcheck(load().hyb_batch_poll_all(b, st, J), b)
+    return list(st), list(J)
+
+
+def hyb_batch_poll(b, slot):
+    st, J = ct.c_int32(0), ct.c_double(0.0)
+    _bcheck(load().hyb_batch_poll(b, int(slot), ct.byref(st), ct.byref(J)), b)
+    return st.value, J.value
+
+
+def hyb_batch_release(b, slot):
+    _bcheck(load().hyb_batch_release(b, int(slot)), b)
+
+
+def hyb_batch_last_error(b):
+    m = load().hyb_batch_last_error(b)
+    return m.decode() if m else ""
 
 
 # ---- convenience wrapper ----
