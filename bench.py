@@ -143,7 +143,7 @@ def roofline(wl, dt, solver, f32, reps=50):
     achieved = b / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(wl.name, f32),
-            "kernel": "k_interior<%s,false>" % ("float" if f32 else "double"),
+            "kernel": "k_interior<%s,false,*> (forward FDM+FEM interior)" % ("float" if f32 else "double"),
             "bytes_per_launch": b, "avg_launch_ms": round(ms, 5)}
 
 

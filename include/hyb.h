@@ -220,6 +220,8 @@ hyb_status hyb_time_interior(hyb_ctx *ctx, const double *sigma_dev, double dt, i
  *   which 1: the multipliers of level 0 of the last adjoint sweep, i.e. the
  *            cotangent of u^0 (grid part; the FEM part is the cotangent of the
  *            FEM copy of u^0, to be added on the FEM box nodes).
+ * Grid nodes strictly inside the hole (o+2, o+C-2)^3 belong to no grid row
+ * (the FEM part holds the solution there) and are returned as 0.
  * u_dev: device [(n_z+1)(n_y+1)(n_x+1)] grid part (nullable);
  * v_dev: device [(C+1)^3] FEM part (nullable; ignored without FEM box).
  * Errors: HYB_E_ARG, HYB_E_STATE (no such sweep yet). */

@@ -9,11 +9,13 @@
 
 namespace hyb {
 
-// Block shapes (64-wide wavefronts): the FDM tile is 64 x TY_FDM columns, the
-// FEM tile 32 x TY_FEM columns; both stream along z.
-constexpr int TX_FDM = 64, TY_FDM = 4;
+// Block shapes (64-wide wavefronts): the FDM tile is 64 x TY_FDM columns
+// (each thread takes RY_FDM neighbouring rows), the FEM tile 32 x TY_FEM
+// columns; both stream along z.
+constexpr int TX_FDM = 64, RY_FDM = 2, TY_FDM = 4 * RY_FDM;
 constexpr int TX_FEM = 32, TY_FEM = 8;
 constexpr int BLOCK = 256;
+static_assert(BLOCK / TX_FDM * RY_FDM == TY_FDM && RY_FDM == 2, "FDM tile: 4 thread rows of 2 grid rows");
 
 // Face condition of one face at one step, 2 bits per face in a packed int.
 enum : int { F_ABC = 0, F_NEUMANN = 1, F_SOURCE = 2 };

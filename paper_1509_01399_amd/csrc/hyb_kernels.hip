@@ -396,9 +396,13 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec(Step<T> s)
 
 template <typename T, bool ADJ>
 __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid);
+template <typename T>
+__device__ __forceinline__ void omega_o_fill(const Step<T> &s, long long t);
 
 // Face nodes (after k_bnd_adj_ec), and in the same launch the FEM rows of the
-// adjoint with the gradient integral (they need nothing of level k).
+// adjoint with the gradient integral (they need nothing of level k) and the
+// omega_o couplings of the FDM rows of level k, left in the level-k array
+// for the interior launch that follows to add.
 template <typename T>
 __device__ __forceinline__ void bnd_adj_body(const Step<T> &s)
 {
@@ -408,7 +412,10 @@ __device__ __forceinline__ void bnd_adj_body(const Step<T> &s)
         return;
     }
     const long long t = (long long)(blockIdx.x - g.n_fem_blocks) * BLOCK + threadIdx.x;
-    if (t >= g.n_fi) return;
+    if (t >= g.n_fi) {
+        if (t < g.n_fi + g.nwo) omega_o_fill(s, t - g.n_fi);
+        return;
+    }
     int x, y, z, f;
     face_node(g, t, x, y, z, f);
     const int d = f >> 1, dir = (f & 1) ? -1 : 1;
@@ -496,39 +503,101 @@ __device__ __forceinline__ T omega_o_term(const Step<T> &s, int ax, int i, int j
     return s.c2 * kappa_edge(s, 2, i, j, ke) * s.Vb[fidx(g, i, j, km)];
 }
 
-// Seven-point leapfrog, eq. (fdmschemeforward), on one column (x,y) for
-// z in [z0, z1), skipping the closed hole [o+2, o+C-2]^3.  The same stencil
-// is the adjoint update of the FDM rows (ADJ adds the omega_o term).
-template <typename T, bool ADJ>
-__device__ __forceinline__ void fdm_column(const Step<T> &s, int x, int y, int z0, int z1, bool hcol)
+// Loads and stores of data touched once per launch (u^{k-1}, u^{k+1}, the
+// FEM history).  With NT they carry the non-temporal hint, so that they do
+// not evict the reused level-k field from the caches; the host selects NT
+// when the three field levels do not fit in the last-level cache.
+template <typename T, bool NT>
+__device__ __forceinline__ T ld_once(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <typename T, bool NT>
+__device__ __forceinline__ void st_once(T *p, T v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+// Adjoint coupling of an FDM row on omega_o (zero elsewhere); (i, j, k) are
+// FEM-local coordinates of the node.
+template <typename T>
+__device__ __forceinline__ T omega_o_adj(const Step<T> &s, int i, int j, int k)
+{
+    const Geo &g = s.g;
+    const bool ii = i > 0 && i < g.C[0], jj = j > 0 && j < g.C[1], kk = k > 0 && k < g.C[2];
+    if (jj && kk && (i == 0 || i == g.C[0])) return omega_o_term(s, 0, i, j, k);
+    if (ii && kk && (j == 0 || j == g.C[1])) return omega_o_term(s, 1, i, j, k);
+    if (ii && jj && (k == 0 || k == g.C[2])) return omega_o_term(s, 2, i, j, k);
+    return (T)0;
+}
+
+// Node t of omega_o (FEM box surface, enumerated like the forward copy):
+// its adjoint coupling, written to the level-k array where the FDM row of the
+// node adds it (zero on the edges of the box surface).
+template <typename T>
+__device__ __forceinline__ void omega_o_fill(const Step<T> &s, long long t)
+{
+    const Geo &g = s.g;
+    int i, j, k;
+    box_surface(t, g.C[0], i, j, k);
+    s.Uc[gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k)] = omega_o_adj(s, i, j, k);
+}
+
+// Seven-point leapfrog, eq. (fdmschemeforward), on two neighbouring columns
+// (x, y) and (x, y+1) (the second when `two`) for z in [z0, z1), skipping the
+// closed hole [o+2, o+C-2]^3.  The rows share their y-neighbour loads (the
+// centre of one row is the y-neighbour of the other) and a register queue
+// along z.  The same stencil is the adjoint update of the FDM rows; there
+// (ADJ) the rows on omega_o add the coupling the boundary launch left in
+// their level-k entry.
+template <typename T, bool ADJ, bool NT>
+__device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, bool two, int z0, int z1, bool hcol0,
+                                         bool hcol1)
 {
     const Geo &g = s.g;
     const long long py = g.px, pz = g.plane;
     long long id = gidx(g, x, y, z0);
     const T c2 = s.c2;
-    // omega_o column flags (adjoint): x/y faces of the FEM box surface need
-    // the term for o < z < o+C, the z faces at z = o and z = o+C
-    const int i = x - g.o[0], j = y - g.o[1];
-    const bool ii = i > 0 && i < g.C[0], jj = j > 0 && j < g.C[1];
-    const bool colx = ADJ && g.has_fem && jj && (i == 0 || i == g.C[0]);
-    const bool coly = ADJ && g.has_fem && ii && (j == 0 || j == g.C[1]);
-    const bool colz = ADJ && g.has_fem && ii && jj;
-    T cm = s.Ub[id - pz], c0 = s.Ub[id];
+    const T *Ub = s.Ub;
+    // adjoint: rows on omega_o.  A column on an x or y face of the box meets
+    // it for o <= z <= o+C, a column inside the box at z = o and z = o+C.
+    const int i = x - g.o[0], j0 = y - g.o[1], C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
+    const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
+    const bool side0 = ib && j0 >= 0 && j0 <= C1 && !(ii && j0 > 0 && j0 < C1);
+    const bool top0 = ib && ii && j0 > 0 && j0 < C1;
+    const bool side1 = ib && j0 + 1 >= 0 && j0 + 1 <= C1 && !(ii && j0 + 1 > 0 && j0 + 1 < C1);
+    const bool top1 = ib && ii && j0 + 1 > 0 && j0 + 1 < C1;
+    T cm0 = Ub[id - pz], c00 = Ub[id];
+    T cm1 = two ? Ub[id + py - pz] : (T)0, c01 = two ? Ub[id + py] : (T)0;
     for (int z = z0; z < z1; ++z, id += pz) {
-        const T cp = s.Ub[id + pz];
-        if (!(hcol && z >= g.hlo[2] && z <= g.hhi[2])) {
-            const T xm = s.Ub[id - 1], xp = s.Ub[id + 1], ym = s.Ub[id - py], yp = s.Ub[id + py];
-            T v = (T)2 * c0 - s.Ua[id] + c2 * (((xm + xp) + (ym + yp)) + (cm + cp) - (T)6 * c0);
-            if constexpr (ADJ) {
-                const int k = z - g.o[2];
-                const bool kk = k > 0 && k < g.C[2];
-                if ((colx || coly) && kk) v += omega_o_term(s, colx ? 0 : 1, i, j, k);
-                else if (colz && (k == 0 || k == g.C[2])) v += omega_o_term(s, 2, i, j, k);
-            }
-            s.Uc[id] = v;
+        const T cp0 = Ub[id + pz];
+        const T cp1 = two ? Ub[id + py + pz] : (T)0;
+        const bool inh = z >= g.hlo[2] && z <= g.hhi[2];
+        const int kz = z - g.o[2];
+        const bool zs = kz >= 0 && kz <= C2, zt = kz == 0 || kz == C2;
+        if (!(hcol0 && inh)) {
+            const T xm = Ub[id - 1], xp = Ub[id + 1], ym = Ub[id - py];
+            const T yp = two ? c01 : Ub[id + py];
+            T v = (T)2 * c00 - ld_once<T, NT>(s.Ua + id) + c2 * (((xm + xp) + (ym + yp)) + (cm0 + cp0) - (T)6 * c00);
+            if constexpr (ADJ)
+                if ((side0 && zs) || (top0 && zt)) v += s.Uc[id];
+            st_once<T, NT>(s.Uc + id, v);
         }
-        cm = c0;
-        c0 = cp;
+        if (two && !(hcol1 && inh)) {
+            const long long i1 = id + py;
+            const T xm = Ub[i1 - 1], xp = Ub[i1 + 1], yp = Ub[i1 + py];
+            T v = (T)2 * c01 - ld_once<T, NT>(s.Ua + i1) + c2 * (((xm + xp) + (c00 + yp)) + (cm1 + cp1) - (T)6 * c01);
+            if constexpr (ADJ)
+                if ((side1 && zs) || (top1 && zt)) v += s.Uc[i1];
+            st_once<T, NT>(s.Uc + i1, v);
+        }
+        cm0 = c00;
+        c00 = cp0;
+        cm1 = c01;
+        c01 = cp1;
     }
 }
 
@@ -541,7 +610,11 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk)
     return (b % 8) * per + b / 8;
 }
 
-template <typename T, bool ADJ>
+// FDM tile: 64 x-lanes starting at a multiple of 64 (rows of the padded
+// field start on a 128-byte line, so a wave's row access covers whole cache
+// lines; the lane on the x = 0 boundary idles) by 4 thread rows of 2 grid
+// rows each, streaming z over the block's chunk.
+template <typename T, bool ADJ, bool NT>
 __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
 {
     const Geo &g = s.g;
@@ -551,15 +624,17 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
     const int t = bid / g.fdm_tiles[0];
     const int by = t % g.fdm_tiles[1];
     const int bz = t / g.fdm_tiles[1];
-    const int x0 = 1 + bx * TX_FDM, y0 = 1 + by * TY_FDM;
-    const int x = x0 + (int)(threadIdx.x % TX_FDM);
-    const int y = y0 + (int)(threadIdx.x / TX_FDM);
-    if (x > g.nx - 2 || y > g.ny - 2) return;
+    const int x = bx * TX_FDM + (int)(threadIdx.x % TX_FDM);
+    const int y = 1 + by * TY_FDM + RY_FDM * (int)(threadIdx.x / TX_FDM);
+    if (x < 1 || x > g.nx - 2 || y > g.ny - 2) return;
+    const bool two = y + 1 <= g.ny - 2;
     const int z0 = 1 + bz * g.zc_fdm;
     const int z1 = min(z0 + g.zc_fdm, g.nz - 1);
-    const bool hcol = g.has_fem && x >= g.hlo[0] && x <= g.hhi[0] && y >= g.hlo[1] && y <= g.hhi[1];
-    if (hcol && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
-    fdm_column<T, ADJ>(s, x, y, z0, z1, hcol);
+    const bool xin = g.has_fem && x >= g.hlo[0] && x <= g.hhi[0];
+    const bool hcol0 = xin && y >= g.hlo[1] && y <= g.hhi[1];
+    const bool hcol1 = xin && y + 1 >= g.hlo[1] && y + 1 <= g.hhi[1];
+    if (hcol0 && (hcol1 || !two) && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
+    fdm_rows<T, ADJ, NT>(s, x, y, two, z0, z1, hcol0, hcol1);
 }
 
 template <typename T, bool ADJ>
@@ -627,7 +702,8 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
                 for (int c = 0; c < 8; ++c) {
                     const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
                     q[c] = (double)s.Vb[id + dx + dy * fy + dz * fz];
-                    hv[c] = (double)H[(i - 2 + dx) + (long long)(j - 2 + dy) * hn0 + (long long)(k - 2 + dz) * hpz];
+                    hv[c] = (double)ld_once<T, true>(H + (i - 2 + dx) + (long long)(j - 2 + dy) * hn0 +
+                                                   (long long)(k - 2 + dz) * hpz);
                 }
                 double acc = 0.0;
 #pragma unroll
@@ -644,7 +720,7 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
             }
         } else {
             if (hin && s.hist)
-                s.hist[(i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz] = v;
+                st_once<T, true>(s.hist + (i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz, v);
         }
         s.Vc[id] = v;
         vm = v0;
@@ -657,23 +733,36 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 // FDM blocks first (their count rounded up to a multiple of 8 for the XCD
 // remap), then, in the forward sweep, the FEM blocks.  The FEM rows of the
 // adjoint run in the boundary launch.
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_interior(Step<T> s)
 {
     const int b = blockIdx.x;
     const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
-    if (b < nf) fdm_tile<T, ADJ>(s, b);
+    if (b < nf) fdm_tile<T, ADJ, NT>(s, b);
     else if constexpr (!ADJ) fem_tile<T, false>(s, b - nf);
+}
+
+// Non-temporal hints pay when the three field levels of all slots of a
+// launch exceed what the 256 MB last-level cache keeps (measured: they slow
+// a cache-resident 257^3 FP32 sweep by a third and speed up larger ones).
+static bool stream_nt(const Geo &g, size_t esz, int slots)
+{
+    return 3.0 * (double)g.plane * g.nz * esz * slots > 224.0 * (1 << 20);
 }
 
 template <typename T>
 void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st)
 {
     const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
-    if (adjoint)
-        hipLaunchKernelGGL((k_interior<T, true>), dim3(nf), dim3(BLOCK), 0, st, s);
-    else
-        hipLaunchKernelGGL((k_interior<T, false>), dim3(nf + s.g.n_fem_blocks), dim3(BLOCK), 0, st, s);
+    const bool nt = stream_nt(s.g, sizeof(T), 1);
+    if (adjoint) {
+        if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), dim3(nf), dim3(BLOCK), 0, st, s);
+        else hipLaunchKernelGGL((k_interior<T, true, false>), dim3(nf), dim3(BLOCK), 0, st, s);
+    } else {
+        const dim3 grid(nf + s.g.n_fem_blocks);
+        if (nt) hipLaunchKernelGGL((k_interior<T, false, true>), grid, dim3(BLOCK), 0, st, s);
+        else hipLaunchKernelGGL((k_interior<T, false, false>), grid, dim3(BLOCK), 0, st, s);
+    }
 }
 
 template <typename T>
@@ -689,7 +778,7 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
     long long inner = 0;
     for (int n : {s.g.nx, s.g.ny, s.g.nz}) inner += 4 * (long long)(n - 2 > 2 ? n - 4 : 0);
     hipLaunchKernelGGL((k_bnd_adj_ec<T>), dim3((unsigned)(1 + (inner + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
-    const long long nb = s.g.n_fem_blocks + (s.g.n_fi + BLOCK - 1) / BLOCK;
+    const long long nb = s.g.n_fem_blocks + (s.g.n_fi + s.g.nwo + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL((k_bnd_adj<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, s);
 }
 
@@ -700,13 +789,13 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 // same geometry (same grid and FEM box) but its own fields, time step and
 // phase; the per-slot work is exactly that of the single-context kernels.
 
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_interior_b(const Step<T> *__restrict__ steps)
 {
     const Step<T> &s = steps[blockIdx.y];
     const int b = blockIdx.x;
     const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
-    if (b < nf) fdm_tile<T, ADJ>(s, b);
+    if (b < nf) fdm_tile<T, ADJ, NT>(s, b);
     else if constexpr (!ADJ) fem_tile<T, false>(s, b - nf);
 }
 
@@ -732,7 +821,10 @@ template <typename T>
 void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st)
 {
     const int nf = (g.n_fdm_blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_interior_b<T, false>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
+    if (stream_nt(g, sizeof(T), n))
+        hipLaunchKernelGGL((k_interior_b<T, false, true>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
+    else
+        hipLaunchKernelGGL((k_interior_b<T, false, false>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
     const long long m = g.n_fi + g.n_ec + g.nwd + g.nwo;
     hipLaunchKernelGGL((k_bnd_fwd_b<T>), dim3((unsigned)((m + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0, st, steps_dev);
 }
@@ -744,10 +836,13 @@ void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t
     for (int q : {g.nx, g.ny, g.nz}) inner += 4 * (long long)(q - 2 > 2 ? q - 4 : 0);
     hipLaunchKernelGGL((k_bnd_adj_ec_b<T>), dim3((unsigned)(1 + (inner + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0,
                        st, steps_dev);
-    const long long nb = g.n_fem_blocks + (g.n_fi + BLOCK - 1) / BLOCK;
+    const long long nb = g.n_fem_blocks + (g.n_fi + g.nwo + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL((k_bnd_adj_b<T>), dim3((unsigned)nb, n), dim3(BLOCK), 0, st, steps_dev);
     const int nf = (g.n_fdm_blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_interior_b<T, true>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev);
+    if (stream_nt(g, sizeof(T), n))
+        hipLaunchKernelGGL((k_interior_b<T, true, true>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev);
+    else
+        hipLaunchKernelGGL((k_interior_b<T, true, false>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -884,7 +979,12 @@ __global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const
     const long long n = (long long)g.nx * g.ny * g.nz;
     for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
         const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), z = (int)(t / ((long long)g.nx * g.ny));
-        if (u) u[t] = (double)((F && on_bnd(g, x, y, z)) ? F[cidx(g, x, y, z)] : U[gidx(g, x, y, z)]);
+        // nodes strictly inside the hole belong to no grid row: no value
+        const bool hole = g.has_fem && x > g.hlo[0] && x < g.hhi[0] && y > g.hlo[1] && y < g.hhi[1] &&
+                          z > g.hlo[2] && z < g.hhi[2];
+        if (u)
+            u[t] = hole ? 0.0
+                        : (double)((F && on_bnd(g, x, y, z)) ? F[cidx(g, x, y, z)] : U[gidx(g, x, y, z)]);
     }
     if (!v || !g.has_fem) return;
     const long long nf = (long long)(g.C[0] + 1) * (g.C[1] + 1) * (g.C[2] + 1);

@@ -1,0 +1,121 @@
+"""GPU parity at full problem sizes, in the launch configuration the benchmark
+times (same solver construction, tiles, z chunks and cache hints), over
+horizons the CPU oracle finishes in seconds to a minute.
+
+Random initial levels u^0, u^{-1} (the Model Problem 1 form of the state
+equation) make every part of the forward step active from the first step:
+the seven-point rows everywhere, the FEM box with its conductivity, both
+overlap copies and the absorbing faces, edges and corners.  The adjoint is
+seeded with a random trace cotangent (mode 1); over the short horizon it
+stays near the trace face, so a longer FP64 run carries it into the FEM box
+for the gradient time-integral.  Bars: FP64 relative L2 <= 1e-12 on the
+trace, the final fields, the cotangent of u^0 and the gradient; FP32
+wavefields <= 1e-5."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1509_01399_amd import hyb
+    assert torch.cuda.is_available()
+    hyb.load()
+    return torch
+
+
+def _t(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _setup(name, seed):
+    from paper_1509_01399_amd import synth
+    wl = synth.WORKLOADS[name]
+    sig = synth.sigma_for(wl, seed)
+    dt = synth.dt_rule(wl.h, sig.max())
+    return wl, sig, dt
+
+
+def _short(torch, orc, name, f32, nt, seed):
+    """Forward from random initial levels and the adjoint of a random trace
+    cotangent: trace, final fields and the cotangent of u^0."""
+    from paper_1509_01399_amd.hyb import Solver
+    wl, sig, dt = _setup(name, seed)
+    n, C, o = wl.n, wl.C, wl.o
+    rng = np.random.default_rng(100 + seed)
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = u0 + 0.05 * rng.standard_normal((n + 1,) * 3)
+    print(f"[fullsize] {name} n={n} C={C} nt={nt} f32={f32}", flush=True)
+    s = Solver(n, C=C, f32=f32)
+    s.set_initial(_t(torch, u0), _t(torch, um1))
+    obs = s.forward(_t(torch, sig), nt, dt, omega=wl.omega).cpu().numpy()
+    u, v = s.wavefield(0)
+    u, v = u.cpu().numpy().ravel(), v.cpu().numpy().ravel()
+    r = rng.standard_normal(obs.shape)
+    s.adjoint(_t(torch, r), mode=1)
+    mu, muv = s.wavefield(1)
+    du0 = mu.cpu().numpy().copy()
+    du0[o:o + C + 1, o:o + C + 1, o:o + C + 1] += muv.cpu().numpy()
+    s.close()
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    ref, vh, uf = orc.forward(g, sig.ravel(), nt, dt, omega=wl.omega, u0=u0, um1=um1, want_vhist=True,
+                              want_ufinal=True)
+    _, du0_ref, _ = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=wl.omega, u0=u0, um1=um1, want_dinit=True)
+    errs = {"trace": rel(obs, ref), "u_final": rel(u, uf), "v_final": rel(v, vh[nt]),
+            "du0": rel(du0.ravel(), du0_ref)}
+    print(f"[fullsize] {name} errors {errs}", flush=True)
+    return errs
+
+
+def test_fullsize_fp64_cg256(env, orc):
+    """256^3 cells, FEM 96^3 (5.3M tetrahedra), FP64: the benchmark's
+    configuration (fields beyond the last-level cache: non-temporal hints)."""
+    e = _short(env, orc, "cg256", False, 24, 0)
+    assert max(e.values()) <= TOL64
+
+
+def test_fullsize_fp64_cg256_gradient(env, orc):
+    """Gradient time-integral at 256^3 / FEM 96^3 in FP64 over 400 steps, long
+    enough for the adjoint of a random trace cotangent to cross the 80 cells
+    between the trace face and the FEM box and reach the eligible cubes while
+    the forward field there (from random initial levels) is non-zero."""
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    wl, sig, dt = _setup("cg256", 2)
+    n, nt = wl.n, 400
+    rng = np.random.default_rng(7)
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = u0 + 0.05 * rng.standard_normal((n + 1,) * 3)
+    r = rng.standard_normal((nt + 1, n + 1, n + 1))
+    print(f"[fullsize] cg256 gradient nt={nt}", flush=True)
+    s = Solver(n, C=wl.C)
+    s.set_initial(_t(torch, u0), _t(torch, um1))
+    s.forward(_t(torch, sig), nt, dt, omega=wl.omega)
+    s.adjoint(_t(torch, r), mode=1)
+    grad, _ = s.gradient(want_J=False)
+    grad = grad.cpu().numpy().ravel()
+    s.close()
+    g = orc.Geometry(n, fem_o=wl.o, fem_c=wl.C)
+    ref = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=wl.omega, u0=u0, um1=um1)
+    nz = np.count_nonzero(ref)
+    print(f"[fullsize] cg256 gradient rel {rel(grad, ref):.3e}, nonzero cubes {nz}, |ref| {np.linalg.norm(ref):.3e}",
+          flush=True)
+    assert nz > 1000 and np.linalg.norm(ref) > 1e-12
+    assert rel(grad, ref) <= TOL64
+
+
+def test_fullsize_fp32_diff384(env, orc):
+    """384^3 cells, FEM 128^3, FP32 fields (the differentiation workload's
+    geometry and conductivity generator), short horizon."""
+    e = _short(env, orc, "diff384", True, 16, 1)
+    assert e["trace"] <= 1e-5 and e["u_final"] <= 1e-5 and e["v_final"] <= 1e-5 and e["du0"] <= 1e-5
