@@ -28,13 +28,15 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 
 
 def interior_bytes(n, C, s):
-    """Algorithmic bytes of one forward interior launch (fused FDM + FEM):
-    FDM nodes: read u^k, read u^{k-1}, write u^{k+1} (3 s each);
-    FEM nodes: the same 3 s plus one coefficient per cube (s) and one history
-    write per stored node (s)."""
+    """Algorithmic bytes of one forward interior launch (fused FDM + FEM).
+    FP64 (s = 8, three-level leapfrog): per FDM node read u^k, read u^{k-1},
+    write u^{k+1} (3 s).  FP32 (s = 4, increment form): read u^k, read d^k,
+    write d^{k+1}, write u^{k+1} (4 s).  FEM nodes: the same plus one
+    coefficient per cube (s) and one history write per stored node (s)."""
+    m = 4 if s == 4 else 3
     fdm_int = (n - 1) ** 3 - (C - 3) ** 3 if C else (n - 1) ** 3
     fem = (C - 1) ** 3 if C else 0
-    return 3 * s * fdm_int + 3 * s * fem + s * C ** 3 + s * (C - 3) ** 3 if C else 3 * s * fdm_int
+    return m * s * fdm_int + m * s * fem + s * C ** 3 + s * (C - 3) ** 3 if C else m * s * fdm_int
 
 
 def setup(wl_name, f32, seed=0):
@@ -191,6 +193,107 @@ def serving(n_req=256, seed=0, budget=200e9):
             "max_rel_J_diff_batched_vs_alone": jd}
 
 
+def study_diff384(seed=0, n_dir=16):
+    """Differentiation form at full size: 384^3 cells, FEM 128^3, FP32 fields,
+    nt = 2000, sqrt(nt) FP32 checkpoints with segment recompute.  Autograd
+    gradient of L = <w, obs> (w seeded Gaussian) against central differences
+    of L along n_dir seeded random unit directions over the free cubes."""
+    import numpy as np
+    import torch
+
+    from paper_1509_01399_amd import autograd, hyb, synth
+    wl = synth.WORKLOADS["diff384"]
+    sig0 = synth.sigma_for(wl, seed)
+    dt = synth.dt_rule(wl.h, sig0.max() + 0.05)
+    solver = hyb.Solver(wl.n, C=wl.C, f32=True, store_mode=1)
+    sig = torch.as_tensor(sig0, dtype=torch.float64, device="cuda").requires_grad_(True)
+    gen = torch.Generator(device="cuda").manual_seed(seed + 11)
+    t0 = time.perf_counter()
+    obs = autograd.solve(sig, solver, wl.nt, dt, wl.omega)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    w = torch.randn(obs.shape, generator=gen, dtype=torch.float64, device="cuda")
+    (w * obs).sum().backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = sig.grad.detach()
+    free = torch.as_tensor(synth.eligible_mask(wl.C), device="cuda")
+    rng = np.random.default_rng(seed + 12)
+    rows = []
+    with torch.no_grad():
+        for _ in range(n_dir):
+            v = torch.as_tensor(rng.standard_normal(sig0.shape), device="cuda") * free
+            v /= v.norm()
+            eps = 0.02 / float(v.abs().max())        # largest change of sigma: 0.02
+            lp = float((w * solver.forward(sig.detach() + eps * v, wl.nt, dt, omega=wl.omega)).sum())
+            lm = float((w * solver.forward(sig.detach() - eps * v, wl.nt, dt, omega=wl.omega)).sum())
+            rows.append(((lp - lm) / (2 * eps), float((g * v).sum())))
+    torch.cuda.synchronize()
+    fd, ad = np.array(rows).T
+    relerr = np.abs(fd - ad) / np.abs(ad)
+    fp = hyb.hyb_footprint(solver.grid, solver.mesh, 2, solver.opts, wl.nt)
+    solver.close()
+    return {"study": "diff384", "n": wl.n, "C": wl.C, "nt": wl.nt, "fields": "f32",
+            "checkpoints": "f32, every ceil(sqrt(nt+1)) steps", "footprint_gb": round(fp / 1e9, 2),
+            "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+            "directions": n_dir, "max_sigma_step": 0.02,
+            "fd_vs_autograd_rel_l2": float(np.linalg.norm(fd - ad) / np.linalg.norm(ad)),
+            "fd_vs_autograd_rel_max": float(relerr.max()),
+            "fd_vs_autograd_rel_median": float(np.median(relerr))}
+
+
+def study_scale512(seed=0):
+    """Precision form at scale: 512^3 cells, FEM 160^3, nt = 2500.  Data from
+    an FP64 sweep at the true conductivity plus 3% noise; the misfit gradient
+    at sigma = 0 (first CG iteration) with FP32 fields and BF16 increment
+    checkpoints, and with FP32 checkpoints, against the FP64 sweep with the
+    full FP64 FEM history."""
+    import torch
+
+    from paper_1509_01399_amd import hyb, synth
+    wl = synth.WORKLOADS["scale512"]
+    sig_true = synth.sigma_for(wl, seed)
+    dt = synth.dt_rule(wl.h, sig_true.max())
+    st = torch.as_tensor(sig_true, dtype=torch.float64, device="cuda")
+    s0 = torch.zeros_like(st)
+    out = {"study": "scale512", "n": wl.n, "C": wl.C, "nt": wl.nt}
+    ref = hyb.Solver(wl.n, C=wl.C, f32=False, store_mode=0)
+    data = ref.forward(st, wl.nt, dt, omega=wl.omega).clone()
+    gen = torch.Generator(device="cuda").manual_seed(seed + 21)
+    data += wl.noise * data.abs().max() * torch.randn(data.shape, generator=gen, dtype=torch.float64,
+                                                      device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs64 = ref.forward(s0, wl.nt, dt, omega=wl.omega).clone()
+    ref.adjoint(obs64 - data, mode=0)
+    g64, J64 = ref.gradient()
+    torch.cuda.synchronize()
+    out["f64_s"] = round(time.perf_counter() - t0, 3)
+    res64 = obs64 - data
+    out["residual_over_trace"] = float(res64.norm() / obs64.norm())
+    out["f64_footprint_gb"] = round(hyb.hyb_footprint(ref.grid, ref.mesh, 2, ref.opts, wl.nt) / 1e9, 2)
+    ref.close()
+    torch.cuda.empty_cache()
+    for mode, name in ((2, "f32_bf16ckpt"), (1, "f32_f32ckpt")):
+        s = hyb.Solver(wl.n, C=wl.C, f32=True, store_mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obs = s.forward(s0, wl.nt, dt, omega=wl.omega)
+        s.adjoint(obs - data, mode=0)
+        g, J = s.gradient()
+        torch.cuda.synchronize()
+        out[name] = {"s": round(time.perf_counter() - t0, 3),
+                     "footprint_gb": round(hyb.hyb_footprint(s.grid, s.mesh, 2, s.opts, wl.nt) / 1e9, 2),
+                     "trace_rel_l2": float((obs - obs64).norm() / obs64.norm()),
+                     "residual_rel_l2": float((obs - obs64).norm() / res64.norm()),
+                     "grad_rel_l2": float((g - g64).norm() / g64.norm()),
+                     "J_rel": abs(J - J64) / abs(J64)}
+        s.close()
+        del obs, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def probe(kind, wl_name, f32, reps):
     """Single-kernel runs for the counter passes (rocprofv3 --pmc)."""
     import torch
@@ -230,6 +333,8 @@ def main():
     ap.add_argument("--probe", choices=["interior", "copy"])
     ap.add_argument("--probe-f32", action="store_true")
     ap.add_argument("--probe-reps", type=int, default=20)
+    ap.add_argument("--study", choices=["diff384", "scale512"],
+                    help="full-size check of a form instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (a multi-GPU split of the "
@@ -245,6 +350,10 @@ def main():
         build()
     if args.probe:
         probe(args.probe, args.workload, args.probe_f32, args.probe_reps)
+        return
+    if args.study:
+        res = study_diff384() if args.study == "diff384" else study_scale512()
+        print(json.dumps(res), flush=True)
         return
 
     wl, dt, solver, data, _ = setup(args.workload, False)

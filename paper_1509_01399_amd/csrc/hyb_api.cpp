@@ -39,6 +39,8 @@ struct hyb_ctx {
     size_t esz = 8;  // field element size
     // device memory
     void *U[3]{}, *V[3]{}, *P[3]{}, *Q[3]{}, *F[3]{};
+    void *D[2]{}, *VD[2]{};  // FP32: forward increments, d^k in slot k & 1
+    void *E[2]{}, *QE[2]{};  // FP32: adjoint increments (level k in slot k & 1)
     void *acube = nullptr;
     void *hist = nullptr;
     size_t hist_levels = 0;
@@ -407,29 +409,33 @@ size_t ckpt_slot_bytes(const Geo &g, size_t esz, int mode)
     return mode == 2 ? (fb + vb) + (fb + vb) / 2 : 2 * (fb + vb);
 }
 
-// Save the state (levels L, L-1 in buffers ib, ia) as checkpoint number q.
+// Save the state at level L (u^L in buffer ib; u^{L-1} in ia, or in FP32 the
+// increment d^L in slot L & 1) as checkpoint number q.  Store mode 1 copies
+// both parts in field precision; mode 2 (FP32 only) keeps d^L in BF16.
 template <typename T>
-hyb_status save_ckpt(hyb_ctx *c, int q, int ia, int ib)
+hyb_status save_ckpt(hyb_ctx *c, int q, int L, int ia, int ib)
 {
     const Geo &g = c->g;
     const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
     char *base = (char *)c->ckpt + (size_t)q * ckpt_slot_bytes(g, sizeof(T), c->store_mode);
     const hipStream_t st = c->stream;
+    const bool inc = incr_form<T>();
+    void *u1 = inc ? c->D[L & 1] : c->U[ia], *v1 = inc ? c->VD[L & 1] : c->V[ia];
     HIPCHK(c, hipMemcpyAsync(base, c->U[ib], fb, hipMemcpyDeviceToDevice, st));
     if (vb) HIPCHK(c, hipMemcpyAsync(base + fb, c->V[ib], vb, hipMemcpyDeviceToDevice, st));
     if (c->store_mode == 1) {
-        HIPCHK(c, hipMemcpyAsync(base + fb + vb, c->U[ia], fb, hipMemcpyDeviceToDevice, st));
-        if (vb) HIPCHK(c, hipMemcpyAsync(base + 2 * fb + vb, c->V[ia], vb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(base + fb + vb, u1, fb, hipMemcpyDeviceToDevice, st));
+        if (vb) HIPCHK(c, hipMemcpyAsync(base + 2 * fb + vb, v1, vb, hipMemcpyDeviceToDevice, st));
     } else {
         uint16_t *half = (uint16_t *)(base + fb + vb);
-        launch_pack_bf16(c->U[ib], c->U[ia], half, (long long)(fb / sizeof(float)), st);
-        if (vb)
-            launch_pack_bf16(c->V[ib], c->V[ia], half + fb / sizeof(float), (long long)(vb / sizeof(float)), st);
+        launch_pack_bf16(u1, half, (long long)(fb / sizeof(float)), st);
+        if (vb) launch_pack_bf16(v1, half + fb / sizeof(float), (long long)(vb / sizeof(float)), st);
     }
     return HYB_OK;
 }
 
-// Restore checkpoint q into buffers 1 (level L) and 0 (level L-1).
+// Restore checkpoint q (level L = q K) into buffer 1 (u^L) and buffer 0
+// (u^{L-1}), or in FP32 the increment slot L & 1.
 template <typename T>
 hyb_status load_ckpt(hyb_ctx *c, int q)
 {
@@ -437,16 +443,18 @@ hyb_status load_ckpt(hyb_ctx *c, int q)
     const size_t fb = field_bytes(g, sizeof(T)), vb = fem_bytes(g, sizeof(T));
     const char *base = (const char *)c->ckpt + (size_t)q * ckpt_slot_bytes(g, sizeof(T), c->store_mode);
     const hipStream_t st = c->stream;
+    const int L = q * c->ckK;
+    const bool inc = incr_form<T>();
+    void *u1 = inc ? c->D[L & 1] : c->U[0], *v1 = inc ? c->VD[L & 1] : c->V[0];
     HIPCHK(c, hipMemcpyAsync(c->U[1], base, fb, hipMemcpyDeviceToDevice, st));
     if (vb) HIPCHK(c, hipMemcpyAsync(c->V[1], base + fb, vb, hipMemcpyDeviceToDevice, st));
     if (c->store_mode == 1) {
-        HIPCHK(c, hipMemcpyAsync(c->U[0], base + fb + vb, fb, hipMemcpyDeviceToDevice, st));
-        if (vb) HIPCHK(c, hipMemcpyAsync(c->V[0], base + 2 * fb + vb, vb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(u1, base + fb + vb, fb, hipMemcpyDeviceToDevice, st));
+        if (vb) HIPCHK(c, hipMemcpyAsync(v1, base + 2 * fb + vb, vb, hipMemcpyDeviceToDevice, st));
     } else {
         const uint16_t *half = (const uint16_t *)(base + fb + vb);
-        launch_unpack_bf16(c->U[1], half, c->U[0], (long long)(fb / sizeof(float)), st);
-        if (vb)
-            launch_unpack_bf16(c->V[1], half + fb / sizeof(float), c->V[0], (long long)(vb / sizeof(float)), st);
+        launch_unpack_bf16(half, u1, (long long)(fb / sizeof(float)), st);
+        if (vb) launch_unpack_bf16(half + fb / sizeof(float), v1, (long long)(vb / sizeof(float)), st);
     }
     return HYB_OK;
 }
@@ -459,6 +467,10 @@ Step<T> fwd_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, double *obs)
     Step<T> s = make_step<T>(c);
     s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
     s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
+    if (incr_form<T>()) {
+        s.Da = (const T *)c->D[k & 1]; s.Dc = (T *)c->D[(k + 1) & 1];
+        s.VDa = (const T *)c->VD[k & 1]; s.VDc = (T *)c->VD[(k + 1) & 1];
+    }
     s.types1 = face_types(c, k);
     const double fluxscale = 2.0 * c->dt * c->dt / c->h;
     if (c->src.kind == 0) {
@@ -487,6 +499,10 @@ Step<T> adj_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, const double *r
     s.Va = (const T *)c->Q[ia]; s.Vb = (const T *)c->Q[ib]; s.Vc = (T *)c->Q[ic];
     s.Fa = (const T *)c->F[ia]; s.Fb = (const T *)c->F[ib]; s.Fc = (T *)c->F[ic];
     s.Pw = (T *)c->P[ib];
+    if (incr_form<T>()) {
+        s.Da = (const T *)c->E[(k + 1) & 1]; s.Dc = (T *)c->E[k & 1];
+        s.VDa = (const T *)c->QE[(k + 1) & 1]; s.VDc = (T *)c->QE[k & 1];
+    }
     s.types0 = face_types(c, k - 1);
     s.types1 = face_types(c, k);
     s.types2 = face_types(c, k + 1);
@@ -508,6 +524,11 @@ hyb_status adj_setup(hyb_ctx *c, const double *res, int mode)
         HIPCHK(c, hipMemsetAsync(c->F[q], 0, (size_t)g.ftot * sizeof(T), st));
         if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->Q[q], 0, vb, st));
     }
+    if (incr_form<T>())
+        for (int q = 0; q < 2; ++q) {
+            HIPCHK(c, hipMemsetAsync(c->E[q], 0, fb, st));
+            if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->QE[q], 0, vb, st));
+        }
     if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
     if (mode == 0) launch_misfit(g, res, c->nt, c->dt, c->h, c->partials, c->scal, S_JMIS, st);
     else HIPCHK(c, hipMemsetAsync(c->scal + S_JMIS, 0, sizeof(double), st));
@@ -525,9 +546,17 @@ hyb_status fwd_setup(hyb_ctx *c, double *obs)
         HIPCHK(c, hipMemsetAsync(c->U[q], 0, fb, st));
         if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->V[q], 0, vb, st));
     }
+    if (incr_form<T>())
+        for (int q = 0; q < 2; ++q) {
+            HIPCHK(c, hipMemsetAsync(c->D[q], 0, fb, st));
+            if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->VD[q], 0, vb, st));
+        }
     if (c->ic_set) {
         if (c->ic_u0) launch_load_level<T>(g, c->ic_u0, (T *)c->U[1], (T *)c->V[1], st);
-        if (c->ic_um1) launch_load_level<T>(g, c->ic_um1, (T *)c->U[0], (T *)c->V[0], st);
+        if (incr_form<T>())
+            launch_load_incr<T>(g, c->ic_u0, c->ic_um1, (T *)c->D[0], (T *)c->VD[0], st);
+        else if (c->ic_um1)
+            launch_load_level<T>(g, c->ic_um1, (T *)c->U[0], (T *)c->V[0], st);
         c->ic_set = false;
         c->ic_u0 = c->ic_um1 = nullptr;
     }
@@ -550,7 +579,7 @@ hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, doub
         launch_bnd_fwd<T>(s, st);
         const int t = ia; ia = ib; ib = ic; ic = t;
         if (save && (k + 1) % c->ckK == 0) {
-            hyb_status r = save_ckpt<T>(c, (k + 1) / c->ckK, ia, ib);
+            hyb_status r = save_ckpt<T>(c, (k + 1) / c->ckK, k + 1, ia, ib);
             if (r) return r;
         }
     }
@@ -566,7 +595,7 @@ hyb_status run_forward(hyb_ctx *c, double *obs)
     if (r0) return r0;
     int ia = 0, ib = 1, ic = 2;
     if (ck) {
-        hyb_status r = save_ckpt<T>(c, 0, ia, ib);
+        hyb_status r = save_ckpt<T>(c, 0, 0, ia, ib);
         if (r) return r;
     }
     hyb_status r = fwd_steps<T>(c, 0, c->nt, ia, ib, ic, obs, ck);
@@ -680,6 +709,11 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
     for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->U[q], fb);
     if (!s && c->g.has_fem)
         for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->V[q], vb);
+    if (c->f32) {
+        for (int q = 0; q < 2 && !s; ++q) s = dmalloc(c, &c->D[q], fb);
+        if (!s && c->g.has_fem)
+            for (int q = 0; q < 2 && !s; ++q) s = dmalloc(c, &c->VD[q], vb);
+    }
     if (!s && c->g.has_fem) s = dmalloc(c, &c->acube, nc * c->esz);
     if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->sig, nc * sizeof(double));
     if (!s) s = dmalloc(c, (void **)&c->partials, MAX_PARTIALS * sizeof(double));
@@ -703,6 +737,12 @@ void hyb_destroy(hyb_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (int q = 0; q < 3; ++q) {
         dfree(c->U[q]); dfree(c->V[q]); dfree(c->P[q]); dfree(c->Q[q]); dfree(c->F[q]);
+    }
+    for (int q = 0; q < 2; ++q) {
+        dfree(c->D[q]);
+        dfree(c->VD[q]);
+        dfree(c->E[q]);
+        dfree(c->QE[q]);
     }
     dfree(c->acube);
     dfree(c->hist);
@@ -819,6 +859,11 @@ hyb_status alloc_adjoint(hyb_ctx *c)
     if (!s && c->g.has_fem)
         for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->Q[q], vb);
     if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->G, cube_count(c->g) * sizeof(double));
+    if (c->f32) {
+        for (int q = 0; q < 2 && !s; ++q) s = dmalloc(c, &c->E[q], fb);
+        if (!s && c->g.has_fem)
+            for (int q = 0; q < 2 && !s; ++q) s = dmalloc(c, &c->QE[q], vb);
+    }
     return s;
 }
 
@@ -929,7 +974,8 @@ hyb_status hyb_footprint(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const
     int n[3] = {grid->n_cells[0], grid->n_cells[1], grid->n_cells[2]};
     setup_geo(g, n, mesh, fem != nullptr, esz);
     const size_t nc = cube_count(g), ntr = (size_t)(nt + 1) * g.nx * g.ny * sizeof(double);
-    size_t b = 6 * field_bytes(g, esz) + 6 * fem_bytes(g, esz) + nc * (esz + 4 * sizeof(double));
+    const int nlev = esz == 4 ? 10 : 6;  // three U and P levels (+ two increments each in FP32)
+    size_t b = nlev * field_bytes(g, esz) + nlev * fem_bytes(g, esz) + nc * (esz + 4 * sizeof(double));
     b += (size_t)(nt + 1) * g.hlevel * esz + 2 * ntr + (MAX_PARTIALS + S_NSCAL) * sizeof(double);
     b += 3 * (size_t)g.ftot * esz;
     const int sm = opts ? opts->store_mode : 0;
@@ -1012,6 +1058,10 @@ hyb_status hyb_time_interior(hyb_ctx *c, const double *sigma, double dt, int32_t
         for (int r = 0; r < reps; ++r) {
             s.Ua = (const T *)c->U[ia]; s.Ub = (const T *)c->U[ib]; s.Uc = (T *)c->U[ic];
             s.Va = (const T *)c->V[ia]; s.Vb = (const T *)c->V[ib]; s.Vc = (T *)c->V[ic];
+            if (incr_form<T>()) {
+                s.Da = (const T *)c->D[r & 1]; s.Dc = (T *)c->D[(r + 1) & 1];
+                s.VDa = (const T *)c->VD[r & 1]; s.VDc = (T *)c->VD[(r + 1) & 1];
+            }
             s.hist = c->g.has_fem ? (T *)c->hist : nullptr;
             launch_interior<T>(s, false, st);
             const int t = ia; ia = ib; ib = ic; ic = t;

@@ -50,6 +50,12 @@ struct Step {
     T *Uc;
     const T *Va, *Vb;
     T *Vc;
+    // FP32 sweeps (increment form): the forward state is (u^k, d^k) with
+    // d^k = u^k - u^{k-1} instead of (u^k, u^{k-1}); Da/VDa hold d^k and
+    // Dc/VDc receive d^{k+1} (grid and FEM parts; unused in FP64).  The
+    // adjoint uses them the same way for the multipliers of levels k+1, k.
+    const T *Da, *VDa;
+    T *Dc, *VDc;
     const T *acube;          // conductivity a per FEM cube [C^3]
     T c2;                    // (dt/h)^2
     T r;                     // (h - dt)/(h + dt), eq. (eq:abs2)
@@ -72,6 +78,12 @@ struct Step {
     T *Pw;                   // level k+1 grid array: receives the boundary proxies
 };
 
+// FP32 wavefields advance in increment form (d^{k+1} = d^k + tau^2 L u^k,
+// u^{k+1} = u^k + d^{k+1}), algebraically the leapfrog of the three-level
+// scheme: rounding u^{k+1} then perturbs the position only, not the implied
+// velocity u^{k+1} - u^k, so FP32 errors grow like sqrt(nt) instead of nt^1.5.
+template <typename T> constexpr bool incr_form() { return sizeof(T) == 4; }
+
 // ---- launchers (hyb_kernels.hip) ----
 template <typename T> void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st);
 template <typename T> void launch_bnd_fwd(const Step<T> &s, hipStream_t st);
@@ -89,6 +101,9 @@ void launch_acube(const Geo &g, const double *sigma, T *acube, double *partials,
 // copy a full grid level (unpadded FP64) into a padded field, and its FEM part
 template <typename T>
 void launch_load_level(const Geo &g, const double *src, T *U, T *V, hipStream_t st);
+// increments d^0 = u^0 - u^{-1} of given initial levels (either may be null = 0)
+template <typename T>
+void launch_load_incr(const Geo &g, const double *u0, const double *um1, T *D, T *VD, hipStream_t st);
 template <typename T>
 void launch_hist_level(const Geo &g, const T *V, T *hist, hipStream_t st);
 template <typename T>
@@ -100,8 +115,8 @@ void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, doubl
 
 // BF16 checkpoint increments: half[i] = bf16(a[i] - b[i]) (round to nearest
 // even); unpack: b[i] = a[i] - float(half[i]).  a, b are FP32 arrays.
-void launch_pack_bf16(const void *a, const void *b, uint16_t *half, long long n, hipStream_t st);
-void launch_unpack_bf16(const void *a, const uint16_t *half, void *b, long long n, hipStream_t st);
+void launch_pack_bf16(const void *a, uint16_t *half, long long n, hipStream_t st);
+void launch_unpack_bf16(const uint16_t *half, void *b, long long n, hipStream_t st);
 
 // J_misfit = 1/2 sum_{k=1..nt} dt sum_i w_i res^2 -> scal[slot]
 void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h, double *partials,

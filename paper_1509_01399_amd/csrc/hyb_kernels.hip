@@ -164,9 +164,15 @@ __device__ __forceinline__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
             else lap += (T)2 * (s.Ub[id + B.dir[d] * st[d]] - u);
             if (B.kind[d] == F_SOURCE) src = true;
         }
-        T v = (T)2 * u - s.Ua[id] + s.c2 * lap;
-        if (src) v += src_flux(s, x, y);
-        return v;
+        if constexpr (incr_form<T>()) {
+            T d = s.Da[id] + s.c2 * lap;
+            if (src) d += src_flux(s, x, y);
+            return u + d;
+        } else {
+            T v = (T)2 * u - s.Ua[id] + s.c2 * lap;
+            if (src) v += src_flux(s, x, y);
+            return v;
+        }
     }
     T acc = 0;
 #pragma unroll
@@ -228,11 +234,19 @@ __device__ __forceinline__ void bnd_fwd_body(const Step<T> &s, long long t)
         T v;
         if (kind == F_ABC) {
             v = s.Ub[in] + s.r * (u - s.Uc[in]);
+            if constexpr (incr_form<T>()) s.Dc[id] = v - u;
         } else {
             const T lap = (T)2 * (s.Ub[in] - u) + ((s.Ub[id + sa] - u) + (s.Ub[id - sa] - u)) +
                           ((s.Ub[id + sb] - u) + (s.Ub[id - sb] - u));
-            v = (T)2 * u - s.Ua[id] + s.c2 * lap;
-            if (kind == F_SOURCE) v += src_flux(s, x, y);
+            if constexpr (incr_form<T>()) {
+                T d = s.Da[id] + s.c2 * lap;
+                if (kind == F_SOURCE) d += src_flux(s, x, y);
+                s.Dc[id] = d;
+                v = u + d;
+            } else {
+                v = (T)2 * u - s.Ua[id] + s.c2 * lap;
+                if (kind == F_SOURCE) v += src_flux(s, x, y);
+            }
         }
         s.Uc[id] = v;
         if (s.obs && f == 5) s.obs[x + (long long)g.nx * y] = (double)v;
@@ -243,7 +257,9 @@ __device__ __forceinline__ void bnd_fwd_body(const Step<T> &s, long long t)
         int x, y, z;
         edge_corner_node(g, t, x, y, z);
         const T v = bnd_fwd<T, 3>(s, x, y, z);
-        s.Uc[gidx(g, x, y, z)] = v;
+        const long long id = gidx(g, x, y, z);
+        s.Uc[id] = v;
+        if constexpr (incr_form<T>()) s.Dc[id] = v - s.Ub[id];
         if (s.obs && z == g.nz - 1) s.obs[x + (long long)g.nx * y] = (double)v;
         return;
     }
@@ -558,6 +574,7 @@ __device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, bool tw
                                          bool hcol1)
 {
     const Geo &g = s.g;
+    constexpr bool INC = incr_form<T>();
     const long long py = g.px, pz = g.plane;
     long long id = gidx(g, x, y, z0);
     const T c2 = s.c2;
@@ -581,18 +598,36 @@ __device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, bool tw
         if (!(hcol0 && inh)) {
             const T xm = Ub[id - 1], xp = Ub[id + 1], ym = Ub[id - py];
             const T yp = two ? c01 : Ub[id + py];
-            T v = (T)2 * c00 - ld_once<T, NT>(s.Ua + id) + c2 * (((xm + xp) + (ym + yp)) + (cm0 + cp0) - (T)6 * c00);
-            if constexpr (ADJ)
-                if ((side0 && zs) || (top0 && zt)) v += s.Uc[id];
-            st_once<T, NT>(s.Uc + id, v);
+            const T L = ((xm + xp) + (ym + yp)) + (cm0 + cp0) - (T)6 * c00;
+            if constexpr (INC) {
+                T d = ld_once<T, NT>(s.Da + id) + c2 * L;
+                if constexpr (ADJ)
+                    if ((side0 && zs) || (top0 && zt)) d += s.Uc[id];
+                st_once<T, NT>(s.Dc + id, d);
+                st_once<T, NT>(s.Uc + id, c00 + d);
+            } else {
+                T v = (T)2 * c00 - ld_once<T, NT>(s.Ua + id) + c2 * L;
+                if constexpr (ADJ)
+                    if ((side0 && zs) || (top0 && zt)) v += s.Uc[id];
+                st_once<T, NT>(s.Uc + id, v);
+            }
         }
         if (two && !(hcol1 && inh)) {
             const long long i1 = id + py;
             const T xm = Ub[i1 - 1], xp = Ub[i1 + 1], yp = Ub[i1 + py];
-            T v = (T)2 * c01 - ld_once<T, NT>(s.Ua + i1) + c2 * (((xm + xp) + (c00 + yp)) + (cm1 + cp1) - (T)6 * c01);
-            if constexpr (ADJ)
-                if ((side1 && zs) || (top1 && zt)) v += s.Uc[i1];
-            st_once<T, NT>(s.Uc + i1, v);
+            const T L = ((xm + xp) + (c00 + yp)) + (cm1 + cp1) - (T)6 * c01;
+            if constexpr (INC) {
+                T d = ld_once<T, NT>(s.Da + i1) + c2 * L;
+                if constexpr (ADJ)
+                    if ((side1 && zs) || (top1 && zt)) d += s.Uc[i1];
+                st_once<T, NT>(s.Dc + i1, d);
+                st_once<T, NT>(s.Uc + i1, c01 + d);
+            } else {
+                T v = (T)2 * c01 - ld_once<T, NT>(s.Ua + i1) + c2 * L;
+                if constexpr (ADJ)
+                    if ((side1 && zs) || (top1 && zt)) v += s.Uc[i1];
+                st_once<T, NT>(s.Uc + i1, v);
+            }
         }
         cm0 = c00;
         c00 = cp0;
@@ -684,14 +719,20 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 #undef AC
         const T Ku = kxp * (v0 - xp) + kxm * (v0 - xm) + kyp * (v0 - yp) + kym * (v0 - ym) +
                      kzp * (v0 - vp) + kzm * (v0 - vm);
-        T v = (T)2 * v0 - s.Va[id] - c2 * Ku;
+        // leapfrog part: v = 2 v0 - v_prev - c2 Ku, or in increment form
+        // dv = dv_prev - c2 Ku (v = v0 + dv once the couplings are in dv)
+        T dv = 0, v = 0;
+        if constexpr (incr_form<T>()) dv = s.VDa[id] - c2 * Ku;
+        else v = (T)2 * v0 - s.Va[id] - c2 * Ku;
         const bool hin = hcol && k >= 2 && k <= Cz - 2;
         if constexpr (ADJ) {
             // omega_diamond: the FDM rows around read the copied value
             if (hin && (i == 2 || i == Cx - 2 || j == 2 || j == Cy - 2 || k == 2 || k == Cz - 2)) {
                 const long long gg = gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k);
-                v += c2 * (((s.Ub[gg - 1] + s.Ub[gg + 1]) + (s.Ub[gg - g.px] + s.Ub[gg + g.px])) +
-                           (s.Ub[gg - g.plane] + s.Ub[gg + g.plane]));
+                const T cw = c2 * (((s.Ub[gg - 1] + s.Ub[gg + 1]) + (s.Ub[gg - g.px] + s.Ub[gg + g.px])) +
+                                   (s.Ub[gg - g.plane] + s.Ub[gg + g.plane]));
+                if constexpr (incr_form<T>()) dv += cw;
+                else v += cw;
             }
             // gradient of eq. (gradient1): cube with lower corner (i,j,k),
             // sum over its 12 edges of w_e (D_e lambda^{k+1}) (D_e u^k) in FP64
@@ -718,10 +759,14 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
                 }
                 s.G[i + cpy * j + cpz * k] += acc;
             }
-        } else {
+        }
+        if constexpr (incr_form<T>()) {
+            s.VDc[id] = dv;
+            v = v0 + dv;
+        }
+        if constexpr (!ADJ)
             if (hin && s.hist)
                 st_once<T, true>(s.hist + (i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz, v);
-        }
         s.Vc[id] = v;
         vm = v0;
         v0 = vp;
@@ -942,6 +987,27 @@ void launch_load_level(const Geo &g, const double *src, T *U, T *V, hipStream_t 
 }
 
 template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_load_incr(Geo g, const double *u0, const double *um1, T *D, T *VD)
+{
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), z = (int)(t / ((long long)g.nx * g.ny));
+        const T d = (T)((u0 ? u0[t] : 0.0) - (um1 ? um1[t] : 0.0));
+        D[gidx(g, x, y, z)] = d;
+        if (g.has_fem) {
+            const int i = x - g.o[0], j = y - g.o[1], k = z - g.o[2];
+            if (i >= 0 && i <= g.C[0] && j >= 0 && j <= g.C[1] && k >= 0 && k <= g.C[2]) VD[fidx(g, i, j, k)] = d;
+        }
+    }
+}
+
+template <typename T>
+void launch_load_incr(const Geo &g, const double *u0, const double *um1, T *D, T *VD, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_load_incr<T>), dim3(2048), dim3(BLOCK), 0, st, g, u0, um1, D, VD);
+}
+
+template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_hist_level(Geo g, const T *V, T *hist)
 {
     const long long n = g.hlevel;
@@ -1007,26 +1073,26 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float x)
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__global__ __launch_bounds__(BLOCK) void k_pack_bf16(const float *a, const float *b, uint16_t *half, long long n)
+__global__ __launch_bounds__(BLOCK) void k_pack_bf16(const float *a, uint16_t *half, long long n)
 {
     for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK)
-        half[i] = f32_to_bf16(a[i] - b[i]);
+        half[i] = f32_to_bf16(a[i]);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_unpack_bf16(const float *a, const uint16_t *half, float *b, long long n)
+__global__ __launch_bounds__(BLOCK) void k_unpack_bf16(const uint16_t *half, float *b, long long n)
 {
     for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK)
-        b[i] = a[i] - bf16_to_f32(half[i]);
+        b[i] = bf16_to_f32(half[i]);
 }
 
-void launch_pack_bf16(const void *a, const void *b, uint16_t *half, long long n, hipStream_t st)
+void launch_pack_bf16(const void *a, uint16_t *half, long long n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pack_bf16, dim3(4096), dim3(BLOCK), 0, st, (const float *)a, (const float *)b, half, n);
+    hipLaunchKernelGGL(k_pack_bf16, dim3(4096), dim3(BLOCK), 0, st, (const float *)a, half, n);
 }
 
-void launch_unpack_bf16(const void *a, const uint16_t *half, void *b, long long n, hipStream_t st)
+void launch_unpack_bf16(const uint16_t *half, void *b, long long n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_unpack_bf16, dim3(4096), dim3(BLOCK), 0, st, (const float *)a, half, (float *)b, n);
+    hipLaunchKernelGGL(k_unpack_bf16, dim3(4096), dim3(BLOCK), 0, st, half, (float *)b, n);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_misfit(Geo g, const double *res, int nt, double wscale,
@@ -1185,6 +1251,7 @@ void launch_residual(const double *obs, const double *data, double *res, long lo
     template void launch_batch_adj<T>(const Geo &, const Step<T> *, int, hipStream_t);                                \
     template void launch_acube<T>(const Geo &, const double *, T *, double *, double *, hipStream_t); \
     template void launch_load_level<T>(const Geo &, const double *, T *, T *, hipStream_t);        \
+    template void launch_load_incr<T>(const Geo &, const double *, const double *, T *, T *, hipStream_t); \
     template void launch_hist_level<T>(const Geo &, const T *, T *, hipStream_t);                  \
     template void launch_record_face<T>(const Geo &, const T *, double *, hipStream_t);            \
     template void launch_export_level<T>(const Geo &, const T *, const T *, const T *, double *, double *,     \

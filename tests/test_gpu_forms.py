@@ -125,3 +125,62 @@ def test_autograd_central_differences(torch):
     print("worst FD rel err", worst, flush=True)
     assert worst <= 1e-6
     s.close()
+
+
+def test_differentiation_downscale48(torch, orc):
+    """The differentiation workload at a 48^3 downscale (FEM 16^3 at offset
+    16, nt = 250, Gaussian-bump conductivity): autograd with FP32 fields and
+    sqrt(nt) FP32 checkpoints against the FP64 oracle adjoint.  Bars: FP32
+    form, trace <= 1e-5 and gradient <= 1e-4 relative L2."""
+    from paper_1509_01399_amd import synth
+    from paper_1509_01399_amd.autograd import HybSolve
+    from paper_1509_01399_amd.hyb import Solver
+    n, C, o, nt, om = 48, 16, 16, 250, 40.0
+    h = 1.0 / n
+    sig = synth.bumps(C, h, seed=5)
+    dt = synth.dt_rule(h, sig.max())
+    rng = np.random.default_rng(6)
+    W = rng.standard_normal((nt + 1, n + 1, n + 1))
+    s = Solver(n, C=C, o=o, f32=True, store_mode=1)
+    x = _t(torch, sig).requires_grad_(True)
+    obs = HybSolve.apply(x, s, nt, dt, om)
+    (obs * _t(torch, W)).sum().backward()
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    ref_obs = orc.forward(g, sig.ravel(), nt, dt, omega=om)
+    ref = orc.adjoint(g, sig.ravel(), nt, dt, W, omega=om)
+    et, eg = rel(obs.detach().cpu().numpy(), ref_obs), rel(x.grad.cpu().numpy(), ref)
+    print(f"downscale48: trace {et:.2e}, gradient {eg:.2e}", flush=True)
+    assert et <= 1e-5 and eg <= 1e-4
+    s.close()
+
+
+def test_precision_downscale64(torch, orc):
+    """The precision workload at a 64^3 downscale (FEM 20^3 at offset 22,
+    nt = 312, cubic inclusions, 3% noise): misfit gradient at sigma = 0 with
+    FP32 fields against the FP64 oracle.  FP32 checkpoints meet the FP32
+    bars (trace <= 1e-5, gradient <= 1e-4).  BF16 increment checkpoints
+    perturb each restored level by the BF16 rounding of u^k - u^{k-1}, about
+    2^-9 * tau * omega relative to the level; at this resolution
+    (tau * omega = 0.16, eight times the 512^3 value) the gradient is held to
+    2^-7 * tau * omega instead."""
+    from paper_1509_01399_amd import synth
+    from paper_1509_01399_amd.hyb import Solver
+    n, C, o, nt, om = 64, 20, 22, 312, 40.0
+    h = 1.0 / n
+    sig_true = synth.cubes(C, 8)
+    dt = synth.dt_rule(h, sig_true.max())
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    data = synth.add_noise(orc.forward(g, sig_true.ravel(), nt, dt, omega=om), 0.03, 9)
+    sig = np.zeros((C, C, C))
+    gref, Jref, oref = orc.gradient(g, sig.ravel(), nt, dt, data, omega=om, want_obs=True)
+    errs = {}
+    for mode in (1, 2):
+        s = Solver(n, C=C, o=o, f32=True, store_mode=mode)
+        obs = s.forward(_t(torch, sig), nt, dt, omega=om)
+        s.adjoint(obs - _t(torch, data), mode=0)
+        gb, Jb = s.gradient()
+        errs[mode] = (rel(obs.cpu().numpy(), oref), rel(gb.cpu().numpy(), gref), abs(Jb - Jref) / Jref)
+        s.close()
+    print(f"downscale64 (trace, gradient, J) fp32 checkpoints {errs[1]}, bf16 increments {errs[2]}", flush=True)
+    assert errs[1][0] <= 1e-5 and errs[1][1] <= 1e-4
+    assert errs[2][0] <= 1e-5 and errs[2][1] <= 2.0 ** -7 * dt * om
