@@ -194,10 +194,12 @@ def serving(n_req=256, seed=0, budget=200e9):
 
 
 def study_diff384(seed=0, n_dir=16):
-    """Differentiation form at full size: 384^3 cells, FEM 128^3, FP32 fields,
-    nt = 2000, sqrt(nt) FP32 checkpoints with segment recompute.  Autograd
-    gradient of L = <w, obs> (w seeded Gaussian) against central differences
-    of L along n_dir seeded random unit directions over the free cubes."""
+    """Differentiation form at full size: 384^3 cells, FEM 128^3, nt = 2000,
+    sqrt(nt) checkpoints with segment recompute.  Gradient of L = <w, obs>
+    (w seeded Gaussian) through the autograd Function, with FP64 and with
+    FP32 fields, against central differences of L along n_dir seeded random
+    unit directions over the free cubes, the differences taken with FP64
+    forward solves (largest change of sigma 0.02)."""
     import numpy as np
     import torch
 
@@ -205,41 +207,53 @@ def study_diff384(seed=0, n_dir=16):
     wl = synth.WORKLOADS["diff384"]
     sig0 = synth.sigma_for(wl, seed)
     dt = synth.dt_rule(wl.h, sig0.max() + 0.05)
-    solver = hyb.Solver(wl.n, C=wl.C, f32=True, store_mode=1)
-    sig = torch.as_tensor(sig0, dtype=torch.float64, device="cuda").requires_grad_(True)
     gen = torch.Generator(device="cuda").manual_seed(seed + 11)
-    t0 = time.perf_counter()
-    obs = autograd.solve(sig, solver, wl.nt, dt, wl.omega)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    w = torch.randn(obs.shape, generator=gen, dtype=torch.float64, device="cuda")
-    (w * obs).sum().backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    g = sig.grad.detach()
+    w = None
+    out = {"study": "diff384", "n": wl.n, "C": wl.C, "nt": wl.nt, "directions": n_dir, "max_sigma_step": 0.02,
+           "checkpoints": "every ceil(sqrt(nt+1)) steps, field precision"}
+    grads = {}
+    for f32 in (False, True):
+        solver = hyb.Solver(wl.n, C=wl.C, f32=f32, store_mode=1)
+        sig = torch.as_tensor(sig0, dtype=torch.float64, device="cuda").requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obs = autograd.solve(sig, solver, wl.nt, dt, wl.omega)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if w is None:
+            w = torch.randn(obs.shape, generator=gen, dtype=torch.float64, device="cuda")
+        (w * obs).sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        key = "f32" if f32 else "f64"
+        grads[key] = sig.grad.detach().clone()
+        out[key] = {"forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+                    "footprint_gb": round(hyb.hyb_footprint(solver.grid, solver.mesh, 2, solver.opts, wl.nt) / 1e9,
+                                          2)}
+        if f32:
+            solver.close()
+        else:
+            fd_solver = solver
+        del obs
     free = torch.as_tensor(synth.eligible_mask(wl.C), device="cuda")
     rng = np.random.default_rng(seed + 12)
     rows = []
     with torch.no_grad():
+        base = torch.as_tensor(sig0, dtype=torch.float64, device="cuda")
         for _ in range(n_dir):
             v = torch.as_tensor(rng.standard_normal(sig0.shape), device="cuda") * free
             v /= v.norm()
-            eps = 0.02 / float(v.abs().max())        # largest change of sigma: 0.02
-            lp = float((w * solver.forward(sig.detach() + eps * v, wl.nt, dt, omega=wl.omega)).sum())
-            lm = float((w * solver.forward(sig.detach() - eps * v, wl.nt, dt, omega=wl.omega)).sum())
-            rows.append(((lp - lm) / (2 * eps), float((g * v).sum())))
-    torch.cuda.synchronize()
-    fd, ad = np.array(rows).T
-    relerr = np.abs(fd - ad) / np.abs(ad)
-    fp = hyb.hyb_footprint(solver.grid, solver.mesh, 2, solver.opts, wl.nt)
-    solver.close()
-    return {"study": "diff384", "n": wl.n, "C": wl.C, "nt": wl.nt, "fields": "f32",
-            "checkpoints": "f32, every ceil(sqrt(nt+1)) steps", "footprint_gb": round(fp / 1e9, 2),
-            "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
-            "directions": n_dir, "max_sigma_step": 0.02,
-            "fd_vs_autograd_rel_l2": float(np.linalg.norm(fd - ad) / np.linalg.norm(ad)),
-            "fd_vs_autograd_rel_max": float(relerr.max()),
-            "fd_vs_autograd_rel_median": float(np.median(relerr))}
+            eps = 0.02 / float(v.abs().max())
+            lp = float((w * fd_solver.forward(base + eps * v, wl.nt, dt, omega=wl.omega)).sum())
+            lm = float((w * fd_solver.forward(base - eps * v, wl.nt, dt, omega=wl.omega)).sum())
+            rows.append(((lp - lm) / (2 * eps), float((grads["f64"] * v).sum()), float((grads["f32"] * v).sum())))
+    fd_solver.close()
+    fd, a64, a32 = np.array(rows).T
+    for key, a in (("f64", a64), ("f32", a32)):
+        out[key]["fd_vs_autograd_rel_l2"] = float(np.linalg.norm(fd - a) / np.linalg.norm(fd))
+        out[key]["fd_vs_autograd_rel_max"] = float((np.abs(fd - a) / np.abs(fd)).max())
+    out["f32_vs_f64_gradient_rel_l2"] = float((grads["f32"] - grads["f64"]).norm() / grads["f64"].norm())
+    return out
 
 
 def study_scale512(seed=0):

@@ -787,12 +787,15 @@ __global__ __launch_bounds__(BLOCK) void k_interior(Step<T> s)
     else if constexpr (!ADJ) fem_tile<T, false>(s, b - nf);
 }
 
-// Non-temporal hints pay when the three field levels of all slots of a
-// launch exceed what the 256 MB last-level cache keeps (measured: they slow
-// a cache-resident 257^3 FP32 sweep by a third and speed up larger ones).
+// Non-temporal hints pay when the field arrays a step streams (three levels,
+// or level pair + increment pair in the FP32 increment form) of all slots of
+// a launch exceed what the 256 MB last-level cache keeps (measured: they slow
+// a cache-resident 257^3 sweep of three FP32 arrays by a third and speed up
+// larger ones).
 static bool stream_nt(const Geo &g, size_t esz, int slots)
 {
-    return 3.0 * (double)g.plane * g.nz * esz * slots > 224.0 * (1 << 20);
+    const double arrays = esz == 4 ? 4.0 : 3.0;
+    return arrays * (double)g.plane * g.nz * esz * slots > 224.0 * (1 << 20);
 }
 
 template <typename T>
