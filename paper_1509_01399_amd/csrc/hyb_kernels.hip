@@ -578,7 +578,12 @@ __device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, bool tw
     const long long py = g.px, pz = g.plane;
     long long id = gidx(g, x, y, z0);
     const T c2 = s.c2;
-    const T *Ub = s.Ub;
+    // distinct arrays: the loads of both rows can be issued before either
+    // row is stored
+    const T *__restrict__ Ub = s.Ub;
+    const T *__restrict__ Ua = INC ? s.Da : s.Ua;  // u^{k-1}, or d^k in the increment form
+    T *__restrict__ Uc = s.Uc;
+    T *__restrict__ Dc = s.Dc;
     // adjoint: rows on omega_o.  A column on an x or y face of the box meets
     // it for o <= z <= o+C, a column inside the box at z = o and z = o+C.
     const int i = x - g.o[0], j0 = y - g.o[1], C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
@@ -590,43 +595,46 @@ __device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, bool tw
     T cm0 = Ub[id - pz], c00 = Ub[id];
     T cm1 = two ? Ub[id + py - pz] : (T)0, c01 = two ? Ub[id + py] : (T)0;
     for (int z = z0; z < z1; ++z, id += pz) {
-        const T cp0 = Ub[id + pz];
-        const T cp1 = two ? Ub[id + py + pz] : (T)0;
+        const long long i1 = id + py;
         const bool inh = z >= g.hlo[2] && z <= g.hhi[2];
+        const bool do0 = !(hcol0 && inh), do1 = two && !(hcol1 && inh);
         const int kz = z - g.o[2];
         const bool zs = kz >= 0 && kz <= C2, zt = kz == 0 || kz == C2;
-        if (!(hcol0 && inh)) {
-            const T xm = Ub[id - 1], xp = Ub[id + 1], ym = Ub[id - py];
-            const T yp = two ? c01 : Ub[id + py];
-            const T L = ((xm + xp) + (ym + yp)) + (cm0 + cp0) - (T)6 * c00;
+        const bool om0 = ADJ && ((side0 && zs) || (top0 && zt)), om1 = ADJ && ((side1 && zs) || (top1 && zt));
+        // all loads of the plane first
+        const T cp0 = Ub[id + pz];
+        const T cp1 = two ? Ub[i1 + pz] : (T)0;
+        T xm0 = 0, xp0 = 0, ym0 = 0, yp0 = c01, ua0 = 0, w0 = 0;
+        T xm1 = 0, xp1 = 0, yp1 = 0, ua1 = 0, w1 = 0;
+        if (do0) {
+            xm0 = Ub[id - 1]; xp0 = Ub[id + 1]; ym0 = Ub[id - py];
+            if (!two) yp0 = Ub[id + py];
+            ua0 = ld_once<T, NT>(Ua + id);
+            if (om0) w0 = Uc[id];
+        }
+        if (do1) {
+            xm1 = Ub[i1 - 1]; xp1 = Ub[i1 + 1]; yp1 = Ub[i1 + py];
+            ua1 = ld_once<T, NT>(Ua + i1);
+            if (om1) w1 = Uc[i1];
+        }
+        if (do0) {
+            const T L = ((xm0 + xp0) + (ym0 + yp0)) + (cm0 + cp0) - (T)6 * c00;
             if constexpr (INC) {
-                T d = ld_once<T, NT>(s.Da + id) + c2 * L;
-                if constexpr (ADJ)
-                    if ((side0 && zs) || (top0 && zt)) d += s.Uc[id];
-                st_once<T, NT>(s.Dc + id, d);
-                st_once<T, NT>(s.Uc + id, c00 + d);
+                const T d = ua0 + c2 * L + w0;
+                st_once<T, NT>(Dc + id, d);
+                st_once<T, NT>(Uc + id, c00 + d);
             } else {
-                T v = (T)2 * c00 - ld_once<T, NT>(s.Ua + id) + c2 * L;
-                if constexpr (ADJ)
-                    if ((side0 && zs) || (top0 && zt)) v += s.Uc[id];
-                st_once<T, NT>(s.Uc + id, v);
+                st_once<T, NT>(Uc + id, (T)2 * c00 - ua0 + c2 * L + w0);
             }
         }
-        if (two && !(hcol1 && inh)) {
-            const long long i1 = id + py;
-            const T xm = Ub[i1 - 1], xp = Ub[i1 + 1], yp = Ub[i1 + py];
-            const T L = ((xm + xp) + (c00 + yp)) + (cm1 + cp1) - (T)6 * c01;
+        if (do1) {
+            const T L = ((xm1 + xp1) + (c00 + yp1)) + (cm1 + cp1) - (T)6 * c01;
             if constexpr (INC) {
-                T d = ld_once<T, NT>(s.Da + i1) + c2 * L;
-                if constexpr (ADJ)
-                    if ((side1 && zs) || (top1 && zt)) d += s.Uc[i1];
-                st_once<T, NT>(s.Dc + i1, d);
-                st_once<T, NT>(s.Uc + i1, c01 + d);
+                const T d = ua1 + c2 * L + w1;
+                st_once<T, NT>(Dc + i1, d);
+                st_once<T, NT>(Uc + i1, c01 + d);
             } else {
-                T v = (T)2 * c01 - ld_once<T, NT>(s.Ua + i1) + c2 * L;
-                if constexpr (ADJ)
-                    if ((side1 && zs) || (top1 && zt)) v += s.Uc[i1];
-                st_once<T, NT>(s.Uc + i1, v);
+                st_once<T, NT>(Uc + i1, (T)2 * c01 - ua1 + c2 * L + w1);
             }
         }
         cm0 = c00;
