@@ -1297,7 +1297,25 @@ hyb_status batch_plan_run(hyb_batch *b, int ticks, int32_t *n_first)
     // launches and transitions in planned order
     for (const Action &a : acts) {
         hyb_batch::Slot &sl = b->slots[a.slot];
-        if (a.kind == 0) {
+        if (a.kind == 0 && a.n == 1) {
+            // a group of one: the plain kernels with the arguments by value
+            const hipStream_t st = b->lanes[a.lane].st;
+            const char *hp = buf[a.lane].data() + a.offset;
+            auto one = [&](auto tag) {
+                using T = decltype(tag);
+                Step<T> s1;
+                std::memcpy(&s1, hp, sizeof s1);
+                if (a.adjoint) {
+                    launch_bnd_adj<T>(s1, st);
+                    launch_interior<T>(s1, true, st);
+                } else {
+                    launch_interior<T>(s1, false, st);
+                    launch_bnd_fwd<T>(s1, st);
+                }
+            };
+            if (a.f32) one(0.0f);
+            else one(0.0);
+        } else if (a.kind == 0) {
             const Geo &g = sl.c->g;
             const hipStream_t st = b->lanes[a.lane].st;
             if (a.f32) {
