@@ -119,3 +119,10 @@ def test_fullsize_fp32_diff384(env, orc):
     geometry and conductivity generator), short horizon."""
     e = _short(env, orc, "diff384", True, 16, 1)
     assert e["trace"] <= 1e-5 and e["u_final"] <= 1e-5 and e["v_final"] <= 1e-5 and e["du0"] <= 1e-5
+
+
+def test_fullsize_fp32_scale512(env, orc):
+    """512^3 cells, FEM 160^3 (24.6M tetrahedra), FP32 fields in increment
+    form with non-temporal hints: the largest configuration, short horizon."""
+    e = _short(env, orc, "scale512", True, 8, 2)
+    assert e["trace"] <= 1e-5 and e["u_final"] <= 1e-5 and e["v_final"] <= 1e-5 and e["du0"] <= 1e-5

@@ -248,3 +248,54 @@ def test_error_paths(env):
     sig[4, 4, 4] = 1.0
     s.forward(sig, 10, 0.25 * h)
     s.sync()
+
+
+# ------------------------------------------------------------ degenerate sizes
+
+def test_minimum_grid_pure_fdm(env, orc):
+    """Two cells per axis: one interior node, every other node on a face,
+    edge or corner; the source face and the absorbing rows meet at the
+    corners."""
+    torch = env
+    n, nt = 2, 12
+    dt = 0.25 / n
+    s = _solver(n, 0)
+    obs = s.forward(None, nt, dt, omega=30.0).cpu().numpy()
+    g = orc.Geometry(n)
+    ref = orc.forward(g, None, nt, dt, omega=30.0)
+    assert np.abs(ref).max() > 0
+    assert rel(obs, ref) <= TOL64
+
+
+@pytest.mark.parametrize("nt", [1, 60])
+def test_minimum_fem_box(env, orc, nt):
+    """The smallest FEM box the overlap allows (5 cells: one free cube) one
+    cell from the outer boundary, random initial levels so that the box is
+    active from the first step, and the shortest horizon (one step)."""
+    torch = env
+    n, C, o = 7, 5, 1
+    h = 1.0 / n
+    bc = (0, 0, 0, 0, 0, 2)
+    rng = np.random.default_rng(11 + nt)
+    sig = np.zeros((C, C, C))
+    sig[2, 2, 2] = 3.0
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = u0 + 0.1 * rng.standard_normal((n + 1,) * 3)
+    dt = 0.25 * h
+    s = _solver(n, C, o=o, bc=bc)
+    s.set_initial(_t(torch, u0), _t(torch, um1))
+    obs = s.forward(_t(torch, sig), nt, dt, omega=30.0).cpu().numpy()
+    g = orc.Geometry(n, bc=bc, fem_o=o, fem_c=C)
+    ref = orc.forward(g, sig.ravel(), nt, dt, omega=30.0, u0=u0, um1=um1)
+    assert rel(obs, ref) <= TOL64
+    r = rng.standard_normal(ref.shape)
+    s.adjoint(_t(torch, r), mode=1)
+    grad, _ = s.gradient(want_J=False)
+    dsig = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=30.0, u0=u0, um1=um1)
+    grad = grad.cpu().numpy().ravel()
+    if nt == 1:
+        # one step pairs u^0 with lambda^1, which lives on the trace face only
+        assert not np.any(dsig) and not np.any(grad)
+    else:
+        assert np.count_nonzero(dsig) == 1
+        assert rel(grad, dsig) <= TOL64
