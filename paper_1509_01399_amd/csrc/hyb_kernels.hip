@@ -83,56 +83,61 @@ __device__ __forceinline__ long long cidx(const Geo &g, int x, int y, int z)
 }
 
 // Boundary threads: face-interior nodes first (z faces, then y, then x; f is
-// the face), then the 12 edges, then the 8 corners.
+// the face), then the 12 edges, then the 8 corners.  The coordinates are
+// formed with selects: assigning them in branches that depend on the thread
+// makes the compiler keep them in scratch memory.
 __device__ __forceinline__ void face_node(const Geo &g, long long t, int &x, int &y, int &z, int &f)
 {
     const long long ax = g.nx - 2, ay = g.ny - 2, az = g.nz - 2;
-    const long long A45 = ax * ay, A23 = ax * az;
+    const long long A45 = ax * ay, A23 = ax * az, A01 = ay * az;
+    long long r, a1;
     if (t < 2 * A45) {
         f = t < A45 ? 4 : 5;
-        const long long r = t % A45;
-        x = 1 + (int)(r % ax); y = 1 + (int)(r / ax); z = f == 4 ? 0 : g.nz - 1;
-        return;
-    }
-    t -= 2 * A45;
-    if (t < 2 * A23) {
+        r = t % A45;
+        a1 = ax;
+    } else if (t - 2 * A45 < 2 * A23) {
+        t -= 2 * A45;
         f = t < A23 ? 2 : 3;
-        const long long r = t % A23;
-        x = 1 + (int)(r % ax); z = 1 + (int)(r / ax); y = f == 2 ? 0 : g.ny - 1;
-        return;
+        r = t % A23;
+        a1 = ax;
+    } else {
+        t -= 2 * A45 + 2 * A23;
+        f = t < A01 ? 0 : 1;
+        r = t % A01;
+        a1 = ay;
     }
-    t -= 2 * A23;
-    const long long A01 = ay * az;
-    f = t < A01 ? 0 : 1;
-    const long long r = t % A01;
-    y = 1 + (int)(r % ay); z = 1 + (int)(r / ay); x = f == 0 ? 0 : g.nx - 1;
+    // tangential positions in storage order, the normal coordinate fixed
+    const int p = 1 + (int)(r % a1), q = 1 + (int)(r / a1);
+    const int d = f >> 1;
+    const bool hi = f & 1;
+    x = d == 0 ? (hi ? g.nx - 1 : 0) : p;
+    y = d == 1 ? (hi ? g.ny - 1 : 0) : (d == 0 ? p : q);
+    z = d == 2 ? (hi ? g.nz - 1 : 0) : q;
 }
 
 __device__ __forceinline__ void edge_corner_node(const Geo &g, long long t, int &x, int &y, int &z)
 {
     const long long ex = g.nx - 2, ey = g.ny - 2, ez = g.nz - 2;
+    // a: axis of the edge (3 for corners); e: edge number on that axis (or
+    // the corner number); p: position along the edge
+    int a;
+    long long e, p = 0;
     if (t < 4 * ex) {
-        const int e = (int)(t / ex);
-        x = 1 + (int)(t % ex); y = (e & 1) ? g.ny - 1 : 0; z = (e & 2) ? g.nz - 1 : 0;
-        return;
+        a = 0; e = t / ex; p = 1 + t % ex;
+    } else if (t - 4 * ex < 4 * ey) {
+        t -= 4 * ex;
+        a = 1; e = t / ey; p = 1 + t % ey;
+    } else if (t - 4 * ex - 4 * ey < 4 * ez) {
+        t -= 4 * ex + 4 * ey;
+        a = 2; e = t / ez; p = 1 + t % ez;
+    } else {
+        a = 3; e = t - 4 * (ex + ey + ez);
     }
-    t -= 4 * ex;
-    if (t < 4 * ey) {
-        const int e = (int)(t / ey);
-        y = 1 + (int)(t % ey); x = (e & 1) ? g.nx - 1 : 0; z = (e & 2) ? g.nz - 1 : 0;
-        return;
-    }
-    t -= 4 * ey;
-    if (t < 4 * ez) {
-        const int e = (int)(t / ez);
-        z = 1 + (int)(t % ez); x = (e & 1) ? g.nx - 1 : 0; y = (e & 2) ? g.ny - 1 : 0;
-        return;
-    }
-    t -= 4 * ez;
-    x = (t & 1) ? g.nx - 1 : 0; y = (t & 2) ? g.ny - 1 : 0; z = (t & 4) ? g.nz - 1 : 0;
+    const bool bx = e & 1, by = a == 0 ? (e & 1) : (e & 2), bz = a == 3 ? (e & 4) : (e & 2);
+    x = a == 0 ? (int)p : (bx ? g.nx - 1 : 0);
+    y = a == 1 ? (int)p : (by ? g.ny - 1 : 0);
+    z = a == 2 ? (int)p : (bz ? g.nz - 1 : 0);
 }
-
-// ---------------------------------------------------------------- forward
 
 template <typename T>
 __device__ __forceinline__ T src_flux(const Step<T> &s, int x, int y)
@@ -358,21 +363,30 @@ __device__ __forceinline__ T bnd_adj(const Step<T> &s, int x, int y, int z)
 // bit 0 / bit 1 of e pick the low or high side of the other two axes).
 __device__ __forceinline__ void edge_node(const Geo &g, int e, int p, int &x, int &y, int &z)
 {
+    // plain selects: assigning the outputs in branches that depend on e
+    // makes the compiler keep them in scratch memory
     const int a = e >> 2, b0 = e & 1, b1 = (e >> 1) & 1;
-    if (a == 0) { x = p; y = b0 ? g.ny - 1 : 0; z = b1 ? g.nz - 1 : 0; }
-    else if (a == 1) { y = p; x = b0 ? g.nx - 1 : 0; z = b1 ? g.nz - 1 : 0; }
-    else { z = p; x = b0 ? g.nx - 1 : 0; y = b1 ? g.ny - 1 : 0; }
+    x = a == 0 ? p : (b0 ? g.nx - 1 : 0);
+    y = a == 1 ? p : ((a == 0 ? b0 : b1) ? g.ny - 1 : 0);
+    z = a == 2 ? p : (b1 ? g.nz - 1 : 0);
 }
 
 // Corners and edges of level k.  Only the two end nodes of each edge read a
 // corner of the same level: block 0 computes the 8 corners, then (after a
 // barrier) the 24 end nodes; all other edge nodes are independent.
+__host__ __device__ __forceinline__ int ec_blocks(const Geo &g)
+{
+    long long inner = 0;
+    for (int n : {g.nx, g.ny, g.nz}) inner += 4 * (long long)(n - 2 > 2 ? n - 4 : 0);
+    return (int)(1 + (inner + BLOCK - 1) / BLOCK);
+}
+
 template <typename T>
-__device__ __forceinline__ void bnd_adj_ec_body(const Step<T> &s)
+__device__ __forceinline__ void bnd_adj_ec_body(const Step<T> &s, int bid)
 {
     const Geo &g = s.g;
     const int L[3] = {g.nx - 2, g.ny - 2, g.nz - 2};
-    if (blockIdx.x == 0) {
+    if (bid == 0) {
         if (threadIdx.x < 8) {
             const int t = threadIdx.x;
             const int x = (t & 1) ? g.nx - 1 : 0, y = (t & 2) ? g.ny - 1 : 0, z = (t & 4) ? g.nz - 1 : 0;
@@ -381,7 +395,9 @@ __device__ __forceinline__ void bnd_adj_ec_body(const Step<T> &s)
         __syncthreads();
         if (threadIdx.x < 24) {
             const int e = threadIdx.x >> 1, end = threadIdx.x & 1;
-            const int Le = L[e >> 2];
+            // select, not a runtime index into the local array (which would
+            // put it in scratch memory)
+            const int Le = (e >> 2) == 0 ? L[0] : ((e >> 2) == 1 ? L[1] : L[2]);
             int x, y, z;
             edge_node(g, e, end ? Le : 1, x, y, z);
             const T mu = bnd_adj(s, x, y, z);
@@ -390,7 +406,7 @@ __device__ __forceinline__ void bnd_adj_ec_body(const Step<T> &s)
         return;
     }
     // inner edge nodes (positions 2..L-1)
-    long long t = (long long)(blockIdx.x - 1) * BLOCK + threadIdx.x;
+    long long t = (long long)(bid - 1) * BLOCK + threadIdx.x;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const long long m = L[a] > 2 ? L[a] - 2 : 0;
@@ -407,7 +423,7 @@ __device__ __forceinline__ void bnd_adj_ec_body(const Step<T> &s)
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec(Step<T> s)
 {
-    bnd_adj_ec_body<T>(s);
+    bnd_adj_ec_body<T>(s, blockIdx.x);
 }
 
 template <typename T, bool ADJ>
@@ -831,13 +847,10 @@ void launch_bnd_fwd(const Step<T> &s, hipStream_t st)
 template <typename T>
 void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 {
-    long long inner = 0;
-    for (int n : {s.g.nx, s.g.ny, s.g.nz}) inner += 4 * (long long)(n - 2 > 2 ? n - 4 : 0);
-    hipLaunchKernelGGL((k_bnd_adj_ec<T>), dim3((unsigned)(1 + (inner + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
+    hipLaunchKernelGGL((k_bnd_adj_ec<T>), dim3((unsigned)ec_blocks(s.g)), dim3(BLOCK), 0, st, s);
     const long long nb = s.g.n_fem_blocks + (s.g.n_fi + s.g.nwo + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL((k_bnd_adj<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, s);
 }
-
 // ---------------------------------------------------------------- batches
 //
 // Batched launches for the request server: blockIdx.y selects a slot whose
@@ -864,7 +877,7 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_fwd_b(const Step<T> *__restrict__
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec_b(const Step<T> *__restrict__ steps)
 {
-    bnd_adj_ec_body<T>(steps[blockIdx.y]);
+    bnd_adj_ec_body<T>(steps[blockIdx.y], blockIdx.x);
 }
 
 template <typename T>
@@ -888,10 +901,7 @@ void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t
 template <typename T>
 void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st)
 {
-    long long inner = 0;
-    for (int q : {g.nx, g.ny, g.nz}) inner += 4 * (long long)(q - 2 > 2 ? q - 4 : 0);
-    hipLaunchKernelGGL((k_bnd_adj_ec_b<T>), dim3((unsigned)(1 + (inner + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0,
-                       st, steps_dev);
+    hipLaunchKernelGGL((k_bnd_adj_ec_b<T>), dim3((unsigned)ec_blocks(g), n), dim3(BLOCK), 0, st, steps_dev);
     const long long nb = g.n_fem_blocks + (g.n_fi + g.nwo + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL((k_bnd_adj_b<T>), dim3((unsigned)nb, n), dim3(BLOCK), 0, st, steps_dev);
     const int nf = (g.n_fdm_blocks + 7) / 8 * 8;
