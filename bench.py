@@ -176,6 +176,9 @@ def serving(n_req=256, seed=0, budget=200e9):
     # paths run at their capacity and the throughputs compare the servers
     rate = 2.0 / mean_service
     reqs = serve.make_requests(n_req, seed, rate, sizes)
+    # resident contexts for every slot the scheduler may use, created before
+    # either timed run (the unbatched path reuses one per size)
+    pool.warm(serve.DEFAULT_CAPS, serve.shapes_of(reqs))
     rb, wb = serve.run_batched(reqs, data, budget=budget, pool=pool)
     ru, wu = serve.run_unbatched(reqs, data, pool=pool)
     peak = pool.used

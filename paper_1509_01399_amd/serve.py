@@ -114,6 +114,23 @@ class Pool:
     def release(self, e):
         e.busy = False
 
+    def warm(self, caps, shapes):
+        """Create the resident contexts up front, as a server does at start-up:
+        up to caps[n] per grid size n (shapes[n] = (C, nt)), smallest sizes
+        first, within the HBM budget."""
+        import torch
+        for n in sorted(caps):
+            C, nt = shapes[n]
+            have = len(self.entries.get(n, []))
+            for _ in range(caps[n] - have):
+                fp = self.footprint(n, C, nt)
+                if self.used + fp > self.budget:
+                    break
+                e = _Entry(n, C, self.f32, self.stream(n))
+                self.entries.setdefault(n, []).append(e)
+                self.used += fp
+        torch.cuda.synchronize()
+
     def close(self):
         self._torch.cuda.synchronize()
         for lst in self.entries.values():
@@ -157,10 +174,15 @@ def make_requests(n_req, seed, rate, sizes=synth.SERVE_SIZES):
 # Concurrency caps per grid size: enough same-size slots to fill the device
 # in one launch (a 64^3 step alone is launch-bound, a 256^3 step alone already
 # streams at HBM rate), few enough that every admitted request advances.
-DEFAULT_CAPS = {64: 32, 96: 16, 128: 8, 192: 4, 256: 4}
-# Time steps enqueued per scheduler pass: the host plans them in one go and
-# polls for finished requests between passes.
-DEFAULT_STEPS_PER_CALL = 64
+DEFAULT_CAPS = {64: 64, 96: 32, 128: 16, 192: 4, 256: 4}
+# Time steps enqueued per scheduler pass: the host plans them 32 at a time
+# and polls for finished requests between passes.
+DEFAULT_STEPS_PER_CALL = 128
+
+
+def shapes_of(requests):
+    """(C, nt) per grid size, for Pool.warm."""
+    return {r.n: (r.C, r.nt) for r in requests}
 
 
 def run_batched(requests, data, budget=200e9, max_slots=64, f32=True, keep_grads=False, pool=None,
