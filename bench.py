@@ -107,7 +107,8 @@ def cpu_baseline(wl, dt, window):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("hyb_kernels.hip", "hyb_internal.h"):
+    # kernels and the host code that fixes their launch geometry
+    for f in ("hyb_kernels.hip", "hyb_internal.h", "hyb_api.cpp"):
         with open(os.path.join(ROOT, "paper_1509_01399_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
