@@ -15,7 +15,7 @@ namespace hyb {
 constexpr int TX_FDM = 64, RY_FDM = 2, TY_FDM = 4 * RY_FDM;
 constexpr int TX_FEM = 32, TY_FEM = 8;
 constexpr int BLOCK = 256;
-static_assert(BLOCK / TX_FDM * RY_FDM == TY_FDM && RY_FDM == 2, "FDM tile: 4 thread rows of 2 grid rows");
+static_assert(BLOCK / TX_FDM * RY_FDM == TY_FDM, "FDM tile: BLOCK / TX_FDM thread rows of RY_FDM grid rows");
 
 // Face condition of one face at one step, 2 bits per face in a packed int.
 enum : int { F_ABC = 0, F_NEUMANN = 1, F_SOURCE = 2 };

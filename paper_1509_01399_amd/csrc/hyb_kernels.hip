@@ -578,24 +578,25 @@ __device__ __forceinline__ void omega_o_fill(const Step<T> &s, long long t)
     s.Uc[gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k)] = omega_o_adj(s, i, j, k);
 }
 
-// Seven-point leapfrog, eq. (fdmschemeforward), on two neighbouring columns
-// (x, y) and (x, y+1) (the second when `two`) for z in [z0, z1), skipping the
-// closed hole [o+2, o+C-2]^3.  The rows share their y-neighbour loads (the
-// centre of one row is the y-neighbour of the other) and a register queue
-// along z.  The same stencil is the adjoint update of the FDM rows; there
-// (ADJ) the rows on omega_o add the coupling the boundary launch left in
-// their level-k entry.
+// Seven-point leapfrog, eq. (fdmschemeforward), on RY_FDM neighbouring
+// columns (x, y) ... (x, y + nr - 1) for z in [z0, z1), skipping rows inside
+// the closed hole [o+2, o+C-2]^3 (bit r of hmask: column r lies in the
+// hole's x-y range).  The rows share their y-neighbour loads (the centre of
+// one row is the y neighbour of the next) and a register queue along z.
+// The same stencil is the adjoint update of the FDM rows; there (ADJ) the
+// rows on omega_o add the coupling the boundary launch left in their
+// level-k entry.
 template <typename T, bool ADJ, bool NT>
-__device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, bool two, int z0, int z1, bool hcol0,
-                                         bool hcol1)
+__device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, int nr, int z0, int z1, unsigned hmask)
 {
+    constexpr int R = RY_FDM;
     const Geo &g = s.g;
     constexpr bool INC = incr_form<T>();
     const long long py = g.px, pz = g.plane;
     long long id = gidx(g, x, y, z0);
     const T c2 = s.c2;
-    // distinct arrays: the loads of both rows can be issued before either
-    // row is stored
+    // distinct arrays: the loads of all rows can be issued before any row is
+    // stored
     const T *__restrict__ Ub = s.Ub;
     const T *__restrict__ Ua = INC ? s.Da : s.Ua;  // u^{k-1}, or d^k in the increment form
     T *__restrict__ Uc = s.Uc;
@@ -604,59 +605,60 @@ __device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, bool tw
     // it for o <= z <= o+C, a column inside the box at z = o and z = o+C.
     const int i = x - g.o[0], j0 = y - g.o[1], C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
     const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
-    const bool side0 = ib && j0 >= 0 && j0 <= C1 && !(ii && j0 > 0 && j0 < C1);
-    const bool top0 = ib && ii && j0 > 0 && j0 < C1;
-    const bool side1 = ib && j0 + 1 >= 0 && j0 + 1 <= C1 && !(ii && j0 + 1 > 0 && j0 + 1 < C1);
-    const bool top1 = ib && ii && j0 + 1 > 0 && j0 + 1 < C1;
-    T cm0 = Ub[id - pz], c00 = Ub[id];
-    T cm1 = two ? Ub[id + py - pz] : (T)0, c01 = two ? Ub[id + py] : (T)0;
+    bool side[R], top[R];
+    T cm[R], c0[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        side[r] = ib && j >= 0 && j <= C1 && !(ii && j > 0 && j < C1);
+        top[r] = ib && ii && j > 0 && j < C1;
+        cm[r] = r < nr ? Ub[id + r * py - pz] : (T)0;
+        c0[r] = r < nr ? Ub[id + r * py] : (T)0;
+    }
     for (int z = z0; z < z1; ++z, id += pz) {
-        const long long i1 = id + py;
         const bool inh = z >= g.hlo[2] && z <= g.hhi[2];
-        const bool do0 = !(hcol0 && inh), do1 = two && !(hcol1 && inh);
         const int kz = z - g.o[2];
         const bool zs = kz >= 0 && kz <= C2, zt = kz == 0 || kz == C2;
-        const bool om0 = ADJ && ((side0 && zs) || (top0 && zt)), om1 = ADJ && ((side1 && zs) || (top1 && zt));
         // all loads of the plane first
-        const T cp0 = Ub[id + pz];
-        const T cp1 = two ? Ub[i1 + pz] : (T)0;
-        T xm0 = 0, xp0 = 0, ym0 = 0, yp0 = c01, ua0 = 0, w0 = 0;
-        T xm1 = 0, xp1 = 0, yp1 = 0, ua1 = 0, w1 = 0;
-        if (do0) {
-            xm0 = Ub[id - 1]; xp0 = Ub[id + 1]; ym0 = Ub[id - py];
-            if (!two) yp0 = Ub[id + py];
-            ua0 = ld_once<T, NT>(Ua + id);
-            if (om0) w0 = Uc[id];
+        T cp[R], xm[R], xp[R], ua[R], w[R];
+        bool dor[R];
+        bool last = false;  // the last present row is computed
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const long long ir = id + r * py;
+            dor[r] = r < nr && !(((hmask >> r) & 1u) && inh);
+            cp[r] = r < nr ? Ub[ir + pz] : (T)0;
+            xm[r] = xp[r] = ua[r] = w[r] = 0;
+            if (dor[r]) {
+                xm[r] = Ub[ir - 1];
+                xp[r] = Ub[ir + 1];
+                ua[r] = ld_once<T, NT>(Ua + ir);
+                if (ADJ && ((side[r] && zs) || (top[r] && zt))) w[r] = Uc[ir];
+            }
+            if (r == nr - 1) last = dor[r];
         }
-        if (do1) {
-            xm1 = Ub[i1 - 1]; xp1 = Ub[i1 + 1]; yp1 = Ub[i1 + py];
-            ua1 = ld_once<T, NT>(Ua + i1);
-            if (om1) w1 = Uc[i1];
-        }
-        if (do0) {
-            const T L = ((xm0 + xp0) + (ym0 + yp0)) + (cm0 + cp0) - (T)6 * c00;
+        const T ylo = dor[0] ? Ub[id - py] : (T)0;
+        const T yhi = last ? Ub[id + nr * py] : (T)0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!dor[r]) continue;
+            const long long ir = id + r * py;
+            const T ym = r == 0 ? ylo : c0[r > 0 ? r - 1 : 0];
+            const T yp = r + 1 < nr ? c0[r + 1 < R ? r + 1 : r] : yhi;
+            const T L = ((xm[r] + xp[r]) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
             if constexpr (INC) {
-                const T d = ua0 + c2 * L + w0;
-                st_once<T, NT>(Dc + id, d);
-                st_once<T, NT>(Uc + id, c00 + d);
+                const T d = ua[r] + c2 * L + w[r];
+                st_once<T, NT>(Dc + ir, d);
+                st_once<T, NT>(Uc + ir, c0[r] + d);
             } else {
-                st_once<T, NT>(Uc + id, (T)2 * c00 - ua0 + c2 * L + w0);
+                st_once<T, NT>(Uc + ir, (T)2 * c0[r] - ua[r] + c2 * L + w[r]);
             }
         }
-        if (do1) {
-            const T L = ((xm1 + xp1) + (c00 + yp1)) + (cm1 + cp1) - (T)6 * c01;
-            if constexpr (INC) {
-                const T d = ua1 + c2 * L + w1;
-                st_once<T, NT>(Dc + i1, d);
-                st_once<T, NT>(Uc + i1, c01 + d);
-            } else {
-                st_once<T, NT>(Uc + i1, (T)2 * c01 - ua1 + c2 * L + w1);
-            }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cm[r] = c0[r];
+            c0[r] = cp[r];
         }
-        cm0 = c00;
-        c00 = cp0;
-        cm1 = c01;
-        c01 = cp1;
     }
 }
 
@@ -686,14 +688,17 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
     const int x = bx * TX_FDM + (int)(threadIdx.x % TX_FDM);
     const int y = 1 + by * TY_FDM + RY_FDM * (int)(threadIdx.x / TX_FDM);
     if (x < 1 || x > g.nx - 2 || y > g.ny - 2) return;
-    const bool two = y + 1 <= g.ny - 2;
+    const int nr = min(RY_FDM, g.ny - 1 - y);  // rows y .. y + nr - 1 <= ny - 2
     const int z0 = 1 + bz * g.zc_fdm;
     const int z1 = min(z0 + g.zc_fdm, g.nz - 1);
     const bool xin = g.has_fem && x >= g.hlo[0] && x <= g.hhi[0];
-    const bool hcol0 = xin && y >= g.hlo[1] && y <= g.hhi[1];
-    const bool hcol1 = xin && y + 1 >= g.hlo[1] && y + 1 <= g.hhi[1];
-    if (hcol0 && (hcol1 || !two) && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
-    fdm_rows<T, ADJ, NT>(s, x, y, two, z0, z1, hcol0, hcol1);
+    unsigned hmask = 0;
+#pragma unroll
+    for (int r = 0; r < RY_FDM; ++r)
+        if (xin && y + r >= g.hlo[1] && y + r <= g.hhi[1]) hmask |= 1u << r;
+    const unsigned all = (1u << nr) - 1u;
+    if ((hmask & all) == all && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
+    fdm_rows<T, ADJ, NT>(s, x, y, nr, z0, z1, hmask);
 }
 
 template <typename T, bool ADJ>
