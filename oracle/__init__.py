@@ -26,6 +26,11 @@ class _Geom(ct.Structure):
                 ("fem_o", ct.c_int32 * 3), ("fem_c", ct.c_int32 * 3)]
 
 
+class _Mesh(ct.Structure):
+    _fields_ = [("n_nodes", ct.c_int64), ("xyz", ct.POINTER(ct.c_double)), ("n_tets", ct.c_int64),
+                ("tet4", ct.POINTER(ct.c_int32))]
+
+
 class _Source(ct.Structure):
     _fields_ = [("kind", ct.c_int32), ("omega", ct.c_double),
                 ("flux", ct.POINTER(ct.c_double)), ("k_on", ct.c_int32)]
@@ -41,32 +46,46 @@ def _load():
             build()
         lib = ct.CDLL(lib_path())
         dp = ct.POINTER(ct.c_double)
-        lib.orc_sizes.argtypes = [ct.POINTER(_Geom), ct.POINTER(ct.c_int64)]
-        lib.orc_forward.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
-                                    ct.c_double, dp, dp, dp, dp, dp]
-        lib.orc_adjoint.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
-                                    ct.c_double, dp, dp, dp, dp, dp, dp, dp]
-        lib.orc_misfit.argtypes = [ct.POINTER(_Geom), ct.c_int, ct.c_double, dp, dp, dp]
+        G, M, S = ct.POINTER(_Geom), ct.POINTER(_Mesh), ct.POINTER(_Source)
+        lib.orc_sizes_m.argtypes = [G, M, ct.POINTER(ct.c_int64)]
+        lib.orc_forward_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp]
+        lib.orc_adjoint_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_misfit.argtypes = [G, ct.c_int, ct.c_double, dp, dp, dp]
         lib.orc_misfit.restype = ct.c_double
-        lib.orc_gradient.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
-                                     ct.c_double, dp, ct.c_double, dp, dp, dp]
-        lib.orc_cg.argtypes = [ct.POINTER(_Geom), dp, ct.POINTER(_Source), ct.c_int,
-                               ct.c_double, dp, ct.c_double, ct.c_double, ct.c_int, dp]
+        lib.orc_gradient_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, ct.c_double, dp, dp, dp]
+        lib.orc_cg_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, ct.c_double, ct.c_double,
+                                 ct.c_int, dp]
         _lib = lib
     return _lib
 
 
 class Geometry:
-    """Outer grid, face boundary conditions and FEM box (cells)."""
+    """Outer grid, face boundary conditions and FEM box (cells).  mesh: an
+    explicit tetrahedral mesh (xyz [nodes, 3], tets [n, 4]) of the FEM box;
+    then sigma and the gradients hold one value per tetrahedron.  Without it
+    the box is split into the 6 tetrahedra of each cube."""
 
     def __init__(self, n, h=None, bc=(ABC, ABC, ABC, ABC, ABC, SOURCE), fem_o=(0, 0, 0),
-                 fem_c=(0, 0, 0)):
+                 fem_c=(0, 0, 0), mesh=None):
         n = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
         self.n = n
         self.h = float(h if h is not None else 1.0 / n[2])
         self.bc = tuple(int(b) for b in bc)
         self.fem_o = (fem_o,) * 3 if np.isscalar(fem_o) else tuple(int(v) for v in fem_o)
         self.fem_c = (fem_c,) * 3 if np.isscalar(fem_c) else tuple(int(v) for v in fem_c)
+        self.mesh = None
+        if mesh is not None:
+            xyz = np.ascontiguousarray(mesh[0], dtype=np.float64)
+            tet = np.ascontiguousarray(mesh[1], dtype=np.int32)
+            self._keep = (xyz, tet)
+            m = _Mesh()
+            m.n_nodes, m.n_tets = xyz.shape[0], tet.shape[0]
+            m.xyz = xyz.ctypes.data_as(ct.POINTER(ct.c_double))
+            m.tet4 = tet.ctypes.data_as(ct.POINTER(ct.c_int32))
+            self.mesh = m
+
+    def _m(self):
+        return ct.byref(self.mesh) if self.mesh is not None else None
 
     def _c(self):
         g = _Geom()
@@ -91,7 +110,7 @@ class Geometry:
 
     def sizes(self):
         out = (ct.c_int64 * 8)()
-        if _load().orc_sizes(ct.byref(self._c()), out):
+        if _load().orc_sizes_m(ct.byref(self._c()), self._m(), out):
             raise ValueError("invalid geometry")
         keys = ("grid_nodes", "face_nodes", "fem_nodes", "fem_cubes", "fem_updated",
                 "fdm_updated", "omega_o", "omega_diamond")
@@ -135,8 +154,8 @@ def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=Non
     vh = np.zeros((nt + 1, sz["fem_nodes"])) if want_vhist and sz["fem_nodes"] else None
     uf = np.zeros(sz["grid_nodes"]) if want_ufinal else None
     s = _src(1 if flux is not None else 0, omega, flux, k_on)
-    rc = lib.orc_forward(ct.byref(g), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
-                         _p(obs), _p(vh), _p(uf))
+    rc = lib.orc_forward_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
+                           _p(obs), _p(vh), _p(uf))
     if rc:
         raise RuntimeError(f"orc_forward failed ({rc})")
     out = [obs]
@@ -150,7 +169,7 @@ def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=Non
 def adjoint(geom, sigma, nt, dt, seed, omega=40.0, flux=None, k_on=0, u0=None, um1=None,
             want_dflux=False, want_dinit=False):
     """Exact discrete adjoint: seed [nt+1, face] is the cotangent of the
-    trace.  Returns dJ/dsigma per cube (Euclidean) and optionally the source
+    trace.  Returns dJ/dsigma per cell (Euclidean) and optionally the source
     cotangent [nt, face] and the cotangents of u^0, u^{-1}."""
     lib = _load()
     g = geom._c()
@@ -164,8 +183,8 @@ def adjoint(geom, sigma, nt, dt, seed, omega=40.0, flux=None, k_on=0, u0=None, u
     du0 = np.zeros(sz["grid_nodes"]) if want_dinit else None
     dum1 = np.zeros(sz["grid_nodes"]) if want_dinit else None
     s = _src(1 if flux is not None else 0, omega, flux, k_on)
-    rc = lib.orc_adjoint(ct.byref(g), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
-                         _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1))
+    rc = lib.orc_adjoint_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
+                           _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1))
     if rc:
         raise RuntimeError(f"orc_adjoint failed ({rc})")
     out = [dsig[:sz["fem_cubes"]]]
@@ -195,8 +214,8 @@ def gradient(geom, sigma, nt, dt, data, gamma=0.01, omega=40.0, want_obs=False):
     J = ct.c_double()
     obs = np.zeros_like(data) if want_obs else None
     s = _src(0, omega)
-    rc = lib.orc_gradient(ct.byref(geom._c()), _p(sigma), ct.byref(s), nt, dt, _p(data),
-                          gamma, _p(grad), ct.byref(J), _p(obs))
+    rc = lib.orc_gradient_m(ct.byref(geom._c()), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(data),
+                            gamma, _p(grad), ct.byref(J), _p(obs))
     if rc:
         raise RuntimeError(f"orc_gradient failed ({rc})")
     return (grad, J.value, obs) if want_obs else (grad, J.value)
@@ -210,8 +229,8 @@ def cg(geom, sigma, nt, dt, data, iters, gamma=0.01, alpha_rel=0.25, omega=40.0)
     data = _f64(data)
     log = np.zeros((iters, 5))
     s = _src(0, omega)
-    rc = lib.orc_cg(ct.byref(geom._c()), _p(sig), ct.byref(s), nt, dt, _p(data), gamma,
-                    alpha_rel, iters, _p(log))
+    rc = lib.orc_cg_m(ct.byref(geom._c()), geom._m(), _p(sig), ct.byref(s), nt, dt, _p(data), gamma,
+                      alpha_rel, iters, _p(log))
     if rc:
         raise RuntimeError(f"orc_cg failed ({rc})")
     return sig, log

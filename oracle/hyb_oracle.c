@@ -87,6 +87,17 @@ typedef struct {
     int32_t k_on;        /* kind 1: the source face is a flux face for k<k_on */
 } orc_source;
 
+/* An explicit tetrahedral mesh of the FEM box (node coordinates in the
+ * grid's units, x = i h; tetrahedra as 4 node ids).  Nodes on the box
+ * surface and on the surface of the inner box [o+2, o+C-2]^3 must be grid
+ * nodes; the conductivity is then one value per tetrahedron. */
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;    /* [n_nodes][3] */
+    int64_t n_tets;
+    const int32_t *tet4;  /* [n_tets][4] */
+} orc_mesh;
+
 typedef struct {
     orc_geom g;
     int nx, ny, nz;        /* grid node counts                                 */
@@ -110,6 +121,8 @@ typedef struct {
     int64_t *wd_g, *wd_f;  /* omega_diamond as grid / FEM-local indices         */
     int64_t nb[4];         /* boundary node counts by codimension 1..3          */
     int64_t *bnd[4];       /* boundary nodes by codimension                     */
+    double *pvol;          /* [ncube] volume of each parameter cell (cube/tet)   */
+    int64_t *fgrid;        /* [fn] grid index of an FEM node on a grid point, -1 */
 } orc_prob;
 
 /* ---------------------------------------------------------------- helpers */
@@ -136,6 +149,7 @@ static void prob_free(orc_prob *P)
     free(P->tet); free(P->tcube); free(P->ke); free(P->mass); free(P->acube);
     free(P->eligible); free(P->fdm_row); free(P->fem_row);
     free(P->wo_g); free(P->wo_f); free(P->wd_g); free(P->wd_f);
+    free(P->pvol); free(P->fgrid);
     for (int c = 1; c <= 3; ++c) free(P->bnd[c]);
     memset(P, 0, sizeof(*P));
 }
@@ -192,11 +206,15 @@ static double tet_grads(const double X[4][3], double G[4][3])
     return fabs(det) / 6.0;
 }
 
+static int prob_init_mesh(orc_prob *P, const orc_mesh *m, const double *sigma);
+
 /* Build the problem: grid node classes, the FEM mesh (each cube of the FEM box
- * split into the 6 Kuhn tetrahedra sharing the cube diagonal), element
- * stiffness matrices from the vertex coordinates, lumped masses, and the
- * overlap node sets of Sec. 3.  sigma may be NULL (a = 1 everywhere). */
-static int prob_init(orc_prob *P, const orc_geom *g, const double *sigma)
+ * split into the 6 Kuhn tetrahedra sharing the cube diagonal, or the given
+ * mesh), element stiffness matrices from the vertex coordinates, lumped
+ * masses, and the overlap node sets of Sec. 3.  sigma may be NULL (a = 1
+ * everywhere); it holds one value per cube, or per tetrahedron of a given
+ * mesh. */
+static int prob_init(orc_prob *P, const orc_geom *g, const orc_mesh *m, const double *sigma)
 {
     memset(P, 0, sizeof(*P));
     if (geom_check(g)) return -1;
@@ -237,7 +255,8 @@ static int prob_init(orc_prob *P, const orc_geom *g, const double *sigma)
         if (cd) P->bnd[cd][P->nb[cd]++] = id;
     }
 
-    if (!P->has_fem) return 0;
+    if (!P->has_fem) return m ? -1 : 0;
+    if (m) return prob_init_mesh(P, m, sigma);
 
     P->fx = C[0] + 1; P->fy = C[1] + 1; P->fz = C[2] + 1;
     P->fn = (int64_t)P->fx * P->fy * P->fz;
@@ -250,6 +269,12 @@ static int prob_init(orc_prob *P, const orc_geom *g, const double *sigma)
     P->acube = (double *)malloc(sizeof(double) * (size_t)P->ncube);
     P->eligible = (uint8_t *)calloc((size_t)P->ncube, 1);
     P->fem_row = (uint8_t *)calloc((size_t)P->fn, 1);
+    P->pvol = (double *)malloc(sizeof(double) * (size_t)P->ncube);
+    P->fgrid = (int64_t *)malloc(sizeof(int64_t) * (size_t)P->fn);
+    for (int64_t c = 0; c < P->ncube; ++c) P->pvol[c] = g->h * g->h * g->h;
+    for (int c = 0; c < P->fz; ++c)
+        for (int b = 0; b < P->fy; ++b)
+            for (int a = 0; a < P->fx; ++a) P->fgrid[fidx(P, a, b, c)] = gidx(P, o[0] + a, o[1] + b, o[2] + c);
 
     static const int perm[6][3] = {{0,1,2},{0,2,1},{1,0,2},{1,2,0},{2,0,1},{2,1,0}};
     int64_t t = 0;
@@ -311,6 +336,106 @@ static int prob_init(orc_prob *P, const orc_geom *g, const double *sigma)
                 if (onb) { P->wo_g[nwo] = gi; P->wo_f[nwo] = fi; ++nwo; }
                 if (onD) { P->wd_g[nwd] = gi; P->wd_f[nwd] = fi; ++nwd; }
             }
+    return 0;
+}
+
+/* FEM part of the problem from an explicit mesh (the grid part is set up).
+ * The parameter cells are the tetrahedra; a tetrahedron is a free parameter
+ * when all its vertices lie in the closed inner box [o+2, o+C-2]^3 (a = 1 on
+ * the two-element overlap, condition (2.3)).  FEM rows: the nodes inside the
+ * open box; omega_o: the mesh nodes on the box surface (grid nodes);
+ * omega_diamond: the grid nodes on the inner box surface, each of which must
+ * be a mesh node.  Returns 0 or -1 (mesh not conforming to the grid). */
+static int prob_init_mesh(orc_prob *P, const orc_mesh *m, const double *sigma)
+{
+    const orc_geom *g = &P->g;
+    const int *o = g->fem_o, *C = g->fem_c;
+    const double h = g->h, tol = 1e-9;
+    if (m->n_nodes < 4 || m->n_tets < 1) return -1;
+    P->fn = m->n_nodes;
+    P->ntet = m->n_tets;
+    P->ncube = m->n_tets;
+    P->tet = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)P->ntet);
+    P->tcube = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->ntet);
+    P->ke = (double *)malloc(sizeof(double) * 16 * (size_t)P->ntet);
+    P->mass = (double *)calloc((size_t)P->fn, sizeof(double));
+    P->acube = (double *)malloc(sizeof(double) * (size_t)P->ncube);
+    P->eligible = (uint8_t *)calloc((size_t)P->ncube, 1);
+    P->fem_row = (uint8_t *)calloc((size_t)P->fn, 1);
+    P->pvol = (double *)malloc(sizeof(double) * (size_t)P->ncube);
+    P->fgrid = (int64_t *)malloc(sizeof(int64_t) * (size_t)P->fn);
+    uint8_t *inner = (uint8_t *)calloc((size_t)P->fn, 1);
+    /* node positions in cells: grid points, box surface, inner box */
+    int64_t nwo = 0;
+    for (int64_t n = 0; n < P->fn; ++n) {
+        double q[3];
+        int grid = 1, inside = 1, surf = 0, in_inner = 1;
+        long long qi[3];
+        for (int d = 0; d < 3; ++d) {
+            q[d] = m->xyz[3 * n + d] / h;
+            qi[d] = llround(q[d]);
+            if (fabs(q[d] - (double)qi[d]) > tol) grid = 0;
+            if (q[d] < o[d] - tol || q[d] > o[d] + C[d] + tol) inside = 0;
+            if (fabs(q[d] - o[d]) <= tol || fabs(q[d] - (o[d] + C[d])) <= tol) surf = 1;
+            if (q[d] < o[d] + 2 - tol || q[d] > o[d] + C[d] - 2 + tol) in_inner = 0;
+        }
+        if (!inside || (surf && !grid)) { free(inner); return -1; }
+        P->fgrid[n] = grid ? gidx(P, (int)qi[0], (int)qi[1], (int)qi[2]) : -1;
+        P->fem_row[n] = (uint8_t)!surf;
+        inner[n] = (uint8_t)in_inner;
+        nwo += surf;
+    }
+    /* elements */
+    for (int64_t t = 0; t < P->ntet; ++t) {
+        double X[4][3], Gr[4][3];
+        int all_inner = 1;
+        for (int q = 0; q < 4; ++q) {
+            int32_t v = m->tet4[4 * t + q];
+            if (v < 0 || v >= P->fn) { free(inner); return -1; }
+            P->tet[4 * t + q] = v;
+            for (int d = 0; d < 3; ++d) X[q][d] = m->xyz[3 * v + d];
+            all_inner &= inner[v];
+        }
+        double vol = tet_grads(X, Gr);
+        if (!(vol > 1e-12 * h * h * h)) { free(inner); return -1; }
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c)
+                P->ke[16 * t + 4 * r + c] = vol * (Gr[r][0] * Gr[c][0] + Gr[r][1] * Gr[c][1] + Gr[r][2] * Gr[c][2]);
+        for (int q = 0; q < 4; ++q) P->mass[P->tet[4 * t + q]] += vol / 4.0;
+        P->tcube[t] = (int32_t)t;
+        P->pvol[t] = vol;
+        P->eligible[t] = (uint8_t)all_inner;
+        P->acube[t] = 1.0 + ((all_inner && sigma) ? sigma[t] : 0.0);
+    }
+    free(inner);
+    /* omega_o: the box-surface nodes; they must be all grid nodes of the surface */
+    int64_t want = (int64_t)(C[0] + 1) * (C[1] + 1) * (C[2] + 1) - (int64_t)(C[0] - 1) * (C[1] - 1) * (C[2] - 1);
+    if (nwo != want) return -1;
+    P->nwo = nwo;
+    P->wo_g = (int64_t *)malloc(sizeof(int64_t) * (size_t)nwo);
+    P->wo_f = (int64_t *)malloc(sizeof(int64_t) * (size_t)nwo);
+    nwo = 0;
+    for (int64_t n = 0; n < P->fn; ++n)
+        if (!P->fem_row[n]) { P->wo_g[nwo] = P->fgrid[n]; P->wo_f[nwo] = n; ++nwo; }
+    /* omega_diamond: grid nodes on the inner box surface, matched to mesh nodes */
+    int64_t *node_at = (int64_t *)malloc(sizeof(int64_t) * (size_t)P->nn);
+    for (int64_t i = 0; i < P->nn; ++i) node_at[i] = -1;
+    for (int64_t n = 0; n < P->fn; ++n)
+        if (P->fgrid[n] >= 0) node_at[P->fgrid[n]] = n;
+    const int L = C[0] - 4;
+    int64_t nwd = 0;
+    P->wd_g = (int64_t *)malloc(sizeof(int64_t) * (size_t)(6 * (L + 1) * (L + 1)));
+    P->wd_f = (int64_t *)malloc(sizeof(int64_t) * (size_t)(6 * (L + 1) * (L + 1)));
+    for (int c = 0; c <= C[2] - 4; ++c)
+        for (int b = 0; b <= C[1] - 4; ++b)
+            for (int a = 0; a <= C[0] - 4; ++a) {
+                if (!(a == 0 || a == C[0] - 4 || b == 0 || b == C[1] - 4 || c == 0 || c == C[2] - 4)) continue;
+                int64_t gi = gidx(P, o[0] + 2 + a, o[1] + 2 + b, o[2] + 2 + c);
+                if (node_at[gi] < 0) { free(node_at); return -1; }
+                P->wd_g[nwd] = gi; P->wd_f[nwd] = node_at[gi]; ++nwd;
+            }
+    P->nwd = nwd;
+    free(node_at);
     return 0;
 }
 
@@ -469,15 +594,12 @@ static int forward_sweep(const orc_prob *P, const orc_source *S, int nt, double 
     if (!Ua || !Ub || !Uc || !Va || !Vb || !Vc || !r) return -2;
     if (u0) memcpy(Ub, u0, gb);
     if (um1) memcpy(Ua, um1, gb);
-    if (P->has_fem) {
-        const int *o = P->g.fem_o;
-        for (int c = 0; c < P->fz; ++c)
-            for (int b = 0; b < P->fy; ++b)
-                for (int a = 0; a < P->fx; ++a) {
-                    int64_t gi = gidx(P, o[0] + a, o[1] + b, o[2] + c), fi = fidx(P, a, b, c);
-                    Vb[fi] = Ub[gi]; Va[fi] = Ua[gi];
-                }
-    }
+    if (P->has_fem)
+        for (int64_t f = 0; f < P->fn; ++f) {
+            /* FEM copies of the initial levels: defined on grid points only */
+            if (P->fgrid[f] >= 0) { Vb[f] = Ub[P->fgrid[f]]; Va[f] = Ua[P->fgrid[f]]; }
+            else if (u0 || um1) { free(Ua); free(Ub); free(Uc); free(Va); free(Vb); free(Vc); free(r); return -1; }
+        }
     double *Um = Ua, *U = Ub, *Up = Uc, *Vm = Va, *V = Vb, *Vp = Vc;
     if (obs) record_face(P, U, obs);
     if (vhist && P->has_fem) memcpy(vhist, V, fb);
@@ -639,16 +761,12 @@ static int adjoint_sweep(const orc_prob *P, const orc_source *S, int nt, double 
     }
     /* level 0 trace, then fold the FEM copies of the initial levels back. */
     for (int q = 0; q < P->nface; ++q) aUp[base + q] += seed[q];
-    if (P->has_fem) {
-        const int *o = P->g.fem_o;
-        for (int c = 0; c < P->fz; ++c)
-            for (int b = 0; b < P->fy; ++b)
-                for (int a = 0; a < P->fx; ++a) {
-                    int64_t gi = gidx(P, o[0] + a, o[1] + b, o[2] + c), fi = fidx(P, a, b, c);
-                    aUp[gi] += aVp[fi];
-                    aU[gi] += aV[fi];
-                }
-    }
+    if (P->has_fem)
+        for (int64_t f = 0; f < P->fn; ++f)
+            if (P->fgrid[f] >= 0) {
+                aUp[P->fgrid[f]] += aVp[f];
+                aU[P->fgrid[f]] += aV[f];
+            }
     if (du0) memcpy(du0, aUp, gb);
     if (dum1) memcpy(dum1, aU, gb);
     free(A0); free(A1); free(A2); free(B0); free(B1); free(B2); free(gs);
@@ -666,13 +784,18 @@ static double face_weight(const orc_prob *P, int i, int j)
 
 /* ---------------------------------------------------------- exported API */
 
+/* Every entry point takes an optional explicit mesh m (NULL: the 6-tetrahedra
+ * split of the FEM box); with a mesh, sigma, dsig and grad hold one value per
+ * tetrahedron.  The names without _m are the same calls without a mesh. */
+
 /* Sizes: out[0] grid nodes, out[1] face nodes, out[2] FEM nodes,
- * out[3] FEM cubes, out[4] FEM-updated nodes, out[5] FDM-updated nodes
- * (interior + boundary), out[6] |omega_o|, out[7] |omega_diamond|. */
-int orc_sizes(const orc_geom *g, int64_t *out)
+ * out[3] parameter cells (cubes, or tetrahedra of a given mesh),
+ * out[4] FEM-updated nodes, out[5] FDM-updated nodes (interior + boundary),
+ * out[6] |omega_o|, out[7] |omega_diamond|. */
+int orc_sizes_m(const orc_geom *g, const orc_mesh *m, int64_t *out)
 {
     orc_prob P;
-    if (prob_init(&P, g, NULL)) return -1;
+    if (prob_init(&P, g, m, NULL)) return -1;
     int64_t nfdm = 0, nfem = 0;
     for (int64_t i = 0; i < P.nn; ++i) nfdm += P.fdm_row[i];
     nfdm += P.nb[1] + P.nb[2] + P.nb[3];
@@ -683,37 +806,53 @@ int orc_sizes(const orc_geom *g, int64_t *out)
     return 0;
 }
 
-/* Forward solve: obs [nt+1][nface]; vhist, u0, um1, ufin optional. */
-int orc_forward(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
-                const double *u0, const double *um1, double *obs, double *vhist, double *ufin)
+int orc_sizes(const orc_geom *g, int64_t *out) { return orc_sizes_m(g, NULL, out); }
+
+/* Forward solve: obs [nt+1][nface]; vhist, u0, um1, ufin optional (initial
+ * levels need every FEM node on a grid point). */
+int orc_forward_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                  double dt, const double *u0, const double *um1, double *obs, double *vhist, double *ufin)
 {
     orc_prob P;
-    if (nt < 0 || !(dt > 0) || prob_init(&P, g, sigma)) return -1;
+    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma)) return -1;
     int rc = forward_sweep(&P, S, nt, dt, u0, um1, obs, vhist, ufin);
     prob_free(&P);
     return rc;
 }
 
+int orc_forward(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
+                const double *u0, const double *um1, double *obs, double *vhist, double *ufin)
+{
+    return orc_forward_m(g, NULL, sigma, S, nt, dt, u0, um1, obs, vhist, ufin);
+}
+
 /* Linear adjoint: given the cotangent seed [nt+1][nface] of the trace,
- * returns dsig [ncube] = dJ/da per cube (Euclidean, zero on non-eligible
- * cubes), and optionally dflux [nt][nface], du0, dum1 [nn]. */
-int orc_adjoint(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
-                const double *u0, const double *um1, const double *seed,
-                double *dsig, double *dflux, double *du0, double *dum1)
+ * returns dsig [cells] = dJ/da per parameter cell (Euclidean, zero on
+ * non-eligible cells), and optionally dflux [nt][nface], du0, dum1 [nn]. */
+int orc_adjoint_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                  double dt, const double *u0, const double *um1, const double *seed, double *dsig,
+                  double *dflux, double *du0, double *dum1)
 {
     orc_prob P;
-    if (nt < 0 || !(dt > 0) || prob_init(&P, g, sigma)) return -1;
+    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma)) return -1;
     double *vh = NULL;
     if (P.has_fem) {
         vh = (double *)malloc(sizeof(double) * (size_t)P.fn * (size_t)(nt + 1));
         if (!vh) { prob_free(&P); return -2; }
-        forward_sweep(&P, S, nt, dt, u0, um1, NULL, vh, NULL);
+        if (forward_sweep(&P, S, nt, dt, u0, um1, NULL, vh, NULL)) { free(vh); prob_free(&P); return -1; }
     }
     if (dflux) memset(dflux, 0, sizeof(double) * (size_t)nt * (size_t)P.nface);
     int rc = adjoint_sweep(&P, S, nt, dt, seed, vh, dsig, dflux, du0, dum1);
     free(vh);
     prob_free(&P);
     return rc;
+}
+
+int orc_adjoint(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
+                const double *u0, const double *um1, const double *seed,
+                double *dsig, double *dflux, double *du0, double *dum1)
+{
+    return orc_adjoint_m(g, NULL, sigma, S, nt, dt, u0, um1, seed, dsig, dflux, du0, dum1);
 }
 
 /* Misfit part of the Tikhonov functional, eq. (functional), and its trace
@@ -723,7 +862,7 @@ double orc_misfit(const orc_geom *g, int nt, double dt, const double *obs, const
                   double *seed)
 {
     orc_prob P;
-    if (prob_init(&P, g, NULL)) return NAN;
+    if (prob_init(&P, g, NULL, NULL)) return NAN;
     double J = 0.0;
     if (seed) memset(seed, 0, sizeof(double) * (size_t)P.nface);
     for (int k = 1; k <= nt; ++k)
@@ -738,15 +877,16 @@ double orc_misfit(const orc_geom *g, int nt, double dt, const double *obs, const
     return J;
 }
 
-/* Gradient of the Tikhonov functional with respect to the per-cube sigma as
+/* Gradient of the Tikhonov functional with respect to the per-cell sigma as
  * an L2 density, the discrete form of eq. (gradient1):
- *   g_c = (1/h^3) dJ_misfit/da_c + gamma (sigma_c - sigma0_c)  (eligible c),
- *   g_c = 0 elsewhere.  Returns J (misfit + regularisation) in *J. */
-int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
-                 const double *data, double gamma, double *grad, double *J, double *obs_out)
+ *   g_c = (1/|c|) dJ_misfit/da_c + gamma (sigma_c - sigma0_c)  (eligible c),
+ *   g_c = 0 elsewhere, |c| the cell volume (h^3 for a cube, |K| for a
+ *   tetrahedron).  Returns J (misfit + regularisation) in *J. */
+int orc_gradient_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                   double dt, const double *data, double gamma, double *grad, double *J, double *obs_out)
 {
     orc_prob P;
-    if (nt < 0 || !(dt > 0) || prob_init(&P, g, sigma) || !P.has_fem) return -1;
+    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma) || !P.has_fem) return -1;
     double *obs = (double *)malloc(sizeof(double) * (size_t)P.nface * (size_t)(nt + 1));
     double *seed = (double *)malloc(sizeof(double) * (size_t)P.nface * (size_t)(nt + 1));
     double *vh = (double *)malloc(sizeof(double) * (size_t)P.fn * (size_t)(nt + 1));
@@ -754,12 +894,12 @@ int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, in
     forward_sweep(&P, S, nt, dt, NULL, NULL, obs, vh, NULL);
     double Jm = orc_misfit(g, nt, dt, obs, data, seed);
     adjoint_sweep(&P, S, nt, dt, seed, vh, grad, NULL, NULL, NULL);
-    double h3 = P.g.h * P.g.h * P.g.h, reg = 0.0;
+    double reg = 0.0;
     for (int64_t c = 0; c < P.ncube; ++c) {
         if (!P.eligible[c]) { grad[c] = 0.0; continue; }
         double s = sigma ? sigma[c] : 0.0;
-        grad[c] = grad[c] / h3 + gamma * s;
-        reg += 0.5 * gamma * h3 * s * s;
+        grad[c] = grad[c] / P.pvol[c] + gamma * s;
+        reg += 0.5 * gamma * P.pvol[c] * s * s;
     }
     if (J) *J = Jm + reg;
     if (obs_out) memcpy(obs_out, obs, sizeof(double) * (size_t)P.nface * (size_t)(nt + 1));
@@ -768,26 +908,32 @@ int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, in
     return 0;
 }
 
+int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
+                 const double *data, double gamma, double *grad, double *J, double *obs_out)
+{
+    return orc_gradient_m(g, NULL, sigma, S, nt, dt, data, gamma, grad, J, obs_out);
+}
+
 /* Algorithm 3 (Sec. 8), `iters` iterations from sigma (in/out).  Per
- * iteration m: g^m from orc_gradient; beta^m = |g^m|^2/|g^{m-1}|^2 (beta^0 = 0);
- * d^m = -g^m + beta^m d^{m-1}; alpha^m = alpha_rel / max|d^m|;
- * sigma <- clip(sigma + alpha^m d^m, 0, 4) on eligible cubes (a in [1,5],
- * eq. (admpar)).  log[5*m + {0..4}] = J, |g|_{L2}, beta, alpha, max|d|. */
-int orc_cg(const orc_geom *g, double *sigma, const orc_source *S, int nt, double dt,
-           const double *data, double gamma, double alpha_rel, int iters, double *log)
+ * iteration m: g^m from orc_gradient; beta^m = |g^m|^2/|g^{m-1}|^2 (beta^0 = 0,
+ * norms with the cell volumes); d^m = -g^m + beta^m d^{m-1};
+ * alpha^m = alpha_rel / max|d^m|; sigma <- clip(sigma + alpha^m d^m, 0, 4)
+ * on eligible cells (a in [1,5], eq. (admpar)).
+ * log[5*m + {0..4}] = J, |g|_{L2}, beta, alpha, max|d|. */
+int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
+             const double *data, double gamma, double alpha_rel, int iters, double *log)
 {
     orc_prob P;
-    if (prob_init(&P, g, NULL) || !P.has_fem) return -1;
+    if (prob_init(&P, g, msh, NULL) || !P.has_fem) return -1;
     int64_t nc = P.ncube;
-    double h3 = P.g.h * P.g.h * P.g.h;
     double *gr = (double *)calloc((size_t)nc, sizeof(double));
     double *d = (double *)calloc((size_t)nc, sizeof(double));
     double gn2_prev = 0.0;
     for (int m = 0; m < iters; ++m) {
         double J = 0.0;
-        if (orc_gradient(g, sigma, S, nt, dt, data, gamma, gr, &J, NULL)) return -1;
+        if (orc_gradient_m(g, msh, sigma, S, nt, dt, data, gamma, gr, &J, NULL)) return -1;
         double gn2 = 0.0;
-        for (int64_t c = 0; c < nc; ++c) gn2 += h3 * gr[c] * gr[c];
+        for (int64_t c = 0; c < nc; ++c) gn2 += P.pvol[c] * gr[c] * gr[c];
         double beta = m == 0 ? 0.0 : gn2 / gn2_prev;
         double dmax = 0.0;
         for (int64_t c = 0; c < nc; ++c) {
@@ -809,4 +955,10 @@ int orc_cg(const orc_geom *g, double *sigma, const orc_source *S, int nt, double
     free(gr); free(d);
     prob_free(&P);
     return 0;
+}
+
+int orc_cg(const orc_geom *g, double *sigma, const orc_source *S, int nt, double dt,
+           const double *data, double gamma, double alpha_rel, int iters, double *log)
+{
+    return orc_cg_m(g, NULL, sigma, S, nt, dt, data, gamma, alpha_rel, iters, log);
 }

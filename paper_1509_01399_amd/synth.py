@@ -167,6 +167,31 @@ def kuhn_box_mesh(o, C, h, origin=(0.0, 0.0, 0.0)):
     return xyz.astype(np.float64), tet
 
 
+def perturbed_box_mesh(o, C, h, seed, amp=0.15):
+    """Unstructured mesh of the FEM box: the 6-tetrahedra split of every cube,
+    with each node strictly inside the inner box (o+2, o+C-2)^3 moved by an
+    offset ~U(-amp h, amp h) per axis.  The two-cell overlap layer and the
+    inner box surface keep their grid nodes (the coupling to the grid needs
+    them); inside, element shapes, volumes and lumped masses vary and every
+    element matrix couples all 4 vertices.  amp <= 0.2 keeps every element
+    positively oriented."""
+    xyz, tet = kuhn_box_mesh(o, C, h)
+    rng = np.random.default_rng(seed)
+    q = np.rint(xyz / h).astype(np.int64) - np.asarray((o,) * 3 if np.isscalar(o) else o)
+    inner = np.all((q > 2) & (q < C - 2), axis=1)
+    xyz = xyz.copy()
+    xyz[inner] += rng.uniform(-amp * h, amp * h, (int(inner.sum()), 3))
+    return xyz, tet
+
+
+def tet_sigma(xyz, tet, sigma_cube, o, C, h):
+    """Per-tetrahedron conductivity sampling a per-cube field at each
+    element's centroid (cube cells of the FEM box)."""
+    cen = xyz[tet].mean(axis=1) / h - np.asarray((o,) * 3 if np.isscalar(o) else o)
+    idx = np.clip(np.floor(cen).astype(np.int64), 0, C - 1)
+    return np.asarray(sigma_cube)[idx[:, 2], idx[:, 1], idx[:, 0]]
+
+
 def poisson_arrivals(n_req, rate, seed):
     """Arrival times (seconds) of a Poisson stream with the given rate."""
     rng = np.random.default_rng(seed)
