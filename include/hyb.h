@@ -16,17 +16,28 @@
  *    fastest.  Faces are ordered x-, x+, y-, y+, z-, z+.  The backscattered
  *    trace (S_T of Sec. 5) is recorded on the z+ face, which is also the
  *    only face that may carry the plane-wave source.
- *  - FEM box: the tetrahedral mesh passed to hyb_create must be the split of
- *    a box of whole grid cells [o, o+C] into 6 tetrahedra per cube sharing
- *    the cube diagonal (a structured P1 mesh conforming to the grid, so that
- *    the FEM and FDM schemes coincide on the overlap, Sec. 1 and Sec. 3).
- *    The box must keep >= 1 cell to the outer boundary and be >= 5 cells
- *    wide.  General unstructured meshes return HYB_E_UNSUPPORTED.
- *  - Conductivity: a = 1 + sigma, sigma piecewise constant per FEM cube
- *    (a subspace of C_h, eq. (p0)), laid out [C_z][C_y][C_x] (x fastest),
- *    FP64.  Cubes within two cells of the FEM boundary are the overlap layer
- *    where a = 1 (condition (2.3)); their sigma is ignored and their gradient
- *    is 0.  Admissible values 0 <= sigma <= 4 (eq. (admpar)).
+ *  - FEM box: a tetrahedral mesh of a box of whole grid cells [o, o+C]
+ *    (its bounding box: cubic, >= 5 cells wide, >= 1 cell to the outer
+ *    boundary).  Two kinds (Sec. 1, Sec. 3, Sec. 7.2):
+ *    structured: the split of every cube into the 6 tetrahedra sharing the
+ *      cube diagonal; the P1 stiffness is then an edge-conductance stencil
+ *      and the FEM rows run in grid-shaped tiles;
+ *    general: any conforming mesh whose box surface carries exactly the grid
+ *      nodes of the surface and in which every grid node of the inner box
+ *      surface [o+2, o+C-2] is a mesh node (the overlap exchanges of
+ *      Algorithm 1 need both); nodes elsewhere may lie anywhere.  The FEM
+ *      rows then run on a sparse table of the assembled stiffness.
+ *    A 6-tetrahedra split is treated as structured unless opts.fem_general
+ *    asks for the general path.
+ *  - Conductivity: a = 1 + sigma, sigma piecewise constant (a subspace of
+ *    C_h, eq. (p0)), FP64.  Structured: one value per FEM cube, laid out
+ *    [C_z][C_y][C_x] (x fastest); cubes within two cells of the FEM
+ *    boundary are the overlap layer where a = 1 (condition (2.3)).  General:
+ *    one value per tetrahedron in the mesh's order; a tetrahedron is free
+ *    when all its vertices lie in the closed inner box [o+2, o+C-2]^3, and
+ *    a = 1 on the others.  sigma outside the free cells is ignored and their
+ *    gradient is 0.  Admissible values 0 <= sigma <= 4 (eq. (admpar)).
+ *    hyb_fem_info gives the number of values.
  *  - Traces: obs / residual / data are FP64 device arrays
  *    [nt+1][(n_x+1)(n_y+1)] (level k = time k*dt; level 0 included).
  *  - Pointers named *_dev are device pointers owned by the caller; they must
@@ -35,10 +46,13 @@
  *    copied during hyb_create.
  *  - Asynchrony: calls enqueue work on opts.hip_stream and return.  Calls
  *    that return a host scalar (J, gnorm) synchronise that stream.
- *  - Errors: argument, mesh, CFL and state errors are detected on the host
- *    before any work is enqueued and leave the context unchanged.  Device
- *    errors are reported as HYB_E_DEVICE by the call that observes them.
- *    hyb_last_error returns a text description of the last error.
+ *  - Errors: argument, mesh and state errors are detected on the host before
+ *    any work is enqueued and leave the context unchanged.  The CFL and
+ *    non-finite sigma checks of a forward sweep run after the conductivity
+ *    is loaded on the device: when they refuse, the previous sweeps of the
+ *    context are no longer available (HYB_E_STATE until the next forward).
+ *    Device errors are reported as HYB_E_DEVICE by the call that observes
+ *    them.  hyb_last_error returns a text description of the last error.
  */
 #ifndef HYB_H
 #define HYB_H
@@ -80,10 +94,10 @@ typedef struct {
 } hyb_fd_grid;
 
 typedef struct {
-    int64_t n_nodes;      /* (C_x+1)(C_y+1)(C_z+1)                                  */
+    int64_t n_nodes;      /* nodes; (C_x+1)(C_y+1)(C_z+1) for the structured split  */
     const double *xyz;    /* host [n_nodes][3] node coordinates                     */
-    int64_t n_tets;       /* 6 C_x C_y C_z                                          */
-    const int32_t *tet4;  /* host [n_tets][4] node ids (0-based)                    */
+    int64_t n_tets;       /* tetrahedra; 6 C_x C_y C_z for the structured split     */
+    const int32_t *tet4;  /* host [n_tets][4] node ids (0-based, either orientation)*/
 } hyb_fem_mesh;
 
 typedef struct {
@@ -101,6 +115,8 @@ typedef struct {
     double gamma;         /* Tikhonov regularisation parameter (eq. (functional))*/
     double alpha_rel;     /* CG step: alpha^m = alpha_rel / max|d^m|            */
     void *hip_stream;     /* hipStream_t for all work; NULL = default stream      */
+    int32_t fem_general;  /* 1: run a 6-tetrahedra split on the general path too
+                             (one sigma per tetrahedron)                         */
 } hyb_opts;
 
 typedef struct {
@@ -118,13 +134,15 @@ typedef struct {
     double gnorm2_prev;   /* |g^{m-1}|^2_{L2} (host copy, informational)         */
 } hyb_cg_state;
 
-/* Create a context.  Validates the grid, the FEM mesh (must be the 6-tet
- * split of a box of grid cells) and the overlap width (must be 2), computes
- * the P1 element stiffness of the mesh from its vertex coordinates and
+/* Create a context.  Validates the grid, the FEM mesh (see FEM box above;
+ * HYB_E_MESH when it does not conform to the grid on the overlap, has two
+ * nodes at one grid point, a degenerate tetrahedron or a node in no
+ * tetrahedron) and the overlap width (must be 2), computes the P1 element
+ * matrices and lumped masses of the mesh from its vertex coordinates and
  * allocates the wavefields.  opts may be NULL (FP64, history, gamma = 0.01,
- * alpha_rel = 0.25, default stream).  fem may be NULL for a pure
- * finite-difference grid (no FEM box, no conductivity).  On success *out
- * owns the device state until hyb_destroy.
+ * alpha_rel = 0.25, default stream, structured path where possible).  fem
+ * may be NULL for a pure finite-difference grid (no FEM box, no
+ * conductivity).  On success *out owns the device state until hyb_destroy.
  * Errors: HYB_E_ARG, HYB_E_MESH, HYB_E_UNSUPPORTED, HYB_E_OOM, HYB_E_DEVICE. */
 hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem,
                       const hyb_overlap *overlap, const hyb_opts *opts, hyb_ctx **out);
@@ -138,17 +156,23 @@ void hyb_destroy(hyb_ctx *ctx);
  * (eq:abs2) and the source of eq. (f), then copies the FEM values to the
  * FDM inner boundary omega_diamond and the FDM values to the FEM boundary
  * omega_o (Algorithm 1).  Zero initial data (Model Problem 2).
- * sigma_dev: device FP64 [C^3] (NULL = a = 1; must be NULL without FEM box).
+ * sigma_dev: device FP64 [n_params] (NULL = a = 1; must be NULL without FEM
+ *            box).
  * obs_dev:   device FP64 [nt+1][face] receives the z+ trace (may be NULL).
  * Keeps what the adjoint needs according to opts.store_mode.
- * Errors: HYB_E_ARG (nt < 1, dt <= 0, source), HYB_E_CFL (dt above
- * h/sqrt(3 max a)), HYB_E_NONFINITE (sigma not finite), HYB_E_OOM. */
+ * Errors: HYB_E_ARG (nt < 1, dt <= 0, source), HYB_E_CFL (structured: dt
+ * above h/sqrt(3 max a); general: dt above h/sqrt(3), or dt^2 times the
+ * Gershgorin bound max_n (|K_nn| + sum_m |K_nm|) / m_n of the FEM rows above
+ * 4, a sufficient stability condition of the lumped-mass leapfrog),
+ * HYB_E_NONFINITE (sigma not finite), HYB_E_OOM. */
 hyb_status hyb_forward(hyb_ctx *ctx, const double *sigma_dev, const hyb_source *src,
                        int32_t nt, double dt, double *obs_dev);
 
 /* Model Problem 1 initial data for the next hyb_forward (and only that one):
  * u0_dev, um1_dev are device FP64 [(n_z+1)(n_y+1)(n_x+1)] levels u^0 and
- * u^{-1} (NULL = zero).  Copied on the stream. */
+ * u^{-1} (NULL = zero).  Copied on the stream.  The FEM nodes take the values
+ * of their grid nodes, so a general mesh with nodes off the grid returns
+ * HYB_E_UNSUPPORTED. */
 hyb_status hyb_set_initial(hyb_ctx *ctx, const double *u0_dev, const double *um1_dev);
 
 /* Adjoint solve: the exact transpose of the last forward sweep, run backward
@@ -166,16 +190,17 @@ hyb_status hyb_set_initial(hyb_ctx *ctx, const double *u0_dev, const double *um1
 hyb_status hyb_adjoint(hyb_ctx *ctx, const double *residual_dev, int32_t mode);
 
 /* Finalise the gradient of the last adjoint into grad_dev (device FP64
- * [C^3]; 0 on overlap cubes):
- *   mode 0: g_c = (1/h^3) dJ/dsigma_c + gamma * sigma_c, the L2 density of
- *           eq. (gradient1) for J of eq. (functional) (a_0 = 1);
+ * [n_params]; 0 outside the free cells):
+ *   mode 0: g_c = (1/|c|) dJ/dsigma_c + gamma * sigma_c, the L2 density of
+ *           eq. (gradient1) for J of eq. (functional) (a_0 = 1), |c| the
+ *           cell volume (h^3, or the tetrahedron's volume);
  *   mode 1: g_c = dL/dsigma_c (Euclidean, no regularisation).
  * J_host (nullable, mode 0 only): J = misfit + regularisation (synchronises).
  * Errors: HYB_E_ARG, HYB_E_STATE. */
 hyb_status hyb_gradient(hyb_ctx *ctx, double *grad_dev, double *J_host);
 
-/* One iteration of Algorithm 3 (Sec. 8) at sigma_dev (device FP64 [C^3],
- * updated in place): forward, residual obs - data, adjoint, gradient g^m,
+/* One iteration of Algorithm 3 (Sec. 8) at sigma_dev (device FP64
+ * [n_params], updated in place): forward, residual obs - data, adjoint, gradient g^m,
  * beta^m = |g^m|^2 / |g^{m-1}|^2 (beta^0 = 0), d^m = -g^m + beta^m d^{m-1},
  * alpha^m = alpha_rel / max|d^m|, sigma <- clip(sigma + alpha^m d^m, 0, 4)
  * on the free cubes.  All of it in FP64 on the device; the direction d lives
@@ -206,6 +231,12 @@ const char *hyb_last_error(const hyb_ctx *ctx);
  * nodes updated per step. */
 hyb_status hyb_counts(const hyb_ctx *ctx, int64_t *fdm, int64_t *fem);
 
+/* The FEM box of a context: *n_params = number of conductivity values
+ * (cubes, or tetrahedra of a general mesh; 0 without FEM box), *general = 1
+ * on the general path, *n_fem_nodes = FEM nodes (length of the FEM part of
+ * hyb_get_wavefield).  Any pointer may be NULL. */
+hyb_status hyb_fem_info(const hyb_ctx *ctx, int64_t *n_params, int32_t *general, int64_t *n_fem_nodes);
+
 /* Average device time (ms) of one launch of the dominant kernel (the fused
  * FDM/FEM interior update of the forward sweep) over `reps` launches on the
  * context's stream, measured with HIP events around the launches, after the
@@ -215,6 +246,16 @@ hyb_status hyb_counts(const hyb_ctx *ctx, int64_t *fdm, int64_t *fem);
 hyb_status hyb_time_interior(hyb_ctx *ctx, const double *sigma_dev, double dt, int32_t reps,
                              double *ms_host);
 
+/* Average device time (ms) of one launch of the FEM row kernel of a general
+ * mesh (which 0: forward rows, which 1: adjoint rows with the gradient
+ * accumulation) over `reps` launches, with HIP events on the context's
+ * stream, at the conductivity and dt of the last forward.  Needs a previous
+ * hyb_forward (and hyb_adjoint for which 1); the launches overwrite the
+ * fields, so the sweeps are no longer available afterwards.  Synchronises.
+ * Errors: HYB_E_ARG, HYB_E_STATE (no general mesh or no previous sweep),
+ * HYB_E_DEVICE. */
+hyb_status hyb_time_fem(hyb_ctx *ctx, int32_t which, int32_t reps, double *ms_host);
+
 /* Copy the newest level of the last sweep to caller buffers (FP64, unpadded):
  *   which 0: u^{nt} of the last forward sweep;
  *   which 1: the multipliers of level 0 of the last adjoint sweep, i.e. the
@@ -223,7 +264,8 @@ hyb_status hyb_time_interior(hyb_ctx *ctx, const double *sigma_dev, double dt, i
  * Grid nodes strictly inside the hole (o+2, o+C-2)^3 belong to no grid row
  * (the FEM part holds the solution there) and are returned as 0.
  * u_dev: device [(n_z+1)(n_y+1)(n_x+1)] grid part (nullable);
- * v_dev: device [(C+1)^3] FEM part (nullable; ignored without FEM box).
+ * v_dev: device [n_fem_nodes] FEM part in the mesh's node order (nullable;
+ *        ignored without FEM box).
  * Errors: HYB_E_ARG, HYB_E_STATE (no such sweep yet). */
 hyb_status hyb_get_wavefield(hyb_ctx *ctx, int32_t which, double *u_dev, double *v_dev);
 
@@ -252,14 +294,14 @@ hyb_status hyb_batch_create(int32_t max_slots, void *hip_stream, hyb_batch **out
 /* Release the batch (synchronises its stream; contexts stay with the caller). */
 void hyb_batch_destroy(hyb_batch *b);
 
-/* Start a solve on context ctx (FEM box required, full-history store mode)
- * in a free slot.  sigma_dev as in hyb_forward; sigma_max: the caller's
+/* Start a solve on context ctx (structured FEM box required, full-history
+ * store mode) in a free slot.  sigma_dev as in hyb_forward; sigma_max: the caller's
  * value of max(sigma) over the free cubes, used for the CFL check without a
  * device round trip; data_dev, obs_dev [nt+1][face] and grad_dev [C^3] are
  * device FP64 buffers owned by the caller and kept valid until the slot is
  * released.  *slot receives the slot number.
  * Errors: HYB_E_ARG, HYB_E_STATE (no free slot / context busy), HYB_E_CFL,
- * HYB_E_UNSUPPORTED (checkpoint store modes), HYB_E_OOM. */
+ * HYB_E_UNSUPPORTED (checkpoint store modes, general meshes), HYB_E_OOM. */
 hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *ctx, const double *sigma_dev, double sigma_max,
                             const hyb_source *src, int32_t nt, double dt, const double *data_dev,
                             double *obs_dev, double *grad_dev, int32_t *slot);

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhyb.so")
 
-SOURCES = ["hyb_kernels.hip", "hyb_api.cpp"]
+SOURCES = ["hyb_kernels.hip", "hyb_gen.hip", "hyb_api.cpp", "hyb_gen_mesh.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code

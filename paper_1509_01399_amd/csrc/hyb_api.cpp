@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "hyb_gen.h"
 #include "hyb_internal.h"
 
 using namespace hyb;
@@ -61,6 +62,11 @@ struct hyb_ctx {
     int ckK = 1, cur_seg = 0;    // segment length and the segment in the history
     bool in_batch = false;       // owned by a batch slot (single calls refused)
     double dt = 0;
+    // general tetrahedral mesh: per-tetrahedron sigma, FEM rows in hyb_gen.hip
+    bool gen = false;
+    bool gen_all_grid = true;    // every FEM node is a grid node (initial levels allowed)
+    long long npar = 0;          // conductivity parameters: cubes, or tetrahedra
+    GenDev gd{};
     std::string err;
 };
 
@@ -109,11 +115,9 @@ double tet_grads(const double X[4][3], double Gr[4][3])
     return std::fabs(det) / 6.0;
 }
 
-// Check that the mesh is the 6-tetrahedra split of a box of grid cells and
-// extract the box and the per-cube P1 stiffness (a = 1), which must be the
-// same for every cube and couple only along the 12 axis edges (then the FEM
-// update is exactly an edge-conductance stencil, which the kernels use).
-hyb_status analyse_mesh(const hyb_fd_grid *gr, const hyb_fem_mesh *m, Mesh *out, hyb_ctx *c)
+// The FEM box [o, o+C] of a mesh: its bounding box, whose corners must be
+// grid nodes, cubic, >= 5 cells wide and >= 1 cell from the outer boundary.
+hyb_status find_box(const hyb_fd_grid *gr, const hyb_fem_mesh *m, Mesh *out, hyb_ctx *c)
 {
     const double h = gr->h;
     if (m->n_nodes < 8 || m->n_tets < 6 || !m->xyz || !m->tet4)
@@ -140,6 +144,19 @@ hyb_status analyse_mesh(const hyb_fd_grid *gr, const hyb_fem_mesh *m, Mesh *out,
     }
     if (out->C[0] != out->C[1] || out->C[1] != out->C[2])
         return fail(c, HYB_E_UNSUPPORTED, "fem mesh: only cubic FEM boxes are supported");
+    return HYB_OK;
+}
+
+// Check that the mesh (of the box found by find_box) is the 6-tetrahedra
+// split of its cubes and extract the per-cube P1 stiffness (a = 1), which
+// must be the same for every cube and couple only along the 12 axis edges
+// (then the FEM update is exactly an edge-conductance stencil, which the
+// structured kernels use).
+hyb_status analyse_kuhn(const hyb_fd_grid *gr, const hyb_fem_mesh *m, Mesh *out, hyb_ctx *c)
+{
+    const double h = gr->h, tol = 1e-7 * h;
+    double lo[3];
+    for (int d = 0; d < 3; ++d) lo[d] = gr->origin[d] + out->o[d] * h;
     const long long fx = out->C[0] + 1, fy = out->C[1] + 1, fz = out->C[2] + 1;
     const long long ncube = (long long)out->C[0] * out->C[1] * out->C[2];
     if (m->n_nodes != fx * fy * fz || m->n_tets != 6 * ncube)
@@ -258,6 +275,29 @@ hyb_status analyse_mesh(const hyb_fd_grid *gr, const hyb_fem_mesh *m, Mesh *out,
     return HYB_OK;
 }
 
+// The FEM mesh: the structured path when it is the 6-tetrahedra split of its
+// box (one sigma per cube), unless `general` asks for the general path; the
+// general path (one sigma per tetrahedron) otherwise.
+hyb_status analyse_fem(const hyb_fd_grid *gr, const hyb_fem_mesh *m, bool general, Mesh *mesh, GenHost *gh,
+                       bool *gen, hyb_ctx *c)
+{
+    hyb_status s = find_box(gr, m, mesh, c);
+    if (s) return s;
+    if (!general) {
+        s = analyse_kuhn(gr, m, mesh, c);
+        if (s == HYB_OK) {
+            *gen = false;
+            return HYB_OK;
+        }
+        if (s == HYB_E_ARG) return s;
+    }
+    std::string err;
+    s = analyse_general(gr, m, mesh->o, mesh->C, *gh, err);
+    if (s) return fail(c, s, err);
+    *gen = true;
+    return HYB_OK;
+}
+
 hyb_status check_grid(const hyb_fd_grid *gr, hyb_ctx *c)
 {
     if (!gr) return fail(c, HYB_E_ARG, "grid is null");
@@ -338,10 +378,26 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
         g.n_fem_blocks = 0;
     }
     g.bnd_blocks = (int)ceil_div(g.nbnd + g.nwd + g.nwo, BLOCK);  // informational
+    g.fem_n = has_fem ? (long long)(g.C[0] + 1) * (g.C[1] + 1) * (g.C[2] + 1) : 0;
+    g.gen = 0;
+}
+
+// A general mesh of the same box: no structured FEM tiles, exchanges or
+// history box; the history holds the nodes [0, nH) of the device numbering.
+void setup_geo_gen(Geo &g, const GenHost &gh)
+{
+    g.gen = 1;
+    g.n_fem_blocks = 0;
+    g.fem_tiles[0] = g.fem_tiles[1] = g.fem_tiles[2] = 0;
+    g.nwd = g.nwo = 0;
+    g.hn[0] = g.hn[1] = g.hn[2] = 0;
+    g.hlevel = gh.nH;
+    g.fem_n = gh.fn;
+    g.bnd_blocks = (int)ceil_div(g.nbnd, BLOCK);
 }
 
 size_t field_bytes(const Geo &g, size_t esz) { return (size_t)g.plane * g.nz * esz; }
-size_t fem_bytes(const Geo &g, size_t esz) { return g.has_fem ? (size_t)g.fplane * (g.C[2] + 1) * esz : 0; }
+size_t fem_bytes(const Geo &g, size_t esz) { return g.has_fem ? (size_t)g.fem_n * esz : 0; }
 size_t cube_count(const Geo &g) { return (size_t)g.C[0] * g.C[1] * g.C[2]; }
 
 int face_types(const hyb_ctx *c, int step)
@@ -372,6 +428,61 @@ void dfree(void *&p)
 {
     if (p) (void)hipFree(p);
     p = nullptr;
+}
+
+template <typename V>
+hyb_status upload(hyb_ctx *c, V *&dst, const std::vector<V> &src)
+{
+    hyb_status s = dmalloc(c, (void **)&dst, std::max<size_t>(src.size(), 1) * sizeof(V));
+    if (s) return s;
+    if (!src.empty()) HIPCHK(c, hipMemcpy(dst, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
+    return HYB_OK;
+}
+
+// Device tables of a general mesh (hyb_gen.h); the omega_diamond / omega_o
+// nodes get their padded grid indices here.
+hyb_status upload_gen(hyb_ctx *c, const GenHost &gh)
+{
+    GenDev &d = c->gd;
+    d.fn = gh.fn; d.nA = gh.nA; d.nH = gh.nH; d.nR = gh.nR; d.ntet = gh.ntet;
+    d.nslice = gh.nslice; d.nnz = gh.nnz; d.nE = gh.nE;
+    c->gen_all_grid = gh.all_grid;
+    const Geo &g = c->g;
+    std::vector<int64_t> wdg(gh.nA), wog(gh.fn - gh.nR);
+    auto pad = [&](long long n) {
+        return gh.gq[3 * n] + g.px * gh.gq[3 * n + 1] + g.plane * (long long)gh.gq[3 * n + 2];
+    };
+    for (long long n = 0; n < gh.nA; ++n) wdg[n] = pad(n);
+    for (long long n = gh.nR; n < gh.fn; ++n) wog[n - gh.nR] = pad(n);
+    hyb_status s = HYB_OK;
+    if (!s) s = upload(c, d.soff, gh.soff);
+    if (!s) s = upload(c, d.eoff, gh.eoff);
+    if (!s) s = upload(c, d.col, gh.col);
+    if (!s) s = upload(c, d.eid, gh.eid);
+    if (!s) s = upload(c, d.cptr, gh.cptr);
+    if (!s) s = upload(c, d.ctet, gh.ctet);
+    if (!s) s = upload(c, d.cw, gh.cw);
+    if (!s) s = upload(c, d.minv, gh.minv);
+    if (!s) s = upload(c, d.ke6, gh.ke6);
+    if (!s) s = upload(c, d.pvol, gh.pvol);
+    if (!s) s = upload(c, d.tetE, gh.tetE);
+    if (!s) s = upload(c, d.orig_of_dev, gh.orig_of_dev);
+    if (!s) s = upload(c, d.grid_lin, gh.grid_lin);
+    if (!s) s = upload(c, d.wdg, wdg);
+    if (!s) s = upload(c, d.wog, wog);
+    if (!s) s = dmalloc(c, &d.kap, (size_t)std::max<long long>(gh.nnz, 1) * c->esz);
+    if (!s) s = dmalloc(c, &d.cn, (size_t)gh.fn * c->esz);
+    if (!s) s = dmalloc(c, (void **)&d.E, (size_t)std::max<long long>(gh.nE, 1) * sizeof(double));
+    return s;
+}
+
+void free_gen(GenDev &d)
+{
+    dfree((void *&)d.soff); dfree((void *&)d.eoff); dfree((void *&)d.col); dfree((void *&)d.eid);
+    dfree((void *&)d.cptr); dfree((void *&)d.ctet); dfree((void *&)d.cw); dfree((void *&)d.minv);
+    dfree((void *&)d.ke6); dfree((void *&)d.pvol); dfree((void *&)d.E); dfree((void *&)d.tetE);
+    dfree((void *&)d.orig_of_dev); dfree((void *&)d.grid_lin); dfree((void *&)d.wdg);
+    dfree((void *&)d.wog); dfree(d.kap); dfree(d.cn);
 }
 
 template <typename T>
@@ -511,6 +622,36 @@ Step<T> adj_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, const double *r
     return s;
 }
 
+// The general FEM step that goes with a grid step: the same buffers (see
+// GenStep), the device tables of the mesh.
+template <typename T>
+GenStep<T> gen_args(const hyb_ctx *c, const Step<T> &s)
+{
+    GenStep<T> q;
+    std::memset(&q, 0, sizeof q);
+    const GenDev &d = c->gd;
+    q.fn = d.fn; q.nA = d.nA; q.nH = d.nH; q.nR = d.nR;
+    q.px = c->g.px; q.plane = c->g.plane;
+    q.soff = d.soff; q.eoff = d.eoff; q.col = d.col;
+    q.kap = (const T *)d.kap; q.cn = (const T *)d.cn;
+    q.wdg = d.wdg; q.wog = d.wog;
+    q.Ub = s.Ub; q.Uc = s.Uc;
+    q.Va = s.Va; q.Vb = s.Vb; q.Vc = s.Vc;
+    q.VDa = s.VDa; q.VDc = s.VDc;
+    q.hist = s.hist;
+    q.E = d.E;
+    q.c2 = s.c2;
+    return q;
+}
+
+// History level L of the FEM nodes [0, nH) from a FEM level (general mesh).
+template <typename T>
+hyb_status gen_hist_level(hyb_ctx *c, const void *V, T *h)
+{
+    HIPCHK(c, hipMemcpyAsync(h, V, (size_t)c->gd.nH * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+    return HYB_OK;
+}
+
 // Zero the multipliers and the gradient accumulator; the misfit J of mode 0.
 template <typename T>
 hyb_status adj_setup(hyb_ctx *c, const double *res, int mode)
@@ -528,7 +669,8 @@ hyb_status adj_setup(hyb_ctx *c, const double *res, int mode)
             HIPCHK(c, hipMemsetAsync(c->E[q], 0, fb, st));
             if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->QE[q], 0, vb, st));
         }
-    if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
+    if (c->gen) HIPCHK(c, hipMemsetAsync(c->gd.E, 0, std::max<long long>(c->gd.nE, 1) * sizeof(double), st));
+    else if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
     if (mode == 0) launch_misfit(g, res, c->nt, c->dt, c->h, c->partials, c->scal, S_JMIS, st);
     else HIPCHK(c, hipMemsetAsync(c->scal + S_JMIS, 0, sizeof(double), st));
     return HYB_OK;
@@ -551,17 +693,29 @@ hyb_status fwd_setup(hyb_ctx *c, double *obs)
             if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->VD[q], 0, vb, st));
         }
     if (c->ic_set) {
-        if (c->ic_u0) launch_load_level<T>(g, c->ic_u0, (T *)c->U[1], (T *)c->V[1], st);
-        if (incr_form<T>())
-            launch_load_incr<T>(g, c->ic_u0, c->ic_um1, (T *)c->D[0], (T *)c->VD[0], st);
-        else if (c->ic_um1)
-            launch_load_level<T>(g, c->ic_um1, (T *)c->U[0], (T *)c->V[0], st);
+        // a general mesh loads its FEM part through its node -> grid map
+        Geo gg = g;
+        if (c->gen) gg.has_fem = 0;
+        if (c->ic_u0) {
+            launch_load_level<T>(gg, c->ic_u0, (T *)c->U[1], (T *)c->V[1], st);
+            if (c->gen) launch_gen_load<T>(c->gd, c->ic_u0, (T *)c->V[1], st);
+        }
+        if (incr_form<T>()) {
+            launch_load_incr<T>(gg, c->ic_u0, c->ic_um1, (T *)c->D[0], (T *)c->VD[0], st);
+            if (c->gen) launch_gen_load_incr<T>(c->gd, c->ic_u0, c->ic_um1, (T *)c->VD[0], st);
+        } else if (c->ic_um1) {
+            launch_load_level<T>(gg, c->ic_um1, (T *)c->U[0], (T *)c->V[0], st);
+            if (c->gen) launch_gen_load<T>(c->gd, c->ic_um1, (T *)c->V[0], st);
+        }
         c->ic_set = false;
         c->ic_u0 = c->ic_um1 = nullptr;
     }
     c->cur_seg = c->store_mode ? c->nt / c->ckK : 0;
     if (obs) launch_record_face<T>(g, (const T *)c->U[1], obs, st);
-    if (T *h0 = hist_ptr<T>(c, 0)) launch_hist_level<T>(g, (const T *)c->V[1], h0, st);
+    if (T *h0 = hist_ptr<T>(c, 0)) {
+        if (c->gen) return gen_hist_level<T>(c, c->V[1], h0);
+        launch_hist_level<T>(g, (const T *)c->V[1], h0, st);
+    }
     return HYB_OK;
 }
 
@@ -575,6 +729,7 @@ hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, doub
     for (int k = k0; k < k1; ++k) {
         const Step<T> s = fwd_step_args<T>(c, k, ia, ib, ic, obs);
         launch_interior<T>(s, false, st);
+        if (c->gen) launch_gen_fwd<T>(gen_args<T>(c, s), st);
         launch_bnd_fwd<T>(s, st);
         const int t = ia; ia = ib; ib = ic; ic = t;
         if (save && (k + 1) % c->ckK == 0) {
@@ -617,7 +772,14 @@ hyb_status load_segment(hyb_ctx *c, int L)
     c->cur_seg = seg;
     c->u_valid = false;
     const int lo = seg * c->ckK, hi = std::min(lo + c->ckK - 1, c->nt);
-    if (T *h0 = hist_ptr<T>(c, lo)) launch_hist_level<T>(c->g, (const T *)c->V[1], h0, c->stream);
+    if (T *h0 = hist_ptr<T>(c, lo)) {
+        if (c->gen) {
+            hyb_status r2 = gen_hist_level<T>(c, c->V[1], h0);
+            if (r2) return r2;
+        } else {
+            launch_hist_level<T>(c->g, (const T *)c->V[1], h0, c->stream);
+        }
+    }
     int ia = 0, ib = 1, ic = 2;
     return fwd_steps<T>(c, lo, hi, ia, ib, ic, nullptr, false);
 }
@@ -637,6 +799,7 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
         }
         const Step<T> s = adj_step_args<T>(c, k, ia, ib, ic, res, mode);
         launch_bnd_adj<T>(s, st);
+        if (c->gen) launch_gen_adj<T>(gen_args<T>(c, s), st);
         launch_interior<T>(s, true, st);
         const int t = ia; ia = ib; ib = ic; ic = t;
     }
@@ -673,10 +836,12 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
     hyb_status s = check_grid(grid, nullptr);
     if (s) return s;
     Mesh mesh;
+    GenHost gh;
+    bool gen = false;
     if (fem) {
         if (!overlap || overlap->width_cells != 2)
             return fail(nullptr, HYB_E_UNSUPPORTED, "overlap: the method uses a two-element overlap");
-        s = analyse_mesh(grid, fem, &mesh, nullptr);
+        s = analyse_fem(grid, fem, opts && opts->fem_general, &mesh, &gh, &gen, nullptr);
         if (s) return s;
     }
     hyb_ctx *c = new hyb_ctx();
@@ -702,8 +867,11 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
     c->esz = c->f32 ? 4 : 8;
     c->mesh = mesh;
     setup_geo(c->g, c->n, mesh, fem != nullptr, c->esz);
+    c->gen = gen;
+    if (gen) setup_geo_gen(c->g, gh);
+    c->npar = gen ? gh.ntet : (long long)cube_count(c->g);
     const size_t fb = field_bytes(c->g, c->esz), vb = fem_bytes(c->g, c->esz);
-    const size_t nc = cube_count(c->g);
+    const size_t nc = (size_t)c->npar;
     s = HYB_OK;
     for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->U[q], fb);
     if (!s && c->g.has_fem)
@@ -713,8 +881,9 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
         if (!s && c->g.has_fem)
             for (int q = 0; q < 2 && !s; ++q) s = dmalloc(c, &c->VD[q], vb);
     }
-    if (!s && c->g.has_fem) s = dmalloc(c, &c->acube, nc * c->esz);
+    if (!s && c->g.has_fem && !gen) s = dmalloc(c, &c->acube, nc * c->esz);
     if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->sig, nc * sizeof(double));
+    if (!s && gen) s = upload_gen(c, gh);
     if (!s) s = dmalloc(c, (void **)&c->partials, MAX_PARTIALS * sizeof(double));
     if (!s) s = dmalloc(c, (void **)&c->scal, S_NSCAL * sizeof(double));
     if (s) {
@@ -744,6 +913,7 @@ void hyb_destroy(hyb_ctx *c)
         dfree(c->QE[q]);
     }
     dfree(c->acube);
+    free_gen(c->gd);
     dfree(c->hist);
     dfree(c->ckpt);
     dfree((void *&)c->sig);
@@ -760,6 +930,8 @@ void hyb_destroy(hyb_ctx *c)
 hyb_status hyb_set_initial(hyb_ctx *c, const double *u0, const double *um1)
 {
     if (!c) return HYB_E_ARG;
+    if (c->gen && !c->gen_all_grid && (u0 || um1))
+        return fail(c, HYB_E_UNSUPPORTED, "initial levels need every FEM node on the grid");
     c->ic_u0 = u0;
     c->ic_um1 = um1;
     c->ic_set = u0 || um1;
@@ -786,26 +958,53 @@ hyb_status prepare_forward(hyb_ctx *c, const double *sigma, const hyb_source *sr
         return fail(c, HYB_E_ARG, "source: unknown kind");
     }
     if (!c->g.has_fem && sigma) return fail(c, HYB_E_ARG, "sigma given without a FEM box");
+    if (sigma_max_host && !std::isfinite(*sigma_max_host))
+        return fail(c, HYB_E_NONFINITE, "sigma_max is not finite");
+    if (c->gen && sigma_max_host) return fail(c, HYB_E_UNSUPPORTED, "general meshes take sigma_max from the device");
     const hipStream_t st = c->stream;
-    double smax = 0.0;
-    if (c->g.has_fem) {
+    // From here on the device conductivity of the context is replaced: a
+    // refused step below also invalidates the previous sweeps.
+    auto refuse = [&](hyb_status e, const char *msg) {
+        c->have_forward = c->have_adjoint = c->u_valid = false;
+        return fail(c, e, msg);
+    };
+    double smax = 0.0, gersh = 0.0;
+    if (c->g.has_fem && c->gen) {
+        if (c->f32) launch_gen_prepare<float>(c->gd, sigma, dt * dt, c->partials, c->scal, st);
+        else launch_gen_prepare<double>(c->gd, sigma, dt * dt, c->partials, c->scal, st);
+        double hs[S_NSCAL];
+        HIPCHK(c, hipMemcpyAsync(hs, c->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (hs[S_BAD] != 0.0) return refuse(HYB_E_NONFINITE, "sigma has non-finite entries");
+        smax = hs[S_SMAX];
+        gersh = hs[S_GERSH];
+    } else if (c->g.has_fem) {
         if (c->f32) launch_acube<float>(c->g, sigma, (float *)c->acube, c->partials, c->scal, st);
         else launch_acube<double>(c->g, sigma, (double *)c->acube, c->partials, c->scal, st);
         if (sigma_max_host) {
-            if (!std::isfinite(*sigma_max_host)) return fail(c, HYB_E_NONFINITE, "sigma_max is not finite");
             smax = *sigma_max_host;
         } else {
             double hs[2];
             HIPCHK(c, hipMemcpyAsync(hs, c->scal + S_SMAX, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(c, hipStreamSynchronize(st));
-            if (hs[1] != 0.0) return fail(c, HYB_E_NONFINITE, "sigma has non-finite entries");
+            if (hs[1] != 0.0) return refuse(HYB_E_NONFINITE, "sigma has non-finite entries");
             smax = hs[0];
         }
     }
-    // CFL condition, eq. (CFL): tau <= h / sqrt(3 a) with the largest a
-    const double amax = 1.0 + std::max(0.0, smax);
-    if (dt > c->h / std::sqrt(3.0 * amax) * (1.0 + 1e-12))
-        return fail(c, HYB_E_CFL, "dt violates the CFL bound h/sqrt(3 a_max)");
+    if (c->gen) {
+        // grid rows (a = 1): tau <= h / sqrt(3); FEM rows on a general mesh:
+        // tau^2 times the Gershgorin bound of M^{-1} K(a) at most 4
+        if (dt > c->h / std::sqrt(3.0) * (1.0 + 1e-12))
+            return refuse(HYB_E_CFL, "dt violates the CFL bound h/sqrt(3) of the grid");
+        if (dt * dt * gersh > 4.0 * (1.0 + 1e-12))
+            return refuse(HYB_E_CFL, "dt violates the bound dt^2 max_n (|K_nn| + sum_m |K_nm|) / m_n <= 4 "
+                                     "of the FEM mesh");
+    } else {
+        // CFL condition, eq. (CFL): tau <= h / sqrt(3 a) with the largest a
+        const double amax = 1.0 + std::max(0.0, smax);
+        if (dt > c->h / std::sqrt(3.0 * amax) * (1.0 + 1e-12))
+            return refuse(HYB_E_CFL, "dt violates the CFL bound h/sqrt(3 a_max)");
+    }
     // sqrt(nt) segmentation of the levels 0..nt (checkpoint modes)
     c->ckK = c->store_mode ? (int)std::ceil(std::sqrt((double)nt + 1.0)) : nt + 1;
     if (c->store_mode) {
@@ -828,9 +1027,9 @@ hyb_status prepare_forward(hyb_ctx *c, const double *sigma, const hyb_source *sr
             if (s) return s;
             c->hist_levels = need;
         }
-        if (sigma) HIPCHK(c, hipMemcpyAsync(c->sig, sigma, cube_count(c->g) * sizeof(double),
+        if (sigma) HIPCHK(c, hipMemcpyAsync(c->sig, sigma, (size_t)c->npar * sizeof(double),
                                            hipMemcpyDeviceToDevice, st));
-        else HIPCHK(c, hipMemsetAsync(c->sig, 0, cube_count(c->g) * sizeof(double), st));
+        else HIPCHK(c, hipMemsetAsync(c->sig, 0, (size_t)c->npar * sizeof(double), st));
     }
     c->nt = nt;
     c->dt = dt;
@@ -857,7 +1056,7 @@ hyb_status alloc_adjoint(hyb_ctx *c)
     for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->F[q], (size_t)c->g.ftot * c->esz);
     if (!s && c->g.has_fem)
         for (int q = 0; q < 3 && !s; ++q) s = dmalloc(c, &c->Q[q], vb);
-    if (!s && c->g.has_fem) s = dmalloc(c, (void **)&c->G, cube_count(c->g) * sizeof(double));
+    if (!s && c->g.has_fem && !c->gen) s = dmalloc(c, (void **)&c->G, cube_count(c->g) * sizeof(double));
     if (c->f32) {
         for (int q = 0; q < 2 && !s; ++q) s = dmalloc(c, &c->E[q], fb);
         if (!s && c->g.has_fem)
@@ -908,8 +1107,11 @@ hyb_status hyb_gradient(hyb_ctx *c, double *grad, double *J)
     // dJ/dsigma_c = -(dt^2/h^2) G_c (G = sum_k sum_e w_e D_e lambda^{k+1} D_e u^k)
     const double dJ = -(c->dt * c->dt) / (h * h);
     const int mode = c->adj_mode;
-    launch_grad_final(c->g, c->G, c->sig, mode == 0 ? dJ / h3 : dJ, c->gamma, mode, h3, grad, c->partials,
-                      c->scal, S_JREG, c->stream);
+    if (c->gen)
+        launch_gen_grad_final(c->gd, c->sig, c->gamma, mode, grad, c->partials, c->scal, S_JREG, c->stream);
+    else
+        launch_grad_final(c->g, c->G, c->sig, mode == 0 ? dJ / h3 : dJ, c->gamma, mode, h3, grad, c->partials,
+                          c->scal, S_JREG, c->stream);
     HIPCHK(c, hipGetLastError());
     if (J) {
         double hs[2];
@@ -927,8 +1129,8 @@ hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_
     if (!data || !sigma || !state) return fail(c, HYB_E_ARG, "cg_step: null argument");
     if (!c->g.has_fem) return fail(c, HYB_E_STATE, "cg_step needs a FEM box");
     hyb_status s = ensure_trace_bufs(c, nt);
-    if (!s) s = dmalloc(c, (void **)&c->dir, cube_count(c->g) * sizeof(double));
-    if (!s) s = dmalloc(c, (void **)&c->grad, cube_count(c->g) * sizeof(double));
+    if (!s) s = dmalloc(c, (void **)&c->dir, (size_t)c->npar * sizeof(double));
+    if (!s) s = dmalloc(c, (void **)&c->grad, (size_t)c->npar * sizeof(double));
     if (s) return s;
     s = hyb_forward(c, sigma, src, nt, dt, c->obsbuf);
     if (s) return s;
@@ -939,9 +1141,15 @@ hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_
     s = hyb_gradient(c, c->grad, nullptr);
     if (s) return s;
     const double h3 = c->h * c->h * c->h;
-    launch_norm2(c->g, c->grad, h3, c->partials, c->scal, S_GN2, c->stream);
-    launch_cg_dir(c->g, c->grad, c->dir, state->iter == 0, c->partials, c->scal, c->stream);
-    launch_cg_update(c->g, c->dir, sigma, c->alpha_rel, c->scal, c->stream);
+    if (c->gen) {
+        launch_gen_norm2(c->gd, c->grad, c->partials, c->scal, S_GN2, c->stream);
+        launch_gen_cg_dir(c->gd, c->grad, c->dir, state->iter == 0, c->partials, c->scal, c->stream);
+        launch_gen_cg_update(c->gd, c->dir, sigma, c->alpha_rel, c->scal, c->stream);
+    } else {
+        launch_norm2(c->g, c->grad, h3, c->partials, c->scal, S_GN2, c->stream);
+        launch_cg_dir(c->g, c->grad, c->dir, state->iter == 0, c->partials, c->scal, c->stream);
+        launch_cg_update(c->g, c->dir, sigma, c->alpha_rel, c->scal, c->stream);
+    }
     HIPCHK(c, hipGetLastError());
     state->iter += 1;
     if (gnorm || J) {
@@ -962,19 +1170,26 @@ hyb_status hyb_footprint(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const
     hyb_status s = check_grid(grid, nullptr);
     if (s) return s;
     Mesh mesh;
+    GenHost gh;
+    bool gen = false;
     if (fem) {
         if (!overlap || overlap->width_cells != 2)
             return fail(nullptr, HYB_E_UNSUPPORTED, "overlap: the method uses a two-element overlap");
-        s = analyse_mesh(grid, fem, &mesh, nullptr);
+        s = analyse_fem(grid, fem, opts && opts->fem_general, &mesh, &gh, &gen, nullptr);
         if (s) return s;
     }
     const size_t esz = (opts && opts->field_f32) ? 4 : 8;
     Geo g{};
     int n[3] = {grid->n_cells[0], grid->n_cells[1], grid->n_cells[2]};
     setup_geo(g, n, mesh, fem != nullptr, esz);
-    const size_t nc = cube_count(g), ntr = (size_t)(nt + 1) * g.nx * g.ny * sizeof(double);
+    if (gen) setup_geo_gen(g, gh);
+    const size_t nc = gen ? (size_t)gh.ntet : cube_count(g), ntr = (size_t)(nt + 1) * g.nx * g.ny * sizeof(double);
     const int nlev = esz == 4 ? 10 : 6;  // three U and P levels (+ two increments each in FP32)
     size_t b = nlev * field_bytes(g, esz) + nlev * fem_bytes(g, esz) + nc * (esz + 4 * sizeof(double));
+    if (gen)  // tables of hyb_gen.h
+        b += (size_t)gh.nnz * (8 + esz) + gh.cw.size() * 12 + (size_t)gh.fn * (8 + esz + 4 + 8) +
+             (size_t)gh.nE * 8 + (size_t)gh.ntet * (6 * 12 + 8) + (size_t)(gh.nA + gh.fn - gh.nR) * 8 +
+             (gh.soff.size() + gh.eoff.size()) * 4 - nc * esz;
     b += (size_t)(nt + 1) * g.hlevel * esz + 2 * ntr + (MAX_PARTIALS + S_NSCAL) * sizeof(double);
     b += 3 * (size_t)g.ftot * esz;
     const int sm = opts ? opts->store_mode : 0;
@@ -1007,7 +1222,16 @@ hyb_status hyb_counts(const hyb_ctx *c, int64_t *fdm, int64_t *fem)
     const long long nn = (long long)g.nx * g.ny * g.nz;
     const long long hole = g.has_fem ? (long long)(g.C[0] - 3) * (g.C[1] - 3) * (g.C[2] - 3) : 0;
     *fdm = nn - hole;
-    *fem = g.has_fem ? (long long)(g.C[0] - 1) * (g.C[1] - 1) * (g.C[2] - 1) : 0;
+    *fem = c->gen ? c->gd.nR : (g.has_fem ? (long long)(g.C[0] - 1) * (g.C[1] - 1) * (g.C[2] - 1) : 0);
+    return HYB_OK;
+}
+
+hyb_status hyb_fem_info(const hyb_ctx *c, int64_t *n_params, int32_t *general, int64_t *n_fem_nodes)
+{
+    if (!c) return HYB_E_ARG;
+    if (n_params) *n_params = c->g.has_fem ? c->npar : 0;
+    if (general) *general = c->gen ? 1 : 0;
+    if (n_fem_nodes) *n_fem_nodes = c->g.has_fem ? c->g.fem_n : 0;
     return HYB_OK;
 }
 
@@ -1020,13 +1244,63 @@ hyb_status hyb_get_wavefield(hyb_ctx *c, int32_t which, double *u, double *v)
     void *const *B = which == 0 ? c->V : c->Q;
     const int q = which == 0 ? c->last_u : c->last_p;
     const void *Fq = which == 1 ? c->F[q] : nullptr;  // true boundary multipliers
+    double *vs = c->gen ? nullptr : v;  // a general mesh exports in the caller's node numbering
     if (c->f32)
-        launch_export_level<float>(c->g, (const float *)A[q], (const float *)B[q], (const float *)Fq, u, v,
+        launch_export_level<float>(c->g, (const float *)A[q], (const float *)B[q], (const float *)Fq, u, vs,
                                    c->stream);
     else
         launch_export_level<double>(c->g, (const double *)A[q], (const double *)B[q], (const double *)Fq, u,
-                                    v, c->stream);
+                                    vs, c->stream);
+    if (c->gen && v) {
+        if (c->f32) launch_gen_export<float>(c->gd, (const float *)B[q], v, c->stream);
+        else launch_gen_export<double>(c->gd, (const double *)B[q], v, c->stream);
+    }
     HIPCHK(c, hipGetLastError());
+    return HYB_OK;
+}
+
+hyb_status hyb_time_fem(hyb_ctx *c, int32_t which, int32_t reps, double *ms)
+{
+    if (!c || !ms || reps < 1 || (which != 0 && which != 1)) return HYB_E_ARG;
+    if (!c->gen) return fail(c, HYB_E_STATE, "time_fem: the FEM box is not a general mesh");
+    if (!c->have_forward || !c->hist) return fail(c, HYB_E_STATE, "time_fem needs a previous forward");
+    if (which == 1 && !c->have_adjoint) return fail(c, HYB_E_STATE, "time_fem (adjoint) needs a previous adjoint");
+    const hipStream_t st = c->stream;
+    // the launches overwrite the wavefields, multipliers and accumulators
+    c->have_forward = false;
+    c->u_valid = false;
+    c->have_adjoint = false;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    auto body = [&](auto tag) -> hyb_status {
+        using T = decltype(tag);
+        Step<T> s = make_step<T>(c);
+        void *const *A = which == 0 ? c->U : c->P;
+        void *const *B = which == 0 ? c->V : c->Q;
+        void *const *I = which == 0 ? c->VD : c->QE;
+        int ia = 0, ib = 1, ic = 2;
+        HIPCHK(c, hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) {
+            s.Ub = (const T *)A[ib]; s.Uc = (T *)A[ic];
+            s.Va = (const T *)B[ia]; s.Vb = (const T *)B[ib]; s.Vc = (T *)B[ic];
+            if (incr_form<T>()) { s.VDa = (const T *)I[r & 1]; s.VDc = (T *)I[(r + 1) & 1]; }
+            s.hist = (T *)c->hist;
+            if (which == 0) launch_gen_fwd<T>(gen_args<T>(c, s), st);
+            else launch_gen_adj<T>(gen_args<T>(c, s), st);
+            const int t = ia; ia = ib; ib = ic; ic = t;
+        }
+        HIPCHK(c, hipEventRecord(e1, st));
+        return HYB_OK;
+    };
+    hyb_status s = c->f32 ? body(0.0f) : body(0.0);
+    if (s) return s;
+    HIPCHK(c, hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(c, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = (double)t / reps;
     return HYB_OK;
 }
 
@@ -1035,9 +1309,11 @@ hyb_status hyb_time_interior(hyb_ctx *c, const double *sigma, double dt, int32_t
     if (!c || !ms || reps < 1 || !(dt > 0)) return HYB_E_ARG;
     const hipStream_t st = c->stream;
     if (c->g.has_fem) {
-        if (c->f32) launch_acube<float>(c->g, sigma, (float *)c->acube, c->partials, c->scal, st);
-        else launch_acube<double>(c->g, sigma, (double *)c->acube, c->partials, c->scal, st);
         if (!c->hist) return fail(c, HYB_E_STATE, "time_interior needs a previous forward (history)");
+        if (!c->gen) {
+            if (c->f32) launch_acube<float>(c->g, sigma, (float *)c->acube, c->partials, c->scal, st);
+            else launch_acube<double>(c->g, sigma, (double *)c->acube, c->partials, c->scal, st);
+        }
     }
     // the launches overwrite the wavefields and the first history level
     c->have_forward = false;
@@ -1388,6 +1664,7 @@ hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *c, const double *sigma, doubl
     if (c->in_batch) return bfail(b, HYB_E_STATE, "context already in a batch slot");
     if (!c->g.has_fem || !data || !obs || !grad) return bfail(b, HYB_E_ARG, "batch: needs a FEM box, data, obs, grad");
     if (c->store_mode != 0) return bfail(b, HYB_E_UNSUPPORTED, "batch: contexts must keep the full history");
+    if (c->gen) return bfail(b, HYB_E_UNSUPPORTED, "batch: general FEM meshes are not batched");
     int q = -1;
     for (int i = 0; i < b->max_slots; ++i)
         if (b->slots[i].state == 0) { q = i; break; }

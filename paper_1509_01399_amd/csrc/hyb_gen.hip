@@ -1,0 +1,414 @@
+// HIP kernels (gfx950) of the FEM box on a general tetrahedral mesh: the
+// lumped-mass P1 update of eq. (fem) and its exact adjoint with the FP64
+// gradient integral of eq. (gradient1), on the sliced ELL tables described
+// in hyb_gen.h.  One thread per row; a wavefront owns one 64-row slice, so
+// its column and kappa loads are contiguous, and the neighbour values are
+// gathered (the node numbering follows the grid order of the cells, so the
+// gathers stay within a few z planes of the box and hit the caches).
+#include <algorithm>
+
+#include "hyb_gen.h"
+#include "hyb_internal.h"
+
+namespace hyb {
+
+namespace {
+
+// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// range of rows so that the rows of a neighbourhood share an L2.
+__device__ __forceinline__ long long gen_row(int nblk)
+{
+    const int per = (nblk + 7) / 8;
+    const int b = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
+    return (long long)b * BLOCK + threadIdx.x;
+}
+
+// Forward row n (level k -> k+1):
+//   v^{k+1}_n = 2 v^k_n - v^{k-1}_n - (dt^2 / m_n) sum_m kappa_nm (v^k_n - v^k_m),
+// or in increment form d^{k+1}_n = d^k_n - (dt^2/m_n) (...), v^{k+1} = v^k + d^{k+1}.
+// Rows on omega_diamond also write their new value into the grid level
+// (Algorithm 2, step 3); the omega_o nodes take the new grid values (step 4).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_fwd(GenStep<T> s, int nblk)
+{
+    const long long n = gen_row(nblk);
+    if (n >= s.fn) return;
+    if (n >= s.nR) {
+        s.Vc[n] = s.Uc[s.wog[n - s.nR]];
+        return;
+    }
+    const int sl = (int)(n >> 6), ln = (int)(n & 63);
+    const int b = s.soff[sl], w = (s.soff[sl + 1] - b) >> 6;
+    const T *__restrict__ Vb = s.Vb;
+    const T *__restrict__ kap = s.kap;
+    const int32_t *__restrict__ col = s.col;
+    const T v0 = Vb[n];
+    T acc = 0;
+#pragma unroll 2
+    for (int j = 0; j < w; ++j) {
+        const int p = b + 64 * j + ln;
+        acc += kap[p] * (v0 - Vb[col[p]]);
+    }
+    const T c = s.cn[n];
+    T v;
+    if constexpr (incr_form<T>()) {
+        const T d = s.VDa[n] - c * acc;
+        s.VDc[n] = d;
+        v = v0 + d;
+    } else {
+        v = (T)2 * v0 - s.Va[n] - c * acc;
+    }
+    s.Vc[n] = v;
+    if (n < s.nA) s.Uc[s.wdg[n]] = v;
+    if (n < s.nH && s.hist) __builtin_nontemporal_store(v, s.hist + n);
+}
+
+// Adjoint row n, computing the multipliers of level k from those of levels
+// k+1 and k+2 (the transpose of the forward rows):
+//   mu^k_n = 2 mu^{k+1}_n - mu^{k+2}_n - sum_m kappa_nm (nu_n - nu_m)
+//            [+ (dt/h)^2 sum of the 6 grid multipliers around n, on omega_diamond]
+// with nu_m = (dt^2 / m_m) mu^{k+1}_m (0 off the rows).  The gradient
+// integral pairs u^k with nu: every edge (n, m), n < m, of the inner box
+// accumulates (nu_n - nu_m)(u^k_n - u^k_m) in FP64.  On omega_o (not a row)
+// the thread leaves sum_m kappa_nm nu_m, the coupling of the FEM rows that
+// read the node, in the grid level k for the grid row of the node to add.
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
+{
+    const long long n = gen_row(nblk);
+    if (n >= s.fn) return;
+    const int sl = (int)(n >> 6), ln = (int)(n & 63);
+    const int b = s.soff[sl], w = (s.soff[sl + 1] - b) >> 6;
+    const T *__restrict__ Vb = s.Vb;
+    const T *__restrict__ cn = s.cn;
+    const T *__restrict__ kap = s.kap;
+    const int32_t *__restrict__ col = s.col;
+    if (n >= s.nR) {
+        T acc = 0;
+#pragma unroll 2
+        for (int j = 0; j < w; ++j) {
+            const int p = b + 64 * j + ln;
+            const int m = col[p];
+            acc += kap[p] * (cn[m] * Vb[m]);
+        }
+        s.Uc[s.wog[n - s.nR]] = acc;
+        return;
+    }
+    const T mu1 = Vb[n];
+    const T nu0 = cn[n] * mu1;
+    const bool hrow = n < s.nH;
+    const T *__restrict__ H = s.hist;
+    int eb = 0;
+    double u0 = 0.0;
+    if (hrow) {
+        eb = s.eoff[sl];
+        u0 = (double)H[n];
+    }
+    T acc = 0;
+#pragma unroll 2
+    for (int j = 0; j < w; ++j) {
+        const int p = b + 64 * j + ln;
+        const int m = col[p];
+        const T num = cn[m] * Vb[m];
+        acc += kap[p] * (nu0 - num);
+        if (hrow && m > n && m < s.nH) {
+            double *e = s.E + eb + 64 * j + ln;
+            *e += ((double)nu0 - (double)num) * (u0 - (double)H[m]);
+        }
+    }
+    T cw = 0;
+    if (n < s.nA) {
+        const long long gg = s.wdg[n];
+        const T *Ub = s.Ub;
+        cw = s.c2 * (((Ub[gg - 1] + Ub[gg + 1]) + (Ub[gg - s.px] + Ub[gg + s.px])) +
+                     (Ub[gg - s.plane] + Ub[gg + s.plane]));
+    }
+    if constexpr (incr_form<T>()) {
+        const T d = s.VDa[n] - acc + cw;
+        s.VDc[n] = d;
+        s.Vc[n] = mu1 + d;
+    } else {
+        s.Vc[n] = (T)2 * mu1 - s.Va[n] - acc + cw;
+    }
+}
+
+__device__ double block_reduce_g(double v, bool is_max)
+{
+    __shared__ double sh[BLOCK / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_down(v, off, 64);
+        v = is_max ? fmax(v, o) : v + o;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v = sh[0];
+        for (int q = 1; q < BLOCK / 64; ++q) v = is_max ? fmax(v, sh[q]) : v + sh[q];
+    }
+    return v;
+}
+
+// Fold the partials of a reduction in a fixed order into scal[slot].
+__global__ __launch_bounds__(BLOCK) void k_final_g(const double *part, int n, int is_max, double scale,
+                                                   double *scal, int slot)
+{
+    double v = 0.0;
+    for (int q = threadIdx.x; q < n; q += BLOCK) v = is_max ? fmax(v, part[q]) : v + part[q];
+    v = block_reduce_g(v, is_max != 0);
+    if (threadIdx.x == 0) scal[slot] = v * scale;
+}
+
+int nparts_g(long long n) { return (int)std::min<long long>(MAX_PARTIALS / 2, (n + BLOCK - 1) / BLOCK); }
+
+__global__ __launch_bounds__(BLOCK) void k_gen_sigma(long long nt, const double *pvol, const double *sigma,
+                                                     double *part_max, double *part_bad)
+{
+    double mx = 0.0, bad = 0.0;
+    if (sigma)
+        for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK) {
+            if (!(pvol[t] > 0.0)) continue;
+            const double sv = sigma[t];
+            if (!isfinite(sv)) bad = 1.0;
+            else mx = fmax(mx, sv);
+        }
+    mx = block_reduce_g(mx, true);
+    __syncthreads();
+    bad = block_reduce_g(bad, true);
+    if (threadIdx.x == 0) { part_max[blockIdx.x] = mx; part_bad[blockIdx.x] = bad; }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_prepare(GenDev d, const double *sigma, double dt2, double *part)
+{
+    double R = 0.0;
+    T *kap = (T *)d.kap, *cn = (T *)d.cn;
+    for (long long n = (long long)blockIdx.x * BLOCK + threadIdx.x; n < d.fn; n += (long long)gridDim.x * BLOCK) {
+        const int sl = (int)(n >> 6), ln = (int)(n & 63);
+        const int b = d.soff[sl], w = (d.soff[sl + 1] - b) >> 6;
+        double s1 = 0.0, s2 = 0.0;
+        for (int j = 0; j < w; ++j) {
+            const int p = b + 64 * j + ln;
+            const int e = d.eid[p];
+            double k = 0.0;
+            if (e >= 0)
+                for (int c = d.cptr[e]; c < d.cptr[e + 1]; ++c) {
+                    const int t = d.ctet[c];
+                    const double a = (sigma && d.pvol[t] > 0.0) ? 1.0 + sigma[t] : 1.0;
+                    k -= a * d.cw[c];
+                }
+            kap[p] = (T)k;
+            s1 += k;
+            s2 += fabs(k);
+        }
+        const bool row = n < d.nR;
+        cn[n] = row ? (T)(dt2 * d.minv[n]) : (T)0;
+        if (row) R = fmax(R, (fabs(s1) + s2) * d.minv[n]);
+    }
+    R = block_reduce_g(R, true);
+    if (threadIdx.x == 0) part[blockIdx.x] = R;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_load(long long fn, const int64_t *lin, const double *src, T *V)
+{
+    for (long long n = (long long)blockIdx.x * BLOCK + threadIdx.x; n < fn; n += (long long)gridDim.x * BLOCK)
+        V[n] = lin[n] >= 0 ? (T)src[lin[n]] : (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_load_incr(long long fn, const int64_t *lin, const double *u0,
+                                                         const double *um1, T *VD)
+{
+    for (long long n = (long long)blockIdx.x * BLOCK + threadIdx.x; n < fn; n += (long long)gridDim.x * BLOCK) {
+        const long long g = lin[n];
+        VD[n] = g >= 0 ? (T)((u0 ? u0[g] : 0.0) - (um1 ? um1[g] : 0.0)) : (T)0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_export(long long fn, const int32_t *orig, const T *V, double *v)
+{
+    for (long long n = (long long)blockIdx.x * BLOCK + threadIdx.x; n < fn; n += (long long)gridDim.x * BLOCK)
+        v[orig[n]] = (double)V[n];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gen_grad_final(long long nt, const int32_t *tetE, const double *ke6,
+                                                          const double *E, const double *pvol,
+                                                          const double *sigma, double gamma, int mode,
+                                                          double *grad, double *part)
+{
+    double reg = 0.0;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK) {
+        double v = 0.0;
+        const double vol = pvol[t];
+        if (vol > 0.0) {
+            double ds = 0.0;
+#pragma unroll
+            for (int u = 0; u < 6; ++u) ds += ke6[6 * t + u] * E[tetE[6 * t + u]];
+            if (mode == 0) {
+                const double sv = sigma ? sigma[t] : 0.0;
+                v = ds / vol + gamma * sv;
+                reg += vol * sv * sv;
+            } else {
+                v = ds;
+            }
+        }
+        grad[t] = v;
+    }
+    reg = block_reduce_g(reg, false);
+    if (threadIdx.x == 0) part[blockIdx.x] = reg;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gen_wsumsq(long long nt, const double *pvol, const double *v,
+                                                      double *part)
+{
+    double acc = 0.0;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK)
+        acc += pvol[t] * v[t] * v[t];
+    acc = block_reduce_g(acc, false);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void k_gen_store_beta(double *scal, int first)
+{
+    if (threadIdx.x == 0) scal[S_BETA] = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gen_cg_dir(long long nt, const double *pvol, const double *grad,
+                                                      double *dir, int first, const double *scal, double *part)
+{
+    const double beta = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
+    double mx = 0.0;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK) {
+        double d = 0.0;
+        if (pvol[t] > 0.0) d = first ? -grad[t] : -grad[t] + beta * dir[t];
+        dir[t] = d;
+        mx = fmax(mx, fabs(d));
+    }
+    mx = block_reduce_g(mx, true);
+    if (threadIdx.x == 0) part[blockIdx.x] = mx;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_gen_cg_update(long long nt, const double *pvol, const double *dir,
+                                                         double *sigma, double alpha_rel, double *scal)
+{
+    const double dmax = scal[S_DMAX];
+    const double alpha = dmax > 0.0 ? alpha_rel / dmax : 0.0;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK) {
+        if (!(pvol[t] > 0.0)) continue;
+        const double sv = sigma[t] + alpha * dir[t];
+        sigma[t] = sv < 0.0 ? 0.0 : (sv > 4.0 ? 4.0 : sv);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
+}
+
+__global__ void k_gen_roll_gn2(double *scal)
+{
+    if (threadIdx.x == 0) scal[S_GN2P] = scal[S_GN2];
+}
+
+int row_blocks(long long fn)
+{
+    const long long nb = (fn + BLOCK - 1) / BLOCK;
+    return (int)((nb + 7) / 8 * 8);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_gen_fwd(const GenStep<T> &s, hipStream_t st)
+{
+    const int nb = (int)((s.fn + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL((k_gen_fwd<T>), dim3(row_blocks(s.fn)), dim3(BLOCK), 0, st, s, nb);
+}
+
+template <typename T>
+void launch_gen_adj(const GenStep<T> &s, hipStream_t st)
+{
+    const int nb = (int)((s.fn + BLOCK - 1) / BLOCK);
+    hipLaunchKernelGGL((k_gen_adj<T>), dim3(row_blocks(s.fn)), dim3(BLOCK), 0, st, s, nb);
+}
+
+template <typename T>
+void launch_gen_prepare(const GenDev &d, const double *sigma, double dt2, double *partials, double *scal,
+                        hipStream_t st)
+{
+    const int n1 = nparts_g(d.ntet);
+    hipLaunchKernelGGL(k_gen_sigma, dim3(n1), dim3(BLOCK), 0, st, d.ntet, d.pvol, sigma, partials,
+                       partials + MAX_PARTIALS / 2);
+    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, n1, 1, 1.0, scal, (int)S_SMAX);
+    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials + MAX_PARTIALS / 2, n1, 1, 1.0, scal,
+                       (int)S_BAD);
+    const int n2 = nparts_g(d.fn);
+    hipLaunchKernelGGL((k_gen_prepare<T>), dim3(n2), dim3(BLOCK), 0, st, d, sigma, dt2, partials);
+    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, n2, 1, 1.0, scal, (int)S_GERSH);
+}
+
+template <typename T>
+void launch_gen_load(const GenDev &d, const double *src, T *V, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gen_load<T>), dim3(nparts_g(d.fn)), dim3(BLOCK), 0, st, d.fn, d.grid_lin, src, V);
+}
+
+template <typename T>
+void launch_gen_load_incr(const GenDev &d, const double *u0, const double *um1, T *VD, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gen_load_incr<T>), dim3(nparts_g(d.fn)), dim3(BLOCK), 0, st, d.fn, d.grid_lin, u0,
+                       um1, VD);
+}
+
+template <typename T>
+void launch_gen_export(const GenDev &d, const T *V, double *v, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gen_export<T>), dim3(nparts_g(d.fn)), dim3(BLOCK), 0, st, d.fn, d.orig_of_dev, V, v);
+}
+
+void launch_gen_grad_final(const GenDev &d, const double *sigma, double gamma, int mode, double *grad,
+                           double *partials, double *scal, int slot, hipStream_t st)
+{
+    const int nb = nparts_g(d.ntet);
+    hipLaunchKernelGGL(k_gen_grad_final, dim3(nb), dim3(BLOCK), 0, st, d.ntet, d.tetE, d.ke6, d.E, d.pvol,
+                       sigma, gamma, mode, grad, partials);
+    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 0.5 * gamma, scal, slot);
+}
+
+void launch_gen_norm2(const GenDev &d, const double *v, double *partials, double *scal, int slot,
+                      hipStream_t st)
+{
+    const int nb = nparts_g(d.ntet);
+    hipLaunchKernelGGL(k_gen_wsumsq, dim3(nb), dim3(BLOCK), 0, st, d.ntet, d.pvol, v, partials);
+    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 1.0, scal, slot);
+}
+
+void launch_gen_cg_dir(const GenDev &d, const double *grad, double *dir, int first, double *partials,
+                       double *scal, hipStream_t st)
+{
+    const int nb = nparts_g(d.ntet);
+    hipLaunchKernelGGL(k_gen_store_beta, dim3(1), dim3(64), 0, st, scal, first);
+    hipLaunchKernelGGL(k_gen_cg_dir, dim3(nb), dim3(BLOCK), 0, st, d.ntet, d.pvol, grad, dir, first, scal,
+                       partials);
+    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, nb, 1, 1.0, scal, (int)S_DMAX);
+}
+
+void launch_gen_cg_update(const GenDev &d, const double *dir, double *sigma, double alpha_rel, double *scal,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gen_cg_update, dim3(nparts_g(d.ntet)), dim3(BLOCK), 0, st, d.ntet, d.pvol, dir, sigma,
+                       alpha_rel, scal);
+    hipLaunchKernelGGL(k_gen_roll_gn2, dim3(1), dim3(64), 0, st, scal);
+}
+
+#define HYB_GEN_INST(T)                                                                            \
+    template void launch_gen_fwd<T>(const GenStep<T> &, hipStream_t);                              \
+    template void launch_gen_adj<T>(const GenStep<T> &, hipStream_t);                              \
+    template void launch_gen_prepare<T>(const GenDev &, const double *, double, double *, double *, \
+                                        hipStream_t);                                              \
+    template void launch_gen_load<T>(const GenDev &, const double *, T *, hipStream_t);            \
+    template void launch_gen_load_incr<T>(const GenDev &, const double *, const double *, T *,     \
+                                          hipStream_t);                                            \
+    template void launch_gen_export<T>(const GenDev &, const T *, double *, hipStream_t);
+HYB_GEN_INST(double)
+HYB_GEN_INST(float)
+
+}  // namespace hyb

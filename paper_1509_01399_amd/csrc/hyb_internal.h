@@ -37,6 +37,9 @@ struct Geo {
     int zc_fdm, zc_fem;       // z chunk per block
     int n_fdm_blocks, n_fem_blocks;
     int bnd_blocks;           // blocks of the boundary kernels
+    long long fem_n;          // FEM nodes ((C+1)^3, or the nodes of a general mesh)
+    int gen;                  // general tetrahedral mesh: the FEM rows run in the
+                              // kernels of hyb_gen.hip (n_fem_blocks = nwd = nwo = 0)
 };
 
 // Arguments of one time step.  In the forward sweep the U/V fields are the
@@ -139,7 +142,7 @@ void launch_residual(const double *obs, const double *data, double *res, long lo
 
 // device scalar slots
 enum : int { S_SMAX = 0, S_BAD = 1, S_JMIS = 2, S_JREG = 3, S_GN2 = 4, S_GN2P = 5, S_BETA = 6,
-             S_DMAX = 7, S_ALPHA = 8, S_NSCAL = 16 };
+             S_DMAX = 7, S_ALPHA = 8, S_GERSH = 9, S_NSCAL = 16 };
 constexpr int MAX_PARTIALS = 4096;
 
 }  // namespace hyb

@@ -27,7 +27,8 @@ EXPORTS = ("hyb_create", "hyb_destroy", "hyb_forward", "hyb_set_initial", "hyb_a
            "hyb_gradient", "hyb_cg_step", "hyb_footprint", "hyb_sync", "hyb_last_error",
            "hyb_counts", "hyb_time_interior", "hyb_get_wavefield", "hyb_batch_create",
            "hyb_batch_destroy", "hyb_batch_submit", "hyb_batch_tick", "hyb_batch_poll",
-           "hyb_batch_release", "hyb_batch_last_error", "hyb_batch_poll_all")
+           "hyb_batch_release", "hyb_batch_last_error", "hyb_batch_poll_all", "hyb_fem_info",
+           "hyb_time_fem")
 
 
 class hyb_fd_grid(ct.Structure):
@@ -46,7 +47,7 @@ class hyb_overlap(ct.Structure):
 
 class hyb_opts(ct.Structure):
     _fields_ = [("field_f32", ct.c_int32), ("store_mode", ct.c_int32), ("gamma", ct.c_double),
-                ("alpha_rel", ct.c_double), ("hip_stream", ct.c_void_p)]
+                ("alpha_rel", ct.c_double), ("hip_stream", ct.c_void_p), ("fem_general", ct.c_int32)]
 
 
 class hyb_source(ct.Structure):
@@ -95,6 +96,8 @@ def load():
     lib.hyb_counts.argtypes = [vp, P(ct.c_int64), P(ct.c_int64)]
     lib.hyb_time_interior.argtypes = [vp, vp, dp, ct.c_int32, P(dp)]
     lib.hyb_get_wavefield.argtypes = [vp, ct.c_int32, vp, vp]
+    lib.hyb_fem_info.argtypes = [vp, P(ct.c_int64), P(ct.c_int32), P(ct.c_int64)]
+    lib.hyb_time_fem.argtypes = [vp, ct.c_int32, ct.c_int32, P(dp)]
     lib.hyb_batch_create.argtypes = [ct.c_int32, vp, P(vp)]
     lib.hyb_batch_destroy.argtypes = [vp]
     lib.hyb_batch_destroy.restype = None
@@ -152,8 +155,9 @@ def make_mesh(xyz, tet4):
     return m
 
 
-def make_opts(f32=False, store_mode=0, gamma=0.01, alpha_rel=0.25, stream=None):
+def make_opts(f32=False, store_mode=0, gamma=0.01, alpha_rel=0.25, stream=None, general=False):
     o = hyb_opts()
+    o.fem_general = int(bool(general))
     o.field_f32 = int(bool(f32))
     o.store_mode = int(store_mode)
     o.gamma = gamma
@@ -247,6 +251,19 @@ def hyb_get_wavefield(ctx, which, u, v=None):
     _check(load().hyb_get_wavefield(ctx, int(which), _ptr(u), _ptr(v)), ctx)
 
 
+def hyb_fem_info(ctx):
+    """(number of conductivity values, general mesh?, FEM nodes)."""
+    a, b, c = ct.c_int64(), ct.c_int32(), ct.c_int64()
+    _check(load().hyb_fem_info(ctx, ct.byref(a), ct.byref(b), ct.byref(c)), ctx)
+    return a.value, bool(b.value), c.value
+
+
+def hyb_time_fem(ctx, which, reps):
+    ms = ct.c_double()
+    _check(load().hyb_time_fem(ctx, int(which), int(reps), ct.byref(ms)), ctx)
+    return ms.value
+
+
 def _bcheck(status, b):
     if status != HYB_OK:
         msg = load().hyb_batch_last_error(b)
@@ -302,10 +319,12 @@ def hyb_batch_last_error(b):
 
 class Solver:
     """One problem on one GPU: outer grid n^3 cells (h = 1/n by default), FEM
-    box of C cells at cell offset o (C = 0: pure finite differences)."""
+    box of C cells at cell offset o (C = 0: pure finite differences).  mesh:
+    (xyz, tets) of the FEM box (default: the 6-tetrahedra split of its cubes);
+    general=True runs even that split on the general-mesh path."""
 
     def __init__(self, n, C=0, o=None, h=None, bc=(0, 0, 0, 0, 0, 2), f32=False, store_mode=0,
-                 gamma=0.01, alpha_rel=0.25, stream=None, mesh=None):
+                 gamma=0.01, alpha_rel=0.25, stream=None, mesh=None, general=False):
         import torch
         from . import synth
         self.torch = torch
@@ -319,8 +338,9 @@ class Solver:
             mesh = synth.kuhn_box_mesh(self.o, C, self.h)
         self.mesh = make_mesh(*mesh) if mesh is not None else None
         self.stream = stream if stream is not None else torch.cuda.current_stream().cuda_stream
-        self.opts = make_opts(f32, store_mode, gamma, alpha_rel, self.stream)
+        self.opts = make_opts(f32, store_mode, gamma, alpha_rel, self.stream, general)
         self.ctx = hyb_create(self.grid, self.mesh, 2, self.opts)
+        self.n_params, self.general, self.n_fem_nodes = hyb_fem_info(self.ctx)
         self.nface = (self.n[0] + 1) * (self.n[1] + 1)
         self.nt = None
         self.generation = 0  # counts forward sweeps (the adjoint uses the last one)
@@ -360,8 +380,8 @@ class Solver:
 
     def gradient(self, grad=None, want_J=True):
         if grad is None:
-            grad = self.torch.zeros((self.C, self.C, self.C), dtype=self.torch.float64,
-                                    device=self._dev())
+            shape = (self.n_params,) if self.general else (self.C, self.C, self.C)
+            grad = self.torch.zeros(shape, dtype=self.torch.float64, device=self._dev())
         J = hyb_gradient(self.ctx, grad, want_J)
         return grad, J
 
@@ -370,15 +390,20 @@ class Solver:
         return hyb_cg_step(self.ctx, data, sigma, make_source(omega), nt, dt, state)
 
     def wavefield(self, which=0):
-        """Newest level of the last sweep as (grid [nz,ny,nx], FEM [C+1]^3 or None)."""
+        """Newest level of the last sweep as (grid [nz,ny,nx], FEM part or None):
+        [C+1]^3 on the structured path, [nodes] in mesh order on a general mesh."""
         t = self.torch
         u = t.zeros((self.n[2] + 1, self.n[1] + 1, self.n[0] + 1), dtype=t.float64, device=self._dev())
-        v = (t.zeros((self.C + 1,) * 3, dtype=t.float64, device=self._dev()) if self.C else None)
+        shape = (self.n_fem_nodes,) if self.general else (self.C + 1,) * 3
+        v = (t.zeros(shape, dtype=t.float64, device=self._dev()) if self.C else None)
         hyb_get_wavefield(self.ctx, which, u, v)
         return u, v
 
     def counts(self):
         return hyb_counts(self.ctx)
+
+    def time_fem(self, which=0, reps=20):
+        return hyb_time_fem(self.ctx, which, reps)
 
     def sync(self):
         hyb_sync(self.ctx)

@@ -1,0 +1,231 @@
+"""GPU parity of the general-mesh FEM path (a general tetrahedral mesh of the
+FEM box, one conductivity per tetrahedron) through the C ABI:
+
+- the 6-tetrahedra split run on the general path equals the structured path
+  (traces, fields, cotangents, per-cube gradients as means of their 6
+  tetrahedra, J), from random initial levels;
+- perturbed (unstructured) meshes against the oracle's mesh mode: traces,
+  final fields, the L2 gradient per tetrahedron and J in FP64 (<= 1e-12) and
+  FP32 (trace <= 1e-5, gradient <= 1e-4); the Euclidean gradient of a random
+  trace cotangent on a box with ragged 64-row slices; two CG iterations;
+- checkpoint store modes, the CFL refusal, and the calls a general mesh
+  refuses.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1509_01399_amd import hyb
+    assert torch.cuda.is_available()
+    hyb.load()
+    return torch
+
+
+def _t(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _case(n, C, seed, amp=0.15, o=None):
+    """Perturbed mesh of the box, per-cube inclusions sampled per tetrahedron."""
+    from paper_1509_01399_amd import synth
+    o = (n - C) // 2 if o is None else o
+    h = 1.0 / n
+    xyz, tet = synth.perturbed_box_mesh(o, C, h, seed=seed, amp=amp)
+    sc = synth.cubes(C, seed=seed, edge=(2, 4), value=(1.0, 3.0))
+    st = synth.tet_sigma(xyz, tet, sc, o, C, h)
+    return o, h, xyz, tet, st
+
+
+def test_general_kuhn_equals_structured(env):
+    from paper_1509_01399_amd import synth
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C = 32, 16
+    o, h = (n - C) // 2, 1.0 / n
+    sc = synth.cubes(C, seed=3, edge=(2, 4), value=(1.0, 3.0))
+    dt, nt, om = 0.2 * h, 90, 30.0
+    rng = np.random.default_rng(4)
+    u0 = rng.standard_normal((n + 1,) * 3)
+    um1 = u0 + 0.05 * rng.standard_normal((n + 1,) * 3)
+    out = {}
+    for general in (False, True):
+        print(f"[general] kuhn n={n} C={C} general={general}", flush=True)
+        s = Solver(n, C=C, general=general)
+        assert s.general == general
+        sig = np.repeat(sc.ravel(), 6) if general else sc
+        s.set_initial(_t(torch, u0), _t(torch, um1))
+        obs = s.forward(_t(torch, sig), nt, dt, omega=om)
+        u, v = s.wavefield(0)
+        data = 0.8 * obs
+        s.adjoint(obs - data, mode=0)
+        mu, mv = s.wavefield(1)
+        g, J = s.gradient()
+        out[general] = dict(obs=obs.cpu().numpy(), u=u.cpu().numpy(), v=v.cpu().numpy(), mu=mu.cpu().numpy(),
+                            mv=mv.cpu().numpy(), g=g.cpu().numpy(), J=J)
+        s.close()
+    a, b = out[False], out[True]
+    for k in ("obs", "u", "v", "mu", "mv"):
+        assert rel(b[k], a[k]) <= TOL64, k
+    assert rel(b["g"].reshape(-1, 6).mean(1), a["g"]) <= TOL64
+    assert abs(b["J"] - a["J"]) <= TOL64 * abs(a["J"])
+    assert np.linalg.norm(a["g"]) > 0
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_general_perturbed_parity(env, orc, f32):
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C = 32, 16
+    o, h, xyz, tet, st = _case(n, C, seed=5)
+    dt, nt, om = 0.18 * h, 170, 30.0
+    g = orc.Geometry(n, fem_o=o, fem_c=C, mesh=(xyz, tet))
+    data = orc.forward(g, 0.6 * st, nt, dt, omega=om)
+    print(f"[general] perturbed n={n} C={C} tets={len(tet)} f32={f32}", flush=True)
+    s = Solver(n, C=C, o=o, mesh=(xyz, tet), f32=f32)
+    assert s.general and s.n_params == len(tet) and s.n_fem_nodes == len(xyz)
+    obs = s.forward(_t(torch, st), nt, dt, omega=om)
+    u, v = s.wavefield(0)
+    s.adjoint(obs - _t(torch, data), mode=0)
+    grad, J = s.gradient()
+    obs, u, v, grad = (x.cpu().numpy() for x in (obs, u, v, grad))
+    s.close()
+    ref, vh, uf = orc.forward(g, st, nt, dt, omega=om, want_vhist=True, want_ufinal=True)
+    gref, Jref = orc.gradient(g, st, nt, dt, data, omega=om)
+    free = gref != 0
+    assert free.sum() > 1000 and np.abs(ref).max() > 1e-3
+    e = {"trace": rel(obs, ref), "u": rel(u, uf), "v": rel(v, vh[nt]), "grad": rel(grad, gref),
+         "J": abs(J - Jref) / abs(Jref)}
+    print(f"[general] perturbed f32={f32} errors {e}", flush=True)
+    assert np.all(grad[~free] == 0)
+    if f32:
+        assert e["trace"] <= 1e-5 and e["u"] <= 1e-5 and e["v"] <= 1e-5
+        assert e["grad"] <= 1e-4 and e["J"] <= 1e-5
+    else:
+        assert max(e.values()) <= TOL64
+
+
+def test_general_ragged_euclidean_gradient(env, orc):
+    """Box of 13 cells off centre (14^3 nodes: ragged 64-row slices), Neumann
+    side faces, the Euclidean gradient of a random trace cotangent (mode 1)."""
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C, o = 30, 13, 9
+    bc = (1, 1, 0, 1, 0, 2)
+    o, h, xyz, tet, st = _case(n, C, seed=8, amp=0.12, o=o)
+    dt, nt, om = 0.18 * h, 140, 25.0
+    rng = np.random.default_rng(9)
+    s = Solver(n, C=C, o=o, mesh=(xyz, tet), bc=bc)
+    obs = s.forward(_t(torch, st), nt, dt, omega=om).cpu().numpy()
+    r = rng.standard_normal(obs.shape)
+    s.adjoint(_t(torch, r), mode=1)
+    grad, _ = s.gradient(want_J=False)
+    grad = grad.cpu().numpy()
+    s.close()
+    g = orc.Geometry(n, bc=bc, fem_o=o, fem_c=C, mesh=(xyz, tet))
+    ref = orc.forward(g, st, nt, dt, omega=om)
+    dref = orc.adjoint(g, st, nt, dt, r, omega=om)
+    print(f"[general] ragged trace {rel(obs, ref):.2e} grad {rel(grad, dref):.2e}", flush=True)
+    assert np.count_nonzero(dref) > 500
+    assert rel(obs, ref) <= TOL64 and rel(grad, dref) <= TOL64
+
+
+def test_general_cg_iterations(env, orc):
+    """Two iterations of Algorithm 3 from sigma = 0.  The residual obs - data
+    is about 1% of the trace, so the traces' rounding differences (~1e-15)
+    reach the gradient at ~1e-13, and each CG update (a step normalised by
+    max|d|, beta from a ratio of norms) amplifies them: the bar on the
+    iterate is 1e-11, as for the structured CG test."""
+    from paper_1509_01399_amd import hyb
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C = 32, 16
+    o, h, xyz, tet, st = _case(n, C, seed=11)
+    dt, nt, om, iters = 0.18 * h, 150, 30.0, 2
+    g = orc.Geometry(n, fem_o=o, fem_c=C, mesh=(xyz, tet))
+    data = orc.forward(g, st, nt, dt, omega=om)
+    s0 = np.zeros(len(tet))
+    sref, log = orc.cg(g, s0, nt, dt, data, iters, omega=om)
+    s = Solver(n, C=C, o=o, mesh=(xyz, tet))
+    sig = _t(torch, s0)
+    state = hyb.hyb_cg_state()
+    out = []
+    for _ in range(iters):
+        out.append(s.cg_step(_t(torch, data), sig, nt, dt, state, omega=om))
+    s.close()
+    gn, Js = np.array(out).T
+    print(f"[general] cg sigma {rel(sig.cpu().numpy(), sref):.2e} |g| {gn} vs {log[:, 1]} J {Js} vs {log[:, 0]}",
+          flush=True)
+    assert np.abs(sref).max() > 0
+    assert rel(sig.cpu().numpy(), sref) <= 1e-11
+    assert np.allclose(gn, log[:, 1], rtol=1e-11, atol=0)
+    assert np.allclose(Js, log[:, 0], rtol=1e-11, atol=0)
+
+
+def test_general_checkpoint_modes(env):
+    """Checkpoints with segment recompute give the same gradient as the full
+    history (FP64, FP32); BF16 checkpoint increments stay close."""
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C = 32, 16
+    o, h, xyz, tet, st = _case(n, C, seed=13)
+    dt, nt, om = 0.18 * h, 150, 30.0
+    grads = {}
+    for f32, mode in ((False, 0), (False, 1), (True, 0), (True, 1), (True, 2)):
+        s = Solver(n, C=C, o=o, mesh=(xyz, tet), f32=f32, store_mode=mode)
+        obs = s.forward(_t(torch, st), nt, dt, omega=om)
+        s.adjoint(0.3 * obs, mode=0)
+        grads[(f32, mode)] = s.gradient(want_J=False)[0].cpu().numpy()
+        s.close()
+    assert np.array_equal(grads[(False, 1)], grads[(False, 0)])
+    assert np.array_equal(grads[(True, 1)], grads[(True, 0)])
+    assert rel(grads[(True, 0)], grads[(False, 0)]) <= 1e-4
+    assert rel(grads[(True, 2)], grads[(True, 0)]) <= 2e-2
+
+
+def test_general_refusals(env):
+    from paper_1509_01399_amd import hyb, synth
+    from paper_1509_01399_amd.hyb import HybError, Solver
+    torch = env
+    n, C = 32, 16
+    o, h, xyz, tet, st = _case(n, C, seed=15)
+    s = Solver(n, C=C, o=o, mesh=(xyz, tet))
+    # dt above the Gershgorin bound of the FEM rows (below h/sqrt(3) of the grid)
+    with pytest.raises(HybError) as e:
+        s.forward(_t(torch, st), 10, 0.5 * h, omega=30.0)
+    assert e.value.status == hyb.HYB_E_CFL
+    # initial levels need every FEM node on the grid
+    with pytest.raises(HybError) as e:
+        s.set_initial(_t(torch, np.zeros((n + 1,) * 3)), None)
+    assert e.value.status == hyb.HYB_E_UNSUPPORTED
+    # general meshes are not batched
+    b = hyb.hyb_batch_create(2)
+    g = torch.zeros(len(tet), dtype=torch.float64, device="cuda")
+    obs = s.trace_buffer(10)
+    with pytest.raises(HybError) as e:
+        hyb.hyb_batch_submit(b, s.ctx, _t(torch, st), float(st.max()), hyb.make_source(30.0), 10, 0.1 * h,
+                             obs, obs, g)
+    assert e.value.status == hyb.HYB_E_UNSUPPORTED
+    hyb.hyb_batch_destroy(b)
+    s.close()
+    # a mesh whose box surface leaves the grid is refused at creation
+    bad = xyz.copy()
+    q = np.rint(bad / h).astype(int) - o
+    i = int(np.nonzero((q[:, 0] == 0) & (q[:, 1] == C // 2) & (q[:, 2] == C // 2))[0][0])
+    bad[i, 2] += 0.2 * h
+    with pytest.raises(HybError) as e:
+        Solver(n, C=C, o=o, mesh=(bad, tet))
+    assert e.value.status == hyb.HYB_E_MESH
+    assert synth is not None
