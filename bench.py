@@ -150,6 +150,122 @@ def roofline(wl, dt, solver, f32, reps=50):
             "bytes_per_launch": b, "avg_launch_ms": round(ms, 5)}
 
 
+def general_mesh_setup(wl, seed=0, amp=0.15):
+    """The workload's geometry with a general FEM mesh: the 6-tetrahedra split
+    of the box with every node strictly inside the inner box moved by up to
+    amp * h per axis, the workload's inclusions sampled per tetrahedron, and a
+    time step of 0.9 times an element-wise bound of the FEM rows' Gershgorin
+    stability limit (the library checks the assembled one, which is lower)."""
+    import numpy as np
+
+    from paper_1509_01399_amd import synth
+    xyz, tet = synth.perturbed_box_mesh(wl.o, wl.C, wl.h, seed=seed + 7, amp=amp)
+    st = synth.tet_sigma(xyz, tet, synth.sigma_for(wl, seed), wl.o, wl.C, wl.h)
+    X = xyz[tet]
+    E = np.transpose(X[:, 1:] - X[:, :1], (0, 2, 1))
+    G = np.linalg.inv(E)
+    G = np.concatenate([-G.sum(1, keepdims=True), G], 1)
+    vol = np.abs(np.linalg.det(E)) / 6
+    ke = vol[:, None, None] * (G @ np.transpose(G, (0, 2, 1)))
+    a = 1.0 + st
+    row = np.zeros(len(xyz))
+    mass = np.zeros(len(xyz))
+    np.add.at(row, tet.ravel(), (a[:, None] * np.abs(ke).sum(2)).ravel())
+    np.add.at(mass, tet.ravel(), np.repeat(vol / 4, 4))
+    dt = min(0.9 * 2.0 / np.sqrt((row / mass).max()), wl.h / np.sqrt(3.0) * 0.9)
+    return xyz, tet, st, dt
+
+
+def general_fem_bytes(xyz, tet, wl, s):
+    """Algorithmic bytes of one launch of the general FEM row kernels (field
+    element size s).  Per row: its column ids and kappa values (4 + s per mesh
+    neighbour), the row's own levels (FP64: read v^k, v^{k-1}, write v^{k+1};
+    FP32 increment form: read v^k, d^k, write d^{k+1}, v^{k+1}) and dt^2/m;
+    the history level of the inner-box nodes; the overlap copies (an 8-byte
+    grid index and the copied value).  The adjoint also reads the neighbour
+    lists of the box surface (its omega_o couplings), the six grid multipliers
+    around each omega_diamond node, and read-modify-writes one FP64
+    accumulator per edge of the inner box.  Neighbour values gathered by
+    several rows are counted once."""
+    import numpy as np
+    h, o, C = wl.h, wl.o, wl.C
+    q = xyz / h - o
+    qi = np.rint(q)
+    grid = np.all(np.abs(q - qi) < 1e-7, axis=1)
+    surf = np.any((np.abs(q) < 1e-7) | (np.abs(q - C) < 1e-7), axis=1)
+    inner = np.all((q > 2 - 1e-7) & (q < C - 2 + 1e-7), axis=1)
+    onD = grid & inner & np.any((np.abs(q - 2) < 1e-7) | (np.abs(q - (C - 2)) < 1e-7), axis=1)
+    pairs = tet[:, [[0, 1], [0, 2], [0, 3], [1, 2], [1, 3], [2, 3]]].reshape(-1, 2).astype(np.int64)
+    pairs.sort(axis=1)
+    key = np.unique(pairs[:, 0] * len(xyz) + pairs[:, 1])
+    ea, eb = key // len(xyz), key % len(xyz)
+    deg = np.bincount(ea, minlength=len(xyz)) + np.bincount(eb, minlength=len(xyz))
+    rows = ~surf
+    m = 4 if s == 4 else 3
+    nR, nH, nA, nS = int(rows.sum()), int(inner.sum()), int(onD.sum()), int(surf.sum())
+    ent_rows, ent_all = int(deg[rows].sum()), int(deg.sum())
+    up_inner = int((inner[ea] & inner[eb]).sum())
+    fwd = ent_rows * (4 + s) + nR * (m * s + s) + nH * s + nS * (8 + 2 * s) + nA * (8 + s)
+    adj = ent_all * (4 + s) + nR * (m * s + s) + nH * s + up_inner * 16 + nS * (8 + s) + nA * (8 + 6 * s)
+    return fwd, adj
+
+
+def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
+    """The CG iteration of the benchmark on a general mesh of the FEM box (the
+    general-mesh path of the library), and the roofline of its FEM row
+    kernels (forward, adjoint) timed with HIP events on the solver's stream."""
+    import torch
+
+    from paper_1509_01399_amd import hyb, synth
+    wl = synth.WORKLOADS[wl_name]
+    t0 = time.perf_counter()
+    xyz, tet, st, dt = general_mesh_setup(wl, seed)
+    solver = hyb.Solver(wl.n, C=wl.C, mesh=(xyz, tet), f32=f32)
+    t_setup = time.perf_counter() - t0
+    assert solver.general
+    sig_true = torch.as_tensor(st, dtype=torch.float64, device="cuda")
+    obs = solver.forward(sig_true, wl.nt, dt, omega=wl.omega)
+    data = torch.as_tensor(synth.add_noise(obs.cpu().numpy(), wl.noise, seed + 1), dtype=torch.float64,
+                           device="cuda")
+    del obs
+    sig = torch.zeros(len(tet), dtype=torch.float64, device="cuda")
+    state = hyb.hyb_cg_state()
+    for _ in range(warmup):
+        solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t1
+    nfdm, nfem = solver.counts()
+    value = 2.0 * (nfdm + nfem) * wl.nt * steps / t / 1e9
+    s = 4 if f32 else 8
+    bf, ba = general_fem_bytes(xyz, tet, wl, s)
+    out = {"workload": f"{wl.name} grid, general FEM mesh", "tets": int(len(tet)), "fem_nodes": int(len(xyz)),
+           "node_shift": "U(-0.15 h, 0.15 h) per axis inside the inner box", "dt_over_h": round(dt / wl.h, 4),
+           "dtype": "f32" if f32 else "f64", "value": round(value, 2), "unit": "Gpt-updates/s",
+           "ms_per_step": round(t / steps * 1e3, 3), "host_setup_s": round(t_setup, 2),
+           "last_J": J, "last_gnorm": gn}
+    for which, b, name in ((0, bf, "forward"), (1, ba, "adjoint")):
+        # each timing call overwrites the sweeps it needs: a CG step before
+        # the warm-up launches and another before the timed ones
+        solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+        hyb.hyb_time_fem(solver.ctx, which, 5)
+        solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+        ms = hyb.hyb_time_fem(solver.ctx, which, 50)
+        ach = b / (ms * 1e-3) / 1e9
+        out[f"roofline_{name}"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+                                   "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                                   "kernel": f"k_gen_{'fwd' if which == 0 else 'adj'}<"
+                                             f"{'float' if f32 else 'double'}>",
+                                   "bytes_per_launch": int(b), "avg_launch_ms": round(ms, 5)}
+    solver.close()
+    del data, sig, sig_true
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving(n_req=256, seed=0, budget=200e9):
     """Serving workload: n_req forward+adjoint+gradient requests, grid sizes
     uniform over {64,96,128,192,256}^3, FP32 fields, Poisson arrivals at
@@ -348,10 +464,11 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--no-general", action="store_true", help="skip the general-mesh leg")
     ap.add_argument("--probe", choices=["interior", "copy"])
     ap.add_argument("--probe-f32", action="store_true")
     ap.add_argument("--probe-reps", type=int, default=20)
-    ap.add_argument("--study", choices=["diff384", "scale512"],
+    ap.add_argument("--study", choices=["diff384", "scale512", "general"],
                     help="full-size check of a form instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -370,7 +487,10 @@ def main():
         probe(args.probe, args.workload, args.probe_f32, args.probe_reps)
         return
     if args.study:
-        res = study_diff384() if args.study == "diff384" else study_scale512()
+        if args.study == "general":
+            res = general_mesh(args.workload, args.steps, args.warmup, f32=args.probe_f32)
+        else:
+            res = study_diff384() if args.study == "diff384" else study_scale512()
         print(json.dumps(res), flush=True)
         return
 
@@ -403,6 +523,11 @@ def main():
         del d2
         torch.cuda.empty_cache()
 
+    gen = None
+    if not args.no_general:
+        gen = general_mesh(args.workload, args.steps, args.warmup)
+        print(f"[bench] general mesh: {gen}", file=sys.stderr, flush=True)
+
     srv = None
     if not args.no_serve:
         srv = serving(args.serve_requests)
@@ -422,7 +547,7 @@ def main():
                    "dt_over_h": round(dt / wl.h, 4), "omega": wl.omega, "noise": wl.noise,
                    "step": "one CG iteration (forward + adjoint + gradient + update)",
                    "parallelism": "single GPU"},
-        "roofline": rl, "cpu_baseline": cpu, "f32_form": f32,
+        "roofline": rl, "cpu_baseline": cpu, "f32_form": f32, "general_mesh": gen,
         "p50_ms": srv["batched"]["p50_ms"] if srv else None,
         "p99_ms": srv["batched"]["p99_ms"] if srv else None,
         "serving": srv,
