@@ -55,6 +55,13 @@ def _load():
         lib.orc_gradient_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, ct.c_double, dp, dp, dp]
         lib.orc_cg_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, ct.c_double, ct.c_double,
                                  ct.c_int, dp]
+        lib.orc_forward_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp]
+        lib.orc_adjoint_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp, dp, dp,
+                                         dp, dp]
+        lib.orc_gradient_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, ct.c_double, dp,
+                                          dp, dp]
+        lib.orc_cg_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, ct.c_double,
+                                    ct.c_double, ct.c_int, dp]
         _lib = lib
     return _lib
 
@@ -141,9 +148,11 @@ def _f64(a, shape=None):
 
 
 def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=None,
-            want_vhist=False, want_ufinal=False):
+            want_vhist=False, want_ufinal=False, taylor=False, f0=None, f1=None):
     """Forward sweep of Algorithm 2.  Returns obs [nt+1, ny+1, nx+1] and,
-    optionally, the FEM history [nt+1, fz, fy, fx] and the final grid level."""
+    optionally, the FEM history [nt+1, fz, fy, fx] and the final grid level.
+    Initial data: levels u0, um1 (leapfrog start), or with taylor=True the
+    Model Problem 1 data f0 = u(x,0), f1 = u_t(x,0) with the Taylor start."""
     lib = _load()
     g = geom._c()
     sz = geom.sizes()
@@ -154,8 +163,13 @@ def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=Non
     vh = np.zeros((nt + 1, sz["fem_nodes"])) if want_vhist and sz["fem_nodes"] else None
     uf = np.zeros(sz["grid_nodes"]) if want_ufinal else None
     s = _src(1 if flux is not None else 0, omega, flux, k_on)
-    rc = lib.orc_forward_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
-                           _p(obs), _p(vh), _p(uf))
+    if taylor:
+        f0, f1 = _f64(f0), _f64(f1)
+        rc = lib.orc_forward_ic_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(f0), _p(f1),
+                                  _p(obs), _p(vh), _p(uf))
+    else:
+        rc = lib.orc_forward_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
+                               _p(obs), _p(vh), _p(uf))
     if rc:
         raise RuntimeError(f"orc_forward failed ({rc})")
     out = [obs]
@@ -167,10 +181,12 @@ def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=Non
 
 
 def adjoint(geom, sigma, nt, dt, seed, omega=40.0, flux=None, k_on=0, u0=None, um1=None,
-            want_dflux=False, want_dinit=False):
+            want_dflux=False, want_dinit=False, taylor=False, f0=None, f1=None, want_ddata=False):
     """Exact discrete adjoint: seed [nt+1, face] is the cotangent of the
     trace.  Returns dJ/dsigma per cell (Euclidean) and optionally the source
-    cotangent [nt, face] and the cotangents of u^0, u^{-1}."""
+    cotangent [nt, face], the cotangents of u^0, u^{-1} (want_dinit) and,
+    with taylor=True (Model Problem 1 data f0, f1), those of f0 and f1
+    (want_ddata)."""
     lib = _load()
     g = geom._c()
     sz = geom.sizes()
@@ -183,8 +199,15 @@ def adjoint(geom, sigma, nt, dt, seed, omega=40.0, flux=None, k_on=0, u0=None, u
     du0 = np.zeros(sz["grid_nodes"]) if want_dinit else None
     dum1 = np.zeros(sz["grid_nodes"]) if want_dinit else None
     s = _src(1 if flux is not None else 0, omega, flux, k_on)
-    rc = lib.orc_adjoint_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
-                           _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1))
+    df0 = np.zeros(sz["grid_nodes"]) if want_ddata else None
+    df1 = np.zeros(sz["grid_nodes"]) if want_ddata else None
+    if taylor:
+        f0, f1 = _f64(f0), _f64(f1)
+        rc = lib.orc_adjoint_ic_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(f0), _p(f1),
+                                  _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1), _p(df0), _p(df1))
+    else:
+        rc = lib.orc_adjoint_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
+                               _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1))
     if rc:
         raise RuntimeError(f"orc_adjoint failed ({rc})")
     out = [dsig[:sz["fem_cubes"]]]
@@ -192,6 +215,8 @@ def adjoint(geom, sigma, nt, dt, seed, omega=40.0, flux=None, k_on=0, u0=None, u
         out.append(dflux)
     if want_dinit:
         out += [du0, dum1]
+    if want_ddata:
+        out += [df0, df1]
     return out[0] if len(out) == 1 else tuple(out)
 
 
@@ -204,8 +229,10 @@ def misfit(geom, nt, dt, obs, data):
     return J, seed
 
 
-def gradient(geom, sigma, nt, dt, data, gamma=0.01, omega=40.0, want_obs=False):
-    """L2 gradient g_c (eq. (gradient1), discrete) and J at sigma."""
+def gradient(geom, sigma, nt, dt, data, gamma=0.01, omega=40.0, want_obs=False, f0=None, f1=None,
+             taylor=False):
+    """L2 gradient g_c (eq. (gradient1), discrete) and J at sigma; with
+    taylor=True the sweeps start from Model Problem 1 data (f0, f1)."""
     lib = _load()
     sz = geom.sizes()
     sigma = _f64(sigma)
@@ -214,23 +241,35 @@ def gradient(geom, sigma, nt, dt, data, gamma=0.01, omega=40.0, want_obs=False):
     J = ct.c_double()
     obs = np.zeros_like(data) if want_obs else None
     s = _src(0, omega)
-    rc = lib.orc_gradient_m(ct.byref(geom._c()), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(data),
-                            gamma, _p(grad), ct.byref(J), _p(obs))
+    if taylor:
+        f0, f1 = _f64(f0), _f64(f1)
+        rc = lib.orc_gradient_ic_m(ct.byref(geom._c()), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(f0),
+                                   _p(f1), _p(data), gamma, _p(grad), ct.byref(J), _p(obs))
+    else:
+        rc = lib.orc_gradient_m(ct.byref(geom._c()), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(data),
+                                gamma, _p(grad), ct.byref(J), _p(obs))
     if rc:
         raise RuntimeError(f"orc_gradient failed ({rc})")
     return (grad, J.value, obs) if want_obs else (grad, J.value)
 
 
-def cg(geom, sigma, nt, dt, data, iters, gamma=0.01, alpha_rel=0.25, omega=40.0):
+def cg(geom, sigma, nt, dt, data, iters, gamma=0.01, alpha_rel=0.25, omega=40.0, f0=None, f1=None,
+       taylor=False):
     """Algorithm 3: returns (sigma after `iters` iterations, log [iters, 5]
-    with columns J, |g|_L2, beta, alpha, max|d|)."""
+    with columns J, |g|_L2, beta, alpha, max|d|).  taylor=True: IP1, every
+    sweep starts from Model Problem 1 data (f0, f1)."""
     lib = _load()
     sig = np.array(sigma, dtype=np.float64, copy=True)
     data = _f64(data)
     log = np.zeros((iters, 5))
     s = _src(0, omega)
-    rc = lib.orc_cg_m(ct.byref(geom._c()), geom._m(), _p(sig), ct.byref(s), nt, dt, _p(data), gamma,
-                      alpha_rel, iters, _p(log))
+    if taylor:
+        f0, f1 = _f64(f0), _f64(f1)
+        rc = lib.orc_cg_ic_m(ct.byref(geom._c()), geom._m(), _p(sig), ct.byref(s), nt, dt, _p(f0), _p(f1),
+                             _p(data), gamma, alpha_rel, iters, _p(log))
+    else:
+        rc = lib.orc_cg_m(ct.byref(geom._c()), geom._m(), _p(sig), ct.byref(s), nt, dt, _p(data), gamma,
+                          alpha_rel, iters, _p(log))
     if rc:
         raise RuntimeError(f"orc_cg failed ({rc})")
     return sig, log

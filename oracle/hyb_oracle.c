@@ -45,7 +45,11 @@
  *     that consumes it (level k+1), which makes the gradient the exact
  *     derivative of the discrete functional;
  *   - CG step length alpha^m = alpha_rel / max|d^m| followed by projection
- *     onto the admissible set 1 <= a <= 5 of eq. (admpar).
+ *     onto the admissible set 1 <= a <= 5 of eq. (admpar);
+ *   - Model Problem 1 (eq. (model1)): the first level follows from the data
+ *     u(x,0) = f0, u_t(x,0) = f1 by the second-order Taylor start
+ *     u^1 = u^0 + tau f1 + (tau^2/2) A(u^0) (orc_ic); the paper names the data
+ *     but not the start.
  *
  * Parity pins (all in the CPU test suite): the FEM rows equal the seven-point
  * rows when a = 1 (the schemes coincide on structured meshes); hybrid with
@@ -53,7 +57,9 @@
  * stencil assembled independently; discrete energy is conserved with
  * reflecting walls; the plane wave matches its closed form and converges at
  * second order; the adjoint passes a dot test; the gradient matches central
- * finite differences.  The CG driver (orc_cg) is pinned only by invariants
+ * finite differences.  The Taylor start reproduces a solution quadratic in
+ * time exactly, converges at second order for a travelling pulse with
+ * non-zero initial velocity, and its adjoint passes a dot test in (f0, f1).  The CG driver (orc_cg) is pinned only by invariants
  * (descent, feasibility, first iterate = projected steepest descent):
  * parity unpinned beyond those.
  */
@@ -486,12 +492,14 @@ static bclass classify(const orc_prob *P, const int *x, int src_on)
 /* ---------------------------------------------------------------- forward */
 
 /* One time step of Algorithm 2 (Sec. 7.5): levels (Um,U) -> Up, (Vm,V) -> Vp.
- * r is FEM scratch of size fn. */
-static void step_forward(const orc_prob *P, int k, double dt, const orc_source *S, int k_on,
+ * r is FEM scratch of size fn.  w2 weights tau^2 in the rows that take the
+ * leapfrog (1; 1/2 in the first step of the Taylor start, see
+ * forward_sweep); the absorbing rows do not depend on it. */
+static void step_forward(const orc_prob *P, int k, double dt, double w2, const orc_source *S, int k_on,
                          const double *Um, const double *U, double *Up,
                          const double *Vm, const double *V, double *Vp, double *r)
 {
-    const double h = P->g.h, h2 = h * h, tau2 = dt * dt;
+    const double h = P->g.h, h2 = h * h, tau2 = w2 * dt * dt;
     const double rr = (h - dt) / (h + dt);  /* coefficient of eq. (eq:abs2) */
     memset(Up, 0, sizeof(double) * (size_t)P->nn);
 
@@ -579,12 +587,31 @@ static void record_face(const orc_prob *P, const double *U, double *row)
     memcpy(row, U + base, sizeof(double) * (size_t)P->nface);
 }
 
-/* Full forward sweep.  u0/um1: optional initial levels u^0, u^{-1} on the
- * whole grid (zero when NULL, Model Problem 2).  obs: [nt+1][nface].
+/* Initial data of a sweep (on the whole grid; NULL arrays are zero).
+ * taylor = 0: the leapfrog starts from the given levels u^0 = u0 and
+ *   u^{-1} = um1 (zero for Model Problem 2).
+ * taylor = 1: Model Problem 1, eq. (model1): u(x,0) = u0 (f_0) and
+ *   u_t(x,0) = f1 (f_1).  The first level is the second-order Taylor
+ *   expansion u^1 = u^0 + tau f_1 + (tau^2/2) A(u^0), A(u^0) the acceleration
+ *   the scheme assigns to level 0 (its leapfrog rows with the source at
+ *   t_0).  Written as a leapfrog step it is the step from the virtual level
+ *   u^{-1} = u^0 - tau f_1 with tau^2 weighted by 1/2:
+ *   2u^0 - (u^0 - tau f_1) + (tau^2/2) A(u^0).  The absorbing rows of
+ *   eq. (eq:abs2) use levels 0 and 1 only and are unchanged. */
+typedef struct {
+    const double *u0, *um1, *f1;
+    int taylor;
+} orc_ic;
+
+static const orc_ic ORC_IC_ZERO = {NULL, NULL, NULL, 0};
+
+/* tau^2 weight of step k. */
+static double step_w2(const orc_ic *ic, int k) { return (ic->taylor && k == 0) ? 0.5 : 1.0; }
+
+/* Full forward sweep from the initial data ic.  obs: [nt+1][nface].
  * vhist (optional): [nt+1][fn] FEM levels.  ufin (optional): u^{nt}. */
 static int forward_sweep(const orc_prob *P, const orc_source *S, int nt, double dt,
-                         const double *u0, const double *um1, double *obs,
-                         double *vhist, double *ufin)
+                         const orc_ic *ic, double *obs, double *vhist, double *ufin)
 {
     int k_on = source_k_on(S, nt, dt);
     size_t gb = sizeof(double) * (size_t)P->nn, fb = sizeof(double) * (size_t)(P->fn ? P->fn : 1);
@@ -592,8 +619,15 @@ static int forward_sweep(const orc_prob *P, const orc_source *S, int nt, double 
     double *Va = (double *)calloc(1, fb), *Vb = (double *)calloc(1, fb), *Vc = (double *)calloc(1, fb);
     double *r = (double *)calloc(1, fb);
     if (!Ua || !Ub || !Uc || !Va || !Vb || !Vc || !r) return -2;
+    const double *u0 = ic->u0, *um1 = ic->taylor ? NULL : ic->um1;
     if (u0) memcpy(Ub, u0, gb);
     if (um1) memcpy(Ua, um1, gb);
+    if (ic->taylor) {
+        /* virtual level u^{-1} = u^0 - tau f_1 */
+        for (int64_t i = 0; i < P->nn; ++i)
+            Ua[i] = (u0 ? u0[i] : 0.0) - (ic->f1 ? dt * ic->f1[i] : 0.0);
+        um1 = Ua;
+    }
     if (P->has_fem)
         for (int64_t f = 0; f < P->fn; ++f) {
             /* FEM copies of the initial levels: defined on grid points only */
@@ -604,7 +638,7 @@ static int forward_sweep(const orc_prob *P, const orc_source *S, int nt, double 
     if (obs) record_face(P, U, obs);
     if (vhist && P->has_fem) memcpy(vhist, V, fb);
     for (int k = 0; k < nt; ++k) {
-        step_forward(P, k, dt, S, k_on, Um, U, Up, Vm, V, Vp, r);
+        step_forward(P, k, dt, step_w2(ic, k), S, k_on, Um, U, Up, Vm, V, Vp, r);
         double *t1 = Um; Um = U; U = Up; Up = t1;          /* swap, Alg. 2 step 5 */
         double *t2 = Vm; Vm = V; V = Vp; Vp = t2;
         if (obs) record_face(P, U, obs + (int64_t)(k + 1) * P->nface);
@@ -621,12 +655,12 @@ static int forward_sweep(const orc_prob *P, const orc_source *S, int nt, double 
  * consumed and pushed to levels k (aU, aV) and k-1 (aUm, aVm).  V is the
  * forward FEM level k (for the conductivity derivative); dsig accumulates
  * dJ/da per cube; dflux (optional) accumulates the source cotangent. */
-static void step_adjoint(const orc_prob *P, int k, double dt, const orc_source *S, int k_on,
+static void step_adjoint(const orc_prob *P, int k, double dt, double w2, const orc_source *S, int k_on,
                          double *aUm, double *aU, double *aUp,
                          double *aVm, double *aV, double *aVp,
                          const double *V, double *dsig, double *dflux, double *gsave)
 {
-    const double h = P->g.h, h2 = h * h, tau2 = dt * dt;
+    const double h = P->g.h, h2 = h * h, tau2 = w2 * dt * dt;
     const double rr = (h - dt) / (h + dt);
 
     /* (iv)^T: V[omega_o] = U[omega_o] was done last, so it is undone first. */
@@ -734,7 +768,7 @@ static void step_adjoint(const orc_prob *P, int k, double dt, const orc_source *
  * vhist: forward FEM levels [nt+1][fn].  Outputs (each optional): dsig
  * [ncube] dJ/da_c (Euclidean), dflux [nt][nface], du0 and dum1 [nn]
  * cotangents of the initial levels. */
-static int adjoint_sweep(const orc_prob *P, const orc_source *S, int nt, double dt,
+static int adjoint_sweep(const orc_prob *P, const orc_source *S, int nt, double dt, const orc_ic *ic,
                          const double *seed, const double *vhist, double *dsig,
                          double *dflux, double *du0, double *dum1)
 {
@@ -751,7 +785,7 @@ static int adjoint_sweep(const orc_prob *P, const orc_source *S, int nt, double 
         /* (v)^T: the trace of level k+1 */
         const double *sd = seed + (int64_t)(k + 1) * P->nface;
         for (int q = 0; q < P->nface; ++q) aUp[base + q] += sd[q];
-        step_adjoint(P, k, dt, S, k_on, aUm, aU, aUp, aVm, aV, aVp,
+        step_adjoint(P, k, dt, step_w2(ic, k), S, k_on, aUm, aU, aUp, aVm, aV, aVp,
                      P->has_fem ? vhist + (int64_t)k * P->fn : NULL, dsig, dflux, gs);
         /* aUp is fully consumed; rotate: level k becomes the newest */
         double *t1 = aUp; aUp = aU; aU = aUm; aUm = t1;
@@ -808,16 +842,32 @@ int orc_sizes_m(const orc_geom *g, const orc_mesh *m, int64_t *out)
 
 int orc_sizes(const orc_geom *g, int64_t *out) { return orc_sizes_m(g, NULL, out); }
 
+static int forward_ic(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                      double dt, const orc_ic *ic, double *obs, double *vhist, double *ufin)
+{
+    orc_prob P;
+    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma)) return -1;
+    int rc = forward_sweep(&P, S, nt, dt, ic, obs, vhist, ufin);
+    prob_free(&P);
+    return rc;
+}
+
 /* Forward solve: obs [nt+1][nface]; vhist, u0, um1, ufin optional (initial
  * levels need every FEM node on a grid point). */
 int orc_forward_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
                   double dt, const double *u0, const double *um1, double *obs, double *vhist, double *ufin)
 {
-    orc_prob P;
-    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma)) return -1;
-    int rc = forward_sweep(&P, S, nt, dt, u0, um1, obs, vhist, ufin);
-    prob_free(&P);
-    return rc;
+    const orc_ic ic = {u0, um1, NULL, 0};
+    return forward_ic(g, m, sigma, S, nt, dt, &ic, obs, vhist, ufin);
+}
+
+/* Forward solve of Model Problem 1 (eq. (model1)) with the Taylor start of
+ * orc_ic: f0 = u(x,0), f1 = u_t(x,0) on the whole grid (NULL = 0). */
+int orc_forward_ic_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                     double dt, const double *f0, const double *f1, double *obs, double *vhist, double *ufin)
+{
+    const orc_ic ic = {f0, NULL, f1, 1};
+    return forward_ic(g, m, sigma, S, nt, dt, &ic, obs, vhist, ufin);
 }
 
 int orc_forward(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
@@ -829,9 +879,9 @@ int orc_forward(const orc_geom *g, const double *sigma, const orc_source *S, int
 /* Linear adjoint: given the cotangent seed [nt+1][nface] of the trace,
  * returns dsig [cells] = dJ/da per parameter cell (Euclidean, zero on
  * non-eligible cells), and optionally dflux [nt][nface], du0, dum1 [nn]. */
-int orc_adjoint_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                  double dt, const double *u0, const double *um1, const double *seed, double *dsig,
-                  double *dflux, double *du0, double *dum1)
+static int adjoint_ic(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                      double dt, const orc_ic *ic, const double *seed, double *dsig, double *dflux,
+                      double *du0, double *dum1)
 {
     orc_prob P;
     if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma)) return -1;
@@ -839,12 +889,48 @@ int orc_adjoint_m(const orc_geom *g, const orc_mesh *m, const double *sigma, con
     if (P.has_fem) {
         vh = (double *)malloc(sizeof(double) * (size_t)P.fn * (size_t)(nt + 1));
         if (!vh) { prob_free(&P); return -2; }
-        if (forward_sweep(&P, S, nt, dt, u0, um1, NULL, vh, NULL)) { free(vh); prob_free(&P); return -1; }
+        if (forward_sweep(&P, S, nt, dt, ic, NULL, vh, NULL)) { free(vh); prob_free(&P); return -1; }
     }
     if (dflux) memset(dflux, 0, sizeof(double) * (size_t)nt * (size_t)P.nface);
-    int rc = adjoint_sweep(&P, S, nt, dt, seed, vh, dsig, dflux, du0, dum1);
+    int rc = adjoint_sweep(&P, S, nt, dt, ic, seed, vh, dsig, dflux, du0, dum1);
     free(vh);
     prob_free(&P);
+    return rc;
+}
+
+int orc_adjoint_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                  double dt, const double *u0, const double *um1, const double *seed, double *dsig,
+                  double *dflux, double *du0, double *dum1)
+{
+    const orc_ic ic = {u0, um1, NULL, 0};
+    return adjoint_ic(g, m, sigma, S, nt, dt, &ic, seed, dsig, dflux, du0, dum1);
+}
+
+/* Adjoint of the Model Problem 1 sweep of orc_forward_ic_m.  Besides dsig and
+ * dflux (as orc_adjoint_m): du0, dum1 [nn] the cotangents of the levels u^0
+ * and of the virtual level u^{-1} = f0 - tau f1 (with the FEM copies folded
+ * back), and df0, df1 [nn] those of the data: df0 = du0 + dum1,
+ * df1 = -tau dum1.  Each output is optional. */
+int orc_adjoint_ic_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                     double dt, const double *f0, const double *f1, const double *seed, double *dsig,
+                     double *dflux, double *du0, double *dum1, double *df0, double *df1)
+{
+    const orc_ic ic = {f0, NULL, f1, 1};
+    orc_prob P;
+    if (prob_init(&P, g, m, NULL)) return -1;
+    int64_t nn = P.nn;
+    prob_free(&P);
+    double *a0 = (double *)malloc(sizeof(double) * (size_t)nn), *a1 = (double *)malloc(sizeof(double) * (size_t)nn);
+    if (!a0 || !a1) { free(a0); free(a1); return -2; }
+    int rc = adjoint_ic(g, m, sigma, S, nt, dt, &ic, seed, dsig, dflux, a0, a1);
+    if (!rc)
+        for (int64_t i = 0; i < nn; ++i) {
+            if (du0) du0[i] = a0[i];
+            if (dum1) dum1[i] = a1[i];
+            if (df0) df0[i] = a0[i] + a1[i];
+            if (df1) df1[i] = -dt * a1[i];
+        }
+    free(a0); free(a1);
     return rc;
 }
 
@@ -882,8 +968,9 @@ double orc_misfit(const orc_geom *g, int nt, double dt, const double *obs, const
  *   g_c = (1/|c|) dJ_misfit/da_c + gamma (sigma_c - sigma0_c)  (eligible c),
  *   g_c = 0 elsewhere, |c| the cell volume (h^3 for a cube, |K| for a
  *   tetrahedron).  Returns J (misfit + regularisation) in *J. */
-int orc_gradient_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                   double dt, const double *data, double gamma, double *grad, double *J, double *obs_out)
+static int gradient_ic(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                       double dt, const orc_ic *ic, const double *data, double gamma, double *grad, double *J,
+                       double *obs_out)
 {
     orc_prob P;
     if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma) || !P.has_fem) return -1;
@@ -891,9 +978,9 @@ int orc_gradient_m(const orc_geom *g, const orc_mesh *m, const double *sigma, co
     double *seed = (double *)malloc(sizeof(double) * (size_t)P.nface * (size_t)(nt + 1));
     double *vh = (double *)malloc(sizeof(double) * (size_t)P.fn * (size_t)(nt + 1));
     if (!obs || !seed || !vh) return -2;
-    forward_sweep(&P, S, nt, dt, NULL, NULL, obs, vh, NULL);
+    if (forward_sweep(&P, S, nt, dt, ic, obs, vh, NULL)) { free(obs); free(seed); free(vh); prob_free(&P); return -1; }
     double Jm = orc_misfit(g, nt, dt, obs, data, seed);
-    adjoint_sweep(&P, S, nt, dt, seed, vh, grad, NULL, NULL, NULL);
+    adjoint_sweep(&P, S, nt, dt, ic, seed, vh, grad, NULL, NULL, NULL);
     double reg = 0.0;
     for (int64_t c = 0; c < P.ncube; ++c) {
         if (!P.eligible[c]) { grad[c] = 0.0; continue; }
@@ -908,6 +995,21 @@ int orc_gradient_m(const orc_geom *g, const orc_mesh *m, const double *sigma, co
     return 0;
 }
 
+int orc_gradient_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                   double dt, const double *data, double gamma, double *grad, double *J, double *obs_out)
+{
+    return gradient_ic(g, m, sigma, S, nt, dt, &ORC_IC_ZERO, data, gamma, grad, J, obs_out);
+}
+
+/* orc_gradient_m for Model Problem 1 data (f0, f1) with the Taylor start. */
+int orc_gradient_ic_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
+                      double dt, const double *f0, const double *f1, const double *data, double gamma,
+                      double *grad, double *J, double *obs_out)
+{
+    const orc_ic ic = {f0, NULL, f1, 1};
+    return gradient_ic(g, m, sigma, S, nt, dt, &ic, data, gamma, grad, J, obs_out);
+}
+
 int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
                  const double *data, double gamma, double *grad, double *J, double *obs_out)
 {
@@ -920,8 +1022,8 @@ int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, in
  * alpha^m = alpha_rel / max|d^m|; sigma <- clip(sigma + alpha^m d^m, 0, 4)
  * on eligible cells (a in [1,5], eq. (admpar)).
  * log[5*m + {0..4}] = J, |g|_{L2}, beta, alpha, max|d|. */
-int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
-             const double *data, double gamma, double alpha_rel, int iters, double *log)
+static int cg_ic(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
+                 const orc_ic *ic, const double *data, double gamma, double alpha_rel, int iters, double *log)
 {
     orc_prob P;
     if (prob_init(&P, g, msh, NULL) || !P.has_fem) return -1;
@@ -931,7 +1033,7 @@ int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_so
     double gn2_prev = 0.0;
     for (int m = 0; m < iters; ++m) {
         double J = 0.0;
-        if (orc_gradient_m(g, msh, sigma, S, nt, dt, data, gamma, gr, &J, NULL)) return -1;
+        if (gradient_ic(g, msh, sigma, S, nt, dt, ic, data, gamma, gr, &J, NULL)) return -1;
         double gn2 = 0.0;
         for (int64_t c = 0; c < nc; ++c) gn2 += P.pvol[c] * gr[c] * gr[c];
         double beta = m == 0 ? 0.0 : gn2 / gn2_prev;
@@ -955,6 +1057,22 @@ int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_so
     free(gr); free(d);
     prob_free(&P);
     return 0;
+}
+
+int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
+             const double *data, double gamma, double alpha_rel, int iters, double *log)
+{
+    return cg_ic(g, msh, sigma, S, nt, dt, &ORC_IC_ZERO, data, gamma, alpha_rel, iters, log);
+}
+
+/* orc_cg_m for Model Problem 1 (IP1): every iteration's forward sweep starts
+ * from (f0, f1) with the Taylor start. */
+int orc_cg_ic_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
+                const double *f0, const double *f1, const double *data, double gamma, double alpha_rel,
+                int iters, double *log)
+{
+    const orc_ic ic = {f0, NULL, f1, 1};
+    return cg_ic(g, msh, sigma, S, nt, dt, &ic, data, gamma, alpha_rel, iters, log);
 }
 
 int orc_cg(const orc_geom *g, double *sigma, const orc_source *S, int nt, double dt,
