@@ -172,8 +172,31 @@ hyb_status hyb_forward(hyb_ctx *ctx, const double *sigma_dev, const hyb_source *
  * u0_dev, um1_dev are device FP64 [(n_z+1)(n_y+1)(n_x+1)] levels u^0 and
  * u^{-1} (NULL = zero).  Copied on the stream.  The FEM nodes take the values
  * of their grid nodes, so a general mesh with nodes off the grid returns
- * HYB_E_UNSUPPORTED. */
+ * HYB_E_UNSUPPORTED.  Ends the Model Problem 1 data of
+ * hyb_set_initial_taylor. */
 hyb_status hyb_set_initial(hyb_ctx *ctx, const double *u0_dev, const double *um1_dev);
+
+/* Model Problem 1 (eq. (model1), Sec. 5): initial data u(x,0) = f0,
+ * u_t(x,0) = f1 for every later forward sweep of the context (those inside
+ * hyb_cg_step included, so a CG run solves IP1), until the next call;
+ * f0_dev = f1_dev = NULL returns to zero data (Model Problem 2, IP2).
+ * f0_dev, f1_dev: device FP64 [(n_z+1)(n_y+1)(n_x+1)] full grid levels (NULL
+ *   = 0 when the other is given); copied into the context on the stream (two
+ *   grid levels of FP64 the context keeps until destroyed), so the caller may
+ *   free them once the copy has run.
+ * The paper gives the data, not the start.  The first level is the
+ * second-order Taylor expansion u^1 = u^0 + dt f1 + (dt^2/2) A(u^0), with
+ * A(u^0) the acceleration the scheme gives level 0: the leapfrog step from
+ * the virtual level u^{-1} = f0 - dt f1 with dt^2 weighted by 1/2 in the
+ * grid, FEM and ghost-node rows (the source flux at t = 0 included).  The
+ * absorbing rows of eq. (eq:abs2) read levels 0 and 1 only and are
+ * unchanged.  hyb_adjoint transposes that step, so the gradient's term of
+ * step 0 carries the weight 1/2; hyb_get_wavefield(which = 1) returns the
+ * cotangent of the level u^0 (with u^{-1} held fixed).
+ * Replaces pending levels of hyb_set_initial, and hyb_set_initial replaces
+ * these data.  Errors: HYB_E_UNSUPPORTED (general mesh with nodes off the
+ * grid), HYB_E_STATE (context in a batch slot), HYB_E_OOM, HYB_E_DEVICE. */
+hyb_status hyb_set_initial_taylor(hyb_ctx *ctx, const double *f0_dev, const double *f1_dev);
 
 /* Adjoint solve: the exact transpose of the last forward sweep, run backward
  * in time (in the interior it is eq. (fdmschemeadjoint) and the second line

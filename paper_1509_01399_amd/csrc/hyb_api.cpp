@@ -51,6 +51,11 @@ struct hyb_ctx {
     double *partials = nullptr, *scal = nullptr;
     const double *ic_u0 = nullptr, *ic_um1 = nullptr;
     bool ic_set = false;
+    // Model Problem 1 data (hyb_set_initial_taylor): f0, f1 copied into the
+    // context (full unpadded FP64 grid levels), used by every forward sweep
+    bool taylor = false;
+    double *tf0 = nullptr, *tf1 = nullptr;
+    bool sweep_taylor = false;   // the last forward sweep started with the Taylor step
     // state of the last forward / adjoint
     bool have_forward = false, have_adjoint = false;
     int nt = 0, k_on = 0, adj_mode = 0;
@@ -493,6 +498,7 @@ Step<T> make_step(const hyb_ctx *c)
     s.g = c->g;
     s.acube = (const T *)c->acube;
     s.c2 = (T)((c->dt / c->h) * (c->dt / c->h));
+    s.w2 = 1.0;
     s.r = (T)((c->h - c->dt) / (c->h + c->dt));
     for (int q = 0; q < 12; ++q) s.w[q] = (T)c->mesh.w[q];
     s.dt = c->dt;
@@ -582,7 +588,12 @@ Step<T> fwd_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, double *obs)
         s.VDa = (const T *)c->VD[k & 1]; s.VDc = (T *)c->VD[(k + 1) & 1];
     }
     s.types1 = face_types(c, k);
-    const double fluxscale = 2.0 * c->dt * c->dt / c->h;
+    // Taylor start: the first step weights dt^2 by 1/2 in the leapfrog rows
+    // (grid, FEM and ghost rows, the source flux included); the absorbing
+    // rows do not contain dt^2 and are unchanged
+    s.w2 = (c->sweep_taylor && k == 0) ? 0.5 : 1.0;
+    s.c2 = (T)(s.w2 * (c->dt / c->h) * (c->dt / c->h));
+    const double fluxscale = s.w2 * 2.0 * c->dt * c->dt / c->h;
     if (c->src.kind == 0) {
         s.flux = nullptr;
         s.srcterm = (T)(fluxscale * std::sin(c->src.omega * ((double)k * c->dt)));
@@ -617,6 +628,10 @@ Step<T> adj_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, const double *r
     s.types1 = face_types(c, k);
     s.types2 = face_types(c, k + 1);
     s.level_rows = k >= 1;
+    // level 0 is read by the rows of step 0 only: with the Taylor start their
+    // dt^2 weight 1/2 enters the transposed rows and the gradient term
+    s.w2 = (c->sweep_taylor && k == 0) ? 0.5 : 1.0;
+    s.c2 = (T)(s.w2 * (c->dt / c->h) * (c->dt / c->h));
     s.res = (mode == 0 && k == 0) ? nullptr : res + (long long)k * nface;
     s.hist = hist_ptr<T>(c, k);
     return s;
@@ -641,6 +656,7 @@ GenStep<T> gen_args(const hyb_ctx *c, const Step<T> &s)
     q.hist = s.hist;
     q.E = d.E;
     q.c2 = s.c2;
+    q.cs = (T)s.w2;
     return q;
 }
 
@@ -692,7 +708,23 @@ hyb_status fwd_setup(hyb_ctx *c, double *obs)
             HIPCHK(c, hipMemsetAsync(c->D[q], 0, fb, st));
             if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->VD[q], 0, vb, st));
         }
-    if (c->ic_set) {
+    c->sweep_taylor = false;
+    if (c->taylor) {
+        // u^0 = f0 and the virtual level u^{-1} = f0 - dt f1 (FP64 fields), or
+        // the increment d^0 = u^0 - u^{-1} = dt f1 (FP32 increment form)
+        Geo gg = g;
+        if (c->gen) gg.has_fem = 0;
+        launch_load_level<T>(gg, c->tf0, (T *)c->U[1], (T *)c->V[1], st);
+        if (c->gen) launch_gen_load<T>(c->gd, c->tf0, (T *)c->V[1], st);
+        if (incr_form<T>()) {
+            launch_load_combo<T>(gg, nullptr, c->tf1, c->dt, (T *)c->D[0], (T *)c->VD[0], st);
+            if (c->gen) launch_gen_load_combo<T>(c->gd, nullptr, c->tf1, c->dt, (T *)c->VD[0], st);
+        } else {
+            launch_load_combo<T>(gg, c->tf0, c->tf1, -c->dt, (T *)c->U[0], (T *)c->V[0], st);
+            if (c->gen) launch_gen_load_combo<T>(c->gd, c->tf0, c->tf1, -c->dt, (T *)c->V[0], st);
+        }
+        c->sweep_taylor = true;
+    } else if (c->ic_set) {
         // a general mesh loads its FEM part through its node -> grid map
         Geo gg = g;
         if (c->gen) gg.has_fem = 0;
@@ -924,6 +956,8 @@ void hyb_destroy(hyb_ctx *c)
     dfree((void *&)c->resbuf);
     dfree((void *&)c->partials);
     dfree((void *&)c->scal);
+    dfree((void *&)c->tf0);
+    dfree((void *&)c->tf1);
     delete c;
 }
 
@@ -935,6 +969,33 @@ hyb_status hyb_set_initial(hyb_ctx *c, const double *u0, const double *um1)
     c->ic_u0 = u0;
     c->ic_um1 = um1;
     c->ic_set = u0 || um1;
+    c->taylor = false;
+    return HYB_OK;
+}
+
+hyb_status hyb_set_initial_taylor(hyb_ctx *c, const double *f0, const double *f1)
+{
+    if (!c) return HYB_E_ARG;
+    if (c->in_batch) return fail(c, HYB_E_STATE, "context is owned by a batch slot");
+    c->ic_set = false;
+    c->ic_u0 = c->ic_um1 = nullptr;
+    if (!f0 && !f1) {
+        c->taylor = false;
+        return HYB_OK;
+    }
+    if (c->gen && !c->gen_all_grid)
+        return fail(c, HYB_E_UNSUPPORTED, "initial data need every FEM node on the grid");
+    const size_t b = (size_t)c->g.nx * c->g.ny * c->g.nz * sizeof(double);
+    for (double **p : {&c->tf0, &c->tf1})
+        if (!*p) {
+            hyb_status s = dmalloc(c, (void **)p, b);
+            if (s) return s;
+        }
+    if (f0) HIPCHK(c, hipMemcpyAsync(c->tf0, f0, b, hipMemcpyDeviceToDevice, c->stream));
+    else HIPCHK(c, hipMemsetAsync(c->tf0, 0, b, c->stream));
+    if (f1) HIPCHK(c, hipMemcpyAsync(c->tf1, f1, b, hipMemcpyDeviceToDevice, c->stream));
+    else HIPCHK(c, hipMemsetAsync(c->tf1, 0, b, c->stream));
+    c->taylor = true;
     return HYB_OK;
 }
 
@@ -1665,6 +1726,8 @@ hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *c, const double *sigma, doubl
     if (!c->g.has_fem || !data || !obs || !grad) return bfail(b, HYB_E_ARG, "batch: needs a FEM box, data, obs, grad");
     if (c->store_mode != 0) return bfail(b, HYB_E_UNSUPPORTED, "batch: contexts must keep the full history");
     if (c->gen) return bfail(b, HYB_E_UNSUPPORTED, "batch: general FEM meshes are not batched");
+    if (c->taylor || c->ic_set)
+        return bfail(b, HYB_E_UNSUPPORTED, "batch: contexts start from zero initial data");
     int q = -1;
     for (int i = 0; i < b->max_slots; ++i)
         if (b->slots[i].state == 0) { q = i; break; }

@@ -94,7 +94,9 @@ struct GenStep {
     T *VDc;
     T *hist;
     double *E;
-    T c2;  // (dt/h)^2 of the grid rows that read omega_diamond
+    T c2;  // (dt/h)^2 of the grid rows that read omega_diamond (times the step weight)
+    T cs;  // weight of dt^2 in this step (1; 1/2 in the first step of the Taylor
+           // start): multiplies cn in the rows and in the gradient pairs
 };
 
 template <typename T> void launch_gen_fwd(const GenStep<T> &s, hipStream_t st);
@@ -114,6 +116,9 @@ void launch_gen_prepare(const GenDev &d, const double *sigma, double dt2, double
 // node); increments d = u0 - um1 (either may be null).
 template <typename T>
 void launch_gen_load(const GenDev &d, const double *src, T *V, hipStream_t st);
+// V = a + cb * b at the grid points of the FEM nodes (either may be null = 0)
+template <typename T>
+void launch_gen_load_combo(const GenDev &d, const double *a, const double *b, double cb, T *V, hipStream_t st);
 template <typename T>
 void launch_gen_load_incr(const GenDev &d, const double *u0, const double *um1, T *VD, hipStream_t st);
 // v[orig_of_dev[n]] = V[n] (FP64, caller's numbering)

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_fwd(GenStep<T> s, int nblk)
         const int p = b + 64 * j + ln;
         acc += kap[p] * (v0 - Vb[col[p]]);
     }
-    const T c = s.cn[n];
+    const T c = s.cs * s.cn[n];
     T v;
     if constexpr (incr_form<T>()) {
         const T d = s.VDa[n] - c * acc;
@@ -89,13 +89,14 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
         for (int j = 0; j < w; ++j) {
             const int p = b + 64 * j + ln;
             const int m = col[p];
-            acc += kap[p] * (cn[m] * Vb[m]);
+            acc += kap[p] * ((s.cs * cn[m]) * Vb[m]);
         }
         s.Uc[s.wog[n - s.nR]] = acc;
         return;
     }
     const T mu1 = Vb[n];
-    const T nu0 = cn[n] * mu1;
+    const T cs = s.cs;
+    const T nu0 = (cs * cn[n]) * mu1;
     const bool hrow = n < s.nH;
     const T *__restrict__ H = s.hist;
     int eb = 0;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
     for (int j = 0; j < w; ++j) {
         const int p = b + 64 * j + ln;
         const int m = col[p];
-        const T num = cn[m] * Vb[m];
+        const T num = (cs * cn[m]) * Vb[m];
         acc += kap[p] * (nu0 - num);
         if (hrow && m > n && m < s.nH) {
             double *e = s.E + eb + 64 * j + ln;
@@ -214,6 +215,16 @@ __global__ __launch_bounds__(BLOCK) void k_gen_load(long long fn, const int64_t 
 {
     for (long long n = (long long)blockIdx.x * BLOCK + threadIdx.x; n < fn; n += (long long)gridDim.x * BLOCK)
         V[n] = lin[n] >= 0 ? (T)src[lin[n]] : (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_gen_load_combo(long long fn, const int64_t *lin, const double *a,
+                                                          const double *b, double cb, T *V)
+{
+    for (long long n = (long long)blockIdx.x * BLOCK + threadIdx.x; n < fn; n += (long long)gridDim.x * BLOCK) {
+        const long long g = lin[n];
+        V[n] = g >= 0 ? (T)((a ? a[g] : 0.0) + (b ? cb * b[g] : 0.0)) : (T)0;
+    }
 }
 
 template <typename T>
@@ -352,6 +363,13 @@ void launch_gen_load(const GenDev &d, const double *src, T *V, hipStream_t st)
 }
 
 template <typename T>
+void launch_gen_load_combo(const GenDev &d, const double *a, const double *b, double cb, T *V, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gen_load_combo<T>), dim3(nparts_g(d.fn)), dim3(BLOCK), 0, st, d.fn, d.grid_lin, a, b,
+                       cb, V);
+}
+
+template <typename T>
 void launch_gen_load_incr(const GenDev &d, const double *u0, const double *um1, T *VD, hipStream_t st)
 {
     hipLaunchKernelGGL((k_gen_load_incr<T>), dim3(nparts_g(d.fn)), dim3(BLOCK), 0, st, d.fn, d.grid_lin, u0,
@@ -405,6 +423,8 @@ void launch_gen_cg_update(const GenDev &d, const double *dir, double *sigma, dou
     template void launch_gen_prepare<T>(const GenDev &, const double *, double, double *, double *, \
                                         hipStream_t);                                              \
     template void launch_gen_load<T>(const GenDev &, const double *, T *, hipStream_t);            \
+    template void launch_gen_load_combo<T>(const GenDev &, const double *, const double *, double, T *, \
+                                           hipStream_t);                                           \
     template void launch_gen_load_incr<T>(const GenDev &, const double *, const double *, T *,     \
                                           hipStream_t);                                            \
     template void launch_gen_export<T>(const GenDev &, const T *, double *, hipStream_t);

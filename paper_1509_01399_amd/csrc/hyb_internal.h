@@ -60,7 +60,11 @@ struct Step {
     const T *Da, *VDa;
     T *Dc, *VDc;
     const T *acube;          // conductivity a per FEM cube [C^3]
-    T c2;                    // (dt/h)^2
+    T c2;                    // (dt/h)^2 (times w2)
+    double w2;               // weight of dt^2 in the leapfrog rows of this step: 1, or
+                             // 1/2 in the first step of the Taylor start (Model
+                             // Problem 1); the adjoint's gradient term of that step
+                             // carries the same weight
     T r;                     // (h - dt)/(h + dt), eq. (eq:abs2)
     T w[12];                 // cube edge weights / h: x-edges [y+2z], y [x+2z], z [x+2y]
     int types0, types1, types2;  // face conditions of steps k-1, k, k+1
@@ -104,6 +108,10 @@ void launch_acube(const Geo &g, const double *sigma, T *acube, double *partials,
 // copy a full grid level (unpadded FP64) into a padded field, and its FEM part
 template <typename T>
 void launch_load_level(const Geo &g, const double *src, T *U, T *V, hipStream_t st);
+// the same for the combination a + cb * b of two full levels (either may be
+// null = 0)
+template <typename T>
+void launch_load_combo(const Geo &g, const double *a, const double *b, double cb, T *U, T *V, hipStream_t st);
 // increments d^0 = u^0 - u^{-1} of given initial levels (either may be null = 0)
 template <typename T>
 void launch_load_incr(const Geo &g, const double *u0, const double *um1, T *D, T *VD, hipStream_t st);

@@ -732,6 +732,8 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
     const bool hcol = i >= 2 && i <= Cx - 2 && j >= 2 && j <= Cy - 2;
     const int hn0 = g.hn[0], hn1 = g.hn[1];
     const long long hpz = (long long)hn0 * hn1;
+    bool qfull = false;  // ql, hl hold plane k of the gradient corners
+    double ql[4] = {0, 0, 0, 0}, hl[4] = {0, 0, 0, 0};
     for (int k = k0; k < k1; ++k, id += fz) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) ahi[q] = A[cb + (q & 1) + (q >> 1) * cpy + (long long)k * cpz];
@@ -765,16 +767,40 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
             }
             // gradient of eq. (gradient1): cube with lower corner (i,j,k),
             // sum over its 12 edges of w_e (D_e lambda^{k+1}) (D_e u^k) in FP64
+            // The corners of plane k come from the previous iteration's plane
+            // k+1 (register queue), so each plane's multipliers and history
+            // values are loaded once per column.  Plain loads for the
+            // history: the four columns around a corner re-read it from L2.
             if (gcol && k >= 2 && k <= Cz - 3) {
                 double q[8], hv[8];
                 const T *H = s.hist;
+                const long long hb = (i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz;
+                if (!qfull) {
+                    ql[0] = (double)v0;
+                    ql[1] = (double)xp;
+                    ql[2] = (double)yp;
+                    ql[3] = (double)s.Vb[id + 1 + fy];
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
-                    q[c] = (double)s.Vb[id + dx + dy * fy + dz * fz];
-                    hv[c] = (double)ld_once<T, true>(H + (i - 2 + dx) + (long long)(j - 2 + dy) * hn0 +
-                                                   (long long)(k - 2 + dz) * hpz);
+                    for (int c = 0; c < 4; ++c) hl[c] = (double)H[hb + (c & 1) + (c >> 1) * hn0];
                 }
+                double qh[4], hh[4];
+                qh[0] = (double)vp;
+                qh[1] = (double)s.Vb[id + fz + 1];
+                qh[2] = (double)s.Vb[id + fz + fy];
+                qh[3] = (double)s.Vb[id + fz + fy + 1];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) hh[c] = (double)H[hb + hpz + (c & 1) + (c >> 1) * hn0];
+                // corner c = dx + 2 dy + 4 dz
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    q[c] = ql[c];
+                    q[c + 4] = qh[c];
+                    hv[c] = hl[c];
+                    hv[c + 4] = hh[c];
+                    ql[c] = qh[c];
+                    hl[c] = hh[c];
+                }
+                qfull = true;
                 double acc = 0.0;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -786,7 +812,9 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
                     acc += (double)w[4 + e] * (q[ay1] - q[ay0]) * (hv[ay1] - hv[ay0]);
                     acc += (double)w[8 + e] * (q[az1] - q[az0]) * (hv[az1] - hv[az0]);
                 }
-                s.G[i + cpy * j + cpz * k] += acc;
+                s.G[i + cpy * j + cpz * k] += s.w2 * acc;
+            } else {
+                qfull = false;
             }
         }
         if constexpr (incr_form<T>()) {
@@ -1010,6 +1038,28 @@ template <typename T>
 void launch_load_level(const Geo &g, const double *src, T *U, T *V, hipStream_t st)
 {
     hipLaunchKernelGGL((k_load_level<T>), dim3(2048), dim3(BLOCK), 0, st, g, src, U, V);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_load_combo(Geo g, const double *a, const double *b, double cb, T *U,
+                                                      T *V)
+{
+    const long long n = (long long)g.nx * g.ny * g.nz;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const int x = (int)(t % g.nx), y = (int)((t / g.nx) % g.ny), z = (int)(t / ((long long)g.nx * g.ny));
+        const T v = (T)((a ? a[t] : 0.0) + (b ? cb * b[t] : 0.0));
+        U[gidx(g, x, y, z)] = v;
+        if (g.has_fem) {
+            const int i = x - g.o[0], j = y - g.o[1], k = z - g.o[2];
+            if (i >= 0 && i <= g.C[0] && j >= 0 && j <= g.C[1] && k >= 0 && k <= g.C[2]) V[fidx(g, i, j, k)] = v;
+        }
+    }
+}
+
+template <typename T>
+void launch_load_combo(const Geo &g, const double *a, const double *b, double cb, T *U, T *V, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_load_combo<T>), dim3(2048), dim3(BLOCK), 0, st, g, a, b, cb, U, V);
 }
 
 template <typename T>
@@ -1277,6 +1327,8 @@ void launch_residual(const double *obs, const double *data, double *res, long lo
     template void launch_batch_adj<T>(const Geo &, const Step<T> *, int, hipStream_t);                                \
     template void launch_acube<T>(const Geo &, const double *, T *, double *, double *, hipStream_t); \
     template void launch_load_level<T>(const Geo &, const double *, T *, T *, hipStream_t);        \
+    template void launch_load_combo<T>(const Geo &, const double *, const double *, double, T *, T *, \
+                                       hipStream_t);                                              \
     template void launch_load_incr<T>(const Geo &, const double *, const double *, T *, T *, hipStream_t); \
     template void launch_hist_level<T>(const Geo &, const T *, T *, hipStream_t);                  \
     template void launch_record_face<T>(const Geo &, const T *, double *, hipStream_t);            \

@@ -28,7 +28,7 @@ EXPORTS = ("hyb_create", "hyb_destroy", "hyb_forward", "hyb_set_initial", "hyb_a
            "hyb_counts", "hyb_time_interior", "hyb_get_wavefield", "hyb_batch_create",
            "hyb_batch_destroy", "hyb_batch_submit", "hyb_batch_tick", "hyb_batch_poll",
            "hyb_batch_release", "hyb_batch_last_error", "hyb_batch_poll_all", "hyb_fem_info",
-           "hyb_time_fem")
+           "hyb_time_fem", "hyb_set_initial_taylor")
 
 
 class hyb_fd_grid(ct.Structure):
@@ -84,6 +84,7 @@ def load():
     lib.hyb_destroy.restype = None
     lib.hyb_forward.argtypes = [vp, vp, P(hyb_source), ct.c_int32, dp, vp]
     lib.hyb_set_initial.argtypes = [vp, vp, vp]
+    lib.hyb_set_initial_taylor.argtypes = [vp, vp, vp]
     lib.hyb_adjoint.argtypes = [vp, vp, ct.c_int32]
     lib.hyb_gradient.argtypes = [vp, vp, P(dp)]
     lib.hyb_cg_step.argtypes = [vp, vp, vp, P(hyb_source), ct.c_int32, dp, P(hyb_cg_state), P(dp),
@@ -197,6 +198,10 @@ def hyb_forward(ctx, sigma, src, nt, dt, obs):
 
 def hyb_set_initial(ctx, u0, um1):
     _check(load().hyb_set_initial(ctx, _ptr(u0), _ptr(um1)), ctx)
+
+
+def hyb_set_initial_taylor(ctx, f0, f1):
+    _check(load().hyb_set_initial_taylor(ctx, _ptr(f0), _ptr(f1)), ctx)
 
 
 def hyb_adjoint(ctx, residual, mode):
@@ -374,6 +379,11 @@ class Solver:
     def set_initial(self, u0=None, um1=None):
         self._ic = (u0, um1)
         hyb_set_initial(self.ctx, u0, um1)
+
+    def set_initial_taylor(self, f0=None, f1=None):
+        """Model Problem 1 data u(x,0) = f0, u_t(x,0) = f1 for every later
+        forward sweep (None, None: back to zero data)."""
+        hyb_set_initial_taylor(self.ctx, f0, f1)
 
     def adjoint(self, residual, mode=0):
         hyb_adjoint(self.ctx, residual, mode)

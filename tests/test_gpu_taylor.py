@@ -1,0 +1,241 @@
+"""GPU parity of Model Problem 1 (eq. (model1)): initial data u(x,0) = f0,
+u_t(x,0) = f1 with the second-order Taylor start (hyb_set_initial_taylor),
+through the C ABI against the oracle's Taylor start:
+
+- FP64 (<= 1e-12): traces, final grid and FEM fields, the cotangent of u^0,
+  the Euclidean gradient of a random trace cotangent, the L2 gradient and J;
+  the paper's Test 1 data f0 = exp(-|x|^2), f1 = 0 and random f1;
+- FP32 fields: trace <= 1e-5, gradient <= 1e-4;
+- checkpoint store modes reproduce the full history bitwise;
+- two CG iterations of IP1 (every sweep from the same data);
+- the 6-tetrahedra split on the general path equals the structured path;
+- zero data equal Model Problem 2 bitwise; the batch path refuses the data.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1509_01399_amd import hyb
+    assert torch.cuda.is_available()
+    hyb.load()
+    return torch
+
+
+def _t(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _grid(n):
+    h = 1.0 / n
+    z, y, x = np.meshgrid(*(np.arange(n + 1) * h,) * 3, indexing="ij")
+    return x, y, z
+
+
+def _data(n, kind, seed=0):
+    """f0, f1 on the (n+1)^3 grid: kind 'paper' is the initial condition of
+    the paper's Test 1 (a Gaussian exp(-|x|^2) at rest); 'moving' adds a
+    smooth random initial velocity."""
+    x, y, z = _grid(n)
+    f0 = np.exp(-(x ** 2 + y ** 2 + z ** 2))
+    if kind == "paper":
+        return f0, None
+    rng = np.random.default_rng(seed)
+    a, b, c = rng.uniform(1, 4, 3)
+    f1 = np.sin(a * x + 0.3) * np.cos(b * y) * np.sin(c * z + 0.1)
+    return f0, f1
+
+
+def _case(seed=0):
+    n, C, o = 24, 10, 7
+    h = 1.0 / n
+    rng = np.random.default_rng(seed)
+    sig = np.zeros((C, C, C))
+    sig[2:C - 2, 2:C - 2, 2:C - 2] = rng.uniform(0, 3, (C - 4,) * 3)
+    return n, C, o, h, sig
+
+
+@pytest.mark.parametrize("kind", ["paper", "moving"])
+def test_taylor_fp64_parity(env, orc, kind):
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C, o, h, sig = _case(3)
+    bc = (0, 1, 0, 0, 1, 2)
+    dt, nt, om = 0.25 * h, 60, 25.0
+    f0, f1 = _data(n, kind, 4)
+    print(f"[taylor] fp64 {kind} n={n} C={C} nt={nt}", flush=True)
+    s = Solver(n, C=C, o=o, bc=bc)
+    s.set_initial_taylor(_t(torch, f0), None if f1 is None else _t(torch, f1))
+    obs = s.forward(_t(torch, sig), nt, dt, omega=om).cpu().numpy()
+    u, v = s.wavefield(0)
+    g = orc.Geometry(n, bc=bc, fem_o=o, fem_c=C)
+    ref, vh, uf = orc.forward(g, sig.ravel(), nt, dt, omega=om, taylor=True, f0=f0, f1=f1, want_vhist=True,
+                              want_ufinal=True)
+    assert rel(obs, ref) <= TOL64
+    assert rel(u.cpu().numpy(), uf) <= TOL64
+    assert rel(v.cpu().numpy(), vh[nt]) <= TOL64
+    # the start differs from the plain leapfrog start from (f0, f0 - dt f1)
+    ref2 = orc.forward(g, sig.ravel(), nt, dt, omega=om, u0=f0,
+                       um1=f0 - dt * (0 if f1 is None else f1))
+    assert rel(ref2, ref) > 1e-6
+    # Euclidean gradient and cotangent of u^0 for a random trace cotangent
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(ref.shape)
+    s.adjoint(_t(torch, r), mode=1)
+    gsig, _ = s.gradient(want_J=False)
+    mu, muv = s.wavefield(1)
+    du0 = mu.cpu().numpy().copy()
+    du0[o:o + C + 1, o:o + C + 1, o:o + C + 1] += muv.cpu().numpy()
+    dsig, du0_ref, _ = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=om, taylor=True, f0=f0, f1=f1,
+                                   want_dinit=True)
+    assert rel(gsig.cpu().numpy(), dsig) <= TOL64
+    assert rel(du0, du0_ref) <= TOL64
+    # L2 gradient and J against data from another conductivity
+    data = orc.forward(g, 0.5 * sig.ravel(), nt, dt, omega=om, taylor=True, f0=f0, f1=f1)
+    obs2 = s.forward(_t(torch, sig), nt, dt, omega=om)
+    s.adjoint(obs2 - _t(torch, data), mode=0)
+    grad, J = s.gradient()
+    gref, Jref = orc.gradient(g, sig.ravel(), nt, dt, data, omega=om, taylor=True, f0=f0, f1=f1)
+    s.close()
+    print(f"[taylor] {kind}: grad err {rel(grad.cpu().numpy(), gref):.2e}, J {J:.6e} vs {Jref:.6e}", flush=True)
+    assert rel(grad.cpu().numpy(), gref) <= TOL64
+    assert abs(J - Jref) <= TOL64 * abs(Jref)
+
+
+def test_taylor_fp32_bounds(env, orc):
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C, o, h, sig = _case(6)
+    dt, nt, om = 0.25 * h, 150, 30.0
+    f0, f1 = _data(n, "moving", 7)
+    print(f"[taylor] fp32 n={n} nt={nt}", flush=True)
+    s = Solver(n, C=C, o=o, f32=True)
+    s.set_initial_taylor(_t(torch, f0), _t(torch, f1))
+    obs = s.forward(_t(torch, sig), nt, dt, omega=om).cpu().numpy()
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    ref = orc.forward(g, sig.ravel(), nt, dt, omega=om, taylor=True, f0=f0, f1=f1)
+    r = np.random.default_rng(8).standard_normal(ref.shape)
+    s.adjoint(_t(torch, r), mode=1)
+    gsig, _ = s.gradient(want_J=False)
+    s.close()
+    dsig = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=om, taylor=True, f0=f0, f1=f1)
+    e_t, e_g = rel(obs, ref), rel(gsig.cpu().numpy(), dsig)
+    print(f"[taylor] fp32 trace {e_t:.2e} grad {e_g:.2e}", flush=True)
+    assert e_t <= 1e-5 and e_g <= 1e-4
+
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_taylor_checkpoints_bitwise(env, f32):
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C, o, h, sig = _case(9)
+    dt, nt, om = 0.25 * h, 70, 30.0
+    f0, f1 = _data(n, "moving", 10)
+    r = _t(torch, np.random.default_rng(11).standard_normal((nt + 1, n + 1, n + 1)))
+    out = []
+    for mode in (0, 1):
+        s = Solver(n, C=C, o=o, f32=f32, store_mode=mode)
+        s.set_initial_taylor(_t(torch, f0), _t(torch, f1))
+        obs = s.forward(_t(torch, sig), nt, dt, omega=om)
+        s.adjoint(r, mode=1)
+        gsig, _ = s.gradient(want_J=False)
+        out.append((obs.cpu().numpy(), gsig.cpu().numpy()))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_taylor_cg_ip1(env, orc):
+    """IP1: two iterations of Algorithm 3 where every sweep starts from the
+    Model Problem 1 data."""
+    from paper_1509_01399_amd import hyb
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C, o, h, sig_true = _case(12)
+    dt, nt, om = 0.25 * h, 120, 30.0
+    f0, f1 = _data(n, "moving", 13)
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    data = orc.forward(g, sig_true.ravel(), nt, dt, omega=om, taylor=True, f0=f0, f1=f1)
+    sig_ref, log = orc.cg(g, np.zeros(C ** 3), nt, dt, data, 2, omega=om, taylor=True, f0=f0, f1=f1)
+    s = Solver(n, C=C, o=o)
+    s.set_initial_taylor(_t(torch, f0), _t(torch, f1))
+    sig = torch.zeros((C,) * 3, dtype=torch.float64, device="cuda")
+    st = hyb.hyb_cg_state()
+    d = _t(torch, data)
+    for m in range(2):
+        gn, J = s.cg_step(d, sig, nt, dt, st, omega=om)
+        print(f"[taylor] cg {m}: |g| {gn:.6e} vs {log[m, 1]:.6e}, J {J:.6e} vs {log[m, 0]:.6e}", flush=True)
+        assert abs(gn - log[m, 1]) <= 1e-11 * log[m, 1]
+        assert abs(J - log[m, 0]) <= 1e-11 * log[m, 0]
+    s.close()
+    assert rel(sig.cpu().numpy(), sig_ref) <= 1e-11
+
+
+def test_taylor_general_kuhn_equals_structured(env):
+    from paper_1509_01399_amd import synth
+    from paper_1509_01399_amd.hyb import Solver
+    torch = env
+    n, C = 32, 16
+    o, h = (n - C) // 2, 1.0 / n
+    sc = synth.cubes(C, seed=14, edge=(2, 4), value=(1.0, 3.0))
+    dt, nt, om = 0.2 * h, 80, 30.0
+    f0, f1 = _data(n, "moving", 15)
+    out = {}
+    for general in (False, True):
+        print(f"[taylor] kuhn general={general}", flush=True)
+        s = Solver(n, C=C, general=general)
+        sig = np.repeat(sc.ravel(), 6) if general else sc
+        s.set_initial_taylor(_t(torch, f0), _t(torch, f1))
+        obs = s.forward(_t(torch, sig), nt, dt, omega=om)
+        u, v = s.wavefield(0)
+        s.adjoint(obs - 0.8 * obs, mode=0)
+        mu, mv = s.wavefield(1)
+        gr, J = s.gradient()
+        out[general] = dict(obs=obs.cpu().numpy(), u=u.cpu().numpy(), v=v.cpu().numpy(), mu=mu.cpu().numpy(),
+                            mv=mv.cpu().numpy(), g=gr.cpu().numpy(), J=J)
+        s.close()
+    a, b = out[False], out[True]
+    for k in ("obs", "u", "v", "mu", "mv"):
+        assert rel(b[k], a[k]) <= TOL64, k
+    assert rel(b["g"].reshape(-1, 6).mean(1), a["g"]) <= TOL64
+    assert abs(b["J"] - a["J"]) <= TOL64 * abs(a["J"])
+
+
+def test_taylor_zero_data_and_refusals(env):
+    from paper_1509_01399_amd import hyb
+    from paper_1509_01399_amd.hyb import HybError, Solver
+    torch = env
+    n, C, o, h, sig = _case(16)
+    dt, nt, om = 0.25 * h, 50, 30.0
+    s = Solver(n, C=C, o=o)
+    a = s.forward(_t(torch, sig), nt, dt, omega=om).cpu().numpy()
+    zero = torch.zeros((n + 1,) * 3, dtype=torch.float64, device="cuda")
+    s.set_initial_taylor(zero, zero)
+    b = s.forward(_t(torch, sig), nt, dt, omega=om).cpu().numpy()
+    assert np.array_equal(a, b)
+    # the batch path starts from zero data only
+    bt = hyb.hyb_batch_create(2)
+    obs = torch.zeros((nt + 1, n + 1, n + 1), dtype=torch.float64, device="cuda")
+    grad = torch.zeros((C,) * 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(HybError) as ei:
+        hyb.hyb_batch_submit(bt, s.ctx, _t(torch, sig), float(sig.max()), hyb.make_source(om), nt, dt, obs, obs,
+                             grad)
+    assert ei.value.status == hyb.HYB_E_UNSUPPORTED
+    hyb.hyb_batch_destroy(bt)
+    # back to Model Problem 2
+    s.set_initial_taylor(None, None)
+    c = s.forward(_t(torch, sig), nt, dt, omega=om).cpu().numpy()
+    assert np.array_equal(a, c)
+    s.close()
