@@ -48,20 +48,13 @@ def _load():
         dp = ct.POINTER(ct.c_double)
         G, M, S = ct.POINTER(_Geom), ct.POINTER(_Mesh), ct.POINTER(_Source)
         lib.orc_sizes_m.argtypes = [G, M, ct.POINTER(ct.c_int64)]
-        lib.orc_forward_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp]
-        lib.orc_adjoint_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp, dp, dp]
-        lib.orc_misfit.argtypes = [G, ct.c_int, ct.c_double, dp, dp, dp]
+        ci, cd = ct.c_int, ct.c_double
+        lib.orc_forward_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, dp, dp]
+        lib.orc_adjoint_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_misfit.argtypes = [G, ci, cd, dp, dp, dp]
         lib.orc_misfit.restype = ct.c_double
-        lib.orc_gradient_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, ct.c_double, dp, dp, dp]
-        lib.orc_cg_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, ct.c_double, ct.c_double,
-                                 ct.c_int, dp]
-        lib.orc_forward_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp]
-        lib.orc_adjoint_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, dp, dp, dp, dp,
-                                         dp, dp]
-        lib.orc_gradient_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, ct.c_double, dp,
-                                          dp, dp]
-        lib.orc_cg_ic_m.argtypes = [G, M, dp, S, ct.c_int, ct.c_double, dp, dp, dp, ct.c_double,
-                                    ct.c_double, ct.c_int, dp]
+        lib.orc_gradient_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, cd, dp, dp, ct.POINTER(cd), dp]
+        lib.orc_cg_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, cd, cd, ci, dp]
         _lib = lib
     return _lib
 
@@ -147,29 +140,33 @@ def _f64(a, shape=None):
     return a
 
 
+def _init(u0, um1, taylor, f0, f1):
+    """(u0, u1, taylor) of the oracle's _x calls: levels (u0, um1), or the
+    Model Problem 1 data (f0, f1) when taylor."""
+    if taylor:
+        return _f64(f0), _f64(f1), 1
+    return _f64(u0), _f64(um1), 0
+
+
 def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=None,
-            want_vhist=False, want_ufinal=False, taylor=False, f0=None, f1=None):
+            want_vhist=False, want_ufinal=False, taylor=False, f0=None, f1=None, eps=None):
     """Forward sweep of Algorithm 2.  Returns obs [nt+1, ny+1, nx+1] and,
     optionally, the FEM history [nt+1, fz, fy, fx] and the final grid level.
     Initial data: levels u0, um1 (leapfrog start), or with taylor=True the
-    Model Problem 1 data f0 = u(x,0), f1 = u_t(x,0) with the Taylor start."""
+    Model Problem 1 data f0 = u(x,0), f1 = u_t(x,0) with the Taylor start.
+    eps: 1/c^2 per FEM cube (None = 1)."""
     lib = _load()
     g = geom._c()
     sz = geom.sizes()
-    sigma = _f64(sigma)
+    sigma, eps = _f64(sigma), _f64(eps)
     flux = _f64(flux)
-    u0, um1 = _f64(u0), _f64(um1)
+    a0, a1, tay = _init(u0, um1, taylor, f0, f1)
     obs = np.zeros((nt + 1, geom.n[1] + 1, geom.n[0] + 1))
     vh = np.zeros((nt + 1, sz["fem_nodes"])) if want_vhist and sz["fem_nodes"] else None
     uf = np.zeros(sz["grid_nodes"]) if want_ufinal else None
     s = _src(1 if flux is not None else 0, omega, flux, k_on)
-    if taylor:
-        f0, f1 = _f64(f0), _f64(f1)
-        rc = lib.orc_forward_ic_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(f0), _p(f1),
-                                  _p(obs), _p(vh), _p(uf))
-    else:
-        rc = lib.orc_forward_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
-                               _p(obs), _p(vh), _p(uf))
+    rc = lib.orc_forward_x(ct.byref(g), geom._m(), _p(sigma), _p(eps), ct.byref(s), nt, dt, _p(a0), _p(a1), tay,
+                           _p(obs), _p(vh), _p(uf))
     if rc:
         raise RuntimeError(f"orc_forward failed ({rc})")
     out = [obs]
@@ -181,36 +178,35 @@ def forward(geom, sigma, nt, dt, omega=40.0, flux=None, k_on=0, u0=None, um1=Non
 
 
 def adjoint(geom, sigma, nt, dt, seed, omega=40.0, flux=None, k_on=0, u0=None, um1=None,
-            want_dflux=False, want_dinit=False, taylor=False, f0=None, f1=None, want_ddata=False):
+            want_dflux=False, want_dinit=False, taylor=False, f0=None, f1=None, want_ddata=False,
+            eps=None, want_deps=False):
     """Exact discrete adjoint: seed [nt+1, face] is the cotangent of the
-    trace.  Returns dJ/dsigma per cell (Euclidean) and optionally the source
-    cotangent [nt, face], the cotangents of u^0, u^{-1} (want_dinit) and,
-    with taylor=True (Model Problem 1 data f0, f1), those of f0 and f1
-    (want_ddata)."""
+    trace.  Returns dJ/dsigma per cell (Euclidean) and optionally, in this
+    order: dJ/d(1/c^2) per cube (want_deps), the source cotangent [nt, face],
+    the cotangents of u^0, u^{-1} (want_dinit) and, with taylor=True (Model
+    Problem 1 data f0, f1), those of f0 and f1 (want_ddata)."""
     lib = _load()
     g = geom._c()
     sz = geom.sizes()
-    sigma = _f64(sigma)
+    sigma, eps = _f64(sigma), _f64(eps)
     flux = _f64(flux)
     seed = _f64(seed)
-    u0, um1 = _f64(u0), _f64(um1)
+    a0, a1, tay = _init(u0, um1, taylor, f0, f1)
     dsig = np.zeros(max(sz["fem_cubes"], 1))
+    deps = np.zeros(max(sz["fem_cubes"], 1)) if want_deps else None
     dflux = np.zeros((nt, geom.nface)) if want_dflux else None
     du0 = np.zeros(sz["grid_nodes"]) if want_dinit else None
     dum1 = np.zeros(sz["grid_nodes"]) if want_dinit else None
-    s = _src(1 if flux is not None else 0, omega, flux, k_on)
     df0 = np.zeros(sz["grid_nodes"]) if want_ddata else None
     df1 = np.zeros(sz["grid_nodes"]) if want_ddata else None
-    if taylor:
-        f0, f1 = _f64(f0), _f64(f1)
-        rc = lib.orc_adjoint_ic_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(f0), _p(f1),
-                                  _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1), _p(df0), _p(df1))
-    else:
-        rc = lib.orc_adjoint_m(ct.byref(g), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(u0), _p(um1),
-                               _p(seed), _p(dsig), _p(dflux), _p(du0), _p(dum1))
+    s = _src(1 if flux is not None else 0, omega, flux, k_on)
+    rc = lib.orc_adjoint_x(ct.byref(g), geom._m(), _p(sigma), _p(eps), ct.byref(s), nt, dt, _p(a0), _p(a1), tay,
+                           _p(seed), _p(dsig), _p(deps), _p(dflux), _p(du0), _p(dum1), _p(df0), _p(df1))
     if rc:
         raise RuntimeError(f"orc_adjoint failed ({rc})")
     out = [dsig[:sz["fem_cubes"]]]
+    if want_deps:
+        out.append(deps[:sz["fem_cubes"]])
     if want_dflux:
         out.append(dflux)
     if want_dinit:
@@ -230,46 +226,47 @@ def misfit(geom, nt, dt, obs, data):
 
 
 def gradient(geom, sigma, nt, dt, data, gamma=0.01, omega=40.0, want_obs=False, f0=None, f1=None,
-             taylor=False):
+             taylor=False, eps=None, want_geps=False):
     """L2 gradient g_c (eq. (gradient1), discrete) and J at sigma; with
-    taylor=True the sweeps start from Model Problem 1 data (f0, f1)."""
+    taylor=True the sweeps start from Model Problem 1 data (f0, f1); eps:
+    1/c^2 per cube.  Returns (grad, J[, geps][, obs]); geps is the L2
+    density of dJ_misfit/d(1/c^2)."""
     lib = _load()
     sz = geom.sizes()
-    sigma = _f64(sigma)
+    sigma, eps = _f64(sigma), _f64(eps)
     data = _f64(data)
     grad = np.zeros(sz["fem_cubes"])
+    geps = np.zeros(sz["fem_cubes"]) if want_geps else None
     J = ct.c_double()
     obs = np.zeros_like(data) if want_obs else None
+    a0, a1, tay = _init(None, None, taylor, f0, f1)
     s = _src(0, omega)
-    if taylor:
-        f0, f1 = _f64(f0), _f64(f1)
-        rc = lib.orc_gradient_ic_m(ct.byref(geom._c()), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(f0),
-                                   _p(f1), _p(data), gamma, _p(grad), ct.byref(J), _p(obs))
-    else:
-        rc = lib.orc_gradient_m(ct.byref(geom._c()), geom._m(), _p(sigma), ct.byref(s), nt, dt, _p(data),
-                                gamma, _p(grad), ct.byref(J), _p(obs))
+    rc = lib.orc_gradient_x(ct.byref(geom._c()), geom._m(), _p(sigma), _p(eps), ct.byref(s), nt, dt, _p(a0),
+                            _p(a1), tay, _p(data), gamma, _p(grad), _p(geps), ct.byref(J), _p(obs))
     if rc:
         raise RuntimeError(f"orc_gradient failed ({rc})")
-    return (grad, J.value, obs) if want_obs else (grad, J.value)
+    out = [grad, J.value]
+    if want_geps:
+        out.append(geps)
+    if want_obs:
+        out.append(obs)
+    return tuple(out)
 
 
 def cg(geom, sigma, nt, dt, data, iters, gamma=0.01, alpha_rel=0.25, omega=40.0, f0=None, f1=None,
-       taylor=False):
+       taylor=False, eps=None):
     """Algorithm 3: returns (sigma after `iters` iterations, log [iters, 5]
     with columns J, |g|_L2, beta, alpha, max|d|).  taylor=True: IP1, every
-    sweep starts from Model Problem 1 data (f0, f1)."""
+    sweep starts from Model Problem 1 data (f0, f1); eps: a known 1/c^2 per
+    cube."""
     lib = _load()
     sig = np.array(sigma, dtype=np.float64, copy=True)
     data = _f64(data)
     log = np.zeros((iters, 5))
+    a0, a1, tay = _init(None, None, taylor, f0, f1)
     s = _src(0, omega)
-    if taylor:
-        f0, f1 = _f64(f0), _f64(f1)
-        rc = lib.orc_cg_ic_m(ct.byref(geom._c()), geom._m(), _p(sig), ct.byref(s), nt, dt, _p(f0), _p(f1),
-                             _p(data), gamma, alpha_rel, iters, _p(log))
-    else:
-        rc = lib.orc_cg_m(ct.byref(geom._c()), geom._m(), _p(sig), ct.byref(s), nt, dt, _p(data), gamma,
-                          alpha_rel, iters, _p(log))
+    rc = lib.orc_cg_x(ct.byref(geom._c()), geom._m(), _p(sig), _p(_f64(eps)), ct.byref(s), nt, dt, _p(a0), _p(a1),
+                      tay, _p(data), gamma, alpha_rel, iters, _p(log))
     if rc:
         raise RuntimeError(f"orc_cg failed ({rc})")
     return sig, log

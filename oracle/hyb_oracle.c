@@ -46,6 +46,10 @@
  *     derivative of the discrete functional;
  *   - CG step length alpha^m = alpha_rel / max|d^m| followed by projection
  *     onto the admissible set 1 <= a <= 5 of eq. (admpar);
+ *   - variable wave speed (eq. (modelhyb)): the coefficient 1/c^2 of the
+ *     time derivative is piecewise constant per free cube like a, and 1
+ *     elsewhere (condition (coefic)); it weights the element mass matrices,
+ *     so each lumped mass is sum_K (1/c^2)_K |K| / 4 (prob_init);
  *   - Model Problem 1 (eq. (model1)): the first level follows from the data
  *     u(x,0) = f0, u_t(x,0) = f1 by the second-order Taylor start
  *     u^1 = u^0 + tau f1 + (tau^2/2) A(u^0) (orc_ic); the paper names the data
@@ -59,7 +63,10 @@
  * second order; the adjoint passes a dot test; the gradient matches central
  * finite differences.  The Taylor start reproduces a solution quadratic in
  * time exactly, converges at second order for a travelling pulse with
- * non-zero initial velocity, and its adjoint passes a dot test in (f0, f1).  The CG driver (orc_cg) is pinned only by invariants
+ * non-zero initial velocity, and its adjoint passes a dot test in (f0, f1).
+ * With 1/c^2 the sweep equals an independent whole-grid formulation whose
+ * masses come from brute-force Kuhn mass shares, conserves the discrete
+ * energy with those masses, and dJ/d(1/c^2) matches central differences.  The CG driver (orc_cg) is pinned only by invariants
  * (descent, feasibility, first iterate = projected steepest descent):
  * parity unpinned beyond those.
  */
@@ -128,6 +135,9 @@ typedef struct {
     int64_t nb[4];         /* boundary node counts by codimension 1..3          */
     int64_t *bnd[4];       /* boundary nodes by codimension                     */
     double *pvol;          /* [ncube] volume of each parameter cell (cube/tet)   */
+    double *ecube;         /* [ncube] wave-speed coefficient 1/c^2 per cube      */
+                           /* (lattice mode; 1 on non-free cubes), or NULL       */
+    double *tvol;          /* [ntet] tetrahedron volumes (lattice mode)          */
     int64_t *fgrid;        /* [fn] grid index of an FEM node on a grid point, -1 */
 } orc_prob;
 
@@ -155,7 +165,7 @@ static void prob_free(orc_prob *P)
     free(P->tet); free(P->tcube); free(P->ke); free(P->mass); free(P->acube);
     free(P->eligible); free(P->fdm_row); free(P->fem_row);
     free(P->wo_g); free(P->wo_f); free(P->wd_g); free(P->wd_f);
-    free(P->pvol); free(P->fgrid);
+    free(P->pvol); free(P->fgrid); free(P->ecube); free(P->tvol);
     for (int c = 1; c <= 3; ++c) free(P->bnd[c]);
     memset(P, 0, sizeof(*P));
 }
@@ -219,8 +229,13 @@ static int prob_init_mesh(orc_prob *P, const orc_mesh *m, const double *sigma);
  * mesh), element stiffness matrices from the vertex coordinates, lumped
  * masses, and the overlap node sets of Sec. 3.  sigma may be NULL (a = 1
  * everywhere); it holds one value per cube, or per tetrahedron of a given
- * mesh. */
-static int prob_init(orc_prob *P, const orc_geom *g, const orc_mesh *m, const double *sigma)
+ * mesh.  eps (lattice mode only; NULL = 1): the coefficient 1/c^2 of the
+ * time derivative in eq. (modelhyb), one value per cube, used on the free
+ * cubes (c = 1 near and outside the FEM box, condition (coefic)); it weights
+ * the element mass matrices, so the lumped mass of node i is
+ * sum_{K containing i} eps_K |K| / 4. */
+static int prob_init(orc_prob *P, const orc_geom *g, const orc_mesh *m, const double *sigma,
+                     const double *eps)
 {
     memset(P, 0, sizeof(*P));
     if (geom_check(g)) return -1;
@@ -262,7 +277,7 @@ static int prob_init(orc_prob *P, const orc_geom *g, const orc_mesh *m, const do
     }
 
     if (!P->has_fem) return m ? -1 : 0;
-    if (m) return prob_init_mesh(P, m, sigma);
+    if (m) return eps ? -1 : prob_init_mesh(P, m, sigma);
 
     P->fx = C[0] + 1; P->fy = C[1] + 1; P->fz = C[2] + 1;
     P->fn = (int64_t)P->fx * P->fy * P->fz;
@@ -277,6 +292,8 @@ static int prob_init(orc_prob *P, const orc_geom *g, const orc_mesh *m, const do
     P->fem_row = (uint8_t *)calloc((size_t)P->fn, 1);
     P->pvol = (double *)malloc(sizeof(double) * (size_t)P->ncube);
     P->fgrid = (int64_t *)malloc(sizeof(int64_t) * (size_t)P->fn);
+    P->ecube = (double *)malloc(sizeof(double) * (size_t)P->ncube);
+    P->tvol = (double *)malloc(sizeof(double) * (size_t)P->ntet);
     for (int64_t c = 0; c < P->ncube; ++c) P->pvol[c] = g->h * g->h * g->h;
     for (int c = 0; c < P->fz; ++c)
         for (int b = 0; b < P->fy; ++b)
@@ -292,6 +309,7 @@ static int prob_init(orc_prob *P, const orc_geom *g, const orc_mesh *m, const do
                            c >= 2 && c < C[2] - 2;
                 P->eligible[cube] = (uint8_t)elig;
                 P->acube[cube] = 1.0 + ((elig && sigma) ? sigma[cube] : 0.0);
+                P->ecube[cube] = (elig && eps) ? eps[cube] : 1.0;
                 for (int p = 0; p < 6; ++p, ++t) {
                     int v[3] = {a, b, c};
                     double X[4][3];
@@ -307,7 +325,8 @@ static int prob_init(orc_prob *P, const orc_geom *g, const orc_mesh *m, const do
                             P->ke[16 * t + 4 * r + s] =
                                 vol * (Gr[r][0] * Gr[s][0] + Gr[r][1] * Gr[s][1] +
                                        Gr[r][2] * Gr[s][2]);
-                    for (int q = 0; q < 4; ++q) P->mass[P->tet[4 * t + q]] += vol / 4.0;
+                    for (int q = 0; q < 4; ++q) P->mass[P->tet[4 * t + q]] += P->ecube[cube] * vol / 4.0;
+                    P->tvol[t] = vol;
                     P->tcube[t] = (int32_t)cube;
                 }
             }
@@ -603,8 +622,6 @@ typedef struct {
     int taylor;
 } orc_ic;
 
-static const orc_ic ORC_IC_ZERO = {NULL, NULL, NULL, 0};
-
 /* tau^2 weight of step k. */
 static double step_w2(const orc_ic *ic, int k) { return (ic->taylor && k == 0) ? 0.5 : 1.0; }
 
@@ -658,7 +675,8 @@ static int forward_sweep(const orc_prob *P, const orc_source *S, int nt, double 
 static void step_adjoint(const orc_prob *P, int k, double dt, double w2, const orc_source *S, int k_on,
                          double *aUm, double *aU, double *aUp,
                          double *aVm, double *aV, double *aVp,
-                         const double *V, double *dsig, double *dflux, double *gsave)
+                         const double *V, double *dsig, double *dflux, double *gsave,
+                         double *deps, double *rsave)
 {
     const double h = P->g.h, h2 = h * h, tau2 = w2 * dt * dt;
     const double rr = (h - dt) / (h + dt);
@@ -743,6 +761,31 @@ static void step_adjoint(const orc_prob *P, int k, double dt, double w2, const o
                 if (P->eligible[cube]) dsig[cube] += gq * s;
             }
         }
+        /* wave-speed coefficient: the FEM row n divides by its lumped mass
+         * m_n, so dJ/dm_n = (cotangent of v_n^{k+1}) tau^2 (K u^k)_n / m_n^2
+         * = -gsave_n (K u^k)_n / m_n, and m_n = sum_{K containing n}
+         * eps_K |K| / 4 passes it to the cubes. */
+        if (deps && P->ecube) {
+            memset(rsave, 0, sizeof(double) * (size_t)P->fn);
+            for (int64_t t = 0; t < P->ntet; ++t) {
+                const int32_t *v = P->tet + 4 * t;
+                const double *ke = P->ke + 16 * t;
+                double a = P->acube[P->tcube[t]];
+                for (int q = 0; q < 4; ++q) {
+                    double s = 0.0;
+                    for (int w = 0; w < 4; ++w) s += ke[4 * q + w] * V[v[w]];
+                    rsave[v[q]] += a * s;
+                }
+            }
+            for (int64_t n = 0; n < P->fn; ++n)
+                rsave[n] = P->fem_row[n] ? -gsave[n] * rsave[n] / P->mass[n] : 0.0;
+            for (int64_t t = 0; t < P->ntet; ++t) {
+                int64_t cube = P->tcube[t];
+                if (!P->eligible[cube]) continue;
+                const int32_t *v = P->tet + 4 * t;
+                for (int q = 0; q < 4; ++q) deps[cube] += P->tvol[t] / 4.0 * rsave[v[q]];
+            }
+        }
     }
 
     /* (i)^T: FDM rows. */
@@ -769,24 +812,25 @@ static void step_adjoint(const orc_prob *P, int k, double dt, double w2, const o
  * [ncube] dJ/da_c (Euclidean), dflux [nt][nface], du0 and dum1 [nn]
  * cotangents of the initial levels. */
 static int adjoint_sweep(const orc_prob *P, const orc_source *S, int nt, double dt, const orc_ic *ic,
-                         const double *seed, const double *vhist, double *dsig,
+                         const double *seed, const double *vhist, double *dsig, double *deps,
                          double *dflux, double *du0, double *dum1)
 {
     int k_on = source_k_on(S, nt, dt);
     size_t gb = sizeof(double) * (size_t)P->nn, fb = sizeof(double) * (size_t)(P->fn ? P->fn : 1);
     double *A0 = (double *)calloc(1, gb), *A1 = (double *)calloc(1, gb), *A2 = (double *)calloc(1, gb);
     double *B0 = (double *)calloc(1, fb), *B1 = (double *)calloc(1, fb), *B2 = (double *)calloc(1, fb);
-    double *gs = (double *)calloc(1, fb);
-    if (!A0 || !A1 || !A2 || !B0 || !B1 || !B2 || !gs) return -2;
+    double *gs = (double *)calloc(1, fb), *rs = (double *)calloc(1, fb);
+    if (!A0 || !A1 || !A2 || !B0 || !B1 || !B2 || !gs || !rs) return -2;
     double *aUm = A0, *aU = A1, *aUp = A2, *aVm = B0, *aV = B1, *aVp = B2;
     int64_t base = gidx(P, 0, 0, P->nz - 1);
     if (dsig && P->has_fem) memset(dsig, 0, sizeof(double) * (size_t)P->ncube);
+    if (deps && P->has_fem) memset(deps, 0, sizeof(double) * (size_t)P->ncube);
     for (int k = nt - 1; k >= 0; --k) {
         /* (v)^T: the trace of level k+1 */
         const double *sd = seed + (int64_t)(k + 1) * P->nface;
         for (int q = 0; q < P->nface; ++q) aUp[base + q] += sd[q];
         step_adjoint(P, k, dt, step_w2(ic, k), S, k_on, aUm, aU, aUp, aVm, aV, aVp,
-                     P->has_fem ? vhist + (int64_t)k * P->fn : NULL, dsig, dflux, gs);
+                     P->has_fem ? vhist + (int64_t)k * P->fn : NULL, dsig, dflux, gs, deps, rs);
         /* aUp is fully consumed; rotate: level k becomes the newest */
         double *t1 = aUp; aUp = aU; aU = aUm; aUm = t1;
         memset(aUm, 0, gb);
@@ -803,7 +847,7 @@ static int adjoint_sweep(const orc_prob *P, const orc_source *S, int nt, double 
             }
     if (du0) memcpy(du0, aUp, gb);
     if (dum1) memcpy(dum1, aU, gb);
-    free(A0); free(A1); free(A2); free(B0); free(B1); free(B2); free(gs);
+    free(A0); free(A1); free(A2); free(B0); free(B1); free(B2); free(gs); free(rs);
     return 0;
 }
 
@@ -820,7 +864,12 @@ static double face_weight(const orc_prob *P, int i, int j)
 
 /* Every entry point takes an optional explicit mesh m (NULL: the 6-tetrahedra
  * split of the FEM box); with a mesh, sigma, dsig and grad hold one value per
- * tetrahedron.  The names without _m are the same calls without a mesh. */
+ * tetrahedron.  The _x calls take every option:
+ *   eps:  1/c^2 per cube (lattice mode only; NULL = 1), see prob_init;
+ *   u0, u1, taylor: initial data, see orc_ic (taylor = 0: levels u^0 = u0,
+ *         u^{-1} = u1; taylor = 1: Model Problem 1 data f0 = u0, f1 = u1).
+ * The names without _x are the same calls with eps = NULL and the given
+ * levels (or zero data); without _m also without a mesh. */
 
 /* Sizes: out[0] grid nodes, out[1] face nodes, out[2] FEM nodes,
  * out[3] parameter cells (cubes, or tetrahedra of a given mesh),
@@ -829,7 +878,7 @@ static double face_weight(const orc_prob *P, int i, int j)
 int orc_sizes_m(const orc_geom *g, const orc_mesh *m, int64_t *out)
 {
     orc_prob P;
-    if (prob_init(&P, g, m, NULL)) return -1;
+    if (prob_init(&P, g, m, NULL, NULL)) return -1;
     int64_t nfdm = 0, nfem = 0;
     for (int64_t i = 0; i < P.nn; ++i) nfdm += P.fdm_row[i];
     nfdm += P.nb[1] + P.nb[2] + P.nb[3];
@@ -842,58 +891,69 @@ int orc_sizes_m(const orc_geom *g, const orc_mesh *m, int64_t *out)
 
 int orc_sizes(const orc_geom *g, int64_t *out) { return orc_sizes_m(g, NULL, out); }
 
-static int forward_ic(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                      double dt, const orc_ic *ic, double *obs, double *vhist, double *ufin)
+/* Forward solve: obs [nt+1][nface]; vhist [nt+1][fn], ufin [nn] optional
+ * (initial data need every FEM node on a grid point). */
+int orc_forward_x(const orc_geom *g, const orc_mesh *m, const double *sigma, const double *eps,
+                  const orc_source *S, int nt, double dt, const double *u0, const double *u1, int taylor,
+                  double *obs, double *vhist, double *ufin)
 {
     orc_prob P;
-    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma)) return -1;
-    int rc = forward_sweep(&P, S, nt, dt, ic, obs, vhist, ufin);
+    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma, eps)) return -1;
+    const orc_ic ic = {u0, taylor ? NULL : u1, taylor ? u1 : NULL, taylor};
+    int rc = forward_sweep(&P, S, nt, dt, &ic, obs, vhist, ufin);
     prob_free(&P);
     return rc;
 }
 
-/* Forward solve: obs [nt+1][nface]; vhist, u0, um1, ufin optional (initial
- * levels need every FEM node on a grid point). */
 int orc_forward_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
                   double dt, const double *u0, const double *um1, double *obs, double *vhist, double *ufin)
 {
-    const orc_ic ic = {u0, um1, NULL, 0};
-    return forward_ic(g, m, sigma, S, nt, dt, &ic, obs, vhist, ufin);
-}
-
-/* Forward solve of Model Problem 1 (eq. (model1)) with the Taylor start of
- * orc_ic: f0 = u(x,0), f1 = u_t(x,0) on the whole grid (NULL = 0). */
-int orc_forward_ic_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                     double dt, const double *f0, const double *f1, double *obs, double *vhist, double *ufin)
-{
-    const orc_ic ic = {f0, NULL, f1, 1};
-    return forward_ic(g, m, sigma, S, nt, dt, &ic, obs, vhist, ufin);
+    return orc_forward_x(g, m, sigma, NULL, S, nt, dt, u0, um1, 0, obs, vhist, ufin);
 }
 
 int orc_forward(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
                 const double *u0, const double *um1, double *obs, double *vhist, double *ufin)
 {
-    return orc_forward_m(g, NULL, sigma, S, nt, dt, u0, um1, obs, vhist, ufin);
+    return orc_forward_x(g, NULL, sigma, NULL, S, nt, dt, u0, um1, 0, obs, vhist, ufin);
 }
 
 /* Linear adjoint: given the cotangent seed [nt+1][nface] of the trace,
  * returns dsig [cells] = dJ/da per parameter cell (Euclidean, zero on
- * non-eligible cells), and optionally dflux [nt][nface], du0, dum1 [nn]. */
-static int adjoint_ic(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                      double dt, const orc_ic *ic, const double *seed, double *dsig, double *dflux,
-                      double *du0, double *dum1)
+ * non-eligible cells) and, each optional: deps [cubes] = dJ/d(1/c^2) per
+ * cube (Euclidean, zero on non-eligible cubes; lattice mode), dflux
+ * [nt][nface], du0 and dum1 [nn] the cotangents of the levels u^0 and u^{-1}
+ * (with the FEM copies folded back), and with taylor df0, df1 [nn] those of
+ * the Model Problem 1 data: u^{-1} = f0 - tau f1, so df0 = du0 + dum1 and
+ * df1 = -tau dum1. */
+int orc_adjoint_x(const orc_geom *g, const orc_mesh *m, const double *sigma, const double *eps,
+                  const orc_source *S, int nt, double dt, const double *u0, const double *u1, int taylor,
+                  const double *seed, double *dsig, double *deps, double *dflux, double *du0, double *dum1,
+                  double *df0, double *df1)
 {
     orc_prob P;
-    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma)) return -1;
-    double *vh = NULL;
+    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma, eps)) return -1;
+    const orc_ic ic = {u0, taylor ? NULL : u1, taylor ? u1 : NULL, taylor};
+    size_t gb = sizeof(double) * (size_t)P.nn;
+    double *vh = NULL, *a0 = (double *)malloc(gb), *a1 = (double *)malloc(gb);
+    if (!a0 || !a1) { free(a0); free(a1); prob_free(&P); return -2; }
     if (P.has_fem) {
         vh = (double *)malloc(sizeof(double) * (size_t)P.fn * (size_t)(nt + 1));
-        if (!vh) { prob_free(&P); return -2; }
-        if (forward_sweep(&P, S, nt, dt, ic, NULL, vh, NULL)) { free(vh); prob_free(&P); return -1; }
+        if (!vh) { free(a0); free(a1); prob_free(&P); return -2; }
+        if (forward_sweep(&P, S, nt, dt, &ic, NULL, vh, NULL)) {
+            free(vh); free(a0); free(a1); prob_free(&P);
+            return -1;
+        }
     }
     if (dflux) memset(dflux, 0, sizeof(double) * (size_t)nt * (size_t)P.nface);
-    int rc = adjoint_sweep(&P, S, nt, dt, ic, seed, vh, dsig, dflux, du0, dum1);
-    free(vh);
+    int rc = adjoint_sweep(&P, S, nt, dt, &ic, seed, vh, dsig, deps, dflux, a0, a1);
+    if (!rc)
+        for (int64_t i = 0; i < P.nn; ++i) {
+            if (du0) du0[i] = a0[i];
+            if (dum1) dum1[i] = a1[i];
+            if (df0) df0[i] = a0[i] + a1[i];
+            if (df1) df1[i] = -dt * a1[i];
+        }
+    free(vh); free(a0); free(a1);
     prob_free(&P);
     return rc;
 }
@@ -902,36 +962,8 @@ int orc_adjoint_m(const orc_geom *g, const orc_mesh *m, const double *sigma, con
                   double dt, const double *u0, const double *um1, const double *seed, double *dsig,
                   double *dflux, double *du0, double *dum1)
 {
-    const orc_ic ic = {u0, um1, NULL, 0};
-    return adjoint_ic(g, m, sigma, S, nt, dt, &ic, seed, dsig, dflux, du0, dum1);
-}
-
-/* Adjoint of the Model Problem 1 sweep of orc_forward_ic_m.  Besides dsig and
- * dflux (as orc_adjoint_m): du0, dum1 [nn] the cotangents of the levels u^0
- * and of the virtual level u^{-1} = f0 - tau f1 (with the FEM copies folded
- * back), and df0, df1 [nn] those of the data: df0 = du0 + dum1,
- * df1 = -tau dum1.  Each output is optional. */
-int orc_adjoint_ic_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                     double dt, const double *f0, const double *f1, const double *seed, double *dsig,
-                     double *dflux, double *du0, double *dum1, double *df0, double *df1)
-{
-    const orc_ic ic = {f0, NULL, f1, 1};
-    orc_prob P;
-    if (prob_init(&P, g, m, NULL)) return -1;
-    int64_t nn = P.nn;
-    prob_free(&P);
-    double *a0 = (double *)malloc(sizeof(double) * (size_t)nn), *a1 = (double *)malloc(sizeof(double) * (size_t)nn);
-    if (!a0 || !a1) { free(a0); free(a1); return -2; }
-    int rc = adjoint_ic(g, m, sigma, S, nt, dt, &ic, seed, dsig, dflux, a0, a1);
-    if (!rc)
-        for (int64_t i = 0; i < nn; ++i) {
-            if (du0) du0[i] = a0[i];
-            if (dum1) dum1[i] = a1[i];
-            if (df0) df0[i] = a0[i] + a1[i];
-            if (df1) df1[i] = -dt * a1[i];
-        }
-    free(a0); free(a1);
-    return rc;
+    return orc_adjoint_x(g, m, sigma, NULL, S, nt, dt, u0, um1, 0, seed, dsig, NULL, dflux, du0, dum1, NULL,
+                         NULL);
 }
 
 int orc_adjoint(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
@@ -948,7 +980,7 @@ double orc_misfit(const orc_geom *g, int nt, double dt, const double *obs, const
                   double *seed)
 {
     orc_prob P;
-    if (prob_init(&P, g, NULL, NULL)) return NAN;
+    if (prob_init(&P, g, NULL, NULL, NULL)) return NAN;
     double J = 0.0;
     if (seed) memset(seed, 0, sizeof(double) * (size_t)P.nface);
     for (int k = 1; k <= nt; ++k)
@@ -967,25 +999,36 @@ double orc_misfit(const orc_geom *g, int nt, double dt, const double *obs, const
  * an L2 density, the discrete form of eq. (gradient1):
  *   g_c = (1/|c|) dJ_misfit/da_c + gamma (sigma_c - sigma0_c)  (eligible c),
  *   g_c = 0 elsewhere, |c| the cell volume (h^3 for a cube, |K| for a
- *   tetrahedron).  Returns J (misfit + regularisation) in *J. */
-static int gradient_ic(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                       double dt, const orc_ic *ic, const double *data, double gamma, double *grad, double *J,
-                       double *obs_out)
+ *   tetrahedron).  Returns J (misfit + regularisation) in *J.  geps
+ *   (optional, lattice mode): the L2 density (1/h^3) dJ_misfit/d(1/c^2) per
+ *   free cube (the functional regularises a only), 0 elsewhere. */
+int orc_gradient_x(const orc_geom *g, const orc_mesh *m, const double *sigma, const double *eps,
+                   const orc_source *S, int nt, double dt, const double *u0, const double *u1, int taylor,
+                   const double *data, double gamma, double *grad, double *geps, double *J, double *obs_out)
 {
     orc_prob P;
-    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma) || !P.has_fem) return -1;
+    if (nt < 0 || !(dt > 0) || prob_init(&P, g, m, sigma, eps) || !P.has_fem) return -1;
+    const orc_ic ic = {u0, taylor ? NULL : u1, taylor ? u1 : NULL, taylor};
     double *obs = (double *)malloc(sizeof(double) * (size_t)P.nface * (size_t)(nt + 1));
     double *seed = (double *)malloc(sizeof(double) * (size_t)P.nface * (size_t)(nt + 1));
     double *vh = (double *)malloc(sizeof(double) * (size_t)P.fn * (size_t)(nt + 1));
-    if (!obs || !seed || !vh) return -2;
-    if (forward_sweep(&P, S, nt, dt, ic, obs, vh, NULL)) { free(obs); free(seed); free(vh); prob_free(&P); return -1; }
+    if (!obs || !seed || !vh) { free(obs); free(seed); free(vh); prob_free(&P); return -2; }
+    if (forward_sweep(&P, S, nt, dt, &ic, obs, vh, NULL)) {
+        free(obs); free(seed); free(vh); prob_free(&P);
+        return -1;
+    }
     double Jm = orc_misfit(g, nt, dt, obs, data, seed);
-    adjoint_sweep(&P, S, nt, dt, ic, seed, vh, grad, NULL, NULL, NULL);
+    adjoint_sweep(&P, S, nt, dt, &ic, seed, vh, grad, geps, NULL, NULL, NULL);
     double reg = 0.0;
     for (int64_t c = 0; c < P.ncube; ++c) {
-        if (!P.eligible[c]) { grad[c] = 0.0; continue; }
+        if (!P.eligible[c]) {
+            grad[c] = 0.0;
+            if (geps) geps[c] = 0.0;
+            continue;
+        }
         double s = sigma ? sigma[c] : 0.0;
         grad[c] = grad[c] / P.pvol[c] + gamma * s;
+        if (geps) geps[c] /= P.pvol[c];
         reg += 0.5 * gamma * P.pvol[c] * s * s;
     }
     if (J) *J = Jm + reg;
@@ -998,16 +1041,7 @@ static int gradient_ic(const orc_geom *g, const orc_mesh *m, const double *sigma
 int orc_gradient_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
                    double dt, const double *data, double gamma, double *grad, double *J, double *obs_out)
 {
-    return gradient_ic(g, m, sigma, S, nt, dt, &ORC_IC_ZERO, data, gamma, grad, J, obs_out);
-}
-
-/* orc_gradient_m for Model Problem 1 data (f0, f1) with the Taylor start. */
-int orc_gradient_ic_m(const orc_geom *g, const orc_mesh *m, const double *sigma, const orc_source *S, int nt,
-                      double dt, const double *f0, const double *f1, const double *data, double gamma,
-                      double *grad, double *J, double *obs_out)
-{
-    const orc_ic ic = {f0, NULL, f1, 1};
-    return gradient_ic(g, m, sigma, S, nt, dt, &ic, data, gamma, grad, J, obs_out);
+    return orc_gradient_x(g, m, sigma, NULL, S, nt, dt, NULL, NULL, 0, data, gamma, grad, NULL, J, obs_out);
 }
 
 int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, int nt, double dt,
@@ -1020,20 +1054,25 @@ int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, in
  * iteration m: g^m from orc_gradient; beta^m = |g^m|^2/|g^{m-1}|^2 (beta^0 = 0,
  * norms with the cell volumes); d^m = -g^m + beta^m d^{m-1};
  * alpha^m = alpha_rel / max|d^m|; sigma <- clip(sigma + alpha^m d^m, 0, 4)
- * on eligible cells (a in [1,5], eq. (admpar)).
+ * on eligible cells (a in [1,5], eq. (admpar)).  Every sweep uses the same
+ * eps and initial data (IP1 when taylor).
  * log[5*m + {0..4}] = J, |g|_{L2}, beta, alpha, max|d|. */
-static int cg_ic(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
-                 const orc_ic *ic, const double *data, double gamma, double alpha_rel, int iters, double *log)
+int orc_cg_x(const orc_geom *g, const orc_mesh *msh, double *sigma, const double *eps, const orc_source *S,
+             int nt, double dt, const double *u0, const double *u1, int taylor, const double *data, double gamma,
+             double alpha_rel, int iters, double *log)
 {
     orc_prob P;
-    if (prob_init(&P, g, msh, NULL) || !P.has_fem) return -1;
+    if (prob_init(&P, g, msh, NULL, NULL) || !P.has_fem) return -1;
     int64_t nc = P.ncube;
     double *gr = (double *)calloc((size_t)nc, sizeof(double));
     double *d = (double *)calloc((size_t)nc, sizeof(double));
     double gn2_prev = 0.0;
     for (int m = 0; m < iters; ++m) {
         double J = 0.0;
-        if (gradient_ic(g, msh, sigma, S, nt, dt, ic, data, gamma, gr, &J, NULL)) return -1;
+        if (orc_gradient_x(g, msh, sigma, eps, S, nt, dt, u0, u1, taylor, data, gamma, gr, NULL, &J, NULL)) {
+            free(gr); free(d); prob_free(&P);
+            return -1;
+        }
         double gn2 = 0.0;
         for (int64_t c = 0; c < nc; ++c) gn2 += P.pvol[c] * gr[c] * gr[c];
         double beta = m == 0 ? 0.0 : gn2 / gn2_prev;
@@ -1062,17 +1101,7 @@ static int cg_ic(const orc_geom *g, const orc_mesh *msh, double *sigma, const or
 int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
              const double *data, double gamma, double alpha_rel, int iters, double *log)
 {
-    return cg_ic(g, msh, sigma, S, nt, dt, &ORC_IC_ZERO, data, gamma, alpha_rel, iters, log);
-}
-
-/* orc_cg_m for Model Problem 1 (IP1): every iteration's forward sweep starts
- * from (f0, f1) with the Taylor start. */
-int orc_cg_ic_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
-                const double *f0, const double *f1, const double *data, double gamma, double alpha_rel,
-                int iters, double *log)
-{
-    const orc_ic ic = {f0, NULL, f1, 1};
-    return cg_ic(g, msh, sigma, S, nt, dt, &ic, data, gamma, alpha_rel, iters, log);
+    return orc_cg_x(g, msh, sigma, NULL, S, nt, dt, NULL, NULL, 0, data, gamma, alpha_rel, iters, log);
 }
 
 int orc_cg(const orc_geom *g, double *sigma, const orc_source *S, int nt, double dt,

@@ -52,8 +52,26 @@ def kuhn_cube_stiffness(h):
     return K
 
 
+def kuhn_cube_lumped_share():
+    """Row sums of the P1 mass of the 6 Kuhn tetrahedra of a unit cube,
+    lumped: share[l] = sum over the tetrahedra containing local node l of
+    |K| / 4 (brute force from the vertex coordinates; they sum to 1)."""
+    share = np.zeros(8)
+    for perm in itertools.permutations(range(3)):
+        p = np.zeros(3, int)
+        verts = [p.copy()]
+        for ax in perm:
+            p[ax] += 1
+            verts.append(p.copy())
+        X = np.array(verts, float)
+        vol = abs(np.linalg.det((X[1:] - X[0]).T)) / 6.0
+        for v in verts:
+            share[int(v[0] + 2 * v[1] + 4 * v[2])] += vol / 4.0
+    return share
+
+
 class Merged:
-    def __init__(self, n, h, bc, fem_o=None, fem_c=None, sigma=None):
+    def __init__(self, n, h, bc, fem_o=None, fem_c=None, sigma=None, eps=None):
         self.n = tuple(n)
         self.h = h
         self.bc = tuple(bc)
@@ -119,6 +137,18 @@ class Merged:
             W[tuple(sl)] *= 0.5
             sl[2 - d] = -1
             W[tuple(sl)] *= 0.5
+        if eps is not None:
+            # the coefficient 1/c^2 of the free cubes weights their lumped
+            # Kuhn mass shares (every other cube keeps 1/c^2 = 1)
+            o, C = fem_o, fem_c
+            e = np.asarray(eps, float).reshape(C[2], C[1], C[0])
+            share = kuhn_cube_lumped_share()
+            for kz in range(2, C[2] - 2):
+                for ky in range(2, C[1] - 2):
+                    for kx in range(2, C[0] - 2):
+                        for l in range(8):
+                            x, y, z = o[0] + kx + (l & 1), o[1] + ky + ((l >> 1) & 1), o[2] + kz + (l >> 2)
+                            W[z, y, x] += h ** 3 * (e[kz, ky, kx] - 1.0) * share[l]
         self.W = W
         # face trapezoid weights on z+
         fw = np.full((ny, nx), h * h)
