@@ -198,6 +198,36 @@ hyb_status hyb_set_initial(hyb_ctx *ctx, const double *u0_dev, const double *um1
  * grid), HYB_E_STATE (context in a batch slot), HYB_E_OOM, HYB_E_DEVICE. */
 hyb_status hyb_set_initial_taylor(hyb_ctx *ctx, const double *f0_dev, const double *f1_dev);
 
+/* Variable wave speed: the coefficient 1/c^2 of the time derivative in
+ * eq. (modelhyb), for every later sweep of the context until the next call
+ * (NULL: c = 1, the model problems of Sec. 5).  Structured FEM boxes only.
+ * eps_dev: device FP64 [C_z][C_y][C_x], 1/c^2 per FEM cube; used on the free
+ *   cubes (c = 1 near and outside the FEM box, condition (coefic)), ignored
+ *   elsewhere; copied into the context.  Values must be finite and > 0.
+ * It weights the element mass matrices (M^K_ij = (phi_i/c^2, phi_j)_K,
+ * Sec. 7.2), so after lumping the FEM row of node n divides by
+ * m_n = sum_{K containing n} (1/c^2)_K |K| / 4; the 6-tetrahedra split gives
+ * a cube's diagonal ends 1/4 of its volume and its other corners 1/12.  The
+ * CFL check of hyb_forward becomes dt <= h sqrt(eps_min / (3 a_max)).
+ * Synchronises the stream once (validation on the host); invalidates the
+ * previous sweeps.  Errors: HYB_E_ARG (no FEM box, values not finite or
+ * <= 0), HYB_E_UNSUPPORTED (general mesh), HYB_E_STATE (context in a batch
+ * slot), HYB_E_OOM, HYB_E_DEVICE. */
+hyb_status hyb_set_wave_speed(hyb_ctx *ctx, const double *eps_dev);
+
+/* Derivative of the last adjoint's functional with respect to 1/c^2 per
+ * cube, after hyb_adjoint (the exact derivative of the discrete scheme:
+ * each FEM row's lumped mass is differentiated, using the second difference
+ * of the node's forward levels k+1, k, k-1).
+ * geps_dev: device FP64 [C_z][C_y][C_x]; mode 0 adjoint: the L2 density
+ *   (1/h^3) dJ_misfit/d(1/c^2) (no regularisation term: the functional
+ *   regularises a only); mode 1: the Euclidean dL/d(1/c^2).  0 on cubes that
+ *   are not free.
+ * Errors: HYB_E_ARG, HYB_E_STATE (no wave speed set, or no adjoint),
+ * HYB_E_UNSUPPORTED (checkpoint store modes: the full FEM history is
+ * needed). */
+hyb_status hyb_gradient_eps(hyb_ctx *ctx, double *geps_dev);
+
 /* Adjoint solve: the exact transpose of the last forward sweep, run backward
  * in time (in the interior it is eq. (fdmschemeadjoint) and the second line
  * of eq. (fem); boundary, source and exchange rows are transposed exactly).

@@ -56,6 +56,12 @@ struct hyb_ctx {
     bool taylor = false;
     double *tf0 = nullptr, *tf1 = nullptr;
     bool sweep_taylor = false;   // the last forward sweep started with the Taylor step
+    // variable wave speed (hyb_set_wave_speed): 1/c^2 per cube, per-node
+    // 1/m (field precision), per-node dJ/dm (FP64), history box of u^{-1}
+    bool vm = false;
+    double eps_min = 1.0;
+    double *epsc = nullptr, *Gm = nullptr;
+    void *minv = nullptr, *hm1 = nullptr;
     // state of the last forward / adjoint
     bool have_forward = false, have_adjoint = false;
     int nt = 0, k_on = 0, adj_mode = 0;
@@ -499,6 +505,7 @@ Step<T> make_step(const hyb_ctx *c)
     s.acube = (const T *)c->acube;
     s.c2 = (T)((c->dt / c->h) * (c->dt / c->h));
     s.w2 = 1.0;
+    s.minv = c->vm ? (const T *)c->minv : nullptr;
     s.r = (T)((c->h - c->dt) / (c->h + c->dt));
     for (int q = 0; q < 12; ++q) s.w[q] = (T)c->mesh.w[q];
     s.dt = c->dt;
@@ -634,6 +641,12 @@ Step<T> adj_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, const double *r
     s.c2 = (T)(s.w2 * (c->dt / c->h) * (c->dt / c->h));
     s.res = (mode == 0 && k == 0) ? nullptr : res + (long long)k * nface;
     s.hist = hist_ptr<T>(c, k);
+    if (c->vm && c->store_mode == 0 && c->g.has_fem) {
+        // dJ/dm needs the history levels k+1, k, k-1 of the node (full history)
+        s.Gm = c->Gm;
+        s.hnext = k < c->nt ? hist_ptr<T>(c, k + 1) : nullptr;
+        s.hprev = k >= 1 ? hist_ptr<T>(c, k - 1) : (const T *)c->hm1;
+    }
     return s;
 }
 
@@ -687,6 +700,7 @@ hyb_status adj_setup(hyb_ctx *c, const double *res, int mode)
         }
     if (c->gen) HIPCHK(c, hipMemsetAsync(c->gd.E, 0, std::max<long long>(c->gd.nE, 1) * sizeof(double), st));
     else if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
+    if (c->vm && c->store_mode == 0) HIPCHK(c, hipMemsetAsync(c->Gm, 0, g.fem_n * sizeof(double), st));
     if (mode == 0) launch_misfit(g, res, c->nt, c->dt, c->h, c->partials, c->scal, S_JMIS, st);
     else HIPCHK(c, hipMemsetAsync(c->scal + S_JMIS, 0, sizeof(double), st));
     return HYB_OK;
@@ -743,6 +757,11 @@ hyb_status fwd_setup(hyb_ctx *c, double *obs)
         c->ic_u0 = c->ic_um1 = nullptr;
     }
     c->cur_seg = c->store_mode ? c->nt / c->ckK : 0;
+    if (c->vm && c->store_mode == 0) {
+        // history box of the level u^{-1}: the second difference of step 0
+        if (incr_form<T>()) launch_hist_diff<T>(g, (const T *)c->V[1], (const T *)c->VD[0], (T *)c->hm1, st);
+        else launch_hist_diff<T>(g, (const T *)c->V[0], nullptr, (T *)c->hm1, st);
+    }
     if (obs) launch_record_face<T>(g, (const T *)c->U[1], obs, st);
     if (T *h0 = hist_ptr<T>(c, 0)) {
         if (c->gen) return gen_hist_level<T>(c, c->V[1], h0);
@@ -958,6 +977,10 @@ void hyb_destroy(hyb_ctx *c)
     dfree((void *&)c->scal);
     dfree((void *&)c->tf0);
     dfree((void *&)c->tf1);
+    dfree((void *&)c->epsc);
+    dfree((void *&)c->Gm);
+    dfree(c->minv);
+    dfree(c->hm1);
     delete c;
 }
 
@@ -970,6 +993,69 @@ hyb_status hyb_set_initial(hyb_ctx *c, const double *u0, const double *um1)
     c->ic_um1 = um1;
     c->ic_set = u0 || um1;
     c->taylor = false;
+    return HYB_OK;
+}
+
+hyb_status hyb_set_wave_speed(hyb_ctx *c, const double *eps)
+{
+    if (!c) return HYB_E_ARG;
+    if (c->in_batch) return fail(c, HYB_E_STATE, "context is owned by a batch slot");
+    if (!c->g.has_fem) return fail(c, HYB_E_ARG, "a wave speed needs a FEM box");
+    if (c->gen) return fail(c, HYB_E_UNSUPPORTED, "variable wave speed on a general mesh");
+    const Geo &g = c->g;
+    const hipStream_t st = c->stream;
+    if (!eps) {
+        if (c->vm) c->have_forward = c->have_adjoint = c->u_valid = false;
+        c->vm = false;
+        return HYB_OK;
+    }
+    // validate on the host (a one-off call): finite and positive on the
+    // free cubes, and the smallest value for the CFL bound
+    const long long nc = cube_count(g);
+    std::vector<double> h(nc);
+    HIPCHK(c, hipMemcpyAsync(h.data(), eps, nc * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    double emin = 1.0;
+    for (int z = 2; z < g.C[2] - 2; ++z)
+        for (int y = 2; y < g.C[1] - 2; ++y)
+            for (int x = 2; x < g.C[0] - 2; ++x) {
+                const double e = h[x + (long long)g.C[0] * (y + (long long)g.C[1] * z)];
+                if (!std::isfinite(e) || !(e > 0.0)) return fail(c, HYB_E_ARG, "1/c^2 must be finite and > 0");
+                emin = std::min(emin, e);
+            }
+    if (!c->epsc) {
+        hyb_status r = dmalloc(c, (void **)&c->epsc, nc * sizeof(double));
+        if (!r) r = dmalloc(c, (void **)&c->Gm, g.fem_n * sizeof(double));
+        if (!r) r = dmalloc(c, &c->minv, g.fem_n * c->esz);
+        if (!r) r = dmalloc(c, &c->hm1, std::max<long long>(g.hlevel, 1) * c->esz);
+        if (r) {
+            dfree((void *&)c->epsc);
+            dfree((void *&)c->Gm);
+            dfree(c->minv);
+            dfree(c->hm1);
+            return r;
+        }
+    }
+    HIPCHK(c, hipMemcpyAsync(c->epsc, eps, nc * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (c->f32) launch_minv<float>(g, c->epsc, (float *)c->minv, st);
+    else launch_minv<double>(g, c->epsc, (double *)c->minv, st);
+    HIPCHK(c, hipGetLastError());
+    c->eps_min = emin;
+    c->vm = true;
+    c->have_forward = c->have_adjoint = c->u_valid = false;
+    return HYB_OK;
+}
+
+hyb_status hyb_gradient_eps(hyb_ctx *c, double *geps)
+{
+    if (!c || !geps) return HYB_E_ARG;
+    if (!c->vm) return fail(c, HYB_E_STATE, "no wave speed set (hyb_set_wave_speed)");
+    if (!c->have_adjoint) return fail(c, HYB_E_STATE, "hyb_gradient_eps needs a previous hyb_adjoint");
+    if (c->store_mode != 0)
+        return fail(c, HYB_E_UNSUPPORTED, "dJ/d(1/c^2) needs the full FEM history (store mode 0)");
+    const double h3 = c->h * c->h * c->h;
+    launch_eps_grad(c->g, c->Gm, c->adj_mode == 0 ? 1.0 / h3 : 1.0, geps, c->stream);
+    HIPCHK(c, hipGetLastError());
     return HYB_OK;
 }
 
@@ -1061,10 +1147,14 @@ hyb_status prepare_forward(hyb_ctx *c, const double *sigma, const hyb_source *sr
             return refuse(HYB_E_CFL, "dt violates the bound dt^2 max_n (|K_nn| + sum_m |K_nm|) / m_n <= 4 "
                                      "of the FEM mesh");
     } else {
-        // CFL condition, eq. (CFL): tau <= h / sqrt(3 a) with the largest a
+        // CFL condition, eq. (CFL): tau <= h / sqrt(3 a) with the largest a;
+        // with a variable wave speed tau <= h sqrt(eps_min / (3 a_max))
+        // (eps = 1/c^2; the lumped mass of a node is at least eps_min h^3)
         const double amax = 1.0 + std::max(0.0, smax);
-        if (dt > c->h / std::sqrt(3.0 * amax) * (1.0 + 1e-12))
-            return refuse(HYB_E_CFL, "dt violates the CFL bound h/sqrt(3 a_max)");
+        const double emin = c->vm ? std::min(1.0, c->eps_min) : 1.0;
+        if (dt > c->h * std::sqrt(emin / (3.0 * amax)) * (1.0 + 1e-12))
+            return refuse(HYB_E_CFL, c->vm ? "dt violates the CFL bound h sqrt(eps_min / (3 a_max))"
+                                           : "dt violates the CFL bound h/sqrt(3 a_max)");
     }
     // sqrt(nt) segmentation of the levels 0..nt (checkpoint modes)
     c->ckK = c->store_mode ? (int)std::ceil(std::sqrt((double)nt + 1.0)) : nt + 1;
@@ -1728,6 +1818,7 @@ hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *c, const double *sigma, doubl
     if (c->gen) return bfail(b, HYB_E_UNSUPPORTED, "batch: general FEM meshes are not batched");
     if (c->taylor || c->ic_set)
         return bfail(b, HYB_E_UNSUPPORTED, "batch: contexts start from zero initial data");
+    if (c->vm) return bfail(b, HYB_E_UNSUPPORTED, "batch: contexts have a constant wave speed");
     int q = -1;
     for (int i = 0; i < b->max_slots; ++i)
         if (b->slots[i].state == 0) { q = i; break; }

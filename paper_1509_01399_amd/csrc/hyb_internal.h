@@ -83,6 +83,10 @@ struct Step {
     const T *Fa, *Fb;        // boundary multipliers of levels k+2, k+1 (face arrays)
     T *Fc;                   // boundary multipliers of level k
     T *Pw;                   // level k+1 grid array: receives the boundary proxies
+    // variable wave speed (null: 1/c^2 = 1)
+    const T *minv;           // [(C+1)^3] h^3 / (lumped mass) per FEM node
+    double *Gm;              // adjoint: FP64 dJ/dm per FEM node (h^3 units), or null
+    const T *hnext, *hprev;  // adjoint: history levels k+1 (null at k = nt) and k-1
 };
 
 // FP32 wavefields advance in increment form (d^{k+1} = d^k + tau^2 L u^k,
@@ -147,6 +151,19 @@ void launch_cg_update(const Geo &g, const double *dir, double *sigma, double alp
                       hipStream_t st);
 void launch_residual(const double *obs, const double *data, double *res, long long n,
                      hipStream_t st);
+
+// Variable wave speed: minv[n] = 1 / m_n of each FEM node from 1/c^2 per
+// cube (1 outside the free cubes): m_n = (3 (e_a + e_b) + sum of the other 6
+// incident cubes) / 12, e_a, e_b the two cubes whose Kuhn diagonal ends at n.
+template <typename T>
+void launch_minv(const Geo &g, const double *eps, T *minv, hipStream_t st);
+// dJ/d(1/c^2) per cube from the per-node dJ/dm: the same shares (1/4 at the
+// diagonal ends, 1/12 elsewhere); mode 0 divides by h^3 (L2 density), 0 on
+// cubes that are not free.
+void launch_eps_grad(const Geo &g, const double *Gm, double scale, double *geps, hipStream_t st);
+// history box of a - b (b may be null) for the level u^{-1}
+template <typename T>
+void launch_hist_diff(const Geo &g, const T *a, const T *b, T *hist, hipStream_t st);
 
 // device scalar slots
 enum : int { S_SMAX = 0, S_BAD = 1, S_JMIS = 2, S_JREG = 3, S_GN2 = 4, S_GN2P = 5, S_BETA = 6,

@@ -426,7 +426,7 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec(Step<T> s)
     bnd_adj_ec_body<T>(s, blockIdx.x);
 }
 
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool VM>
 __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid);
 template <typename T>
 __device__ __forceinline__ void omega_o_fill(const Step<T> &s, long long t);
@@ -435,12 +435,12 @@ __device__ __forceinline__ void omega_o_fill(const Step<T> &s, long long t);
 // adjoint with the gradient integral (they need nothing of level k) and the
 // omega_o couplings of the FDM rows of level k, left in the level-k array
 // for the interior launch that follows to add.
-template <typename T>
+template <typename T, bool VM>
 __device__ __forceinline__ void bnd_adj_body(const Step<T> &s)
 {
     const Geo &g = s.g;
     if ((int)blockIdx.x < g.n_fem_blocks) {
-        fem_tile<T, true>(s, blockIdx.x);
+        fem_tile<T, true, VM>(s, blockIdx.x);
         return;
     }
     const long long t = (long long)(blockIdx.x - g.n_fem_blocks) * BLOCK + threadIdx.x;
@@ -481,10 +481,10 @@ __device__ __forceinline__ void bnd_adj_body(const Step<T> &s)
     s.Pw[id] = (w1 * fb + w0 * mu) / s.c2;  // what the interior stencil reads
 }
 
-template <typename T>
+template <typename T, bool VM>
 __global__ __launch_bounds__(BLOCK) void k_bnd_adj(Step<T> s)
 {
-    bnd_adj_body<T>(s);
+    bnd_adj_body<T, VM>(s);
 }
 
 // ---------------------------------------------------------------- interior
@@ -701,7 +701,12 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
     fdm_rows<T, ADJ, NT>(s, x, y, nr, z0, z1, hmask);
 }
 
-template <typename T, bool ADJ>
+// FEM rows of one tile (forward, or with ADJ the adjoint rows and the
+// gradient integral).  Variable wave speed: the forward row divides by its
+// own lumped mass (s.minv = 1/m per node, h^3 units; uniform when null); the
+// adjoint rows (VM) apply the transposed stencil to nu = minv * mu, pair nu
+// with u^k in the conductivity gradient, and accumulate dJ/dm per node.
+template <typename T, bool ADJ, bool VM>
 __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 {
     const Geo &g = s.g;
@@ -727,6 +732,13 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
     const long long fy = g.fpx, fz = g.fplane;
     long long id = fidx(g, i, j, k0);
     T vm = s.Vb[id - fz], v0 = s.Vb[id];
+    constexpr bool AV = ADJ && VM;
+    const T *__restrict__ Mi = s.minv;
+    T mm = 1, m0 = 1;  // minv of the planes k-1, k (AV)
+    if constexpr (AV) {
+        mm = Mi[id - fz];
+        m0 = Mi[id];
+    }
     // adjoint gradient: multipliers and history on the 4 corners (x,y)+{0,1}
     const bool gcol = ADJ && i >= 2 && i <= Cx - 3 && j >= 2 && j <= Cy - 3;
     const bool hcol = i >= 2 && i <= Cx - 2 && j >= 2 && j <= Cy - 2;
@@ -739,6 +751,16 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
         for (int q = 0; q < 4; ++q) ahi[q] = A[cb + (q & 1) + (q >> 1) * cpy + (long long)k * cpz];
         const T vp = s.Vb[id + fz];
         const T xm = s.Vb[id - 1], xp = s.Vb[id + 1], ym = s.Vb[id - fy], yp = s.Vb[id + fy];
+        // operand of the stencil: the level itself, or nu = minv * mu (AV)
+        T mp = 1, nxm = xm, nxp = xp, nym = ym, nyp = yp;
+        if constexpr (AV) {
+            mp = Mi[id + fz];
+            nxm = Mi[id - 1] * xm;
+            nxp = Mi[id + 1] * xp;
+            nym = Mi[id - fy] * ym;
+            nyp = Mi[id + fy] * yp;
+        }
+        const T n0 = AV ? m0 * v0 : v0, nzm = AV ? mm * vm : vm, nzp = AV ? mp * vp : vp;
         // a(dx,dy,dz): dz = 0 -> alo, 1 -> ahi
 #define AC(dx, dy, dz) ((dz) ? ahi[(dx) + 2 * (dy)] : alo[(dx) + 2 * (dy)])
         const T kxp = w[0] * AC(1, 1, 1) + w[1] * AC(1, 0, 1) + w[2] * AC(1, 1, 0) + w[3] * AC(1, 0, 0);
@@ -748,13 +770,17 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
         const T kzp = w[8] * AC(1, 1, 1) + w[9] * AC(0, 1, 1) + w[10] * AC(1, 0, 1) + w[11] * AC(0, 0, 1);
         const T kzm = w[8] * AC(1, 1, 0) + w[9] * AC(0, 1, 0) + w[10] * AC(1, 0, 0) + w[11] * AC(0, 0, 0);
 #undef AC
-        const T Ku = kxp * (v0 - xp) + kxm * (v0 - xm) + kyp * (v0 - yp) + kym * (v0 - ym) +
-                     kzp * (v0 - vp) + kzm * (v0 - vm);
+        const T Ku = kxp * (n0 - nxp) + kxm * (n0 - nxm) + kyp * (n0 - nyp) + kym * (n0 - nym) +
+                     kzp * (n0 - nzp) + kzm * (n0 - nzm);
         // leapfrog part: v = 2 v0 - v_prev - c2 Ku, or in increment form
-        // dv = dv_prev - c2 Ku (v = v0 + dv once the couplings are in dv)
+        // dv = dv_prev - c2 Ku (v = v0 + dv once the couplings are in dv);
+        // a forward row with variable mass scales c2 by its own minv
+        T cm = c2;
+        if constexpr (!ADJ)
+            if (Mi) cm = c2 * Mi[id];
         T dv = 0, v = 0;
-        if constexpr (incr_form<T>()) dv = s.VDa[id] - c2 * Ku;
-        else v = (T)2 * v0 - s.Va[id] - c2 * Ku;
+        if constexpr (incr_form<T>()) dv = s.VDa[id] - cm * Ku;
+        else v = (T)2 * v0 - s.Va[id] - cm * Ku;
         const bool hin = hcol && k >= 2 && k <= Cz - 2;
         if constexpr (ADJ) {
             // omega_diamond: the FDM rows around read the copied value
@@ -776,18 +802,24 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
                 const T *H = s.hist;
                 const long long hb = (i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz;
                 if (!qfull) {
-                    ql[0] = (double)v0;
-                    ql[1] = (double)xp;
-                    ql[2] = (double)yp;
-                    ql[3] = (double)s.Vb[id + 1 + fy];
+                    ql[0] = (double)n0;
+                    ql[1] = (double)nxp;
+                    ql[2] = (double)nyp;
+                    ql[3] = AV ? (double)(Mi[id + 1 + fy] * s.Vb[id + 1 + fy]) : (double)s.Vb[id + 1 + fy];
 #pragma unroll
                     for (int c = 0; c < 4; ++c) hl[c] = (double)H[hb + (c & 1) + (c >> 1) * hn0];
                 }
                 double qh[4], hh[4];
-                qh[0] = (double)vp;
-                qh[1] = (double)s.Vb[id + fz + 1];
-                qh[2] = (double)s.Vb[id + fz + fy];
-                qh[3] = (double)s.Vb[id + fz + fy + 1];
+                qh[0] = (double)nzp;
+                if constexpr (AV) {
+                    qh[1] = (double)(Mi[id + fz + 1] * s.Vb[id + fz + 1]);
+                    qh[2] = (double)(Mi[id + fz + fy] * s.Vb[id + fz + fy]);
+                    qh[3] = (double)(Mi[id + fz + fy + 1] * s.Vb[id + fz + fy + 1]);
+                } else {
+                    qh[1] = (double)s.Vb[id + fz + 1];
+                    qh[2] = (double)s.Vb[id + fz + fy];
+                    qh[3] = (double)s.Vb[id + fz + fy + 1];
+                }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) hh[c] = (double)H[hb + hpz + (c & 1) + (c >> 1) * hn0];
                 // corner c = dx + 2 dy + 4 dz
@@ -816,6 +848,16 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
             } else {
                 qfull = false;
             }
+            // wave speed: row n reads u^{k+1}_n = ... - c2 (K u^k)_n / m_n, so
+            // d u^{k+1}_n / d m_n = -(u^{k+1} - 2 u^k + u^{k-1})_n / m_n and
+            // dJ/dm_n gains mu_n^{k+1} times that (FP64); the history levels
+            // k+1, k, k-1 of the node give the second difference
+            if constexpr (AV)
+                if (hin && s.Gm && s.hnext) {
+                    const long long hb0 = (i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz;
+                    const double d2 = ((double)s.hnext[hb0] - 2.0 * (double)s.hist[hb0]) + (double)s.hprev[hb0];
+                    s.Gm[id] -= (double)v0 * d2 * (double)m0;
+                }
         }
         if constexpr (incr_form<T>()) {
             s.VDc[id] = dv;
@@ -827,6 +869,10 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
         s.Vc[id] = v;
         vm = v0;
         v0 = vp;
+        if constexpr (AV) {
+            mm = m0;
+            m0 = mp;
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) alo[q] = ahi[q];
     }
@@ -841,7 +887,7 @@ __global__ __launch_bounds__(BLOCK) void k_interior(Step<T> s)
     const int b = blockIdx.x;
     const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
     if (b < nf) fdm_tile<T, ADJ, NT>(s, b);
-    else if constexpr (!ADJ) fem_tile<T, false>(s, b - nf);
+    else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
 }
 
 // Non-temporal hints pay when the field arrays a step streams (three levels,
@@ -882,7 +928,8 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 {
     hipLaunchKernelGGL((k_bnd_adj_ec<T>), dim3((unsigned)ec_blocks(s.g)), dim3(BLOCK), 0, st, s);
     const long long nb = s.g.n_fem_blocks + (s.g.n_fi + s.g.nwo + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL((k_bnd_adj<T>), dim3((unsigned)nb), dim3(BLOCK), 0, st, s);
+    if (s.minv) hipLaunchKernelGGL((k_bnd_adj<T, true>), dim3((unsigned)nb), dim3(BLOCK), 0, st, s);
+    else hipLaunchKernelGGL((k_bnd_adj<T, false>), dim3((unsigned)nb), dim3(BLOCK), 0, st, s);
 }
 // ---------------------------------------------------------------- batches
 //
@@ -898,7 +945,7 @@ __global__ __launch_bounds__(BLOCK) void k_interior_b(const Step<T> *__restrict_
     const int b = blockIdx.x;
     const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
     if (b < nf) fdm_tile<T, ADJ, NT>(s, b);
-    else if constexpr (!ADJ) fem_tile<T, false>(s, b - nf);
+    else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
 }
 
 template <typename T>
@@ -916,7 +963,7 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_adj_ec_b(const Step<T> *__restric
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_bnd_adj_b(const Step<T> *__restrict__ steps)
 {
-    bnd_adj_body<T>(steps[blockIdx.y]);
+    bnd_adj_body<T, false>(steps[blockIdx.y]);
 }
 
 template <typename T>
@@ -1038,6 +1085,75 @@ template <typename T>
 void launch_load_level(const Geo &g, const double *src, T *U, T *V, hipStream_t st)
 {
     hipLaunchKernelGGL((k_load_level<T>), dim3(2048), dim3(BLOCK), 0, st, g, src, U, V);
+}
+
+// eps of FEM-local cube (a, b, c): 1/c^2 on free cubes, 1 elsewhere
+__device__ __forceinline__ double eps_at(const Geo &g, const double *eps, int a, int b, int c)
+{
+    if (a < 2 || b < 2 || c < 2 || a > g.C[0] - 3 || b > g.C[1] - 3 || c > g.C[2] - 3) return 1.0;
+    return eps[a + (long long)g.C[0] * (b + (long long)g.C[1] * c)];
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_minv(Geo g, const double *eps, T *minv)
+{
+    const long long n = g.fem_n;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const int i = (int)(t % g.fpx), j = (int)((t / g.fpx) % (g.fplane / g.fpx)), k = (int)(t / g.fplane);
+        // the node is corner (dx,dy,dz) of cube (i-dx, j-dy, k-dz); the Kuhn
+        // diagonal joins corners (0,0,0) and (1,1,1)
+        double ends = eps_at(g, eps, i, j, k) + eps_at(g, eps, i - 1, j - 1, k - 1);
+        double others = 0.0;
+#pragma unroll
+        for (int q = 1; q < 7; ++q)
+            others += eps_at(g, eps, i - (q & 1), j - ((q >> 1) & 1), k - (q >> 2));
+        minv[t] = (T)(12.0 / (3.0 * ends + others));
+    }
+}
+
+template <typename T>
+void launch_minv(const Geo &g, const double *eps, T *minv, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_minv<T>), dim3(1024), dim3(BLOCK), 0, st, g, eps, minv);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_eps_grad(Geo g, const double *Gm, double scale, double *geps)
+{
+    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK) {
+        const int a = (int)(c % g.C[0]), b = (int)((c / g.C[0]) % g.C[1]), z = (int)(c / ((long long)g.C[0] * g.C[1]));
+        double v = 0.0;
+        if (a >= 2 && b >= 2 && z >= 2 && a <= g.C[0] - 3 && b <= g.C[1] - 3 && z <= g.C[2] - 3) {
+            const long long n0 = fidx(g, a, b, z);
+            double ends = Gm[n0] + Gm[n0 + 1 + g.fpx + g.fplane], others = 0.0;
+#pragma unroll
+            for (int q = 1; q < 7; ++q) others += Gm[n0 + (q & 1) + ((q >> 1) & 1) * g.fpx + (q >> 2) * g.fplane];
+            v = scale * (3.0 * ends + others) / 12.0;
+        }
+        geps[c] = v;
+    }
+}
+
+void launch_eps_grad(const Geo &g, const double *Gm, double scale, double *geps, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_eps_grad, dim3(1024), dim3(BLOCK), 0, st, g, Gm, scale, geps);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_hist_diff(Geo g, const T *a, const T *b, T *hist)
+{
+    const long long n = g.hlevel;
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
+        const int p = (int)(t % g.hn[0]), q = (int)((t / g.hn[0]) % g.hn[1]), r = (int)(t / ((long long)g.hn[0] * g.hn[1]));
+        const long long f = fidx(g, 2 + p, 2 + q, 2 + r);
+        hist[t] = b ? a[f] - b[f] : a[f];
+    }
+}
+
+template <typename T>
+void launch_hist_diff(const Geo &g, const T *a, const T *b, T *hist, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_hist_diff<T>), dim3(1024), dim3(BLOCK), 0, st, g, a, b, hist);
 }
 
 template <typename T>
@@ -1329,6 +1445,8 @@ void launch_residual(const double *obs, const double *data, double *res, long lo
     template void launch_load_level<T>(const Geo &, const double *, T *, T *, hipStream_t);        \
     template void launch_load_combo<T>(const Geo &, const double *, const double *, double, T *, T *, \
                                        hipStream_t);                                              \
+    template void launch_minv<T>(const Geo &, const double *, T *, hipStream_t);                   \
+    template void launch_hist_diff<T>(const Geo &, const T *, const T *, T *, hipStream_t);         \
     template void launch_load_incr<T>(const Geo &, const double *, const double *, T *, T *, hipStream_t); \
     template void launch_hist_level<T>(const Geo &, const T *, T *, hipStream_t);                  \
     template void launch_record_face<T>(const Geo &, const T *, double *, hipStream_t);            \

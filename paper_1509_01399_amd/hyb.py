@@ -28,7 +28,7 @@ EXPORTS = ("hyb_create", "hyb_destroy", "hyb_forward", "hyb_set_initial", "hyb_a
            "hyb_counts", "hyb_time_interior", "hyb_get_wavefield", "hyb_batch_create",
            "hyb_batch_destroy", "hyb_batch_submit", "hyb_batch_tick", "hyb_batch_poll",
            "hyb_batch_release", "hyb_batch_last_error", "hyb_batch_poll_all", "hyb_fem_info",
-           "hyb_time_fem", "hyb_set_initial_taylor")
+           "hyb_time_fem", "hyb_set_initial_taylor", "hyb_set_wave_speed", "hyb_gradient_eps")
 
 
 class hyb_fd_grid(ct.Structure):
@@ -85,6 +85,8 @@ def load():
     lib.hyb_forward.argtypes = [vp, vp, P(hyb_source), ct.c_int32, dp, vp]
     lib.hyb_set_initial.argtypes = [vp, vp, vp]
     lib.hyb_set_initial_taylor.argtypes = [vp, vp, vp]
+    lib.hyb_set_wave_speed.argtypes = [vp, vp]
+    lib.hyb_gradient_eps.argtypes = [vp, vp]
     lib.hyb_adjoint.argtypes = [vp, vp, ct.c_int32]
     lib.hyb_gradient.argtypes = [vp, vp, P(dp)]
     lib.hyb_cg_step.argtypes = [vp, vp, vp, P(hyb_source), ct.c_int32, dp, P(hyb_cg_state), P(dp),
@@ -202,6 +204,14 @@ def hyb_set_initial(ctx, u0, um1):
 
 def hyb_set_initial_taylor(ctx, f0, f1):
     _check(load().hyb_set_initial_taylor(ctx, _ptr(f0), _ptr(f1)), ctx)
+
+
+def hyb_set_wave_speed(ctx, eps):
+    _check(load().hyb_set_wave_speed(ctx, _ptr(eps)), ctx)
+
+
+def hyb_gradient_eps(ctx, geps):
+    _check(load().hyb_gradient_eps(ctx, _ptr(geps)), ctx)
 
 
 def hyb_adjoint(ctx, residual, mode):
@@ -384,6 +394,18 @@ class Solver:
         """Model Problem 1 data u(x,0) = f0, u_t(x,0) = f1 for every later
         forward sweep (None, None: back to zero data)."""
         hyb_set_initial_taylor(self.ctx, f0, f1)
+
+    def set_wave_speed(self, eps=None):
+        """1/c^2 per FEM cube for every later sweep (None: c = 1)."""
+        hyb_set_wave_speed(self.ctx, eps)
+
+    def gradient_eps(self, out=None):
+        """dJ/d(1/c^2) per cube after an adjoint (L2 density in mode 0,
+        Euclidean in mode 1)."""
+        if out is None:
+            out = self.torch.zeros((self.C, self.C, self.C), dtype=self.torch.float64, device=self._dev())
+        hyb_gradient_eps(self.ctx, out)
+        return out
 
     def adjoint(self, residual, mode=0):
         hyb_adjoint(self.ctx, residual, mode)
