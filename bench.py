@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -266,6 +267,70 @@ def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
     return out
 
 
+def model_forms(wl_name, steps, warmup, seed=0):
+    """The two model extensions on the benchmark's grid, FP64 fields, one CG
+    iteration per step as in the main line:
+    - Model Problem 1 (IP1): data and every sweep start from the paper's
+      Test 1 initial condition exp(-|x|^2) at rest (Taylor start);
+    - variable wave speed: 1-4 regions with c ~ U(1, 2) in the free cubes
+      (synth.wave_speed), dt = 0.95 h sqrt(min(1/c^2) / 15) (the CFL bound
+      for a <= 5), plus the derivative with respect to 1/c^2 after each
+      iteration (hyb_gradient_eps)."""
+    import numpy as np
+    import torch
+
+    from paper_1509_01399_amd import hyb, synth
+    wl = synth.WORKLOADS[wl_name]
+    sig_true = synth.sigma_for(wl, seed)
+    st = torch.as_tensor(sig_true, dtype=torch.float64, device="cuda")
+    out = {}
+    for form in ("model_problem_1", "wave_speed"):
+        solver = hyb.Solver(wl.n, C=wl.C)
+        dt = synth.dt_rule(wl.h, sig_true.max())
+        if form == "model_problem_1":
+            f0 = torch.as_tensor(synth.gaussian_initial(wl.n), dtype=torch.float64, device="cuda")
+            solver.set_initial_taylor(f0, None)
+            del f0
+        else:
+            eps = synth.wave_speed(wl.C, seed + 5)
+            dt = 0.95 * wl.h * math.sqrt(float(eps.min()) / 15.0)
+            solver.set_wave_speed(torch.as_tensor(eps, dtype=torch.float64, device="cuda"))
+        obs = solver.forward(st, wl.nt, dt, omega=wl.omega)
+        data = torch.as_tensor(synth.add_noise(obs.cpu().numpy(), wl.noise, seed + 1), device="cuda")
+        del obs
+        sig = torch.zeros_like(st)
+        state = hyb.hyb_cg_state()
+        geps = torch.zeros_like(st) if form == "wave_speed" else None
+        for _ in range(warmup):
+            solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        te = 0.0
+        for _ in range(steps):
+            gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+            if geps is not None:
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                solver.gradient_eps(geps)
+                torch.cuda.synchronize()
+                te += time.perf_counter() - t1
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        nfdm, nfem = solver.counts()
+        res = {"value": round(2.0 * (nfdm + nfem) * wl.nt * steps / t / 1e9, 2), "unit": "Gpt-updates/s",
+               "ms_per_step": round(t / steps * 1e3, 3), "dt_over_h": round(dt / wl.h, 4), "dtype": "f64",
+               "last_J": J, "last_gnorm": gn}
+        if geps is not None:
+            res["eps_gradient_ms"] = round(te / steps * 1e3, 3)
+            res["min_inv_c2"] = round(float(eps.min()), 4)
+            res["eps_gradient_norm"] = float(geps.norm())
+        out[form] = res
+        solver.close()
+        del data, sig
+        torch.cuda.empty_cache()
+    return out
+
+
 def serving(n_req=256, seed=0, budget=200e9):
     """Serving workload: n_req forward+adjoint+gradient requests, grid sizes
     uniform over {64,96,128,192,256}^3, FP32 fields, Poisson arrivals at
@@ -465,6 +530,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-general", action="store_true", help="skip the general-mesh leg")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the Model Problem 1 and wave-speed legs")
     ap.add_argument("--probe", choices=["interior", "copy"])
     ap.add_argument("--probe-f32", action="store_true")
     ap.add_argument("--probe-reps", type=int, default=20)
@@ -528,6 +595,11 @@ def main():
         gen = general_mesh(args.workload, args.steps, args.warmup)
         print(f"[bench] general mesh: {gen}", file=sys.stderr, flush=True)
 
+    forms = None
+    if not args.no_forms:
+        forms = model_forms(args.workload, args.steps, args.warmup)
+        print(f"[bench] model forms: {forms}", file=sys.stderr, flush=True)
+
     srv = None
     if not args.no_serve:
         srv = serving(args.serve_requests)
@@ -547,7 +619,7 @@ def main():
                    "dt_over_h": round(dt / wl.h, 4), "omega": wl.omega, "noise": wl.noise,
                    "step": "one CG iteration (forward + adjoint + gradient + update)",
                    "parallelism": "single GPU"},
-        "roofline": rl, "cpu_baseline": cpu, "f32_form": f32, "general_mesh": gen,
+        "roofline": rl, "cpu_baseline": cpu, "f32_form": f32, "general_mesh": gen, "model_forms": forms,
         "p50_ms": srv["batched"]["p50_ms"] if srv else None,
         "p99_ms": srv["batched"]["p99_ms"] if srv else None,
         "serving": srv,

@@ -120,6 +120,33 @@ def bumps(C, h, seed, count=(1, 4), amp=(0.0, 2.0), width=(2.0, 6.0)):
     return s
 
 
+def wave_speed(C, seed, count=(1, 4), edge=(4, 12), speed=(1.0, 2.0)):
+    """1/c^2 per FEM cube: 1-4 cubic regions (edges 4-12 cells) with wave
+    speed c ~ U(1, 2) inside the free cubes, c = 1 elsewhere (the coefficient
+    range c in [1, d2] of condition (coefic) with d2 = 2); overlapping regions
+    keep the faster speed."""
+    rng = np.random.default_rng(seed)
+    c = np.ones((C, C, C))
+    lo, hi = 2, C - 2
+    k = int(rng.integers(count[0], count[1] + 1))
+    for _ in range(k):
+        e = min(int(rng.integers(edge[0], edge[1] + 1)), hi - lo)
+        v = float(rng.uniform(*speed))
+        p = [int(rng.integers(lo, hi - e + 1)) for _ in range(3)]
+        blk = c[p[2]:p[2] + e, p[1]:p[1] + e, p[0]:p[0] + e]
+        np.maximum(blk, v, out=blk)
+    return 1.0 / (c * c)
+
+
+def gaussian_initial(n, h=None):
+    """The initial condition of the paper's Test 1, read with x3^2:
+    u(x, 0) = exp(-(x1^2 + x2^2 + x3^2)) on the (n+1)^3 grid, at rest."""
+    h = 1.0 / n if h is None else h
+    x = np.arange(n + 1) * h
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return np.exp(-(X ** 2 + Y ** 2 + Z ** 2))
+
+
 def sigma_for(wl: Workload, seed=0):
     if wl.inclusions == "symmetric_pair":
         return symmetric_pair(wl.C, seed)
