@@ -535,7 +535,7 @@ def main():
     ap.add_argument("--probe", choices=["interior", "copy"])
     ap.add_argument("--probe-f32", action="store_true")
     ap.add_argument("--probe-reps", type=int, default=20)
-    ap.add_argument("--study", choices=["diff384", "scale512", "general"],
+    ap.add_argument("--study", choices=["diff384", "scale512", "general", "recon"],
                     help="full-size check of a form instead of the benchmark line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -556,6 +556,9 @@ def main():
     if args.study:
         if args.study == "general":
             res = general_mesh(args.workload, args.steps, args.warmup, f32=args.probe_f32)
+        elif args.study == "recon":
+            from paper_1509_01399_amd import study
+            res = study.tables()
         else:
             res = study_diff384() if args.study == "diff384" else study_scale512()
         print(json.dumps(res), flush=True)

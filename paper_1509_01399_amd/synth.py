@@ -147,6 +147,21 @@ def gaussian_initial(n, h=None):
     return np.exp(-(X ** 2 + Y ** 2 + Z ** 2))
 
 
+def face_gaussian(n, omega, width=0.25, h=None):
+    """Initial condition of the reconstruction study's Model Problem 1 test:
+    a Gaussian bump of the given width at the centre of the backscattered
+    face z = 1, scaled by 1/omega (the amplitude of the plane wave the source
+    sends), at rest.  The paper places exp(-|x|^2) at the backscattered side
+    of a domain whose size it does not give, and notes that it changes the
+    data little; at unit amplitude and width on the unit cube it would
+    dominate the trace and its noise."""
+    h = 1.0 / n if h is None else h
+    x = np.arange(n + 1) * h
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    r2 = (X - 0.5) ** 2 + (Y - 0.5) ** 2 + (Z - 1.0) ** 2
+    return np.exp(-r2 / (width * width)) / omega
+
+
 def sigma_for(wl: Workload, seed=0):
     if wl.inclusions == "symmetric_pair":
         return symmetric_pair(wl.C, seed)
