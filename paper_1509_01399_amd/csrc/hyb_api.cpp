@@ -382,11 +382,13 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
         const int zf = 4;  // as for the FDM tiles: measured best
         g.zc_fem = zf;
         g.fem_tiles[2] = (int)ceil_div(g.C[2] - 1, zf);
-        g.n_fem_blocks = (int)(fxy * g.fem_tiles[2]);
+        g.n_fem_tiles = (int)(fxy * g.fem_tiles[2]);
+        // a multiple of 8 for the XCD remap (the extra blocks exit at once)
+        g.n_fem_blocks = (g.n_fem_tiles + 7) / 8 * 8;
     } else {
         g.fem_tiles[0] = g.fem_tiles[1] = g.fem_tiles[2] = 0;
         g.zc_fem = 1;
-        g.n_fem_blocks = 0;
+        g.n_fem_blocks = g.n_fem_tiles = 0;
     }
     g.bnd_blocks = (int)ceil_div(g.nbnd + g.nwd + g.nwo, BLOCK);  // informational
     g.fem_n = has_fem ? (long long)(g.C[0] + 1) * (g.C[1] + 1) * (g.C[2] + 1) : 0;
@@ -398,7 +400,7 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
 void setup_geo_gen(Geo &g, const GenHost &gh)
 {
     g.gen = 1;
-    g.n_fem_blocks = 0;
+    g.n_fem_blocks = g.n_fem_tiles = 0;
     g.fem_tiles[0] = g.fem_tiles[1] = g.fem_tiles[2] = 0;
     g.nwd = g.nwo = 0;
     g.hn[0] = g.hn[1] = g.hn[2] = 0;

@@ -35,7 +35,8 @@ struct Geo {
     long long nwd, nwo;       // |omega_diamond|, |omega_o|
     int fdm_tiles[3], fem_tiles[3];
     int zc_fdm, zc_fem;       // z chunk per block
-    int n_fdm_blocks, n_fem_blocks;
+    int n_fdm_blocks, n_fem_blocks;  // blocks launched (FEM: n_fem_tiles rounded up to 8)
+    int n_fem_tiles;
     int bnd_blocks;           // blocks of the boundary kernels
     long long fem_n;          // FEM nodes ((C+1)^3, or the nodes of a general mesh)
     int gen;                  // general tetrahedral mesh: the FEM rows run in the

@@ -711,6 +711,9 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 {
     const Geo &g = s.g;
     const int Cx = g.C[0], Cy = g.C[1], Cz = g.C[2];
+    // contiguous tile ranges per XCD, as for the FDM tiles
+    bid = xcd_remap(bid, g.n_fem_blocks);
+    if (bid >= g.n_fem_tiles) return;
     const int bx = bid % g.fem_tiles[0];
     const int t = bid / g.fem_tiles[0];
     const int by = t % g.fem_tiles[1];
