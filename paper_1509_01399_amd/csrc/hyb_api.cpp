@@ -485,6 +485,8 @@ hyb_status upload_gen(hyb_ctx *c, const GenHost &gh)
     if (!s) s = upload(c, d.wog, wog);
     if (!s) s = dmalloc(c, &d.kap, (size_t)std::max<long long>(gh.nnz, 1) * c->esz);
     if (!s) s = dmalloc(c, &d.cn, (size_t)gh.fn * c->esz);
+    if (!s) s = dmalloc(c, &d.nu[0], (size_t)gh.fn * c->esz);
+    if (!s) s = dmalloc(c, &d.nu[1], (size_t)gh.fn * c->esz);
     if (!s) s = dmalloc(c, (void **)&d.E, (size_t)std::max<long long>(gh.nE, 1) * sizeof(double));
     return s;
 }
@@ -495,7 +497,7 @@ void free_gen(GenDev &d)
     dfree((void *&)d.cptr); dfree((void *&)d.ctet); dfree((void *&)d.cw); dfree((void *&)d.minv);
     dfree((void *&)d.ke6); dfree((void *&)d.pvol); dfree((void *&)d.E); dfree((void *&)d.tetE);
     dfree((void *&)d.orig_of_dev); dfree((void *&)d.grid_lin); dfree((void *&)d.wdg);
-    dfree((void *&)d.wog); dfree(d.kap); dfree(d.cn);
+    dfree((void *&)d.wog); dfree(d.kap); dfree(d.cn); dfree(d.nu[0]); dfree(d.nu[1]);
 }
 
 template <typename T>
@@ -675,6 +677,19 @@ GenStep<T> gen_args(const hyb_ctx *c, const Step<T> &s)
     return q;
 }
 
+// The adjoint general FEM step computing level k: nu^{k+1} from the launch
+// of level k+1 (parity buffers), nu^k for the launch of level k-1 with the
+// weight of step k-1.
+template <typename T>
+GenStep<T> gen_adj_args(const hyb_ctx *c, const Step<T> &s, int k)
+{
+    GenStep<T> q = gen_args<T>(c, s);
+    q.nu_in = (const T *)c->gd.nu[(k + 1) & 1];
+    q.nu_out = (T *)c->gd.nu[k & 1];
+    q.cs_prev = (T)((c->sweep_taylor && k - 1 == 0) ? 0.5 : 1.0);
+    return q;
+}
+
 // History level L of the FEM nodes [0, nH) from a FEM level (general mesh).
 template <typename T>
 hyb_status gen_hist_level(hyb_ctx *c, const void *V, T *h)
@@ -700,7 +715,11 @@ hyb_status adj_setup(hyb_ctx *c, const double *res, int mode)
             HIPCHK(c, hipMemsetAsync(c->E[q], 0, fb, st));
             if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->QE[q], 0, vb, st));
         }
-    if (c->gen) HIPCHK(c, hipMemsetAsync(c->gd.E, 0, std::max<long long>(c->gd.nE, 1) * sizeof(double), st));
+    if (c->gen) {
+        HIPCHK(c, hipMemsetAsync(c->gd.E, 0, std::max<long long>(c->gd.nE, 1) * sizeof(double), st));
+        // nu^{nt+1} = 0 (no rows at level nt+1); omega_o entries stay 0
+        for (int q = 0; q < 2; ++q) HIPCHK(c, hipMemsetAsync(c->gd.nu[q], 0, (size_t)c->gd.fn * sizeof(T), st));
+    }
     else if (g.has_fem) HIPCHK(c, hipMemsetAsync(c->G, 0, cube_count(g) * sizeof(double), st));
     if (c->vm && c->store_mode == 0) HIPCHK(c, hipMemsetAsync(c->Gm, 0, g.fem_n * sizeof(double), st));
     if (mode == 0) launch_misfit(g, res, c->nt, c->dt, c->h, c->partials, c->scal, S_JMIS, st);
@@ -852,7 +871,7 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
         }
         const Step<T> s = adj_step_args<T>(c, k, ia, ib, ic, res, mode);
         launch_bnd_adj<T>(s, st);
-        if (c->gen) launch_gen_adj<T>(gen_args<T>(c, s), st);
+        if (c->gen) launch_gen_adj<T>(gen_adj_args<T>(c, s, k), st);
         launch_interior<T>(s, true, st);
         const int t = ia; ia = ib; ib = ic; ic = t;
     }
@@ -1440,7 +1459,7 @@ hyb_status hyb_time_fem(hyb_ctx *c, int32_t which, int32_t reps, double *ms)
             if (incr_form<T>()) { s.VDa = (const T *)I[r & 1]; s.VDc = (T *)I[(r + 1) & 1]; }
             s.hist = (T *)c->hist;
             if (which == 0) launch_gen_fwd<T>(gen_args<T>(c, s), st);
-            else launch_gen_adj<T>(gen_args<T>(c, s), st);
+            else launch_gen_adj<T>(gen_adj_args<T>(c, s, r), st);
             const int t = ia; ia = ib; ib = ic; ic = t;
         }
         HIPCHK(c, hipEventRecord(e1, st));

@@ -70,6 +70,7 @@ struct GenDev {
     int32_t *tetE, *orig_of_dev;
     int64_t *grid_lin, *wdg, *wog;  // wdg/wog: padded grid index of omega_diamond / omega_o nodes
     void *kap, *cn;                 // [nnz], [fn] in field precision
+    void *nu[2];                    // [fn] adjoint: nu = cs dt^2/m mu of the levels, by parity
 };
 
 // Arguments of one general FEM step.  Forward: V levels k-1, k, k+1 (or the
@@ -97,6 +98,12 @@ struct GenStep {
     T c2;  // (dt/h)^2 of the grid rows that read omega_diamond (times the step weight)
     T cs;  // weight of dt^2 in this step (1; 1/2 in the first step of the Taylor
            // start): multiplies cn in the rows and in the gradient pairs
+    // adjoint: nu^{k+1} = cs cn mu^{k+1} of every node (written by the launch
+    // that computed level k+1; 0 on omega_o), and the array that receives
+    // nu^k = cs_prev cn mu^k for the next launch (cs_prev: weight of step k-1)
+    const T *nu_in;
+    T *nu_out;
+    T cs_prev;
 };
 
 template <typename T> void launch_gen_fwd(const GenStep<T> &s, hipStream_t st);

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
     const int sl = (int)(n >> 6), ln = (int)(n & 63);
     const int b = s.soff[sl], w = (s.soff[sl + 1] - b) >> 6;
     const T *__restrict__ Vb = s.Vb;
-    const T *__restrict__ cn = s.cn;
+    const T *__restrict__ nu = s.nu_in;
     const T *__restrict__ kap = s.kap;
     const int32_t *__restrict__ col = s.col;
     if (n >= s.nR) {
@@ -88,15 +88,13 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
 #pragma unroll 2
         for (int j = 0; j < w; ++j) {
             const int p = b + 64 * j + ln;
-            const int m = col[p];
-            acc += kap[p] * ((s.cs * cn[m]) * Vb[m]);
+            acc += kap[p] * nu[col[p]];
         }
         s.Uc[s.wog[n - s.nR]] = acc;
         return;
     }
     const T mu1 = Vb[n];
-    const T cs = s.cs;
-    const T nu0 = (cs * cn[n]) * mu1;
+    const T nu0 = nu[n];
     const bool hrow = n < s.nH;
     const T *__restrict__ H = s.hist;
     int eb = 0;
@@ -110,7 +108,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
     for (int j = 0; j < w; ++j) {
         const int p = b + 64 * j + ln;
         const int m = col[p];
-        const T num = (cs * cn[m]) * Vb[m];
+        const T num = nu[m];
         acc += kap[p] * (nu0 - num);
         if (hrow && m > n && m < s.nH) {
             double *e = s.E + eb + 64 * j + ln;
@@ -124,13 +122,16 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
         cw = s.c2 * (((Ub[gg - 1] + Ub[gg + 1]) + (Ub[gg - s.px] + Ub[gg + s.px])) +
                      (Ub[gg - s.plane] + Ub[gg + s.plane]));
     }
+    T mu0;
     if constexpr (incr_form<T>()) {
         const T d = s.VDa[n] - acc + cw;
         s.VDc[n] = d;
-        s.Vc[n] = mu1 + d;
+        mu0 = mu1 + d;
     } else {
-        s.Vc[n] = (T)2 * mu1 - s.Va[n] - acc + cw;
+        mu0 = (T)2 * mu1 - s.Va[n] - acc + cw;
     }
+    s.Vc[n] = mu0;
+    s.nu_out[n] = (s.cs_prev * s.cn[n]) * mu0;
 }
 
 __device__ double block_reduce_g(double v, bool is_max)
