@@ -233,10 +233,8 @@ __device__ __forceinline__ void bnd_fwd_body(const Step<T> &s, long long t)
         const int d = f >> 1, dir = (f & 1) ? -1 : 1;
         const long long sd = d == 0 ? 1 : (d == 1 ? g.px : g.plane);     // inward axis stride
         const long long sa = d == 0 ? g.px : 1, sb = d == 2 ? g.px : g.plane;  // tangential strides
-        const int kind = ftype(s.types1, f);
-        // absorbing x faces: done by the interior launch (fdm_rows)
-        if (d == 0 && kind == F_ABC) return;
         const long long id = gidx(g, x, y, z), in = id + dir * sd;
+        const int kind = ftype(s.types1, f);
         const T u = s.Ub[id];
         T v;
         if (kind == F_ABC) {
@@ -607,16 +605,6 @@ __device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, int nr,
     // it for o <= z <= o+C, a column inside the box at z = o and z = o+C.
     const int i = x - g.o[0], j0 = y - g.o[1], C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
     const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
-    // forward: the absorbing rows (eq. (eq:abs2)) of the face-interior nodes
-    // of the x faces are done here by the lanes next to them.  Every value
-    // such a row reads is in this lane's registers (u_b^k is its x
-    // neighbour, u_b'^k and u_b'^{k+1} its own levels), and on the low face
-    // the store falls into the cache line the wave writes anyway; from the
-    // boundary launch each of these nodes would cost separate cache lines.
-    // (Taking the y and z faces here as well measured slower: their rows in
-    // the boundary launch are coalesced already.)
-    const bool xlo = !ADJ && x == 1 && ftype(s.types1, 0) == F_ABC;
-    const bool xhi = !ADJ && x == g.nx - 2 && ftype(s.types1, 1) == F_ABC;
     bool side[R], top[R];
     T cm[R], c0[R];
 #pragma unroll
@@ -658,25 +646,12 @@ __device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, int nr,
             const T ym = r == 0 ? ylo : c0[r > 0 ? r - 1 : 0];
             const T yp = r + 1 < nr ? c0[r + 1 < R ? r + 1 : r] : yhi;
             const T L = ((xm[r] + xp[r]) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
-            T vn;
             if constexpr (INC) {
                 const T d = ua[r] + c2 * L + w[r];
                 st_once<T, NT>(Dc + ir, d);
-                vn = c0[r] + d;
+                st_once<T, NT>(Uc + ir, c0[r] + d);
             } else {
-                vn = (T)2 * c0[r] - ua[r] + c2 * L + w[r];
-            }
-            st_once<T, NT>(Uc + ir, vn);
-            if constexpr (!ADJ) {
-                // u_b^{k+1} = u_b'^k + r (u_b^k - u_b'^{k+1}) at face node b
-                // = this row's node + off, whose level-k value is ub
-                auto mur = [&](long long off, T ub) {
-                    const T vb = c0[r] + s.r * (ub - vn);
-                    st_once<T, NT>(Uc + ir + off, vb);
-                    if constexpr (INC) st_once<T, NT>(Dc + ir + off, vb - ub);
-                };
-                if (xlo) mur(-1, xm[r]);
-                if (xhi) mur(1, xp[r]);
+                st_once<T, NT>(Uc + ir, (T)2 * c0[r] - ua[r] + c2 * L + w[r]);
             }
         }
 #pragma unroll
