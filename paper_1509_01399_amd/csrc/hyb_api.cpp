@@ -371,7 +371,9 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     // z chunk of 4 planes: measured on 257^3 grids (FP64 and FP32, forward
     // and adjoint), chunks of 4 beat 8, 16 and 32; the extra halo planes are
     // served from the caches while the finer work units balance better.
-    const int zc = 4;
+    // FP32 fields on large grids: 6 planes measured faster (forward 84.9 ->
+    // 83.9 us, adjoint 97.4 -> 95.4 us per step at 257^3; FP64 unchanged).
+    const int zc = (esz == 4 && g.nz > 200) ? 6 : 4;
     g.zc_fdm = zc;
     g.fdm_tiles[2] = (int)ceil_div(g.nz - 2, zc);
     g.n_fdm_blocks = (int)(txy * g.fdm_tiles[2]);
