@@ -99,10 +99,16 @@ def cpu_baseline(wl, dt, window):
         ts.append(time.perf_counter() - t0)
     upd = 2 * (sz["fdm_updated"] + sz["fem_updated"]) * (window - 2)
     t = ts[1] - ts[0]
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": round(upd / t / 1e9, 5), "unit": "Gpt-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{wl.name} full grid ({wl.n}^3 cells, FEM {wl.C}^3): one oracle forward+adjoint "
                       f"of 2 and of {window} steps ({ts[0]:.1f} s, {ts[1]:.1f} s); marginal rate over "
-                      f"the {window - 2} extra step pairs, single thread"}
+                      f"the {window - 2} extra step pairs, single thread of {os.cpu_count()} ({model})"}
 
 
 def kernel_source_hash():
@@ -525,7 +531,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cg256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-window", type=int, default=10)
+    ap.add_argument("--cpu-window", type=int, default=30)
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)

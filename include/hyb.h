@@ -266,7 +266,10 @@ hyb_status hyb_cg_step(hyb_ctx *ctx, const double *data_dev, double *sigma_dev,
                        double *gnorm_host, double *J_host);
 
 /* Device bytes a context with these arguments needs for nt steps (fields,
- * history or checkpoints, accumulators), without allocating anything.
+ * history or checkpoints, accumulators), without allocating anything.  Not
+ * included: the buffers hyb_set_initial_taylor adds (two FP64 grid levels)
+ * and those of hyb_set_wave_speed (per cube 8 bytes, per FEM node 8 bytes
+ * plus one field element, one history level).
  * Errors: HYB_E_ARG, HYB_E_MESH, HYB_E_UNSUPPORTED. */
 hyb_status hyb_footprint(const hyb_fd_grid *grid, const hyb_fem_mesh *fem,
                          const hyb_overlap *overlap, const hyb_opts *opts, int32_t nt,
