@@ -578,90 +578,6 @@ __device__ __forceinline__ void omega_o_fill(const Step<T> &s, long long t)
     s.Uc[gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k)] = omega_o_adj(s, i, j, k);
 }
 
-// Seven-point leapfrog, eq. (fdmschemeforward), on RY_FDM neighbouring
-// columns (x, y) ... (x, y + nr - 1) for z in [z0, z1), skipping rows inside
-// the closed hole [o+2, o+C-2]^3 (bit r of hmask: column r lies in the
-// hole's x-y range).  The rows share their y-neighbour loads (the centre of
-// one row is the y neighbour of the next) and a register queue along z.
-// The same stencil is the adjoint update of the FDM rows; there (ADJ) the
-// rows on omega_o add the coupling the boundary launch left in their
-// level-k entry.
-template <typename T, bool ADJ, bool NT>
-__device__ __forceinline__ void fdm_rows(const Step<T> &s, int x, int y, int nr, int z0, int z1, unsigned hmask)
-{
-    constexpr int R = RY_FDM;
-    const Geo &g = s.g;
-    constexpr bool INC = incr_form<T>();
-    const long long py = g.px, pz = g.plane;
-    long long id = gidx(g, x, y, z0);
-    const T c2 = s.c2;
-    // distinct arrays: the loads of all rows can be issued before any row is
-    // stored
-    const T *__restrict__ Ub = s.Ub;
-    const T *__restrict__ Ua = INC ? s.Da : s.Ua;  // u^{k-1}, or d^k in the increment form
-    T *__restrict__ Uc = s.Uc;
-    T *__restrict__ Dc = s.Dc;
-    // adjoint: rows on omega_o.  A column on an x or y face of the box meets
-    // it for o <= z <= o+C, a column inside the box at z = o and z = o+C.
-    const int i = x - g.o[0], j0 = y - g.o[1], C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
-    const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
-    bool side[R], top[R];
-    T cm[R], c0[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int j = j0 + r;
-        side[r] = ib && j >= 0 && j <= C1 && !(ii && j > 0 && j < C1);
-        top[r] = ib && ii && j > 0 && j < C1;
-        cm[r] = r < nr ? Ub[id + r * py - pz] : (T)0;
-        c0[r] = r < nr ? Ub[id + r * py] : (T)0;
-    }
-    for (int z = z0; z < z1; ++z, id += pz) {
-        const bool inh = z >= g.hlo[2] && z <= g.hhi[2];
-        const int kz = z - g.o[2];
-        const bool zs = kz >= 0 && kz <= C2, zt = kz == 0 || kz == C2;
-        // all loads of the plane first
-        T cp[R], xm[R], xp[R], ua[R], w[R];
-        bool dor[R];
-        bool last = false;  // the last present row is computed
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const long long ir = id + r * py;
-            dor[r] = r < nr && !(((hmask >> r) & 1u) && inh);
-            cp[r] = r < nr ? Ub[ir + pz] : (T)0;
-            xm[r] = xp[r] = ua[r] = w[r] = 0;
-            if (dor[r]) {
-                xm[r] = Ub[ir - 1];
-                xp[r] = Ub[ir + 1];
-                ua[r] = ld_once<T, NT>(Ua + ir);
-                if (ADJ && ((side[r] && zs) || (top[r] && zt))) w[r] = Uc[ir];
-            }
-            if (r == nr - 1) last = dor[r];
-        }
-        const T ylo = dor[0] ? Ub[id - py] : (T)0;
-        const T yhi = last ? Ub[id + nr * py] : (T)0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (!dor[r]) continue;
-            const long long ir = id + r * py;
-            const T ym = r == 0 ? ylo : c0[r > 0 ? r - 1 : 0];
-            const T yp = r + 1 < nr ? c0[r + 1 < R ? r + 1 : r] : yhi;
-            const T L = ((xm[r] + xp[r]) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
-            if constexpr (INC) {
-                const T d = ua[r] + c2 * L + w[r];
-                st_once<T, NT>(Dc + ir, d);
-                st_once<T, NT>(Uc + ir, c0[r] + d);
-            } else {
-                st_once<T, NT>(Uc + ir, (T)2 * c0[r] - ua[r] + c2 * L + w[r]);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            cm[r] = c0[r];
-            c0[r] = cp[r];
-        }
-    }
-}
-
 // Workgroups are dealt round-robin to the 8 XCDs, each with its own L2.
 // Remap so that every XCD gets a contiguous range of tiles: neighbouring
 // tiles (which read each other's rows as halo) then share an L2.
@@ -671,34 +587,145 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk)
     return (b % 8) * per + b / 8;
 }
 
-// FDM tile: 64 x-lanes starting at a multiple of 64 (rows of the padded
-// field start on a 128-byte line, so a wave's row access covers whole cache
-// lines; the lane on the x = 0 boundary idles) by 4 thread rows of 2 grid
-// rows each, streaming z over the block's chunk.
+// FDM tile: the seven-point leapfrog, eq. (fdmschemeforward), on 64 x-lanes
+// starting at a multiple of 64 (rows of the padded field start on a
+// 128-byte line, so a wave's row access covers whole cache lines; the lane
+// on the x = 0 boundary only loads) by 4 thread rows of 2 grid rows each,
+// streaming z over the block's chunk.  Each plane of the tile and its
+// one-node halo (66 x 10 values) is loaded once from memory into one of two
+// LDS buffers; the x and y neighbours are read from LDS and the z neighbours
+// kept in registers, so a node costs one load of its next-plane value (plus
+// its share of the halo and its old level).  Reading the x and y neighbours
+// with vector loads instead (five loads per node, served by L1) measured
+// 11% slower: the stencil was bound by the rate of vector memory
+// instructions, not by HBM.  One barrier per plane: with two buffers a
+// plane's buffer is rewritten only after every thread has passed the
+// barrier that follows its last read.  Every thread of the block reaches
+// every barrier; threads without a row to update still load their part.
+// Rows inside the closed hole [o+2, o+C-2]^3 are skipped; in the adjoint
+// (ADJ) the rows on omega_o add the coupling the boundary launch left in
+// their level-k entry.
 template <typename T, bool ADJ, bool NT>
 __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
 {
+    constexpr int R = RY_FDM, TX = TX_FDM, TY = TY_FDM, LX = TX + 2, LY = TY + 2;
+    constexpr bool INC = incr_form<T>();
+    __shared__ T buf[2][LY][LX];
     const Geo &g = s.g;
     bid = xcd_remap(bid, g.n_fdm_blocks);
     if (bid >= g.n_fdm_blocks) return;
     const int bx = bid % g.fdm_tiles[0];
-    const int t = bid / g.fdm_tiles[0];
-    const int by = t % g.fdm_tiles[1];
-    const int bz = t / g.fdm_tiles[1];
-    const int x = bx * TX_FDM + (int)(threadIdx.x % TX_FDM);
-    const int y = 1 + by * TY_FDM + RY_FDM * (int)(threadIdx.x / TX_FDM);
-    if (x < 1 || x > g.nx - 2 || y > g.ny - 2) return;
-    const int nr = min(RY_FDM, g.ny - 1 - y);  // rows y .. y + nr - 1 <= ny - 2
+    const int tt = bid / g.fdm_tiles[0];
+    const int by = tt % g.fdm_tiles[1];
+    const int bz = tt / g.fdm_tiles[1];
+    const int x0 = bx * TX, y0 = 1 + by * TY;
     const int z0 = 1 + bz * g.zc_fdm;
     const int z1 = min(z0 + g.zc_fdm, g.nz - 1);
+    // the whole tile inside the closed hole: nothing to do (uniform exit)
+    {
+        const int xa = max(x0, 1), xb = min(x0 + TX - 1, g.nx - 2), yb = min(y0 + TY - 1, g.ny - 2);
+        if (g.has_fem && xa >= g.hlo[0] && xb <= g.hhi[0] && y0 >= g.hlo[1] && yb <= g.hhi[1] &&
+            z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2])
+            return;
+    }
+    const int lx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
+    const int x = x0 + lx, y = y0 + R * ty;
+    const long long py = g.px, pz = g.plane;
+    const T c2 = s.c2;
+    const T *__restrict__ Ub = s.Ub;
+    const T *__restrict__ Ua = INC ? s.Da : s.Ua;
+    T *__restrict__ Uc = s.Uc;
+    T *__restrict__ Dc = s.Dc;
+    const bool xval = x <= g.nx - 1;                 // a grid node (loads)
+    const bool xcmp = x >= 1 && x <= g.nx - 2;       // an interior column (updates)
+    // halo columns: wave 1, lanes 0..LY-1 the left one, LY..2LY-1 the right one
+    const bool hcol = ty == 1 && lx < 2 * LY;
+    const int hly = lx < LY ? lx : lx - LY;          // halo row in the tile
+    const int hx = lx < LY ? x0 - 1 : x0 + TX, hy = y0 - 1 + hly;
+    const bool hval = hcol && hx >= 0 && hx <= g.nx - 1 && hy <= g.ny - 1;
+    // halo rows: wave 0 the row below the tile, the last wave the row above
+    const int nw = TY / R;
+    const bool hrow = (ty == 0 || ty == nw - 1) && xval;
+    const int hry = ty == 0 ? y0 - 1 : y0 + TY;
+    const bool hrval = hrow && hry <= g.ny - 1;
+    // rows of this thread: present (a grid row), updated (interior, not in the hole)
+    bool rval[R], rcmp[R], side[R], top[R];
+    const int i = x - g.o[0], C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
+    const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
     const bool xin = g.has_fem && x >= g.hlo[0] && x <= g.hhi[0];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int yr = y + r, j = yr - g.o[1];
+        rval[r] = xval && yr <= g.ny - 1;
+        rcmp[r] = xcmp && yr <= g.ny - 2;
+        side[r] = ib && j >= 0 && j <= C1 && !(ii && j > 0 && j < C1);
+        top[r] = ib && ii && j > 0 && j < C1;
+    }
+    // rows inside the hole's x-y range skip the planes of the hole
     unsigned hmask = 0;
 #pragma unroll
-    for (int r = 0; r < RY_FDM; ++r)
+    for (int r = 0; r < R; ++r)
         if (xin && y + r >= g.hlo[1] && y + r <= g.hhi[1]) hmask |= 1u << r;
-    const unsigned all = (1u << nr) - 1u;
-    if ((hmask & all) == all && z0 >= g.hlo[2] && z1 - 1 <= g.hhi[2]) return;
-    fdm_rows<T, ADJ, NT>(s, x, y, nr, z0, z1, hmask);
+    // prologue: plane z0 into buffer 0, plane z0-1 of the own rows in registers
+    T cm[R], c0[R];
+    long long id = gidx(g, min(x, g.nx - 1), y, z0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        c0[r] = rval[r] ? Ub[id + r * py] : (T)0;
+        cm[r] = rval[r] ? Ub[id + r * py - pz] : (T)0;
+        buf[0][1 + R * ty + r][1 + lx] = c0[r];
+    }
+    if (hval) buf[0][hly][lx < LY ? 0 : LX - 1] = Ub[gidx(g, hx, hy, z0)];
+    if (hrval) buf[0][ty == 0 ? 0 : LY - 1][1 + lx] = Ub[gidx(g, x, hry, z0)];
+    __syncthreads();
+    int cur = 0;
+    for (int z = z0; z < z1; ++z, id += pz) {
+        const int nxt = cur ^ 1;
+        // loads: the next plane (own rows, halo), the old level of this plane
+        T cp[R], ua[R], w[R];
+        bool dor[R];
+        const bool inh = z >= g.hlo[2] && z <= g.hhi[2];
+        const int kz = z - g.o[2];
+        const bool zs = kz >= 0 && kz <= C2, zt = kz == 0 || kz == C2;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const long long ir = id + r * py;
+            cp[r] = rval[r] ? Ub[ir + pz] : (T)0;
+            dor[r] = rcmp[r] && !(((hmask >> r) & 1u) && inh);
+            ua[r] = dor[r] ? ld_once<T, NT>(Ua + ir) : (T)0;
+            w[r] = (ADJ && dor[r] && ((side[r] && zs) || (top[r] && zt))) ? Uc[ir] : (T)0;
+        }
+        const T hv = hval ? Ub[gidx(g, hx, hy, z + 1)] : (T)0;
+        const T hr = hrval ? Ub[gidx(g, x, hry, z + 1)] : (T)0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!dor[r]) continue;
+            const long long ir = id + r * py;
+            const int ly = 1 + R * ty + r;
+            const T xm = buf[cur][ly][lx], xp = buf[cur][ly][lx + 2];
+            const T ym = buf[cur][ly - 1][1 + lx], yp = buf[cur][ly + 1][1 + lx];
+            const T L = ((xm + xp) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
+            if constexpr (INC) {
+                const T d = ua[r] + c2 * L + w[r];
+                st_once<T, NT>(Dc + ir, d);
+                st_once<T, NT>(Uc + ir, c0[r] + d);
+            } else {
+                st_once<T, NT>(Uc + ir, (T)2 * c0[r] - ua[r] + c2 * L + w[r]);
+            }
+        }
+        // the next plane into the other buffer
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[nxt][1 + R * ty + r][1 + lx] = cp[r];
+        if (hval) buf[nxt][hly][lx < LY ? 0 : LX - 1] = hv;
+        if (hrval) buf[nxt][ty == 0 ? 0 : LY - 1][1 + lx] = hr;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            cm[r] = c0[r];
+            c0[r] = cp[r];
+        }
+        cur = nxt;
+    }
 }
 
 // FEM rows of one tile (forward, or with ADJ the adjoint rows and the
