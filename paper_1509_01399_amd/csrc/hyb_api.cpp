@@ -368,15 +368,20 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     g.fdm_tiles[0] = (int)ceil_div(g.nx - 1, TX_FDM);
     g.fdm_tiles[1] = (int)ceil_div(g.ny - 2, TY_FDM);
     const long long txy = (long long)g.fdm_tiles[0] * g.fdm_tiles[1];
-    // z chunk of 4 planes: measured on 257^3 grids (FP64 and FP32, forward
-    // and adjoint), chunks of 4 beat 8, 16 and 32; the extra halo planes are
-    // served from the caches while the finer work units balance better.
-    // FP32 fields on large grids: 6 planes measured faster (forward 84.9 ->
-    // 83.9 us, adjoint 97.4 -> 95.4 us per step at 257^3; FP64 unchanged).
-    const int zc = (esz == 4 && g.nz > 200) ? 6 : 4;
-    g.zc_fdm = zc;
-    g.fdm_tiles[2] = (int)ceil_div(g.nz - 2, zc);
-    g.n_fdm_blocks = (int)(txy * g.fdm_tiles[2]);
+    // Planes per z chunk, measured per precision and sweep on 257^3 grids
+    // (us per step, forward / adjoint, chunks of 4 / 6 / 8 / 12 / 16):
+    // FP64 forward 94.3 / 96.2 / 95.7 / 96.9 / 107.8, adjoint 110.9 / 112.7 /
+    // 106.5 / 119.3 / 106.1; FP32 (chunks of 6 / 8 / 12) forward 81.9 / 81.9
+    // / 88.7, adjoint 94.3 / 95.8 / 100.6.  Chunk counts that
+    // divide into whole rounds of resident blocks balance best; small grids
+    // keep 4 planes for parallelism.
+    const bool big = g.nz > 200;
+    const int zc[2] = {esz == 4 && big ? 6 : 4, big ? (esz == 4 ? 6 : 8) : 4};
+    for (int a = 0; a < 2; ++a) {
+        g.zc_fdm[a] = zc[a];
+        g.fdm_zt[a] = (int)ceil_div(g.nz - 2, zc[a]);
+        g.n_fdm_blocks[a] = (int)(txy * g.fdm_zt[a]);
+    }
     if (has_fem) {
         g.fem_tiles[0] = (int)ceil_div(g.C[0] - 1, TX_FEM);
         g.fem_tiles[1] = (int)ceil_div(g.C[1] - 1, TY_FEM);

@@ -33,9 +33,12 @@ struct Geo {
     long long n_fi, n_ec;     // face-interior nodes; edge and corner nodes
     long long foff[6], ftot;  // compact per-face arrays of boundary values
     long long nwd, nwo;       // |omega_diamond|, |omega_o|
-    int fdm_tiles[3], fem_tiles[3];
-    int zc_fdm, zc_fem;       // z chunk per block
-    int n_fdm_blocks, n_fem_blocks;  // blocks launched (FEM: n_fem_tiles rounded up to 8)
+    int fdm_tiles[2], fem_tiles[3];  // tiles along x, y (FDM); x, y, z (FEM)
+    // FDM z chunks per tile column, planes per chunk and blocks launched, for
+    // the forward [0] and the adjoint [1] sweep
+    int fdm_zt[2], zc_fdm[2], n_fdm_blocks[2];
+    int zc_fem;               // FEM planes per chunk
+    int n_fem_blocks;         // FEM blocks launched: n_fem_tiles rounded up to 8
     int n_fem_tiles;
     int bnd_blocks;           // blocks of the boundary kernels
     long long fem_n;          // FEM nodes ((C+1)^3, or the nodes of a general mesh)

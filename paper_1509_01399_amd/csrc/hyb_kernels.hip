@@ -612,15 +612,15 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
     constexpr bool INC = incr_form<T>();
     __shared__ T buf[2][LY][LX];
     const Geo &g = s.g;
-    bid = xcd_remap(bid, g.n_fdm_blocks);
-    if (bid >= g.n_fdm_blocks) return;
+    bid = xcd_remap(bid, g.n_fdm_blocks[ADJ]);
+    if (bid >= g.n_fdm_blocks[ADJ]) return;
     const int bx = bid % g.fdm_tiles[0];
     const int tt = bid / g.fdm_tiles[0];
     const int by = tt % g.fdm_tiles[1];
     const int bz = tt / g.fdm_tiles[1];
     const int x0 = bx * TX, y0 = 1 + by * TY;
-    const int z0 = 1 + bz * g.zc_fdm;
-    const int z1 = min(z0 + g.zc_fdm, g.nz - 1);
+    const int z0 = 1 + bz * g.zc_fdm[ADJ];
+    const int z1 = min(z0 + g.zc_fdm[ADJ], g.nz - 1);
     // the whole tile inside the closed hole: nothing to do (uniform exit)
     {
         const int xa = max(x0, 1), xb = min(x0 + TX - 1, g.nx - 2), yb = min(y0 + TY - 1, g.ny - 2);
@@ -911,11 +911,16 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 // FDM blocks first (their count rounded up to a multiple of 8 for the XCD
 // remap), then, in the forward sweep, the FEM blocks.  The FEM rows of the
 // adjoint run in the boundary launch.
+//
+// At most 64 VGPRs (8 waves per SIMD): the FP64 forward kernel otherwise
+// takes 72 for its FEM tiles and holds 7 waves; with the bound it spills one
+// register and measured 94.3 -> 92.4 us per forward step at 257^3 (adjoint
+// and FP32 unchanged).
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK) void k_interior(Step<T> s)
+__global__ __launch_bounds__(BLOCK, 8) void k_interior(Step<T> s)
 {
     const int b = blockIdx.x;
-    const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
+    const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
     if (b < nf) fdm_tile<T, ADJ, NT>(s, b);
     else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
 }
@@ -934,7 +939,7 @@ static bool stream_nt(const Geo &g, size_t esz, int slots)
 template <typename T>
 void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st)
 {
-    const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
+    const int nf = (s.g.n_fdm_blocks[adjoint ? 1 : 0] + 7) / 8 * 8;
     const bool nt = stream_nt(s.g, sizeof(T), 1);
     if (adjoint) {
         if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), dim3(nf), dim3(BLOCK), 0, st, s);
@@ -969,11 +974,11 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 // phase; the per-slot work is exactly that of the single-context kernels.
 
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK) void k_interior_b(const Step<T> *__restrict__ steps)
+__global__ __launch_bounds__(BLOCK, 8) void k_interior_b(const Step<T> *__restrict__ steps)
 {
     const Step<T> &s = steps[blockIdx.y];
     const int b = blockIdx.x;
-    const int nf = (s.g.n_fdm_blocks + 7) / 8 * 8;
+    const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
     if (b < nf) fdm_tile<T, ADJ, NT>(s, b);
     else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
 }
@@ -999,7 +1004,7 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_adj_b(const Step<T> *__restrict__
 template <typename T>
 void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st)
 {
-    const int nf = (g.n_fdm_blocks + 7) / 8 * 8;
+    const int nf = (g.n_fdm_blocks[0] + 7) / 8 * 8;
     if (stream_nt(g, sizeof(T), n))
         hipLaunchKernelGGL((k_interior_b<T, false, true>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
     else
@@ -1014,7 +1019,7 @@ void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t
     hipLaunchKernelGGL((k_bnd_adj_ec_b<T>), dim3((unsigned)ec_blocks(g), n), dim3(BLOCK), 0, st, steps_dev);
     const long long nb = g.n_fem_blocks + (g.n_fi + g.nwo + BLOCK - 1) / BLOCK;
     hipLaunchKernelGGL((k_bnd_adj_b<T>), dim3((unsigned)nb, n), dim3(BLOCK), 0, st, steps_dev);
-    const int nf = (g.n_fdm_blocks + 7) / 8 * 8;
+    const int nf = (g.n_fdm_blocks[1] + 7) / 8 * 8;
     if (stream_nt(g, sizeof(T), n))
         hipLaunchKernelGGL((k_interior_b<T, true, true>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev);
     else
