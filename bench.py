@@ -33,11 +33,16 @@ def interior_bytes(n, C, s):
     FP64 (s = 8, three-level leapfrog): per FDM node read u^k, read u^{k-1},
     write u^{k+1} (3 s).  FP32 (s = 4, increment form): read u^k, read d^k,
     write d^{k+1}, write u^{k+1} (4 s).  FEM nodes: the same plus one
-    coefficient per cube (s) and one history write per stored node (s)."""
+    coefficient per cube (s) and one history write per stored node (s).
+    Rows of the two absorbing x faces (the launch computes them): read u^k,
+    write u^{k+1} (and d^{k+1} in FP32)."""
     m = 4 if s == 4 else 3
     fdm_int = (n - 1) ** 3 - (C - 3) ** 3 if C else (n - 1) ** 3
     fem = (C - 1) ** 3 if C else 0
-    return m * s * fdm_int + m * s * fem + s * C ** 3 + s * (C - 3) ** 3 if C else m * s * fdm_int
+    xface = 2 * (n - 1) ** 2 * (m - 1) * s
+    if not C:
+        return m * s * fdm_int + xface
+    return m * s * fdm_int + m * s * fem + s * C ** 3 + s * (C - 3) ** 3 + xface
 
 
 def setup(wl_name, f32, seed=0):

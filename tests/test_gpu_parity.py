@@ -55,7 +55,8 @@ def test_forward_tiny40_fp64(env, orc):
     assert rel(obs, ref) <= TOL64
 
 
-@pytest.mark.parametrize("case", ["fdm_abc", "fdm_waveguide", "hyb_ragged", "hyb_neumann_mix", "hyb_o1"])
+@pytest.mark.parametrize("case", ["fdm_abc", "fdm_waveguide", "fdm_thin_abc", "hyb_ragged", "hyb_neumann_mix",
+                                  "hyb_o1"])
 def test_forward_shapes_and_bcs(env, orc, case):
     torch = env
     from paper_1509_01399_amd import synth
@@ -64,6 +65,9 @@ def test_forward_shapes_and_bcs(env, orc, case):
         n, C, o, bc = (37, 37, 37), 0, None, (A, A, A, A, A, S)
     elif case == "fdm_waveguide":
         n, C, o, bc = (3, 2, 70), 0, None, (N, N, N, N, A, S)
+    elif case == "fdm_thin_abc":
+        # one interior column: both absorbing x-face rows from one wave
+        n, C, o, bc = (2, 9, 40), 0, None, (A, A, N, A, A, S)
     elif case == "hyb_ragged":
         n, C, o, bc = (67, 45, 29), 9, (40, 17, 11), (A, A, A, A, A, S)
     elif case == "hyb_neumann_mix":
@@ -82,9 +86,12 @@ def test_forward_shapes_and_bcs(env, orc, case):
     nt = 150
     s = _solver(n, C, o=o, bc=bc, h=h)
     obs = s.forward(_t(torch, sig) if C else None, nt, dt, omega=30.0).cpu().numpy()
+    u, _ = s.wavefield(0)
     g = orc.Geometry(n, h=h, bc=bc, fem_o=o if C else 0, fem_c=C)
-    ref = orc.forward(g, sig, nt, dt, omega=30.0)
+    ref, uf = orc.forward(g, sig, nt, dt, omega=30.0, want_ufinal=True)
     assert rel(obs, ref) <= TOL64
+    # the final grid level, boundary rows included
+    assert rel(u.cpu().numpy().ravel(), uf) <= TOL64
 
 
 def test_forward_initial_levels_and_fields(env, orc):
