@@ -987,12 +987,14 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 // remap), then, in the forward sweep, the FEM blocks.  The FEM rows of the
 // adjoint run in the boundary launch.
 //
-// At most 64 VGPRs (8 waves per SIMD): the FP64 forward kernel otherwise
-// takes 72 for its FEM tiles and holds 7 waves; with the bound it spills one
-// register and measured 94.3 -> 92.4 us per forward step at 257^3 (adjoint
-// and FP32 unchanged).
+// FP32: at most 64 VGPRs (8 waves per SIMD), measured 77.4 -> 76.7 us per
+// forward step at 257^3.  FP64 runs unbounded (72 VGPRs, 7 waves): bounded,
+// its forward kernel spills and measured 79.1 us against 77.5 us per launch.
+template <typename T>
+constexpr int interior_waves() { return sizeof(T) == 4 ? 8 : 1; }
+
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK, 8) void k_interior(Step<T> s)
+__global__ __launch_bounds__(BLOCK, interior_waves<T>()) void k_interior(Step<T> s)
 {
     const int b = blockIdx.x;
     const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
@@ -1055,7 +1057,7 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 // phase; the per-slot work is exactly that of the single-context kernels.
 
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK, 8) void k_interior_b(const Step<T> *__restrict__ steps)
+__global__ __launch_bounds__(BLOCK, interior_waves<T>()) void k_interior_b(const Step<T> *__restrict__ steps)
 {
     const Step<T> &s = steps[blockIdx.y];
     const int b = blockIdx.x;
