@@ -363,7 +363,7 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     } else {
         g.nwd = g.nwo = 0;
     }
-    // x tiles start at multiples of TX_FDM (x = 0 included, idle), so that
+    // x tiles start at multiples of TX_FDM (x = 0 included: no stencil row), so that
     // they cover the interior [1, nx-2]
     g.fdm_tiles[0] = (int)ceil_div(g.nx - 1, TX_FDM);
     g.fdm_tiles[1] = (int)ceil_div(g.ny - 2, TY_FDM);

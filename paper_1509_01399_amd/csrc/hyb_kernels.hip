@@ -626,7 +626,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk)
 // FDM tile: the seven-point leapfrog, eq. (fdmschemeforward), on 64 x-lanes
 // starting at a multiple of 64 (rows of the padded field start on a
 // 128-byte line, so a wave's row access covers whole cache lines; the lane
-// on the x = 0 boundary only loads) by 4 thread rows of 2 grid rows each,
+// on the x = 0 boundary has no stencil row) by 4 thread rows of 2 grid rows each,
 // streaming z over the block's chunk.  Each plane of the tile and its
 // one-node halo (66 x 10 values) is loaded once from memory into one of two
 // LDS buffers; the x and y neighbours are read from LDS and the z neighbours
@@ -700,7 +700,7 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
     // Absorbing x faces of the forward step, eq. (eq:abs2): a face row needs
     // the old values of the face node and of its inward neighbour, both in
     // the staged plane, and the new value of the neighbour, computed in this
-    // wave.  The x = 0 lane (which only loads) takes the row of x = 0 with
+    // wave.  The x = 0 lane (no stencil row of its own) takes the row of x = 0 with
     // the new value of lane x = 1, stored by the wave's own store
     // instruction; the lane at x = nx-2 adds the row of x = nx-1.  The
     // boundary launch then skips those rows, which touched a cache line per
