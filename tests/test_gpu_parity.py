@@ -131,6 +131,48 @@ def test_forward_initial_levels_and_fields(env, orc):
     assert rel(gsig.cpu().numpy().ravel(), dsig) <= TOL64
 
 
+
+@pytest.mark.parametrize("f32", [False, True])
+def test_tall_grid_large_chunks(env, orc, f32):
+    """Grids above 200 planes take the large-grid z chunks (FP64 adjoint 8
+    planes, FP32 6), here with a ragged last chunk (209 planes) and the FEM
+    box near the trace face so that the adjoint reaches it: final grid level,
+    trace, cotangent of u^0 and conductivity gradient against the oracle."""
+    torch = env
+    n, C, o = (20, 20, 210), 10, (5, 5, 190)
+    h = 1.0 / 20
+    bc = (0, 0, 1, 0, 0, 2)
+    rng = np.random.default_rng(71)
+    sig = np.zeros((C, C, C))
+    sig[2:C - 2, 2:C - 2, 2:C - 2] = rng.uniform(0, 3, (C - 4,) * 3)
+    shape = (n[2] + 1, n[1] + 1, n[0] + 1)
+    u0 = rng.standard_normal(shape)
+    um1 = u0 + 0.1 * rng.standard_normal(shape)
+    dt, nt = 0.2 * h, 80
+    s = _solver(n, C, o=o, f32=f32, bc=bc, h=h)
+    s.set_initial(_t(torch, u0), _t(torch, um1))
+    print(f"[tall] f32={f32} n={n} C={C} o={o} nt={nt}", flush=True)
+    obs = s.forward(_t(torch, sig), nt, dt, omega=25.0).cpu().numpy()
+    u, _ = s.wavefield(0)
+    g = orc.Geometry(n, h=h, bc=bc, fem_o=o, fem_c=C)
+    ref, uf = orc.forward(g, sig.ravel(), nt, dt, omega=25.0, u0=u0, um1=um1, want_ufinal=True)
+    r = rng.standard_normal(ref.shape)
+    s.adjoint(_t(torch, r), mode=1)
+    gsig, _ = s.gradient(want_J=False)
+    mu, muv = s.wavefield(1)
+    du0 = mu.cpu().numpy().copy()
+    du0[o[2]:o[2] + C + 1, o[1]:o[1] + C + 1, o[0]:o[0] + C + 1] += muv.cpu().numpy()
+    s.close()
+    dsig, du0_ref, _ = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=25.0, u0=u0, um1=um1, want_dinit=True)
+    e = (rel(obs, ref), rel(u.cpu().numpy().ravel(), uf), rel(du0.ravel(), du0_ref),
+         rel(gsig.cpu().numpy().ravel(), dsig))
+    print(f"[tall] trace {e[0]:.2e} field {e[1]:.2e} du0 {e[2]:.2e} dsig {e[3]:.2e}", flush=True)
+    assert np.linalg.norm(dsig) > 0
+    if f32:
+        assert e[0] <= 1e-5 and e[1] <= 1e-5 and e[2] <= 1e-4 and e[3] <= 1e-4
+    else:
+        assert max(e) <= TOL64
+
 # ------------------------------------------------------------------ adjoint
 
 def test_gradient_and_J_tiny40(env, orc):
