@@ -54,7 +54,8 @@ def _load():
         lib.orc_misfit.argtypes = [G, ci, cd, dp, dp, dp]
         lib.orc_misfit.restype = ct.c_double
         lib.orc_gradient_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, cd, dp, dp, ct.POINTER(cd), dp]
-        lib.orc_cg_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, cd, cd, ci, dp]
+        lib.orc_cg_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, cd, cd, ci, ci, dp]
+        lib.orc_cg_x.restype = ci
         _lib = lib
     return _lib
 
@@ -254,19 +255,21 @@ def gradient(geom, sigma, nt, dt, data, gamma=0.01, omega=40.0, want_obs=False, 
 
 
 def cg(geom, sigma, nt, dt, data, iters, gamma=0.01, alpha_rel=0.25, omega=40.0, f0=None, f1=None,
-       taylor=False, eps=None):
-    """Algorithm 3: returns (sigma after `iters` iterations, log [iters, 5]
-    with columns J, |g|_L2, beta, alpha, max|d|).  taylor=True: IP1, every
+       taylor=False, eps=None, max_trials=8):
+    """Algorithm 3 with the backtracking step rule: returns (sigma after the
+    iterations run, log [iterations run, 8] with columns J^m, |g^m|_L2,
+    beta^m, alpha taken (0: none), max|d^m|, trials, restart, J(sigma^{m+1})).
+    The run ends early when no trial step lowers J.  taylor=True: IP1, every
     sweep starts from Model Problem 1 data (f0, f1); eps: a known 1/c^2 per
     cube."""
     lib = _load()
     sig = np.array(sigma, dtype=np.float64, copy=True)
     data = _f64(data)
-    log = np.zeros((iters, 5))
+    log = np.zeros((iters, 8))
     a0, a1, tay = _init(None, None, taylor, f0, f1)
     s = _src(0, omega)
     rc = lib.orc_cg_x(ct.byref(geom._c()), geom._m(), _p(sig), _p(_f64(eps)), ct.byref(s), nt, dt, _p(a0), _p(a1),
-                      tay, _p(data), gamma, alpha_rel, iters, _p(log))
-    if rc:
+                      tay, _p(data), gamma, alpha_rel, max_trials, iters, _p(log))
+    if rc < 0:
         raise RuntimeError(f"orc_cg failed ({rc})")
-    return sig, log
+    return sig, log[:rc]

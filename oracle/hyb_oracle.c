@@ -44,8 +44,11 @@
  *   - gradient time pairing: u^k is paired with the multiplier of the update
  *     that consumes it (level k+1), which makes the gradient the exact
  *     derivative of the discrete functional;
- *   - CG step length alpha^m = alpha_rel / max|d^m| followed by projection
- *     onto the admissible set 1 <= a <= 5 of eq. (admpar);
+ *   - CG step length (cited to another work by the paper): backtracking
+ *     from alpha_rel / max|d^m| by halving until the projected point lowers
+ *     J, projection onto the admissible set 1 <= a <= 5 of eq. (admpar); a
+ *     Fletcher-Reeves direction that is no descent direction restarts as
+ *     -g^m (orc_cg_x);
  *   - variable wave speed (eq. (modelhyb)): the coefficient 1/c^2 of the
  *     time derivative is piecewise constant per free cube like a, and 1
  *     elsewhere (condition (coefic)); it weights the element mass matrices,
@@ -66,9 +69,11 @@
  * non-zero initial velocity, and its adjoint passes a dot test in (f0, f1).
  * With 1/c^2 the sweep equals an independent whole-grid formulation whose
  * masses come from brute-force Kuhn mass shares, conserves the discrete
- * energy with those masses, and dJ/d(1/c^2) matches central differences.  The CG driver (orc_cg) is pinned only by invariants
- * (descent, feasibility, first iterate = projected steepest descent):
- * parity unpinned beyond those.
+ * energy with those masses, and dJ/d(1/c^2) matches central differences.
+ * The CG driver (orc_cg) is pinned by rebuilding its iterates from
+ * independent gradient evaluations with the formulas of Algorithm 3
+ * (beta^m, d^m, the trial steps and the acceptance test), by the first
+ * trial being the fixed step alpha_rel / max|d|, and by J decreasing.
  */
 #include <math.h>
 #include <stdint.h>
@@ -1050,62 +1055,132 @@ int orc_gradient(const orc_geom *g, const double *sigma, const orc_source *S, in
     return orc_gradient_m(g, NULL, sigma, S, nt, dt, data, gamma, grad, J, obs_out);
 }
 
-/* Algorithm 3 (Sec. 8), `iters` iterations from sigma (in/out).  Per
- * iteration m: g^m from orc_gradient; beta^m = |g^m|^2/|g^{m-1}|^2 (beta^0 = 0,
- * norms with the cell volumes); d^m = -g^m + beta^m d^{m-1};
- * alpha^m = alpha_rel / max|d^m|; sigma <- clip(sigma + alpha^m d^m, 0, 4)
- * on eligible cells (a in [1,5], eq. (admpar)).  Every sweep uses the same
- * eps and initial data (IP1 when taylor).
- * log[5*m + {0..4}] = J, |g|_{L2}, beta, alpha, max|d|. */
-int orc_cg_x(const orc_geom *g, const orc_mesh *msh, double *sigma, const double *eps, const orc_source *S,
-             int nt, double dt, const double *u0, const double *u1, int taylor, const double *data, double gamma,
-             double alpha_rel, int iters, double *log)
+/* J of eq. (functional) at sigma (a_0 = 1): one forward sweep, the misfit
+ * of orc_misfit and the Tikhonov term 1/2 gamma sum_c |c| sigma_c^2 over the
+ * eligible cells. */
+static int functional_at(const orc_geom *g, const orc_mesh *m, const double *sigma, const double *eps,
+                         const orc_source *S, int nt, double dt, const double *u0, const double *u1, int taylor,
+                         const double *data, double gamma, double *J)
 {
     orc_prob P;
-    if (prob_init(&P, g, msh, NULL, NULL) || !P.has_fem) return -1;
-    int64_t nc = P.ncube;
-    double *gr = (double *)calloc((size_t)nc, sizeof(double));
-    double *d = (double *)calloc((size_t)nc, sizeof(double));
-    double gn2_prev = 0.0;
-    for (int m = 0; m < iters; ++m) {
-        double J = 0.0;
-        if (orc_gradient_x(g, msh, sigma, eps, S, nt, dt, u0, u1, taylor, data, gamma, gr, NULL, &J, NULL)) {
-            free(gr); free(d); prob_free(&P);
-            return -1;
-        }
-        double gn2 = 0.0;
-        for (int64_t c = 0; c < nc; ++c) gn2 += P.pvol[c] * gr[c] * gr[c];
-        double beta = m == 0 ? 0.0 : gn2 / gn2_prev;
-        double dmax = 0.0;
-        for (int64_t c = 0; c < nc; ++c) {
-            d[c] = P.eligible[c] ? -gr[c] + beta * d[c] : 0.0;
-            if (fabs(d[c]) > dmax) dmax = fabs(d[c]);
-        }
-        double alpha = dmax > 0.0 ? alpha_rel / dmax : 0.0;
-        for (int64_t c = 0; c < nc; ++c) {
-            if (!P.eligible[c]) continue;
-            double s = sigma[c] + alpha * d[c];
-            sigma[c] = s < 0.0 ? 0.0 : (s > 4.0 ? 4.0 : s);
-        }
-        gn2_prev = gn2;
-        if (log) {
-            log[5 * m + 0] = J; log[5 * m + 1] = sqrt(gn2); log[5 * m + 2] = beta;
-            log[5 * m + 3] = alpha; log[5 * m + 4] = dmax;
-        }
-    }
-    free(gr); free(d);
+    if (prob_init(&P, g, m, sigma, eps) || !P.has_fem) return -1;
+    const orc_ic ic = {u0, taylor ? NULL : u1, taylor ? u1 : NULL, taylor};
+    double *obs = (double *)malloc(sizeof(double) * (size_t)P.nface * (size_t)(nt + 1));
+    if (!obs) { prob_free(&P); return -2; }
+    if (forward_sweep(&P, S, nt, dt, &ic, obs, NULL, NULL)) { free(obs); prob_free(&P); return -1; }
+    double reg = 0.0;
+    for (int64_t c = 0; c < P.ncube; ++c)
+        if (P.eligible[c]) reg += 0.5 * gamma * P.pvol[c] * sigma[c] * sigma[c];
+    *J = orc_misfit(g, nt, dt, obs, data, NULL) + reg;
+    free(obs);
     prob_free(&P);
     return 0;
 }
 
-int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
-             const double *data, double gamma, double alpha_rel, int iters, double *log)
+#define ORC_CG_LOGW 8
+
+/* Algorithm 3 (Sec. 8), at most `iters` iterations from sigma (in/out).
+ * Iteration m:
+ *   g^m and J^m = J(sigma^m) from orc_gradient_x (eq. (gradient1));
+ *   beta^m = |g^m|^2 / |g^{m-1}|^2, beta^0 = 0 (Fletcher-Reeves; L2 norms
+ *   weighted by the cell volumes);
+ *   d^m = -g^m + beta^m d^{m-1} on eligible cells; when m > 0 and the
+ *   slope sum_c |c| g^m_c d^m_c over the cells that can move (not held by a
+ *   bound: sigma_c = 0 with d_c < 0, or sigma_c = 4 with d_c > 0) is >= 0,
+ *   the projected direction does not descend and it restarts as d^m = -g^m;
+ *   step length (the paper refers to another work for it; reading R9):
+ *   trial steps alpha_t = 2^{-t} alpha_rel / max|d^m| for t = 0, 1, ...,
+ *   max_trials - 1; the first trial whose projected point
+ *   sigma_t = clip(sigma^m + alpha_t d^m, 0, 4) on eligible cells (a in
+ *   [1, 5], eq. (admpar)) has J(sigma_t) < J^m becomes sigma^{m+1}.  When
+ *   no trial lowers J, sigma stays and the iteration ends the run (the norms
+ *   have stabilised, Step 3).
+ * Every sweep uses the same eps and initial data (IP1 when taylor).
+ * log[ORC_CG_LOGW*m + {0..7}] = J^m, |g^m|_{L2}, beta^m (as computed, before
+ * a restart), alpha taken (0 if none), max|d^m|, trials run, restart (1/0),
+ * J(sigma^{m+1}).
+ * Returns the number of iterations run (a stalled one included), negative
+ * on error. */
+int orc_cg_x(const orc_geom *g, const orc_mesh *msh, double *sigma, const double *eps, const orc_source *S,
+             int nt, double dt, const double *u0, const double *u1, int taylor, const double *data, double gamma,
+             double alpha_rel, int max_trials, int iters, double *log)
 {
-    return orc_cg_x(g, msh, sigma, NULL, S, nt, dt, NULL, NULL, 0, data, gamma, alpha_rel, iters, log);
+    orc_prob P;
+    if (max_trials < 1 || prob_init(&P, g, msh, NULL, NULL) || !P.has_fem) return -1;
+    int64_t nc = P.ncube;
+    double *gr = (double *)calloc((size_t)nc, sizeof(double));
+    double *d = (double *)calloc((size_t)nc, sizeof(double));
+    double *trial = (double *)calloc((size_t)nc, sizeof(double));
+    double gn2_prev = 0.0;
+    int m = 0, rc = 0;
+    if (!gr || !d || !trial) rc = -2;
+    for (; m < iters && rc == 0; ++m) {
+        double J = 0.0;
+        if (orc_gradient_x(g, msh, sigma, eps, S, nt, dt, u0, u1, taylor, data, gamma, gr, NULL, &J, NULL)) {
+            rc = -1;
+            break;
+        }
+        double gn2 = 0.0;
+        for (int64_t c = 0; c < nc; ++c) gn2 += P.pvol[c] * gr[c] * gr[c];
+        double beta = m == 0 ? 0.0 : gn2 / gn2_prev;
+        /* slope of J(clip(sigma + alpha d)) at alpha = 0+: cells held by a
+         * bound (sigma = 0 moving down, sigma = 4 moving up) do not move */
+        double gd = 0.0;
+        for (int64_t c = 0; c < nc; ++c) {
+            d[c] = P.eligible[c] ? -gr[c] + beta * d[c] : 0.0;
+            int held = (sigma[c] <= 0.0 && d[c] < 0.0) || (sigma[c] >= 4.0 && d[c] > 0.0);
+            if (!held) gd += P.pvol[c] * gr[c] * d[c];
+        }
+        int restart = m > 0 && gd >= 0.0;
+        if (restart)
+            for (int64_t c = 0; c < nc; ++c) d[c] = P.eligible[c] ? -gr[c] : 0.0;
+        double dmax = 0.0;
+        for (int64_t c = 0; c < nc; ++c)
+            if (fabs(d[c]) > dmax) dmax = fabs(d[c]);
+        double alpha = 0.0, Jnext = J;
+        int t = 0, taken = 0;
+        while (dmax > 0.0 && t < max_trials && !taken) {
+            double at = ldexp(alpha_rel / dmax, -t);
+            for (int64_t c = 0; c < nc; ++c) {
+                if (!P.eligible[c]) { trial[c] = sigma[c]; continue; }
+                double s = sigma[c] + at * d[c];
+                trial[c] = s < 0.0 ? 0.0 : (s > 4.0 ? 4.0 : s);
+            }
+            double Jt = 0.0;
+            if (functional_at(g, msh, trial, eps, S, nt, dt, u0, u1, taylor, data, gamma, &Jt)) {
+                rc = -1;
+                break;
+            }
+            ++t;
+            if (Jt < J) {
+                taken = 1;
+                alpha = at;
+                Jnext = Jt;
+                memcpy(sigma, trial, sizeof(double) * (size_t)nc);
+            }
+        }
+        gn2_prev = gn2;
+        if (log) {
+            double *r = log + ORC_CG_LOGW * m;
+            r[0] = J; r[1] = sqrt(gn2); r[2] = beta; r[3] = alpha;
+            r[4] = dmax; r[5] = t; r[6] = restart; r[7] = Jnext;
+        }
+        if (!taken && rc == 0) { ++m; break; }
+    }
+    free(gr); free(d); free(trial);
+    prob_free(&P);
+    return rc ? rc : m;
+}
+
+int orc_cg_m(const orc_geom *g, const orc_mesh *msh, double *sigma, const orc_source *S, int nt, double dt,
+             const double *data, double gamma, double alpha_rel, int max_trials, int iters, double *log)
+{
+    return orc_cg_x(g, msh, sigma, NULL, S, nt, dt, NULL, NULL, 0, data, gamma, alpha_rel, max_trials, iters,
+                    log);
 }
 
 int orc_cg(const orc_geom *g, double *sigma, const orc_source *S, int nt, double dt,
-           const double *data, double gamma, double alpha_rel, int iters, double *log)
+           const double *data, double gamma, double alpha_rel, int max_trials, int iters, double *log)
 {
-    return orc_cg_m(g, NULL, sigma, S, nt, dt, data, gamma, alpha_rel, iters, log);
+    return orc_cg_m(g, NULL, sigma, S, nt, dt, data, gamma, alpha_rel, max_trials, iters, log);
 }

@@ -361,29 +361,143 @@ def test_misfit_quadrature_closed_form(orc):
 
 # ------------------------------------------------------------------- CG
 
-def test_cg_invariants(orc):
-    """Algorithm 3: the first direction is -g^0, steps are bounded by
-    alpha_rel in the max norm, a stays in the admissible set [1,5]
-    (eq. (admpar)), the functional decreases and the iterate moves towards
-    the true conductivity (noise-free data from the same grid)."""
-    # omega = 10 keeps about 7 cells per wavelength on this 12-cell grid; at
-    # omega = 40 the wave is aliased and a relative step of 0.25 overshoots.
+def _cg_case(orc):
+    """A 12-cell grid at omega = 10 (about 7 cells per wavelength) with
+    noise-free data of one 2^3-cell inclusion: the Fletcher-Reeves direction
+    descends here, so the recurrence is exercised without restarts."""
     n, o, C = 12, 2, 8
     h = 1.0 / n
     dt, nt, om = 0.25 * h, 120, 10.0
     g = orc.Geometry(n, fem_o=o, fem_c=C)
-    el = _eligible(C)
     true = np.zeros((C,) * 3)
     true[3:5, 3:5, 3:5] = 2.0
-    true = true.ravel()
-    data = orc.forward(g, true, nt, dt, omega=om)
+    data = orc.forward(g, true.ravel(), nt, dt, omega=om)
+    return g, C, h, dt, nt, om, true.ravel(), data
+
+
+def _functional(orc, g, sig, nt, dt, om, data, el, h, gamma=0.01):
+    """J of eq. (functional) from a forward solve and the misfit, with the
+    Tikhonov term summed here."""
+    obs = orc.forward(g, sig, nt, dt, omega=om)
+    return orc.misfit(g, nt, dt, obs, data)[0] + 0.5 * gamma * h ** 3 * np.sum(sig[el] ** 2)
+
+
+def _rebuild_cg(orc, g, C, h, dt, nt, om, data, s0, iters, max_trials=8, alpha_rel=0.25):
+    """Algorithm 3 (Sec. 8, Step 2) rebuilt from independent gradient
+    evaluations: beta^m = |g^m|^2/|g^{m-1}|^2, d^m = -g^m + beta^m d^{m-1},
+    restart to -g^m when the slope over the cells free to move is >= 0,
+    trial steps 2^{-t} alpha_rel / max|d^m| until the projected point lowers
+    J.  Returns the iterates and the per-iteration log."""
+    el = _eligible(C)
+    h3 = h ** 3
+    sig, d, gn2p = s0.copy(), np.zeros(C ** 3), None
+    sigs, rows = [], []
+    for m in range(iters):
+        gm, Jm = orc.gradient(g, sig, nt, dt, data, omega=om)
+        gn2 = h3 * np.sum(gm * gm)
+        beta = 0.0 if m == 0 else gn2 / gn2p
+        d = np.where(el, -gm + beta * d, 0.0)
+        held = ((sig <= 0) & (d < 0)) | ((sig >= 4) & (d > 0))
+        restart = m > 0 and h3 * np.sum(np.where(held, 0.0, gm * d)) >= 0
+        if restart:
+            d = np.where(el, -gm, 0.0)
+        dmax = np.max(np.abs(d))
+        taken, t, alpha, Jn = False, 0, 0.0, Jm
+        while dmax > 0 and t < max_trials and not taken:
+            a = alpha_rel / dmax * 2.0 ** -t
+            trial = np.where(el, np.clip(sig + a * d, 0.0, 4.0), sig)
+            Jt = _functional(orc, g, trial, nt, dt, om, data, el, h)
+            t += 1
+            if Jt < Jm:
+                taken, alpha, Jn, sig = True, a, Jt, trial
+        gn2p = gn2
+        rows.append([Jm, np.sqrt(gn2), beta, alpha, dmax, t, float(restart), Jn])
+        sigs.append(sig.copy())
+        if not taken:
+            break
+    return sigs, np.array(rows)
+
+
+def test_cg_recurrence_rebuilt(orc):
+    """Algorithm 3 (Sec. 8): every iterate of the oracle's CG equals the
+    iterate rebuilt with the paper's formulas from independent gradient
+    evaluations (beta^m, d^m, the trial steps and the acceptance test), and
+    the logged beta, step, max|d|, trial count, restart flag and J agree.
+    The case keeps the Fletcher-Reeves term (beta^m > 0, no restart) and
+    needs more than one trial in one iteration, so an inverted beta, a
+    dropped d^{m-1}, a wrong halving or acceptance test fails here."""
+    g, C, h, dt, nt, om, true, data = _cg_case(orc)
+    s0 = np.zeros(C ** 3)
+    iters = 5
+    sigs, rows = _rebuild_cg(orc, g, C, h, dt, nt, om, data, s0, iters)
+    assert len(rows) == iters
+    assert np.all(rows[1:, 2] > 0.1) and not np.any(rows[:, 6])   # beta used, no restart
+    assert np.max(rows[:, 5]) > 1                                   # a halving happened
+    for m in range(iters):
+        sig_o, log = orc.cg(g, s0, nt, dt, data, m + 1, omega=om)
+        assert len(log) == m + 1
+        assert np.max(np.abs(sig_o - sigs[m])) <= 1e-14 * max(1.0, np.max(np.abs(sigs[m])))
+        r = rows[m]
+        assert log[m, 5] == r[5] and log[m, 6] == r[6]
+        for col in (0, 1, 2, 3, 4, 7):
+            assert abs(log[m, col] - r[col]) <= 1e-13 * abs(r[col]) + 1e-300, (m, col, log[m, col], r[col])
+
+
+def test_cg_first_trial_is_the_fixed_step(orc):
+    """When the first trial lowers J, the step is alpha_rel / max|d| of the
+    fixed-step rule: sigma^1 = clip(sigma^0 - 0.25 g^0 / max|g^0|, 0, 4)."""
+    g, C, h, dt, nt, om, true, data = _cg_case(orc)
     s0 = np.zeros(C ** 3)
     g0, J0 = orc.gradient(g, s0, nt, dt, data, omega=om)
-    s1, log1 = orc.cg(g, s0, nt, dt, data, 1, omega=om)
+    s1, log = orc.cg(g, s0, nt, dt, data, 1, omega=om)
+    assert log[0, 5] == 1
     alpha = 0.25 / np.max(np.abs(g0))
     assert np.allclose(s1, np.clip(s0 - alpha * g0, 0, 4), rtol=0, atol=1e-15)
+    assert log[0, 7] < log[0, 0]
+
+
+def test_cg_invariants(orc):
+    """Algorithm 3: a stays in the admissible set [1,5] (eq. (admpar)),
+    cells outside the free cubes keep a = 1 (condition (2.3)), J falls at
+    every iteration and the iterate moves towards the true conductivity
+    (noise-free data from the same grid)."""
+    g, C, h, dt, nt, om, true, data = _cg_case(orc)
+    el = _eligible(C)
+    s0 = np.zeros(C ** 3)
     s3, log = orc.cg(g, s0, nt, dt, data, 4, omega=om)
-    assert np.all(log[:, 0][1:] < log[:, 0][:-1])
+    assert np.all(log[:, 7] < log[:, 0]) and np.all(log[1:, 0] == log[:-1, 7])
     assert np.all((s3 >= 0) & (s3 <= 4))
     assert np.all(s3[~el] == 0)
     assert np.linalg.norm(s3 - true) < np.linalg.norm(s0 - true)
+
+
+def test_cg_stalls_at_a_minimum(orc):
+    """Data generated at sigma = 0 and gamma = 0: J(0) = 0 is the minimum,
+    g^0 = 0, no trial can lower J, sigma stays and the run ends after one
+    iteration."""
+    g, C, h, dt, nt, om, true, data0 = _cg_case(orc)
+    data = orc.forward(g, np.zeros(C ** 3), nt, dt, omega=om)
+    s, log = orc.cg(g, np.zeros(C ** 3), nt, dt, data, 3, gamma=0.0, omega=om)
+    assert len(log) == 1 and log[0, 3] == 0 and log[0, 5] == 0 and np.all(s == 0)
+
+
+def test_cg_descends_on_tiny40(orc):
+    """The tiny workload (40^3 grid, FEM box 16^3, omega = 40, 300 steps,
+    two 3^3 inclusions of sigma = 2): the fixed step alpha_rel / max|d| of
+    the first iteration raises J, the backtracking steps lower it at every
+    iteration."""
+    from paper_1509_01399_amd import synth
+    wl = synth.WORKLOADS["tiny40"]
+    true = synth.sigma_for(wl, 0).ravel()
+    dt = synth.dt_rule(wl.h, true.max())
+    g = orc.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
+    data = orc.forward(g, true, wl.nt, dt, omega=wl.omega)
+    el = _eligible(wl.C)
+    s0 = np.zeros(wl.C ** 3)
+    g0, J0 = orc.gradient(g, s0, wl.nt, dt, data, omega=wl.omega)
+    fixed = np.where(el, np.clip(-0.25 / np.max(np.abs(g0)) * g0, 0, 4), 0.0)
+    assert _functional(orc, g, fixed, wl.nt, dt, wl.omega, data, el, wl.h) > J0
+    s, log = orc.cg(g, s0, wl.nt, dt, data, 3, omega=wl.omega)
+    assert len(log) == 3 and log[0, 5] > 1
+    assert np.all(log[:, 7] < log[:, 0]) and np.all(log[1:, 0] == log[:-1, 7])
+    assert np.all((s >= 0) & (s <= 4)) and np.all(s[~el] == 0)
