@@ -113,10 +113,11 @@ typedef struct {
                                 precision) with segment recompute;
                              2: as 1, checkpoint increments in BF16             */
     double gamma;         /* Tikhonov regularisation parameter (eq. (functional))*/
-    double alpha_rel;     /* CG step: alpha^m = alpha_rel / max|d^m|            */
+    double alpha_rel;     /* CG: first trial step alpha_rel / max|d^m|          */
     void *hip_stream;     /* hipStream_t for all work; NULL = default stream      */
     int32_t fem_general;  /* 1: run a 6-tetrahedra split on the general path too
                              (one sigma per tetrahedron)                         */
+    int32_t cg_max_trials;/* CG: trial steps per iteration (0: 8)               */
 } hyb_opts;
 
 typedef struct {
@@ -130,8 +131,18 @@ typedef struct {
 } hyb_source;
 
 typedef struct {
-    int32_t iter;         /* CG iterations done (0 before the first)             */
+    int32_t iter;         /* CG iterations done (0 before the first); set to 0 to
+                             start a new run (beta^0 = 0)                        */
     double gnorm2_prev;   /* |g^{m-1}|^2_{L2} (host copy, informational)         */
+    /* outputs of the last hyb_cg_step */
+    double beta;          /* beta^m as computed (0 when m = 0)                   */
+    double dmax;          /* max|d^m| of the direction searched                  */
+    double alpha;         /* step taken (0 when no trial lowered J)              */
+    double J_next;        /* J at the returned sigma                             */
+    int32_t trials;       /* trial points evaluated, one forward sweep each      */
+    int32_t restart;      /* 1: the direction restarted as -g^m                   */
+    int32_t stalled;      /* 1: no trial lowered J; sigma unchanged, stop         */
+    int32_t forwards;     /* forward sweeps the call ran                         */
 } hyb_cg_state;
 
 /* Create a context.  Validates the grid, the FEM mesh (see FEM box above;
@@ -252,15 +263,28 @@ hyb_status hyb_adjoint(hyb_ctx *ctx, const double *residual_dev, int32_t mode);
  * Errors: HYB_E_ARG, HYB_E_STATE. */
 hyb_status hyb_gradient(hyb_ctx *ctx, double *grad_dev, double *J_host);
 
-/* One iteration of Algorithm 3 (Sec. 8) at sigma_dev (device FP64
- * [n_params], updated in place): forward, residual obs - data, adjoint, gradient g^m,
- * beta^m = |g^m|^2 / |g^{m-1}|^2 (beta^0 = 0), d^m = -g^m + beta^m d^{m-1},
- * alpha^m = alpha_rel / max|d^m|, sigma <- clip(sigma + alpha^m d^m, 0, 4)
- * on the free cubes.  All of it in FP64 on the device; the direction d lives
- * in the context.  state (in/out) counts iterations; *gnorm_host (nullable)
- * receives |g^m|_{L2} for the stopping test (synchronises), *J_host the
- * functional at sigma^m.
- * Errors: as hyb_forward/hyb_adjoint. */
+/* One iteration m of Algorithm 3 (Sec. 8) at sigma^m = sigma_dev (device FP64
+ * [n_params], updated in place to sigma^{m+1}), all in FP64 on the device:
+ *   1. forward at sigma^m (skipped when the previous call's accepted trial
+ *      was this sigma: same state, data_dev, source, nt, dt, and sigma_dev
+ *      bitwise unchanged, which the call checks on the device), residual
+ *      obs - data, adjoint, gradient g^m of eq. (gradient1) and J^m;
+ *   2. beta^m = |g^m|^2 / |g^{m-1}|^2 (beta^0 = 0; L2 norms weighted by the
+ *      cell volumes), d^m = -g^m + beta^m d^{m-1} on the free cells; when
+ *      m > 0 and the slope sum |c| g_c d_c over the cells free to move (not
+ *      held by a bound: sigma = 0 moving down, sigma = 4 moving up) is >= 0,
+ *      d^m = -g^m (restart);
+ *   3. step length (the paper refers to another work for it): trial steps
+ *      alpha_t = 2^-t alpha_rel / max|d^m|, t = 0 .. opts.cg_max_trials - 1;
+ *      each trial point clip(sigma^m + alpha_t d^m, 0, 4) (free cells,
+ *      eq. (admpar)) costs one forward sweep; the first with J < J^m becomes
+ *      sigma^{m+1}.  When none lowers J, sigma stays, state->stalled = 1 and
+ *      the run should stop.
+ * The direction d lives in the context.  state (in/out): iter counts
+ * iterations, the other fields report the call.  *gnorm_host (nullable)
+ * receives |g^m|_{L2} for the stopping test, *J_host (nullable) J^m; the call
+ * synchronises the stream once per trial.
+ * Errors: as hyb_forward/hyb_adjoint; HYB_E_ARG for a null pointer. */
 hyb_status hyb_cg_step(hyb_ctx *ctx, const double *data_dev, double *sigma_dev,
                        const hyb_source *src, int32_t nt, double dt, hyb_cg_state *state,
                        double *gnorm_host, double *J_host);
@@ -372,7 +396,9 @@ hyb_status hyb_batch_tick(hyb_batch *b, int32_t steps, int32_t *n_active);
 
 /* State of a slot: -1 free, 0 running, 1 all work enqueued, 2 finished
  * (results valid; *J_host, nullable, receives J = misfit + regularisation),
- * 3 failed.  Does not block. */
+ * 3 failed: sigma had non-finite entries, or its maximum on the device
+ * exceeded the sigma_max given to hyb_batch_submit (the CFL check used that
+ * value); hyb_batch_last_error names the reason.  Does not block. */
 hyb_status hyb_batch_poll(hyb_batch *b, int32_t slot, int32_t *state, double *J_host);
 
 /* hyb_batch_poll for every slot: state[max_slots], J[max_slots] (nullable). */

@@ -35,6 +35,7 @@ struct hyb_ctx {
     int bc[6]{};
     int f32 = 0, store_mode = 0;
     double gamma = 0.01, alpha_rel = 0.25;
+    int max_trials = 8;          // CG trial steps per iteration
     hipStream_t stream = nullptr;
     Mesh mesh;
     size_t esz = 8;  // field element size
@@ -45,7 +46,12 @@ struct hyb_ctx {
     void *acube = nullptr;
     void *hist = nullptr;
     size_t hist_levels = 0;
-    double *sig = nullptr, *G = nullptr, *dir = nullptr, *grad = nullptr;
+    double *sig = nullptr, *G = nullptr, *dir = nullptr, *grad = nullptr, *trial = nullptr;
+    // CG: the last forward sweep ran at the accepted trial point that the
+    // previous hyb_cg_step wrote to cg_sigma (with these data), so the next
+    // iteration can start from it
+    bool cg_ready = false;
+    const double *cg_sigma = nullptr, *cg_data = nullptr;
     double *obsbuf = nullptr, *resbuf = nullptr;
     size_t tracebuf_levels = 0;
     double *partials = nullptr, *scal = nullptr;
@@ -942,6 +948,11 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
         c->gamma = opts->gamma;
         c->alpha_rel = opts->alpha_rel;
         c->stream = (hipStream_t)opts->hip_stream;
+        if (opts->cg_max_trials < 0 || opts->cg_max_trials > 60) {
+            delete c;
+            return fail(nullptr, HYB_E_ARG, "opts: cg_max_trials must be in [0, 60]");
+        }
+        if (opts->cg_max_trials > 0) c->max_trials = opts->cg_max_trials;
     }
     c->esz = c->f32 ? 4 : 8;
     c->mesh = mesh;
@@ -999,6 +1010,7 @@ void hyb_destroy(hyb_ctx *c)
     dfree((void *&)c->G);
     dfree((void *&)c->dir);
     dfree((void *&)c->grad);
+    dfree((void *&)c->trial);
     dfree((void *&)c->obsbuf);
     dfree((void *&)c->resbuf);
     dfree((void *&)c->partials);
@@ -1223,6 +1235,7 @@ hyb_status prepare_forward(hyb_ctx *c, const double *sigma, const hyb_source *sr
     }
     c->have_forward = false;
     c->have_adjoint = false;
+    c->cg_ready = false;
     c->src = *src;
     return HYB_OK;
 }
@@ -1242,6 +1255,46 @@ hyb_status alloc_adjoint(hyb_ctx *c)
             for (int q = 0; q < 2 && !s; ++q) s = dmalloc(c, &c->QE[q], vb);
     }
     return s;
+}
+
+}  // namespace
+
+namespace {
+
+bool same_source(const hyb_source &a, const hyb_source &b)
+{
+    return a.kind == b.kind && a.omega == b.omega && a.flux_dev == b.flux_dev && a.k_on == b.k_on;
+}
+
+Params cg_params(const hyb_ctx *c)
+{
+    Params p;
+    p.n = c->npar;
+    for (int d = 0; d < 3; ++d) p.C[d] = c->g.C[d];
+    p.pvol = c->gen ? c->gd.pvol : nullptr;
+    p.h3 = c->h * c->h * c->h;
+    return p;
+}
+
+// Forward sweep at sigma into the context's trace buffer, then the residual
+// obs - data and its misfit J -> scal[slot].
+hyb_status cg_forward(hyb_ctx *c, const double *sigma, const hyb_source *src, int32_t nt, double dt,
+                      const double *data, int slot)
+{
+    hyb_status s = hyb_forward(c, sigma, src, nt, dt, c->obsbuf);
+    if (s) return s;
+    const long long ntr = (long long)(nt + 1) * c->g.nx * c->g.ny;
+    launch_residual(c->obsbuf, data, c->resbuf, ntr, c->stream);
+    launch_misfit(c->g, c->resbuf, nt, dt, c->h, c->partials, c->scal, slot, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return HYB_OK;
+}
+
+hyb_status read_scal(hyb_ctx *c, double *hs)
+{
+    HIPCHK(c, hipMemcpyAsync(hs, c->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HYB_OK;
 }
 
 }  // namespace
@@ -1305,40 +1358,88 @@ hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_
                        double dt, hyb_cg_state *state, double *gnorm, double *J)
 {
     if (!c) return HYB_E_ARG;
-    if (!data || !sigma || !state) return fail(c, HYB_E_ARG, "cg_step: null argument");
+    if (!data || !sigma || !state || !src) return fail(c, HYB_E_ARG, "cg_step: null argument");
     if (!c->g.has_fem) return fail(c, HYB_E_STATE, "cg_step needs a FEM box");
+    if (c->in_batch) return fail(c, HYB_E_STATE, "context is busy in a batch");
+    if (state->iter < 0) return fail(c, HYB_E_ARG, "cg_step: state->iter < 0");
     hyb_status s = ensure_trace_bufs(c, nt);
     if (!s) s = dmalloc(c, (void **)&c->dir, (size_t)c->npar * sizeof(double));
     if (!s) s = dmalloc(c, (void **)&c->grad, (size_t)c->npar * sizeof(double));
+    if (!s) s = dmalloc(c, (void **)&c->trial, (size_t)c->npar * sizeof(double));
     if (s) return s;
-    s = hyb_forward(c, sigma, src, nt, dt, c->obsbuf);
-    if (s) return s;
-    const long long ntr = (long long)(nt + 1) * c->g.nx * c->g.ny;
-    launch_residual(c->obsbuf, data, c->resbuf, ntr, c->stream);
+    const hipStream_t st = c->stream;
+    const Params p = cg_params(c);
+    double hs[S_NSCAL];
+    // 1. the forward sweep at sigma^m, unless the accepted trial of the
+    // previous iteration left it (then sigma must still hold that point)
+    bool reuse = state->iter > 0 && c->cg_ready && c->have_forward && c->cg_sigma == sigma &&
+                 c->cg_data == data && c->nt == nt && c->dt == dt && same_source(c->src, *src);
+    if (reuse) {
+        launch_differ(sigma, c->sig, c->npar, c->partials, c->scal, S_DIFF, st);
+        s = read_scal(c, hs);
+        if (s) return s;
+        reuse = hs[S_DIFF] == 0.0;
+    }
+    c->cg_ready = false;
+    int forwards = 0;
+    if (!reuse) {
+        s = cg_forward(c, sigma, src, nt, dt, data, S_JMIST);
+        if (s) return s;
+        ++forwards;
+    }
     s = hyb_adjoint(c, c->resbuf, 0);
     if (s) return s;
     s = hyb_gradient(c, c->grad, nullptr);
     if (s) return s;
-    const double h3 = c->h * c->h * c->h;
-    if (c->gen) {
-        launch_gen_norm2(c->gd, c->grad, c->partials, c->scal, S_GN2, c->stream);
-        launch_gen_cg_dir(c->gd, c->grad, c->dir, state->iter == 0, c->partials, c->scal, c->stream);
-        launch_gen_cg_update(c->gd, c->dir, sigma, c->alpha_rel, c->scal, c->stream);
-    } else {
-        launch_norm2(c->g, c->grad, h3, c->partials, c->scal, S_GN2, c->stream);
-        launch_cg_dir(c->g, c->grad, c->dir, state->iter == 0, c->partials, c->scal, c->stream);
-        launch_cg_update(c->g, c->dir, sigma, c->alpha_rel, c->scal, c->stream);
-    }
+    // 2. direction (beta, restart) and its max norm
+    const int first = state->iter == 0;
+    launch_cg_norm2(p, c->grad, c->partials, c->scal, S_GN2, st);
+    launch_cg_dir(p, c->grad, c->dir, sigma, first, c->partials, c->scal, st);
     HIPCHK(c, hipGetLastError());
-    state->iter += 1;
-    if (gnorm || J) {
-        double hs[S_NSCAL];
-        HIPCHK(c, hipMemcpyAsync(hs, c->scal, S_NSCAL * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        state->gnorm2_prev = hs[S_GN2];
-        if (gnorm) *gnorm = std::sqrt(hs[S_GN2]);
-        if (J) *J = hs[S_JMIS] + hs[S_JREG];
+    s = read_scal(c, hs);
+    if (s) return s;
+    const double Jm = hs[S_JMIS] + hs[S_JREG], gn2 = hs[S_GN2], dmax = hs[S_DMAX];
+    state->beta = hs[S_BETA];
+    state->dmax = dmax;
+    state->restart = hs[S_RESTART] != 0.0;
+    // 3. trial steps 2^-t alpha_rel / max|d| until J falls below J^m
+    bool taken = false;
+    int t = 0;
+    double alpha = 0.0, Jn = Jm;
+    while (dmax > 0.0 && t < c->max_trials && !taken) {
+        launch_cg_trial(p, c->dir, sigma, c->trial, c->alpha_rel, t, c->gamma, c->partials, c->scal, st);
+        HIPCHK(c, hipGetLastError());
+        s = cg_forward(c, c->trial, src, nt, dt, data, S_JMIST);
+        if (s) return s;
+        ++forwards;
+        ++t;
+        s = read_scal(c, hs);
+        if (s) return s;
+        const double Jt = hs[S_JMIST] + hs[S_JREGT];
+        if (Jt < Jm) {
+            taken = true;
+            alpha = hs[S_ALPHA];
+            Jn = Jt;
+            HIPCHK(c, hipMemcpyAsync(sigma, c->trial, (size_t)c->npar * sizeof(double), hipMemcpyDeviceToDevice,
+                                     st));
+        }
     }
+    launch_cg_roll(c->scal, st);
+    HIPCHK(c, hipGetLastError());
+    if (taken) {
+        c->cg_ready = true;
+        c->cg_sigma = sigma;
+        c->cg_data = data;
+    }
+    state->iter += 1;
+    state->gnorm2_prev = gn2;
+    state->alpha = alpha;
+    state->J_next = Jn;
+    state->trials = t;
+    state->stalled = taken ? 0 : 1;
+    state->forwards = forwards;
+    if (gnorm) *gnorm = std::sqrt(gn2);
+    if (J) *J = Jm;
     return HYB_OK;
 }
 
@@ -1547,7 +1648,9 @@ struct hyb_batch {
         const double *data = nullptr;
         double *obs = nullptr, *grad = nullptr;
         hipEvent_t done = nullptr;
-        double *J_host = nullptr;  // pinned triple: non-finite flag, misfit, regularisation
+        double *J_host = nullptr;  // pinned quadruple: device max sigma, non-finite flag, misfit,
+                                   // regularisation
+        double sigma_max = 0.0;    // the caller's max sigma, used for the CFL check
         int lane = 0;
     };
     // one lane per stream: slots of different lanes run concurrently on the
@@ -1652,8 +1755,9 @@ void finish_adjoint(hyb_batch::Slot &sl)
     const double h = c->h, h3 = h * h * h, dJ = -(c->dt * c->dt) / (h * h);
     launch_grad_final(c->g, c->G, c->sig, dJ / h3, c->gamma, 0, h3, sl.grad, c->partials, c->scal, S_JREG,
                       c->stream);
-    // non-finite flag of sigma, misfit, regularisation
-    (void)hipMemcpyAsync(sl.J_host, c->scal + S_BAD, 3 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    // device max sigma, non-finite flag of sigma, misfit, regularisation
+    static_assert(S_SMAX == 0 && S_BAD == 1 && S_JMIS == 2 && S_JREG == 3, "slot quadruple layout");
+    (void)hipMemcpyAsync(sl.J_host, c->scal + S_SMAX, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     (void)hipEventRecord(sl.done, c->stream);
 }
 
@@ -1808,11 +1912,11 @@ hyb_status hyb_batch_create(int32_t max_slots, void *hip_stream, hyb_batch **out
     // per plan and lane: TICKS_PER_PLAN ticks of at most max_slots step
     // structs in at most max_slots groups, each group aligned to 256 bytes
     b->entry = (size_t)TICKS_PER_PLAN * (size_t)max_slots * (sizeof(Step<double>) + 256);
-    bool ok = hipHostMalloc((void **)&b->h_J, 3 * sizeof(double) * max_slots) == hipSuccess &&
+    bool ok = hipHostMalloc((void **)&b->h_J, 4 * sizeof(double) * max_slots) == hipSuccess &&
               lane_of(b, (hipStream_t)hip_stream) == 0;
     for (int q = 0; ok && q < max_slots; ++q) {
         ok = hipEventCreateWithFlags(&b->slots[q].done, hipEventDisableTiming) == hipSuccess;
-        b->slots[q].J_host = b->h_J + 3 * q;
+        b->slots[q].J_host = b->h_J + 4 * q;
     }
     if (!ok) {
         hyb_batch_destroy(b);
@@ -1864,6 +1968,7 @@ hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *c, const double *sigma, doubl
     sl.state = 1;
     sl.k = 0; sl.ia = 0; sl.ib = 1; sl.ic = 2;
     sl.data = data; sl.obs = obs; sl.grad = grad;
+    sl.sigma_max = sigma_max;
     sl.lane = lane;
     c->in_batch = true;
     *slot = q;
@@ -1910,8 +2015,17 @@ hyb_status hyb_batch_poll(hyb_batch *b, int32_t slot, int32_t *state, double *J)
     if (st == 3) {
         const hipError_t e = hipEventQuery(sl.done);
         if (e == hipSuccess) {
-            st = sl.J_host[0] != 0.0 ? 4 : 5;  // failed (non-finite sigma) or finished
-            if (J) *J = sl.J_host[1] + sl.J_host[2];
+            // failed: non-finite sigma, or a larger max sigma on the device
+            // than the caller's (the CFL check of the submission used the
+            // caller's value); finished otherwise
+            const bool bad = sl.J_host[1] != 0.0;
+            const bool cfl = sl.J_host[0] > std::max(0.0, sl.sigma_max) * (1.0 + 1e-12) + 1e-300;
+            st = (bad || cfl) ? 4 : 5;
+            if (bad) b->err = "batch: slot " + std::to_string(slot) + ": sigma has non-finite entries";
+            else if (cfl)
+                b->err = "batch: slot " + std::to_string(slot) + ": max sigma on the device " +
+                         std::to_string(sl.J_host[0]) + " exceeds the submitted sigma_max (CFL check)";
+            if (J) *J = sl.J_host[2] + sl.J_host[3];
         } else if (e != hipErrorNotReady) {
             return bfail(b, HYB_E_DEVICE, "batch: device error");
         }

@@ -137,13 +137,5 @@ void launch_gen_export(const GenDev &d, const T *V, double *v, hipStream_t st);
 // scal[slot] = 0.5 gamma sum_t |t| sigma_t^2; mode 1: g_t = dJ/da_t.
 void launch_gen_grad_final(const GenDev &d, const double *sigma, double gamma, int mode, double *grad,
                            double *partials, double *scal, int slot, hipStream_t st);
-// scal[slot] = sum_t |t| v_t^2 over free tetrahedra
-void launch_gen_norm2(const GenDev &d, const double *v, double *partials, double *scal, int slot,
-                      hipStream_t st);
-// CG direction and update on the free tetrahedra (as for the cubes)
-void launch_gen_cg_dir(const GenDev &d, const double *grad, double *dir, int first, double *partials,
-                       double *scal, hipStream_t st);
-void launch_gen_cg_update(const GenDev &d, const double *dir, double *sigma, double alpha_rel, double *scal,
-                          hipStream_t st);
 
 }  // namespace hyb

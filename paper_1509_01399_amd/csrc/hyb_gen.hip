@@ -272,54 +272,6 @@ __global__ __launch_bounds__(BLOCK) void k_gen_grad_final(long long nt, const in
     if (threadIdx.x == 0) part[blockIdx.x] = reg;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_gen_wsumsq(long long nt, const double *pvol, const double *v,
-                                                      double *part)
-{
-    double acc = 0.0;
-    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK)
-        acc += pvol[t] * v[t] * v[t];
-    acc = block_reduce_g(acc, false);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
-}
-
-__global__ void k_gen_store_beta(double *scal, int first)
-{
-    if (threadIdx.x == 0) scal[S_BETA] = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
-}
-
-__global__ __launch_bounds__(BLOCK) void k_gen_cg_dir(long long nt, const double *pvol, const double *grad,
-                                                      double *dir, int first, const double *scal, double *part)
-{
-    const double beta = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
-    double mx = 0.0;
-    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK) {
-        double d = 0.0;
-        if (pvol[t] > 0.0) d = first ? -grad[t] : -grad[t] + beta * dir[t];
-        dir[t] = d;
-        mx = fmax(mx, fabs(d));
-    }
-    mx = block_reduce_g(mx, true);
-    if (threadIdx.x == 0) part[blockIdx.x] = mx;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_gen_cg_update(long long nt, const double *pvol, const double *dir,
-                                                         double *sigma, double alpha_rel, double *scal)
-{
-    const double dmax = scal[S_DMAX];
-    const double alpha = dmax > 0.0 ? alpha_rel / dmax : 0.0;
-    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nt; t += (long long)gridDim.x * BLOCK) {
-        if (!(pvol[t] > 0.0)) continue;
-        const double sv = sigma[t] + alpha * dir[t];
-        sigma[t] = sv < 0.0 ? 0.0 : (sv > 4.0 ? 4.0 : sv);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
-}
-
-__global__ void k_gen_roll_gn2(double *scal)
-{
-    if (threadIdx.x == 0) scal[S_GN2P] = scal[S_GN2];
-}
-
 int row_blocks(long long fn)
 {
     const long long nb = (fn + BLOCK - 1) / BLOCK;
@@ -390,32 +342,6 @@ void launch_gen_grad_final(const GenDev &d, const double *sigma, double gamma, i
     hipLaunchKernelGGL(k_gen_grad_final, dim3(nb), dim3(BLOCK), 0, st, d.ntet, d.tetE, d.ke6, d.E, d.pvol,
                        sigma, gamma, mode, grad, partials);
     hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 0.5 * gamma, scal, slot);
-}
-
-void launch_gen_norm2(const GenDev &d, const double *v, double *partials, double *scal, int slot,
-                      hipStream_t st)
-{
-    const int nb = nparts_g(d.ntet);
-    hipLaunchKernelGGL(k_gen_wsumsq, dim3(nb), dim3(BLOCK), 0, st, d.ntet, d.pvol, v, partials);
-    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 1.0, scal, slot);
-}
-
-void launch_gen_cg_dir(const GenDev &d, const double *grad, double *dir, int first, double *partials,
-                       double *scal, hipStream_t st)
-{
-    const int nb = nparts_g(d.ntet);
-    hipLaunchKernelGGL(k_gen_store_beta, dim3(1), dim3(64), 0, st, scal, first);
-    hipLaunchKernelGGL(k_gen_cg_dir, dim3(nb), dim3(BLOCK), 0, st, d.ntet, d.pvol, grad, dir, first, scal,
-                       partials);
-    hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, nb, 1, 1.0, scal, (int)S_DMAX);
-}
-
-void launch_gen_cg_update(const GenDev &d, const double *dir, double *sigma, double alpha_rel, double *scal,
-                          hipStream_t st)
-{
-    hipLaunchKernelGGL(k_gen_cg_update, dim3(nparts_g(d.ntet)), dim3(BLOCK), 0, st, d.ntet, d.pvol, dir, sigma,
-                       alpha_rel, scal);
-    hipLaunchKernelGGL(k_gen_roll_gn2, dim3(1), dim3(64), 0, st, scal);
 }
 
 #define HYB_GEN_INST(T)                                                                            \

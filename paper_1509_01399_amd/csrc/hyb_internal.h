@@ -144,15 +144,29 @@ void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h,
 void launch_grad_final(const Geo &g, const double *G, const double *sigma, double coefG,
                        double gamma, int mode, double h3, double *grad, double *partials,
                        double *scal, int slot, hipStream_t st);
-// CG: scal[gn2] = h^3 sum g^2; direction update d = -g + beta d with
-// beta = scal[gn2]/scal[gn2_prev] (0 on the first iteration); scal[dmax];
-// sigma update with alpha = alpha_rel / scal[dmax]; then gn2_prev <- gn2.
-void launch_norm2(const Geo &g, const double *v, double h3, double *partials, double *scal, int slot,
-                  hipStream_t st);
-void launch_cg_dir(const Geo &g, const double *grad, double *dir, int first, double *partials,
-                   double *scal, hipStream_t st);
-void launch_cg_update(const Geo &g, const double *dir, double *sigma, double alpha_rel, double *scal,
-                      hipStream_t st);
+// Conductivity parameters for the CG kernels: the C^3 cubes of a structured
+// box (weight h^3 on free cubes) or the tetrahedra of a general mesh
+// (weight = volume on free tetrahedra); weight 0 = not free.
+struct Params {
+    long long n;
+    int C[3];
+    const double *pvol;  // general mesh: weight per tetrahedron; null = structured cubes
+    double h3;
+};
+// Algorithm 3.  norm2: scal[slot] = sum w v^2.  dir: d = -g + beta d with
+// beta = scal[GN2]/scal[GN2P] (0 when first); restart d = -g when not first
+// and the slope over the cells free to move is >= 0; scal[BETA, SLOPE,
+// RESTART, DMAX].  trial: trial = clip(sigma + 2^{-t} alpha_rel / DMAX d) on
+// free cells, scal[ALPHA], scal[JREGT] = gamma/2 sum w trial^2.  roll:
+// GN2P <- GN2.  differ: scal[slot] = 1 when a and b differ anywhere.
+void launch_cg_norm2(const Params &p, const double *v, double *partials, double *scal, int slot, hipStream_t st);
+void launch_cg_dir(const Params &p, const double *grad, double *dir, const double *sigma, int first,
+                   double *partials, double *scal, hipStream_t st);
+void launch_cg_trial(const Params &p, const double *dir, const double *sigma, double *trial, double alpha_rel,
+                     int t, double gamma, double *partials, double *scal, hipStream_t st);
+void launch_cg_roll(double *scal, hipStream_t st);
+void launch_differ(const double *a, const double *b, long long n, double *partials, double *scal, int slot,
+                   hipStream_t st);
 void launch_residual(const double *obs, const double *data, double *res, long long n,
                      hipStream_t st);
 
@@ -171,7 +185,8 @@ void launch_hist_diff(const Geo &g, const T *a, const T *b, T *hist, hipStream_t
 
 // device scalar slots
 enum : int { S_SMAX = 0, S_BAD = 1, S_JMIS = 2, S_JREG = 3, S_GN2 = 4, S_GN2P = 5, S_BETA = 6,
-             S_DMAX = 7, S_ALPHA = 8, S_GERSH = 9, S_NSCAL = 16 };
+             S_DMAX = 7, S_ALPHA = 8, S_GERSH = 9, S_SLOPE = 10, S_RESTART = 11, S_JMIST = 12, S_JREGT = 13,
+             S_DIFF = 14, S_NSCAL = 16 };
 constexpr int MAX_PARTIALS = 4096;
 
 }  // namespace hyb

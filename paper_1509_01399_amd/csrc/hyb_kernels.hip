@@ -761,7 +761,19 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
             if (dor[r]) {
                 const T xm = buf[cur][ly][lx];
                 const T ym = buf[cur][ly - 1][1 + lx], yp = buf[cur][ly + 1][1 + lx];
-                const T L = ((xm + xp) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
+                // FP32 (increment form): the Laplacian as a sum of neighbour
+                // differences, each exact in FP32 while the neighbours are
+                // within a factor 2 of the node (Sterbenz), so a smooth field
+                // does not lose its second difference to cancellation.  With
+                // the sum-then-subtract form a plane wave on a 512-cell axis
+                // over 2500 steps kept 1.5e-5 trace error, with this one
+                // 4.6e-7 (FP64 reference, x-y uniform field).
+                T L;
+                if constexpr (INC)
+                    L = ((xm - c0[r]) + (xp - c0[r])) + ((ym - c0[r]) + (yp - c0[r])) +
+                        ((cm[r] - c0[r]) + (cp[r] - c0[r]));
+                else
+                    L = ((xm + xp) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
                 if constexpr (INC) {
                     d = ua[r] + c2 * L + w[r];
                     v = c0[r] + d;
@@ -1464,67 +1476,146 @@ void launch_grad_final(const Geo &g, const double *G, const double *sigma, doubl
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 0.5 * gamma * h3, scal, slot);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_sumsq(long long n, const double *v, double *part)
+// ---------------------------------------------------------------- CG
+//
+// Algorithm 3 on the conductivity parameters: cubes of a structured box or
+// tetrahedra of a general mesh, each with its L2 weight (cell volume) when
+// it is free and weight 0 otherwise (those cells never move).
+
+__device__ __forceinline__ double pweight(const Params &p, long long c)
+{
+    if (p.pvol) return p.pvol[c];
+    const int i = (int)(c % p.C[0]);
+    const int j = (int)((c / p.C[0]) % p.C[1]);
+    const int k = (int)(c / ((long long)p.C[0] * p.C[1]));
+    return (i >= 2 && i < p.C[0] - 2 && j >= 2 && j < p.C[1] - 2 && k >= 2 && k < p.C[2] - 2) ? p.h3 : 0.0;
+}
+
+// partial sums of w v^2 (L2 norm with the cell volumes)
+__global__ __launch_bounds__(BLOCK) void k_wsumsq(Params p, const double *v, double *part)
 {
     double acc = 0.0;
-    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK)
-        acc += v[c] * v[c];
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < p.n; c += (long long)gridDim.x * BLOCK)
+        acc += pweight(p, c) * v[c] * v[c];
     acc = block_reduce(acc, false);
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-void launch_norm2(const Geo &g, const double *v, double h3, double *partials, double *scal, int slot,
-                  hipStream_t st)
+void launch_cg_norm2(const Params &p, const double *v, double *partials, double *scal, int slot, hipStream_t st)
 {
-    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
-    const int nb = nparts(n);
-    hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(BLOCK), 0, st, n, v, partials);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, h3, scal, slot);
+    const int nb = nparts(p.n);
+    hipLaunchKernelGGL(k_wsumsq, dim3(nb), dim3(BLOCK), 0, st, p, v, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 1.0, scal, slot);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_cg_dir(Geo g, const double *grad, double *dir, int first,
-                                                  const double *scal, double *part)
+// Fletcher-Reeves direction d = -g + beta d^{m-1} on free cells (beta^0 = 0)
+// and per block: max|d|, max|g| and the slope sum w g d over the cells free
+// to move (a cell held by a bound, sigma = 0 moving down or sigma = 4 moving
+// up, does not move under the projection).
+constexpr int DIR_PARTS = MAX_PARTIALS / 4;
+
+__global__ __launch_bounds__(BLOCK) void k_cg_dir(Params p, const double *grad, double *dir, const double *sigma,
+                                                  int first, const double *scal, double *part)
 {
-    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
     const double beta = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
-    double mx = 0.0;
-    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK) {
+    double dm = 0.0, gm = 0.0, slope = 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < p.n; c += (long long)gridDim.x * BLOCK) {
+        const double w = pweight(p, c);
         double d = 0.0;
-        if (cube_free(g, c)) d = first ? -grad[c] : -grad[c] + beta * dir[c];
+        if (w > 0.0) {
+            const double g = grad[c], sv = sigma[c];
+            d = first ? -g : -g + beta * dir[c];
+            const bool held = (sv <= 0.0 && d < 0.0) || (sv >= 4.0 && d > 0.0);
+            if (!held) slope += w * g * d;
+            gm = fmax(gm, fabs(g));
+        }
         dir[c] = d;
-        mx = fmax(mx, fabs(d));
+        dm = fmax(dm, fabs(d));
     }
-    mx = block_reduce(mx, true);
-    if (threadIdx.x == 0) part[blockIdx.x] = mx;
+    dm = block_reduce(dm, true);
+    __syncthreads();
+    gm = block_reduce(gm, true);
+    __syncthreads();
+    slope = block_reduce(slope, false);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = dm;
+        part[DIR_PARTS + blockIdx.x] = gm;
+        part[2 * DIR_PARTS + blockIdx.x] = slope;
+    }
 }
 
-__global__ void k_store_beta(double *scal, int first)
+// Folds the direction partials (fixed order) and decides the iteration:
+// beta, restart when m > 0 and the slope is >= 0 (then d = -g), and max|d|
+// of the direction searched.
+__global__ __launch_bounds__(BLOCK) void k_cg_decide(const double *part, int nb, int first, double *scal)
 {
-    if (threadIdx.x == 0) scal[S_BETA] = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
+    double dm = 0.0, gm = 0.0, slope = 0.0;
+    for (int q = threadIdx.x; q < nb; q += BLOCK) {
+        dm = fmax(dm, part[q]);
+        gm = fmax(gm, part[DIR_PARTS + q]);
+        slope += part[2 * DIR_PARTS + q];
+    }
+    dm = block_reduce(dm, true);
+    __syncthreads();
+    gm = block_reduce(gm, true);
+    __syncthreads();
+    slope = block_reduce(slope, false);
+    if (threadIdx.x == 0) {
+        const bool restart = !first && slope >= 0.0;
+        scal[S_BETA] = first ? 0.0 : scal[S_GN2] / scal[S_GN2P];
+        scal[S_SLOPE] = slope;
+        scal[S_RESTART] = restart ? 1.0 : 0.0;
+        scal[S_DMAX] = restart ? gm : dm;
+    }
 }
 
-void launch_cg_dir(const Geo &g, const double *grad, double *dir, int first, double *partials,
-                   double *scal, hipStream_t st)
+__global__ __launch_bounds__(BLOCK) void k_cg_restart(Params p, const double *grad, double *dir, const double *scal)
 {
-    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
-    const int nb = nparts(n);
-    hipLaunchKernelGGL(k_store_beta, dim3(1), dim3(64), 0, st, scal, first);
-    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(BLOCK), 0, st, g, grad, dir, first, scal, partials);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 1, 1.0, scal, (int)S_DMAX);
+    if (scal[S_RESTART] == 0.0) return;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < p.n; c += (long long)gridDim.x * BLOCK)
+        dir[c] = pweight(p, c) > 0.0 ? -grad[c] : 0.0;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_cg_update(Geo g, const double *dir, double *sigma, double alpha_rel,
-                                                     double *scal)
+void launch_cg_dir(const Params &p, const double *grad, double *dir, const double *sigma, int first,
+                   double *partials, double *scal, hipStream_t st)
 {
-    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
+    const int nb = std::min(nparts(p.n), DIR_PARTS);
+    hipLaunchKernelGGL(k_cg_dir, dim3(nb), dim3(BLOCK), 0, st, p, grad, dir, sigma, first, scal, partials);
+    hipLaunchKernelGGL(k_cg_decide, dim3(1), dim3(BLOCK), 0, st, partials, nb, first, scal);
+    hipLaunchKernelGGL(k_cg_restart, dim3(nparts(p.n)), dim3(BLOCK), 0, st, p, grad, dir, scal);
+}
+
+// Trial point t of the step search: sigma_t = clip(sigma + alpha_t d, 0, 4)
+// on free cells (the others copy sigma), alpha_t = 2^{-t} alpha_rel / max|d|;
+// partials of w sigma_t^2 for the Tikhonov term of J(sigma_t).
+__global__ __launch_bounds__(BLOCK) void k_cg_trial(Params p, const double *dir, const double *sigma, double *trial,
+                                                    double alpha_rel, int t, double *scal, double *part)
+{
     const double dmax = scal[S_DMAX];
-    const double alpha = dmax > 0.0 ? alpha_rel / dmax : 0.0;
-    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK) {
-        if (!cube_free(g, c)) continue;
-        const double sv = sigma[c] + alpha * dir[c];
-        sigma[c] = sv < 0.0 ? 0.0 : (sv > 4.0 ? 4.0 : sv);
+    const double alpha = dmax > 0.0 ? ldexp(alpha_rel / dmax, -t) : 0.0;
+    double reg = 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < p.n; c += (long long)gridDim.x * BLOCK) {
+        const double w = pweight(p, c);
+        double sv = sigma[c];
+        if (w > 0.0) {
+            sv += alpha * dir[c];
+            sv = sv < 0.0 ? 0.0 : (sv > 4.0 ? 4.0 : sv);
+            reg += w * sv * sv;
+        }
+        trial[c] = sv;
     }
+    reg = block_reduce(reg, false);
+    if (threadIdx.x == 0) part[blockIdx.x] = reg;
     if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
+}
+
+void launch_cg_trial(const Params &p, const double *dir, const double *sigma, double *trial, double alpha_rel,
+                     int t, double gamma, double *partials, double *scal, hipStream_t st)
+{
+    const int nb = nparts(p.n);
+    hipLaunchKernelGGL(k_cg_trial, dim3(nb), dim3(BLOCK), 0, st, p, dir, sigma, trial, alpha_rel, t, scal,
+                       partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 0.5 * gamma, scal, (int)S_JREGT);
 }
 
 __global__ void k_roll_gn2(double *scal)
@@ -1532,12 +1623,27 @@ __global__ void k_roll_gn2(double *scal)
     if (threadIdx.x == 0) scal[S_GN2P] = scal[S_GN2];
 }
 
-void launch_cg_update(const Geo &g, const double *dir, double *sigma, double alpha_rel, double *scal,
-                      hipStream_t st)
+void launch_cg_roll(double *scal, hipStream_t st)
 {
-    const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
-    hipLaunchKernelGGL(k_cg_update, dim3(nparts(n)), dim3(BLOCK), 0, st, g, dir, sigma, alpha_rel, scal);
     hipLaunchKernelGGL(k_roll_gn2, dim3(1), dim3(64), 0, st, scal);
+}
+
+// 1 when two FP64 arrays differ anywhere (bitwise, NaN-safe)
+__global__ __launch_bounds__(BLOCK) void k_differ(const double *a, const double *b, long long n, double *part)
+{
+    double diff = 0.0;
+    for (long long c = (long long)blockIdx.x * BLOCK + threadIdx.x; c < n; c += (long long)gridDim.x * BLOCK)
+        if (__double_as_longlong(a[c]) != __double_as_longlong(b[c])) diff = 1.0;
+    diff = block_reduce(diff, true);
+    if (threadIdx.x == 0) part[blockIdx.x] = diff;
+}
+
+void launch_differ(const double *a, const double *b, long long n, double *partials, double *scal, int slot,
+                   hipStream_t st)
+{
+    const int nb = nparts(n);
+    hipLaunchKernelGGL(k_differ, dim3(nb), dim3(BLOCK), 0, st, a, b, n, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 1, 1.0, scal, slot);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_residual(const double *obs, const double *data, double *res,

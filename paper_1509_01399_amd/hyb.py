@@ -47,7 +47,8 @@ class hyb_overlap(ct.Structure):
 
 class hyb_opts(ct.Structure):
     _fields_ = [("field_f32", ct.c_int32), ("store_mode", ct.c_int32), ("gamma", ct.c_double),
-                ("alpha_rel", ct.c_double), ("hip_stream", ct.c_void_p), ("fem_general", ct.c_int32)]
+                ("alpha_rel", ct.c_double), ("hip_stream", ct.c_void_p), ("fem_general", ct.c_int32),
+                ("cg_max_trials", ct.c_int32)]
 
 
 class hyb_source(ct.Structure):
@@ -56,7 +57,10 @@ class hyb_source(ct.Structure):
 
 
 class hyb_cg_state(ct.Structure):
-    _fields_ = [("iter", ct.c_int32), ("gnorm2_prev", ct.c_double)]
+    _fields_ = [("iter", ct.c_int32), ("gnorm2_prev", ct.c_double), ("beta", ct.c_double),
+                ("dmax", ct.c_double), ("alpha", ct.c_double), ("J_next", ct.c_double),
+                ("trials", ct.c_int32), ("restart", ct.c_int32), ("stalled", ct.c_int32),
+                ("forwards", ct.c_int32)]
 
 
 class HybError(RuntimeError):
@@ -158,8 +162,10 @@ def make_mesh(xyz, tet4):
     return m
 
 
-def make_opts(f32=False, store_mode=0, gamma=0.01, alpha_rel=0.25, stream=None, general=False):
+def make_opts(f32=False, store_mode=0, gamma=0.01, alpha_rel=0.25, stream=None, general=False,
+              cg_max_trials=0):
     o = hyb_opts()
+    o.cg_max_trials = int(cg_max_trials)
     o.fem_general = int(bool(general))
     o.field_f32 = int(bool(f32))
     o.store_mode = int(store_mode)
@@ -418,7 +424,10 @@ class Solver:
         return grad, J
 
     def cg_step(self, data, sigma, nt, dt, state, omega=40.0):
-        self.generation += 1  # runs a forward sweep
+        """One iteration of Algorithm 3 (sigma updated in place); returns
+        (|g^m|, J^m); state reports beta, the step, trials, restart and
+        whether the run stalled."""
+        self.generation += 1  # runs forward sweeps
         return hyb_cg_step(self.ctx, data, sigma, make_source(omega), nt, dt, state)
 
     def wavefield(self, which=0):

@@ -48,6 +48,7 @@ class Result:
     finished: float
     J: float
     grad: object = None  # host copy when kept
+    obs: object = None   # host copy of the trace when kept
 
     @property
     def latency(self):
@@ -186,7 +187,7 @@ def shapes_of(requests):
 
 
 def run_batched(requests, data, budget=200e9, max_slots=64, f32=True, keep_grads=False, pool=None,
-                caps=None, steps_per_call=DEFAULT_STEPS_PER_CALL):
+                caps=None, steps_per_call=DEFAULT_STEPS_PER_CALL, keep_obs=False):
     """Continuous batching.  Admission: the oldest arrived request whose size
     is below its concurrency cap and whose footprint fits.  Returns (results
     sorted by id, wall seconds)."""
@@ -231,15 +232,16 @@ def run_batched(requests, data, budget=200e9, max_slots=64, f32=True, keep_grads
                     r, e, adm = running.pop(slot)
                     n_run[r.n] -= 1
                     fin = time.perf_counter() - t0
-                    g = None
-                    if keep_grads:
+                    g = o = None
+                    if keep_grads or keep_obs:
                         with torch.cuda.stream(e.stream):
-                            g = e.grad.cpu().numpy().copy()
+                            g = e.grad.cpu().numpy().copy() if keep_grads else None
+                            o = e.obs[:r.nt + 1].cpu().numpy().copy() if keep_obs else None
                     hyb.hyb_batch_release(b, slot)
                     pool.release(e)
                     if st == 3:
-                        raise RuntimeError(f"request {r.id} failed: non-finite sigma")
-                    results.append(Result(r.id, r.n, r.arrival, adm, fin, J, g))
+                        raise RuntimeError(f"request {r.id} failed: {hyb.hyb_batch_last_error(b)}")
+                    results.append(Result(r.id, r.n, r.arrival, adm, fin, J, g, o))
             if not running and not queued and head < len(waiting):
                 wait = waiting[head].arrival - (time.perf_counter() - t0)
                 if wait > 0:
@@ -255,7 +257,7 @@ def run_batched(requests, data, budget=200e9, max_slots=64, f32=True, keep_grads
     return sorted(results, key=lambda x: x.id), wall
 
 
-def run_unbatched(requests, data, f32=True, keep_grads=False, pool=None):
+def run_unbatched(requests, data, f32=True, keep_grads=False, pool=None, keep_obs=False):
     """Baseline: one request at a time, in arrival order, through hyb_forward,
     hyb_adjoint and hyb_gradient on resident contexts."""
     import torch
@@ -277,8 +279,9 @@ def run_unbatched(requests, data, f32=True, keep_grads=False, pool=None):
                 _, J = s.gradient(e.grad, want_J=True)
                 fin = time.perf_counter() - t0
                 g = e.grad.cpu().numpy().copy() if keep_grads else None
+                o = obs[:r.nt + 1].cpu().numpy().copy() if keep_obs else None
             pool.release(e)
-            results.append(Result(r.id, r.n, r.arrival, adm, fin, J, g))
+            results.append(Result(r.id, r.n, r.arrival, adm, fin, J, g, o))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
     finally:

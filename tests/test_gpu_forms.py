@@ -65,7 +65,8 @@ def test_bf16_checkpoints_error(torch, orc):
     gref, Jref = orc.gradient(g, sig.ravel(), 300, dt, data, omega=40.0)
     g32, J32, _ = _grad_J(torch, 40, 16, sig, data, 300, dt, 40.0, f32=True, store_mode=0)
     gb, Jb, _ = _grad_J(torch, 40, 16, sig, data, 300, dt, 40.0, f32=True, store_mode=2)
-    e32, eb = rel(g32, gref), rel(gb, gref)
+    from tests.fpcheck import err32
+    e32, eb = err32(g32, gref), err32(gb, gref)
     print(f"gradient rel err vs oracle: fp32 history {e32:.2e}, fp32+bf16 checkpoints {eb:.2e}; "
           f"bf16 vs fp32 history {rel(gb, g32):.2e}", flush=True)
     assert e32 <= 1e-4
@@ -148,7 +149,8 @@ def test_differentiation_downscale48(torch, orc):
     g = orc.Geometry(n, fem_o=o, fem_c=C)
     ref_obs = orc.forward(g, sig.ravel(), nt, dt, omega=om)
     ref = orc.adjoint(g, sig.ravel(), nt, dt, W, omega=om)
-    et, eg = rel(obs.detach().cpu().numpy(), ref_obs), rel(x.grad.cpu().numpy(), ref)
+    from tests.fpcheck import err32
+    et, eg = err32(obs.detach().cpu().numpy(), ref_obs), err32(x.grad.cpu().numpy(), ref)
     print(f"downscale48: trace {et:.2e}, gradient {eg:.2e}", flush=True)
     assert et <= 1e-5 and eg <= 1e-4
     s.close()
@@ -173,13 +175,14 @@ def test_precision_downscale64(torch, orc):
     data = synth.add_noise(orc.forward(g, sig_true.ravel(), nt, dt, omega=om), 0.03, 9)
     sig = np.zeros((C, C, C))
     gref, Jref, oref = orc.gradient(g, sig.ravel(), nt, dt, data, omega=om, want_obs=True)
+    from tests.fpcheck import err32
     errs = {}
     for mode in (1, 2):
         s = Solver(n, C=C, o=o, f32=True, store_mode=mode)
         obs = s.forward(_t(torch, sig), nt, dt, omega=om)
         s.adjoint(obs - _t(torch, data), mode=0)
         gb, Jb = s.gradient()
-        errs[mode] = (rel(obs.cpu().numpy(), oref), rel(gb.cpu().numpy(), gref), abs(Jb - Jref) / Jref)
+        errs[mode] = (err32(obs.cpu().numpy(), oref), err32(gb.cpu().numpy(), gref), abs(Jb - Jref) / Jref)
         s.close()
     print(f"downscale64 (trace, gradient, J) fp32 checkpoints {errs[1]}, bf16 increments {errs[2]}", flush=True)
     assert errs[1][0] <= 1e-5 and errs[1][1] <= 1e-4

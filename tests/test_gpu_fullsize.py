@@ -71,8 +71,9 @@ def _short(torch, orc, name, f32, nt, seed):
     ref, vh, uf = orc.forward(g, sig.ravel(), nt, dt, omega=wl.omega, u0=u0, um1=um1, want_vhist=True,
                               want_ufinal=True)
     _, du0_ref, _ = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=wl.omega, u0=u0, um1=um1, want_dinit=True)
-    errs = {"trace": rel(obs, ref), "u_final": rel(u, uf), "v_final": rel(v, vh[nt]),
-            "du0": rel(du0.ravel(), du0_ref)}
+    from tests.fpcheck import err32
+    m = err32 if f32 else rel
+    errs = {"trace": m(obs, ref), "u_final": m(u, uf), "v_final": m(v, vh[nt]), "du0": m(du0.ravel(), du0_ref)}
     print(f"[fullsize] {name} errors {errs}", flush=True)
     return errs
 

@@ -7,7 +7,7 @@ FEM box, one conductivity per tetrahedron) through the C ABI:
 - perturbed (unstructured) meshes against the oracle's mesh mode: traces,
   final fields, the L2 gradient per tetrahedron and J in FP64 (<= 1e-12) and
   FP32 (trace <= 1e-5, gradient <= 1e-4); the Euclidean gradient of a random
-  trace cotangent on a box with ragged 64-row slices; two CG iterations;
+  trace cotangent on a box with ragged 64-row slices; three CG iterations;
 - checkpoint store modes, the CFL refusal, and the calls a general mesh
   refuses.
 """
@@ -106,7 +106,9 @@ def test_general_perturbed_parity(env, orc, f32):
     gref, Jref = orc.gradient(g, st, nt, dt, data, omega=om)
     free = gref != 0
     assert free.sum() > 1000 and np.abs(ref).max() > 1e-3
-    e = {"trace": rel(obs, ref), "u": rel(u, uf), "v": rel(v, vh[nt]), "grad": rel(grad, gref),
+    from tests.fpcheck import err32
+    m = err32 if f32 else rel
+    e = {"trace": m(obs, ref), "u": m(u, uf), "v": m(v, vh[nt]), "grad": m(grad, gref),
          "J": abs(J - Jref) / abs(Jref)}
     print(f"[general] perturbed f32={f32} errors {e}", flush=True)
     assert np.all(grad[~free] == 0)
@@ -143,35 +145,25 @@ def test_general_ragged_euclidean_gradient(env, orc):
 
 
 def test_general_cg_iterations(env, orc):
-    """Two iterations of Algorithm 3 from sigma = 0.  The residual obs - data
-    is about 1% of the trace, so the traces' rounding differences (~1e-15)
-    reach the gradient at ~1e-13, and each CG update (a step normalised by
-    max|d|, beta from a ratio of norms) amplifies them: the bar on the
-    iterate is 1e-11, as for the structured CG test."""
-    from paper_1509_01399_amd import hyb
+    """Three iterations of Algorithm 3 from sigma = 0 on a perturbed mesh,
+    every logged value against the oracle's mesh mode.  300 steps, so the
+    scattered wave is back on the observed face and the residual is ~3% of
+    the trace."""
+    from tests.cg_parity import run_and_compare
     from paper_1509_01399_amd.hyb import Solver
     torch = env
     n, C = 32, 16
-    o, h, xyz, tet, st = _case(n, C, seed=11)
-    dt, nt, om, iters = 0.18 * h, 150, 30.0, 2
+    o, h, xyz, tet, st = _case(n, C, seed=12)
+    dt, nt, om, iters = 0.18 * h, 300, 30.0, 3
     g = orc.Geometry(n, fem_o=o, fem_c=C, mesh=(xyz, tet))
     data = orc.forward(g, st, nt, dt, omega=om)
     s0 = np.zeros(len(tet))
+    obs0 = orc.forward(g, s0, nt, dt, omega=om)
     sref, log = orc.cg(g, s0, nt, dt, data, iters, omega=om)
+    assert len(log) == iters
     s = Solver(n, C=C, o=o, mesh=(xyz, tet))
-    sig = _t(torch, s0)
-    state = hyb.hyb_cg_state()
-    out = []
-    for _ in range(iters):
-        out.append(s.cg_step(_t(torch, data), sig, nt, dt, state, omega=om))
+    run_and_compare(torch, s, data, s0, nt, dt, om, log, sref, obs0, "general")
     s.close()
-    gn, Js = np.array(out).T
-    print(f"[general] cg sigma {rel(sig.cpu().numpy(), sref):.2e} |g| {gn} vs {log[:, 1]} J {Js} vs {log[:, 0]}",
-          flush=True)
-    assert np.abs(sref).max() > 0
-    assert rel(sig.cpu().numpy(), sref) <= 1e-11
-    assert np.allclose(gn, log[:, 1], rtol=1e-11, atol=0)
-    assert np.allclose(Js, log[:, 0], rtol=1e-11, atol=0)
 
 
 def test_general_checkpoint_modes(env):
@@ -191,7 +183,8 @@ def test_general_checkpoint_modes(env):
         s.close()
     assert np.array_equal(grads[(False, 1)], grads[(False, 0)])
     assert np.array_equal(grads[(True, 1)], grads[(True, 0)])
-    assert rel(grads[(True, 0)], grads[(False, 0)]) <= 1e-4
+    from tests.fpcheck import err32
+    assert err32(grads[(True, 0)], grads[(False, 0)]) <= 1e-4
     assert rel(grads[(True, 2)], grads[(True, 0)]) <= 2e-2
 
 

@@ -7,7 +7,7 @@ through the C ABI against the oracle's Taylor start:
   the paper's Test 1 data f0 = exp(-|x|^2), f1 = 0 and random f1;
 - FP32 fields: trace <= 1e-5, gradient <= 1e-4;
 - checkpoint store modes reproduce the full history bitwise;
-- two CG iterations of IP1 (every sweep from the same data);
+- three CG iterations of IP1 (every sweep from the same data);
 - the 6-tetrahedra split on the general path equals the structured path;
 - zero data equal Model Problem 2 bitwise; the batch path refuses the data.
 """
@@ -131,7 +131,8 @@ def test_taylor_fp32_bounds(env, orc):
     gsig, _ = s.gradient(want_J=False)
     s.close()
     dsig = orc.adjoint(g, sig.ravel(), nt, dt, r, omega=om, taylor=True, f0=f0, f1=f1)
-    e_t, e_g = rel(obs, ref), rel(gsig.cpu().numpy(), dsig)
+    from tests.fpcheck import err32
+    e_t, e_g = err32(obs, ref), err32(gsig.cpu().numpy(), dsig)
     print(f"[taylor] fp32 trace {e_t:.2e} grad {e_g:.2e}", flush=True)
     assert e_t <= 1e-5 and e_g <= 1e-4
 
@@ -158,29 +159,24 @@ def test_taylor_checkpoints_bitwise(env, f32):
 
 
 def test_taylor_cg_ip1(env, orc):
-    """IP1: two iterations of Algorithm 3 where every sweep starts from the
-    Model Problem 1 data."""
-    from paper_1509_01399_amd import hyb
-    from paper_1509_01399_amd.hyb import Solver
+    """IP1: three iterations of Algorithm 3 where every sweep starts from the
+    Model Problem 1 data, every logged value against the oracle."""
+    from tests.cg_parity import run_and_compare
     torch = env
     n, C, o, h, sig_true = _case(12)
     dt, nt, om = 0.25 * h, 120, 30.0
     f0, f1 = _data(n, "moving", 13)
     g = orc.Geometry(n, fem_o=o, fem_c=C)
     data = orc.forward(g, sig_true.ravel(), nt, dt, omega=om, taylor=True, f0=f0, f1=f1)
-    sig_ref, log = orc.cg(g, np.zeros(C ** 3), nt, dt, data, 2, omega=om, taylor=True, f0=f0, f1=f1)
+    s0 = np.zeros(C ** 3)
+    obs0 = orc.forward(g, s0, nt, dt, omega=om, taylor=True, f0=f0, f1=f1)
+    sig_ref, log = orc.cg(g, s0, nt, dt, data, 3, omega=om, taylor=True, f0=f0, f1=f1)
+    assert len(log) == 3
+    from paper_1509_01399_amd.hyb import Solver
     s = Solver(n, C=C, o=o)
     s.set_initial_taylor(_t(torch, f0), _t(torch, f1))
-    sig = torch.zeros((C,) * 3, dtype=torch.float64, device="cuda")
-    st = hyb.hyb_cg_state()
-    d = _t(torch, data)
-    for m in range(2):
-        gn, J = s.cg_step(d, sig, nt, dt, st, omega=om)
-        print(f"[taylor] cg {m}: |g| {gn:.6e} vs {log[m, 1]:.6e}, J {J:.6e} vs {log[m, 0]:.6e}", flush=True)
-        assert abs(gn - log[m, 1]) <= 1e-11 * log[m, 1]
-        assert abs(J - log[m, 0]) <= 1e-11 * log[m, 0]
+    run_and_compare(torch, s, data, s0.reshape((C,) * 3), nt, dt, om, log, sig_ref, obs0, "taylor")
     s.close()
-    assert rel(sig.cpu().numpy(), sig_ref) <= 1e-11
 
 
 def test_taylor_general_kuhn_equals_structured(env):
