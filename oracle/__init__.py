@@ -51,6 +51,8 @@ def _load():
         ci, cd = ct.c_int, ct.c_double
         lib.orc_forward_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, dp, dp]
         lib.orc_adjoint_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, dp, dp, dp, dp, dp, dp, dp]
+        lib.orc_threads.argtypes = [ci]
+        lib.orc_threads.restype = ci
         lib.orc_misfit.argtypes = [G, ci, cd, dp, dp, dp]
         lib.orc_misfit.restype = ct.c_double
         lib.orc_gradient_x.argtypes = [G, M, dp, dp, S, ci, cd, dp, dp, ci, dp, cd, dp, dp, ct.POINTER(cd), dp]
@@ -58,6 +60,12 @@ def _load():
         lib.orc_cg_x.restype = ci
         _lib = lib
     return _lib
+
+
+def threads(n=0):
+    """Threads of the oracle's FDM rows (n > 0 sets them); returns the number
+    in use.  Results are the same for every thread count."""
+    return _load().orc_threads(int(n))
 
 
 class Geometry:

@@ -77,6 +77,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -528,7 +531,10 @@ static void step_forward(const orc_prob *P, int k, double dt, double w2, const o
     memset(Up, 0, sizeof(double) * (size_t)P->nn);
 
     /* (i) FDM rows: u^{k+1} = tau^2 Lap u^k + 2 u^k - u^{k-1},
-     *     eq. (fdmschemeforward) with the seven-point Laplacian. */
+     *     eq. (fdmschemeforward) with the seven-point Laplacian.  Every row
+     *     writes only its own node, so the z planes run on parallel threads
+     *     with the same result as one thread. */
+#pragma omp parallel for schedule(static)
     for (int kk = 1; kk < P->nz - 1; ++kk)
         for (int j = 1; j < P->ny - 1; ++j)
             for (int i = 1; i < P->nx - 1; ++i) {
@@ -793,23 +799,40 @@ static void step_adjoint(const orc_prob *P, int k, double dt, double w2, const o
         }
     }
 
-    /* (i)^T: FDM rows. */
-    for (int kk = 1; kk < P->nz - 1; ++kk)
-        for (int j = 1; j < P->ny - 1; ++j)
-            for (int i = 1; i < P->nx - 1; ++i) {
-                int64_t id = gidx(P, i, j, kk);
-                if (!P->fdm_row[id]) continue;
-                double g = aUp[id];
-                aUp[id] = 0.0;
-                const int64_t st[3] = {1, P->nx, (int64_t)P->nx * P->ny};
-                for (int d = 0; d < 3; ++d) {
-                    aU[id + st[d]] += tau2 / h2 * g;
-                    aU[id - st[d]] += tau2 / h2 * g;
-                    aU[id] -= 2.0 * tau2 / h2 * g;
+    /* (i)^T: FDM rows.  The row of node m reads u^k at m and its six
+     * neighbours and u^{k-1} at m, so its cotangent g_m = aUp[m] goes to
+     * aU[m] with weight 2 - 6 tau^2/h^2, to aU of each neighbour with
+     * tau^2/h^2 and to aUm[m] with -1.  Gathered per receiving node (its own
+     * row first, then the neighbours' rows in a fixed order), every node is
+     * written by one thread only: the z planes run in parallel with the same
+     * result as one thread.  aUp is read in a first pass and cleared in a
+     * second. */
+    {
+        const double c = tau2 / h2;
+        const int64_t st[3] = {1, P->nx, (int64_t)P->nx * P->ny};
+        const int n3[3] = {P->nx, P->ny, P->nz};
+#pragma omp parallel for schedule(static)
+        for (int kk = 0; kk < P->nz; ++kk)
+            for (int j = 0; j < P->ny; ++j)
+                for (int i = 0; i < P->nx; ++i) {
+                    int64_t id = gidx(P, i, j, kk);
+                    const int x[3] = {i, j, kk};
+                    double acc = aU[id];
+                    if (P->fdm_row[id]) {
+                        double g = aUp[id];
+                        acc += (2.0 - 6.0 * c) * g;
+                        aUm[id] -= g;
+                    }
+                    for (int d = 0; d < 3; ++d) {
+                        if (x[d] > 0 && P->fdm_row[id - st[d]]) acc += c * aUp[id - st[d]];
+                        if (x[d] < n3[d] - 1 && P->fdm_row[id + st[d]]) acc += c * aUp[id + st[d]];
+                    }
+                    aU[id] = acc;
                 }
-                aU[id] += 2.0 * g;
-                aUm[id] -= g;
-            }
+#pragma omp parallel for schedule(static)
+        for (int64_t id = 0; id < P->nn; ++id)
+            if (P->fdm_row[id]) aUp[id] = 0.0;
+    }
 }
 
 /* Reverse sweep.  seed: [nt+1][nface] cotangent of the recorded trace.
@@ -866,6 +889,19 @@ static double face_weight(const orc_prob *P, int i, int j)
 }
 
 /* ---------------------------------------------------------- exported API */
+
+/* Threads of the FDM rows (OpenMP over z planes; n <= 0 leaves the setting);
+ * returns the number now in use.  Results do not depend on it. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* Every entry point takes an optional explicit mesh m (NULL: the 6-tetrahedra
  * split of the FEM box); with a mesh, sigma, dsig and grad hold one value per

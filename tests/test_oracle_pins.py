@@ -501,3 +501,27 @@ def test_cg_descends_on_tiny40(orc):
     assert len(log) == 3 and log[0, 5] > 1
     assert np.all(log[:, 7] < log[:, 0]) and np.all(log[1:, 0] == log[:-1, 7])
     assert np.all((s >= 0) & (s <= 4)) and np.all(s[~el] == 0)
+
+
+def test_threads_do_not_change_results(orc):
+    """The FDM rows run over z planes on OpenMP threads (forward rows write
+    their own node; the transposed rows are gathered per receiving node), the
+    FEM and boundary rows on one thread: trace, gradient and J are bitwise
+    the same for one thread and for several."""
+    n, o, C = 20, 5, 10
+    h = 1.0 / n
+    dt, nt, om = 0.25 * h, 90, 30.0
+    g = orc.Geometry(n, fem_o=o, fem_c=C)
+    rng = np.random.default_rng(71)
+    sig = _rand_sigma(C, rng)
+    data = 1e-3 * rng.standard_normal((nt + 1, n + 1, n + 1))
+    keep = orc.threads()
+    out = []
+    try:
+        for th in (1, 4):
+            assert orc.threads(th) == th
+            out.append(orc.gradient(g, sig, nt, dt, data, omega=om, want_obs=True))
+    finally:
+        orc.threads(keep)
+    (g1, J1, o1), (g4, J4, o4) = out
+    assert np.array_equal(o1, o4) and np.array_equal(g1, g4) and J1 == J4
