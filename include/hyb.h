@@ -263,6 +263,21 @@ hyb_status hyb_adjoint(hyb_ctx *ctx, const double *residual_dev, int32_t mode);
  * Errors: HYB_E_ARG, HYB_E_STATE. */
 hyb_status hyb_gradient(hyb_ctx *ctx, double *grad_dev, double *J_host);
 
+/* hyb_gradient for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same gradient of the last adjoint into grad_dev (device FP64 [n_params],
+ * as hyb_gradient), and J (mode 0: misfit + regularisation; mode 1: 0) into
+ * J_dev (device FP64 [1], nullable) instead of a host pointer, so nothing is
+ * allocated and the stream is not synchronised.  The reduction scratch (one
+ * partial sum per 256 parameters and the scalars) is a static device array
+ * of 131 200 bytes that each GPU holds until the process ends; calls on one
+ * GPU share it, so calls that overlap on one GPU (other streams, other
+ * threads) race.  The context's own buffers must exist already (they do
+ * after hyb_adjoint).
+ * Errors: HYB_E_ARG, HYB_E_STATE (no adjoint), HYB_E_UNSUPPORTED (more than
+ * 4 194 304 parameters: the scratch is full), HYB_E_DEVICE. */
+hyb_status hyb_gradient_noalloc(hyb_ctx *ctx, double *grad_dev, double *J_dev);
+
 /* One iteration m of Algorithm 3 (Sec. 8) at sigma^m = sigma_dev (device FP64
  * [n_params], updated in place to sigma^{m+1}), all in FP64 on the device:
  *   1. forward at sigma^m (skipped when the previous call's accepted trial

@@ -1354,6 +1354,34 @@ hyb_status hyb_gradient(hyb_ctx *c, double *grad, double *J)
     return HYB_OK;
 }
 
+hyb_status hyb_gradient_noalloc(hyb_ctx *c, double *grad, double *J_dev)
+{
+    if (!c) return HYB_E_ARG;
+    if (!grad) return fail(c, HYB_E_ARG, "grad is null");
+    if (!c->g.has_fem) return fail(c, HYB_E_STATE, "gradient needs a FEM box");
+    // one partial sum per block of 256 parameters, all in the scratch array
+    const long long nb = ceil_div(c->npar, BLOCK);
+    if (nb > NOALLOC_PARTS)
+        return fail(c, HYB_E_UNSUPPORTED, "hyb_gradient_noalloc: " + std::to_string(c->npar) +
+                                              " parameters, the scratch holds partials for at most " +
+                                              std::to_string((long long)NOALLOC_PARTS * BLOCK));
+    if (!c->have_adjoint) return fail(c, HYB_E_STATE, "gradient before adjoint");
+    double *scr = nullptr;
+    HIPCHK(c, noalloc_scratch(&scr));
+    double *part = scr, *sc = scr + NOALLOC_PARTS;
+    const double h = c->h, h3 = h * h * h;
+    const double dJ = -(c->dt * c->dt) / (h * h);
+    const int mode = c->adj_mode;
+    if (c->gen)
+        launch_gen_grad_final(c->gd, c->sig, c->gamma, mode, grad, part, sc, 0, c->stream, (int)nb);
+    else
+        launch_grad_final(c->g, c->G, c->sig, mode == 0 ? dJ / h3 : dJ, c->gamma, mode, h3, grad, part, sc, 0,
+                          c->stream, (int)nb);
+    if (J_dev) launch_sum_J(c->scal + S_JMIS, sc, mode, J_dev, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return HYB_OK;
+}
+
 hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_source *src, int32_t nt,
                        double dt, hyb_cg_state *state, double *gnorm, double *J)
 {

@@ -136,6 +136,6 @@ void launch_gen_export(const GenDev &d, const T *V, double *v, hipStream_t st);
 // of K^t_pair E_pair (free t).  mode 0: g_t = dJ/da_t / |t| + gamma sigma_t,
 // scal[slot] = 0.5 gamma sum_t |t| sigma_t^2; mode 1: g_t = dJ/da_t.
 void launch_gen_grad_final(const GenDev &d, const double *sigma, double gamma, int mode, double *grad,
-                           double *partials, double *scal, int slot, hipStream_t st);
+                           double *partials, double *scal, int slot, hipStream_t st, int blocks = 0);
 
 }  // namespace hyb

@@ -336,9 +336,9 @@ void launch_gen_export(const GenDev &d, const T *V, double *v, hipStream_t st)
 }
 
 void launch_gen_grad_final(const GenDev &d, const double *sigma, double gamma, int mode, double *grad,
-                           double *partials, double *scal, int slot, hipStream_t st)
+                           double *partials, double *scal, int slot, hipStream_t st, int blocks)
 {
-    const int nb = nparts_g(d.ntet);
+    const int nb = blocks > 0 ? blocks : nparts_g(d.ntet);
     hipLaunchKernelGGL(k_gen_grad_final, dim3(nb), dim3(BLOCK), 0, st, d.ntet, d.tetE, d.ke6, d.E, d.pvol,
                        sigma, gamma, mode, grad, partials);
     hipLaunchKernelGGL(k_final_g, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 0.5 * gamma, scal, slot);

@@ -143,7 +143,7 @@ void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h,
 // gradient finalisation (see hyb_gradient); reg -> scal[slot] (0.5 gamma h^3 sum sigma^2)
 void launch_grad_final(const Geo &g, const double *G, const double *sigma, double coefG,
                        double gamma, int mode, double h3, double *grad, double *partials,
-                       double *scal, int slot, hipStream_t st);
+                       double *scal, int slot, hipStream_t st, int blocks = 0);
 // Conductivity parameters for the CG kernels: the C^3 cubes of a structured
 // box (weight h^3 on free cubes) or the tetrahedra of a general mesh
 // (weight = volume on free tetrahedra); weight 0 = not free.
@@ -182,6 +182,14 @@ void launch_eps_grad(const Geo &g, const double *Gm, double scale, double *geps,
 // history box of a - b (b may be null) for the level u^{-1}
 template <typename T>
 void launch_hist_diff(const Geo &g, const T *a, const T *b, T *hist, hipStream_t st);
+
+// hyb_gradient_noalloc: a file-scope device array of NOALLOC_PARTS partial
+// sums and NOALLOC_SCAL scalars (131 200 bytes per GPU); *out = its address
+// on the current device (resolved once per device).
+constexpr int NOALLOC_PARTS = 16384, NOALLOC_SCAL = 16, NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(double **out);
+// J[0] = mode 0 ? jmis[0] + jreg[0] : 0
+void launch_sum_J(const double *jmis, const double *jreg, int mode, double *J, hipStream_t st);
 
 // device scalar slots
 enum : int { S_SMAX = 0, S_BAD = 1, S_JMIS = 2, S_JREG = 3, S_GN2 = 4, S_GN2P = 5, S_BETA = 6,

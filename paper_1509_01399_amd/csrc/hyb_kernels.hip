@@ -28,6 +28,7 @@
 #include "hyb_internal.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace hyb {
 
@@ -1467,10 +1468,10 @@ __global__ __launch_bounds__(BLOCK) void k_grad_final(Geo g, const double *G, co
 
 void launch_grad_final(const Geo &g, const double *G, const double *sigma, double coefG, double gamma,
                        int mode, double h3, double *grad, double *partials, double *scal, int slot,
-                       hipStream_t st)
+                       hipStream_t st, int blocks)
 {
     const long long n = (long long)g.C[0] * g.C[1] * g.C[2];
-    const int nb = nparts(n);
+    const int nb = blocks > 0 ? blocks : nparts(n);
     hipLaunchKernelGGL(k_grad_final, dim3(nb), dim3(BLOCK), 0, st, g, G, sigma, coefG, gamma, mode, grad,
                        partials);
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, 0, 0.5 * gamma * h3, scal, slot);
@@ -1656,6 +1657,48 @@ __global__ __launch_bounds__(BLOCK) void k_residual(const double *obs, const dou
 void launch_residual(const double *obs, const double *data, double *res, long long n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_residual, dim3(nparts(n)), dim3(BLOCK), 0, st, obs, data, res, n);
+}
+
+// ------------------------------------------------------- no-allocation scratch
+//
+// Scratch of hyb_gradient_noalloc, for callers that cannot allocate device
+// memory: the reduction partials (one per block of 256 parameters) and the
+// scalars, in a file-scope device array.  Each GPU the library runs on holds
+// its own copy until the process ends; every call on that GPU shares it.
+// Host code must not pass the array's name to a kernel (on the host it is a
+// stand-in, not a device address): noalloc_scratch resolves the address once
+// per device with hipGetSymbolAddress and the kernels take that pointer.
+static __device__ __align__(256) double scratch[NOALLOC_PARTS + NOALLOC_SCAL];
+
+hipError_t noalloc_scratch(double **out)
+{
+    static std::mutex mu;
+    static double *addr[NOALLOC_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (double *)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+// J = misfit (from the adjoint, in the context's scalars) + regularisation
+// (from the scratch scalars), or 0 for a cotangent adjoint (mode 1).
+__global__ void k_sum_J(const double *jmis, const double *jreg, int mode, double *J)
+{
+    if (threadIdx.x == 0) J[0] = mode == 0 ? jmis[0] + jreg[0] : 0.0;
+}
+
+void launch_sum_J(const double *jmis, const double *jreg, int mode, double *J, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum_J, dim3(1), dim3(64), 0, st, jmis, jreg, mode, J);
 }
 
 // explicit instantiations

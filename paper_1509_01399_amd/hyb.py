@@ -28,7 +28,8 @@ EXPORTS = ("hyb_create", "hyb_destroy", "hyb_forward", "hyb_set_initial", "hyb_a
            "hyb_counts", "hyb_time_interior", "hyb_get_wavefield", "hyb_batch_create",
            "hyb_batch_destroy", "hyb_batch_submit", "hyb_batch_tick", "hyb_batch_poll",
            "hyb_batch_release", "hyb_batch_last_error", "hyb_batch_poll_all", "hyb_fem_info",
-           "hyb_time_fem", "hyb_set_initial_taylor", "hyb_set_wave_speed", "hyb_gradient_eps")
+           "hyb_time_fem", "hyb_set_initial_taylor", "hyb_set_wave_speed", "hyb_gradient_eps",
+           "hyb_gradient_noalloc")
 
 
 class hyb_fd_grid(ct.Structure):
@@ -93,6 +94,7 @@ def load():
     lib.hyb_gradient_eps.argtypes = [vp, vp]
     lib.hyb_adjoint.argtypes = [vp, vp, ct.c_int32]
     lib.hyb_gradient.argtypes = [vp, vp, P(dp)]
+    lib.hyb_gradient_noalloc.argtypes = [vp, vp, vp]
     lib.hyb_cg_step.argtypes = [vp, vp, vp, P(hyb_source), ct.c_int32, dp, P(hyb_cg_state), P(dp),
                                 P(dp)]
     lib.hyb_footprint.argtypes = [P(hyb_fd_grid), P(hyb_fem_mesh), P(hyb_overlap), P(hyb_opts),
@@ -228,6 +230,12 @@ def hyb_gradient(ctx, grad, want_J=False):
     J = ct.c_double(0.0)
     _check(load().hyb_gradient(ctx, _ptr(grad), ct.byref(J) if want_J else None), ctx)
     return J.value if want_J else None
+
+
+def hyb_gradient_noalloc(ctx, grad, J=None):
+    """hyb_gradient without allocation: grad and J (device FP64 [1] or None)
+    are device tensors; nothing is synchronised."""
+    _check(load().hyb_gradient_noalloc(ctx, _ptr(grad), _ptr(J)), ctx)
 
 
 def hyb_cg_step(ctx, data, sigma, src, nt, dt, state, want_norms=True):
