@@ -2,13 +2,18 @@
 FEM/FDM solver on one MI355X, on the 256^3 reconstruction workload (FEM box
 96^3 cells x 6 tetrahedra, 1200 steps, 1-4 cubic inclusions, 3% noise).
 
-One timed step = one iteration of Algorithm 3: forward sweep (1200 steps),
-residual, adjoint sweep with the fused FP64 gradient integral, gradient
-finalisation and the CG update of sigma, all on the device with inputs
-resident in HBM.  value = 2 * (FDM-updated + FEM-updated nodes) * nt * steps /
-wall time.  The line also carries the roofline of the dominant kernel (the
-fused FDM/FEM interior update), timed with HIP events on the solver's
-stream, and the CPU oracle timed on a bounded window of the same workload.
+One timed step = one iteration of Algorithm 3: the adjoint sweep at the
+current iterate with the fused FP64 gradient integral, the gradient
+finalisation, the direction, and one forward sweep per trial step of the
+step search (the accepted trial's sweep serves the next iteration), all on
+the device with inputs resident in HBM.  value = (forward + adjoint sweeps
+run) * (FDM-updated + FEM-updated nodes) * nt / wall time.  The line also
+carries the roofline of the dominant kernel (the fused FDM/FEM interior
+update), timed with HIP events on the solver's stream, the CPU oracle timed
+on a bounded window of the same workload (all host threads and one), and
+legs for the other workloads: the 40^3 parity case (time and errors against
+the oracle), the differentiation workload at 384^3 and the precision
+workload at 512^3 (rate and interior roofline).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--workload cg256] [--probe {interior,copy}]
@@ -28,15 +33,16 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 
 
-def interior_bytes(n, C, s):
-    """Algorithmic bytes of one forward interior launch (fused FDM + FEM).
-    FP64 (s = 8, three-level leapfrog): per FDM node read u^k, read u^{k-1},
-    write u^{k+1} (3 s).  FP32 (s = 4, increment form): read u^k, read d^k,
-    write d^{k+1}, write u^{k+1} (4 s).  FEM nodes: the same plus one
-    coefficient per cube (s) and one history write per stored node (s).
-    Rows of the two absorbing x faces (the launch computes them): read u^k,
-    write u^{k+1} (and d^{k+1} in FP32)."""
-    m = 4 if s == 4 else 3
+def interior_bytes(n, C, s, streams=3):
+    """Algorithmic bytes of one forward interior launch (fused FDM + FEM),
+    the minimum the leapfrog must move with perfect neighbour reuse: per FDM
+    node read u^k, read u^{k-1}, write u^{k+1} (3 s, s the field element
+    size).  FEM nodes: the same plus one coefficient per cube (s) and one
+    history write per stored node (s).  Rows of the two absorbing x faces
+    (the launch computes them): read u^k, write u^{k+1}.  streams=4 counts
+    what the FP32 increment form moves: read u^k, d^k, write d^{k+1}, u^{k+1}
+    (4 s per node, d^{k+1} also on the x faces)."""
+    m = streams
     fdm_int = (n - 1) ** 3 - (C - 3) ** 3 if C else (n - 1) ** 3
     fem = (C - 1) ** 3 if C else 0
     xface = 2 * (n - 1) ** 2 * (m - 1) * s
@@ -63,6 +69,9 @@ def setup(wl_name, f32, seed=0):
 
 
 def run_cg(wl, dt, solver, data, steps, warmup):
+    """warmup + steps CG iterations from sigma = 0; returns the time of the
+    timed ones, the (|g|, J) log, sigma, the forward + adjoint sweeps the
+    timed iterations ran, and their trial counts."""
     import torch
 
     from paper_1509_01399_amd import hyb
@@ -72,27 +81,26 @@ def run_cg(wl, dt, solver, data, steps, warmup):
     for _ in range(warmup):
         log.append(solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega))
     torch.cuda.synchronize()
+    sweeps, trials = 0, []
     t0 = time.perf_counter()
     for _ in range(steps):
         log.append(solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega))
+        sweeps += state.forwards + 1
+        trials.append(state.trials)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0), log, sig
+    return (t1 - t0), log, sig, sweeps, trials
 
 
-def cpu_baseline(wl, dt, window):
-    """The CPU oracle (plain FP64 C, one thread) on windows of the same
-    workload: full grid and FEM box, w forward steps then w adjoint steps (one
-    oracle gradient evaluation) for w = 2 and w = window; the rate is the
-    marginal one between the two windows, so the oracle's mesh set-up is not
-    charged to it."""
+def _oracle_window(wl, dt, window, threads):
+    """Marginal oracle rate on the full grid between windows of 2 and
+    `window` forward+adjoint steps (one oracle gradient evaluation each), so
+    the oracle's mesh set-up is not charged to it."""
     import numpy as np
 
     import oracle
-    from oracle.build import build, lib_path
     from paper_1509_01399_amd import synth
-    if not os.path.exists(lib_path()):
-        build()
+    used = oracle.threads(threads)
     g = oracle.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
     sz = g.sizes()
     sig = synth.sigma_for(wl, 0).ravel()
@@ -103,17 +111,36 @@ def cpu_baseline(wl, dt, window):
         oracle.gradient(g, sig, w, dt, data, omega=wl.omega)
         ts.append(time.perf_counter() - t0)
     upd = 2 * (sz["fdm_updated"] + sz["fem_updated"]) * (window - 2)
-    t = ts[1] - ts[0]
+    return upd / (ts[1] - ts[0]) / 1e9, ts, used
+
+
+def cpu_baseline(wl, dt, window):
+    """The CPU oracle (plain FP64 C; OpenMP over z planes in its FDM rows, the
+    FEM and boundary rows on one thread) on windows of the same workload,
+    once with every host thread and once with one."""
+    import oracle
+    from oracle.build import build, lib_path
+    if not os.path.exists(lib_path()):
+        build()
+    keep = oracle.threads()
+    all_threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        v_all, ts_all, used = _oracle_window(wl, dt, window, all_threads)
+        v_one, ts_one, _ = _oracle_window(wl, dt, window, 1)
+    finally:
+        oracle.threads(keep)
     model = "unknown CPU"
     try:
         with open("/proc/cpuinfo") as fh:
             model = next(ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return {"value": round(upd / t / 1e9, 5), "unit": "Gpt-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{wl.name} full grid ({wl.n}^3 cells, FEM {wl.C}^3): one oracle forward+adjoint "
-                      f"of 2 and of {window} steps ({ts[0]:.1f} s, {ts[1]:.1f} s); marginal rate over "
-                      f"the {window - 2} extra step pairs, single thread of {os.cpu_count()} ({model})"}
+    return {"value": round(v_all, 5), "unit": "Gpt-updates/s", "cores": used, "kind": "oracle",
+            "single_thread": {"value": round(v_one, 5), "cores": 1},
+            "sample": f"{wl.name} full grid ({wl.n}^3 cells, FEM {wl.C}^3): one oracle forward+adjoint of 2 and "
+                      f"of {window} steps; marginal rate over the {window - 2} extra step pairs; {used} threads "
+                      f"({ts_all[0]:.1f} s, {ts_all[1]:.1f} s) and 1 thread ({ts_one[0]:.1f} s, {ts_one[1]:.1f} s)"
+                      f"; host: {os.cpu_count()} CPUs visible, {model}"}
 
 
 def kernel_source_hash():
@@ -147,6 +174,10 @@ def measured_traffic(wl_name, f32):
 
 
 def roofline(wl, dt, solver, f32, reps=50):
+    """Roofline of the forward interior launch: algorithmic bytes (three
+    streams per node, the leapfrog's minimum) over the average launch time
+    measured with HIP events on the solver's stream.  FP32 also reports the
+    fraction by the bytes its increment form moves (four streams)."""
     import torch
     from paper_1509_01399_amd import hyb
     s = 4 if f32 else 8
@@ -156,10 +187,15 @@ def roofline(wl, dt, solver, f32, reps=50):
     ms = hyb.hyb_time_interior(solver.ctx, sig, dt, reps)
     b = interior_bytes(wl.n, wl.C, s)
     achieved = b / (ms * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(wl.name, f32),
-            "kernel": "k_interior<%s,false,*> (forward FDM+FEM interior)" % ("float" if f32 else "double"),
-            "bytes_per_launch": b, "avg_launch_ms": round(ms, 5)}
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(wl.name, f32),
+           "kernel": "k_interior<%s,false,*> (forward FDM+FEM interior)" % ("float" if f32 else "double"),
+           "bytes_per_launch": b, "avg_launch_ms": round(ms, 5)}
+    if f32:
+        b4 = interior_bytes(wl.n, wl.C, s, streams=4)
+        out["increment_form"] = {"bytes_per_launch": b4, "achieved": round(b4 / (ms * 1e-3) / 1e9, 1),
+                                 "frac": round(b4 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    return out
 
 
 def general_mesh_setup(wl, seed=0, amp=0.15):
@@ -245,27 +281,32 @@ def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
     for _ in range(warmup):
         solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
     torch.cuda.synchronize()
+    sweeps = 0
     t1 = time.perf_counter()
     for _ in range(steps):
         gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+        sweeps += state.forwards + 1
     torch.cuda.synchronize()
     t = time.perf_counter() - t1
     nfdm, nfem = solver.counts()
-    value = 2.0 * (nfdm + nfem) * wl.nt * steps / t / 1e9
+    value = sweeps * (nfdm + nfem) * wl.nt / t / 1e9
     s = 4 if f32 else 8
     bf, ba = general_fem_bytes(xyz, tet, wl, s)
     out = {"workload": f"{wl.name} grid, general FEM mesh", "tets": int(len(tet)), "fem_nodes": int(len(xyz)),
            "node_shift": "U(-0.15 h, 0.15 h) per axis inside the inner box", "dt_over_h": round(dt / wl.h, 4),
            "dtype": "f32" if f32 else "f64", "value": round(value, 2), "unit": "Gpt-updates/s",
-           "ms_per_step": round(t / steps * 1e3, 3), "host_setup_s": round(t_setup, 2),
-           "last_J": J, "last_gnorm": gn}
+           "ms_per_step": round(t / steps * 1e3, 3), "sweeps_per_step": round(sweeps / steps, 2),
+           "host_setup_s": round(t_setup, 2), "last_J": J, "last_gnorm": gn}
     for which, b, name in ((0, bf, "forward"), (1, ba, "adjoint")):
-        # each timing call overwrites the sweeps it needs: a CG step before
-        # the warm-up launches and another before the timed ones
-        solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
-        hyb.hyb_time_fem(solver.ctx, which, 5)
-        solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
-        ms = hyb.hyb_time_fem(solver.ctx, which, 50)
+        # each timing call overwrites the sweeps it needs: a forward sweep
+        # (and for the adjoint rows an adjoint sweep) before the warm-up
+        # launches and again before the timed ones
+        for reps in (5, 50):
+            obs = solver.forward(sig, wl.nt, dt, omega=wl.omega)
+            if which == 1:
+                solver.adjoint(obs - data, mode=0)
+            del obs
+            ms = hyb.hyb_time_fem(solver.ctx, which, reps)
         ach = b / (ms * 1e-3) / 1e9
         out[f"roofline_{name}"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
                                    "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
@@ -317,8 +358,10 @@ def model_forms(wl_name, steps, warmup, seed=0):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         te = 0.0
+        sweeps = 0
         for _ in range(steps):
             gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+            sweeps += state.forwards + 1
             if geps is not None:
                 torch.cuda.synchronize()
                 t1 = time.perf_counter()
@@ -328,8 +371,9 @@ def model_forms(wl_name, steps, warmup, seed=0):
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         nfdm, nfem = solver.counts()
-        res = {"value": round(2.0 * (nfdm + nfem) * wl.nt * steps / t / 1e9, 2), "unit": "Gpt-updates/s",
-               "ms_per_step": round(t / steps * 1e3, 3), "dt_over_h": round(dt / wl.h, 4), "dtype": "f64",
+        res = {"value": round(sweeps * (nfdm + nfem) * wl.nt / t / 1e9, 2),
+               "unit": "Gpt-updates/s", "ms_per_step": round(t / steps * 1e3, 3),
+               "sweeps_per_step": round(sweeps / steps, 2), "dt_over_h": round(dt / wl.h, 4), "dtype": "f64",
                "last_J": J, "last_gnorm": gn}
         if geps is not None:
             res["eps_gradient_ms"] = round(te / steps * 1e3, 3)
@@ -504,6 +548,127 @@ def study_scale512(seed=0):
     return out
 
 
+def leg_tiny40(seed=0):
+    """The 40^3 correctness workload (FEM 16^3, 300 steps, two 3^3 inclusions
+    of sigma = 2, noise-free data from the same grid): time of one forward +
+    adjoint + gradient at sigma = 0 and of 3 CG iterations (FP64), and the
+    errors of trace, gradient and J against the oracle.  Launch-bound: the
+    roofline does not apply at this size."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1509_01399_amd import hyb, synth
+    wl = synth.WORKLOADS["tiny40"]
+    sig_true = synth.sigma_for(wl, seed)
+    dt = synth.dt_rule(wl.h, sig_true.max())
+    g = oracle.Geometry(wl.n, fem_o=wl.o, fem_c=wl.C)
+    data_h = oracle.forward(g, sig_true.ravel(), wl.nt, dt, omega=wl.omega)
+    gref, Jref, oref = oracle.gradient(g, np.zeros(wl.C ** 3), wl.nt, dt, data_h, omega=wl.omega, want_obs=True)
+    s = hyb.Solver(wl.n, C=wl.C)
+    data = torch.as_tensor(data_h, device="cuda")
+    s0 = torch.zeros((wl.C,) * 3, dtype=torch.float64, device="cuda")
+    for _ in range(2):  # warm, then timed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obs = s.forward(s0, wl.nt, dt, omega=wl.omega)
+        s.adjoint(obs - data, mode=0)
+        grad, J = s.gradient()
+        t_grad = time.perf_counter() - t0
+    sig = torch.zeros_like(s0)
+    st = hyb.hyb_cg_state()
+    sweeps = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        s.cg_step(data, sig, wl.nt, dt, st, omega=wl.omega)
+        sweeps += st.forwards + 1
+    torch.cuda.synchronize()
+    t_cg = time.perf_counter() - t0
+    nfdm, nfem = s.counts()
+    o, gr = obs.cpu().numpy(), grad.cpu().numpy().ravel()
+    s.close()
+    return {"workload": "tiny40: 40^3 cells, FEM 16^3, nt 300, dt 0.25 h, f64",
+            "forward_adjoint_gradient_ms": round(t_grad * 1e3, 3), "cg3_ms": round(t_cg * 1e3, 3),
+            "cg3_sweeps": sweeps, "cg3_value": round(sweeps * (nfdm + nfem) * wl.nt / t_cg / 1e9, 3),
+            "unit": "Gpt-updates/s",
+            "vs_oracle": {"trace_rel_l2": float(np.linalg.norm(o - oref) / np.linalg.norm(oref)),
+                          "gradient_rel_l2": float(np.linalg.norm(gr - gref) / np.linalg.norm(gref)),
+                          "J_rel": abs(J - Jref) / Jref}}
+
+
+def leg_diff384(seed=0):
+    """The differentiation workload's rate: 384^3 cells, FEM 128^3, 2000
+    steps, FP32 fields with sqrt(nt) FP32 checkpoints; forward through the
+    autograd Function and backward (adjoint with segment recompute, the
+    recompute counted as time, not as updates), and the interior roofline
+    at this size."""
+    import torch
+
+    from paper_1509_01399_amd import autograd, hyb, synth
+    wl = synth.WORKLOADS["diff384"]
+    sig0 = synth.sigma_for(wl, seed)
+    dt = synth.dt_rule(wl.h, sig0.max() + 0.05)
+    solver = hyb.Solver(wl.n, C=wl.C, f32=True, store_mode=1)
+    gen = torch.Generator(device="cuda").manual_seed(seed + 11)
+    w = torch.randn((wl.nt + 1, wl.n + 1, wl.n + 1), generator=gen, dtype=torch.float64, device="cuda")
+    ts = []
+    for _ in range(2):  # warm, then timed
+        sig = torch.as_tensor(sig0, dtype=torch.float64, device="cuda").requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obs = autograd.solve(sig, solver, wl.nt, dt, wl.omega)
+        (w * obs).sum().backward()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        del obs
+    nfdm, nfem = solver.counts()
+    rl = roofline(wl, dt, solver, True)
+    solver.close()
+    del w
+    torch.cuda.empty_cache()
+    return {"workload": "diff384: 384^3 cells, FEM 128^3, nt 2000, f32 fields, sqrt(nt) f32 checkpoints",
+            "value": round(2.0 * (nfdm + nfem) * wl.nt / ts[1] / 1e9, 2), "unit": "Gpt-updates/s",
+            "forward_backward_s": round(ts[1], 3), "dtype": "f32", "roofline": rl}
+
+
+def leg_scale512(seed=0):
+    """The precision workload's rate: 512^3 cells, FEM 160^3, 2500 steps, FP32
+    fields with BF16 checkpoint increments; data from a sweep at the true
+    conductivity plus 3% noise; one forward + adjoint + gradient at sigma = 0
+    timed (recompute counted as time), and the interior roofline."""
+    import torch
+
+    from paper_1509_01399_amd import hyb, synth
+    wl = synth.WORKLOADS["scale512"]
+    sig_true = synth.sigma_for(wl, seed)
+    dt = synth.dt_rule(wl.h, sig_true.max())
+    s = hyb.Solver(wl.n, C=wl.C, f32=True, store_mode=2)
+    st = torch.as_tensor(sig_true, dtype=torch.float64, device="cuda")
+    data = s.forward(st, wl.nt, dt, omega=wl.omega).clone()
+    gen = torch.Generator(device="cuda").manual_seed(seed + 21)
+    data += wl.noise * data.abs().max() * torch.randn(data.shape, generator=gen, dtype=torch.float64,
+                                                      device="cuda")
+    s0 = torch.zeros_like(st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs = s.forward(s0, wl.nt, dt, omega=wl.omega)
+    s.adjoint(obs - data, mode=0)
+    s.gradient()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    nfdm, nfem = s.counts()
+    fp = hyb.hyb_footprint(s.grid, s.mesh, 2, s.opts, wl.nt)
+    rl = roofline(wl, dt, s, True)
+    s.close()
+    del data, obs
+    torch.cuda.empty_cache()
+    return {"workload": "scale512: 512^3 cells, FEM 160^3, nt 2500, f32 fields, bf16 checkpoint increments",
+            "value": round(2.0 * (nfdm + nfem) * wl.nt / t / 1e9, 2), "unit": "Gpt-updates/s",
+            "forward_adjoint_gradient_s": round(t, 3), "footprint_gb": round(fp / 1e9, 1), "dtype": "f32",
+            "roofline": rl}
+
+
 def probe(kind, wl_name, f32, reps):
     """Single-kernel runs for the counter passes (rocprofv3 --pmc)."""
     import torch
@@ -541,6 +706,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--no-general", action="store_true", help="skip the general-mesh leg")
+    ap.add_argument("--no-legs", action="store_true", help="skip the tiny40, diff384 and scale512 legs")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the Model Problem 1 and wave-speed legs")
     ap.add_argument("--probe", choices=["interior", "copy"])
@@ -579,11 +745,10 @@ def main():
     nfdm, nfem = solver.counts()
     print(f"[bench] {wl.name}: n={wl.n} C={wl.C} nt={wl.nt} dt={dt:.6g} fdm={nfdm} fem={nfem}",
           file=sys.stderr, flush=True)
-    t, log, _ = run_cg(wl, dt, solver, data, args.steps, args.warmup)
-    upd = 2.0 * (nfdm + nfem) * wl.nt * args.steps
-    value = upd / t / 1e9
-    print(f"[bench] f64: {t / args.steps * 1e3:.1f} ms/CG-iteration, {value:.1f} Gupd/s; "
-          f"|g| {log[-1][0]:.3e} J {log[-1][1]:.4e}", file=sys.stderr, flush=True)
+    t, log, _, sweeps, trials = run_cg(wl, dt, solver, data, args.steps, args.warmup)
+    value = sweeps * (nfdm + nfem) * wl.nt / t / 1e9
+    print(f"[bench] f64: {t / args.steps * 1e3:.1f} ms/CG-iteration, {sweeps} sweeps, trials {trials}, "
+          f"{value:.1f} Gupd/s; |g| {log[-1][0]:.3e} J {log[-1][1]:.4e}", file=sys.stderr, flush=True)
     rl = roofline(wl, dt, solver, False)
     print(f"[bench] roofline f64 interior: {rl}", file=sys.stderr, flush=True)
     solver.close()
@@ -593,16 +758,23 @@ def main():
     f32 = None
     if not args.no_f32:
         wl2, dt2, s2, d2, _ = setup(args.workload, True)
-        t2, log2, _ = run_cg(wl2, dt2, s2, d2, args.steps, args.warmup)
-        v2 = upd / t2 / 1e9
+        t2, log2, _, sw2, tr2 = run_cg(wl2, dt2, s2, d2, args.steps, args.warmup)
+        v2 = sw2 * (nfdm + nfem) * wl.nt / t2 / 1e9
         rl2 = roofline(wl2, dt2, s2, True)
-        print(f"[bench] f32: {t2 / args.steps * 1e3:.1f} ms/CG-iteration, {v2:.1f} Gupd/s; {rl2}",
-              file=sys.stderr, flush=True)
-        f32 = {"value": round(v2, 2), "ms_per_step": round(t2 / args.steps * 1e3, 3), "dtype": "f32",
-               "roofline": rl2}
+        print(f"[bench] f32: {t2 / args.steps * 1e3:.1f} ms/CG-iteration, {sw2} sweeps, trials {tr2}, "
+              f"{v2:.1f} Gupd/s; {rl2}", file=sys.stderr, flush=True)
+        f32 = {"value": round(v2, 2), "ms_per_step": round(t2 / args.steps * 1e3, 3),
+               "sweeps_per_step": round(sw2 / args.steps, 2), "ms_per_sweep": round(t2 / sw2 * 1e3, 3),
+               "dtype": "f32", "roofline": rl2}
         s2.close()
         del d2
         torch.cuda.empty_cache()
+
+    legs = {}
+    if not args.no_legs:
+        for name, fn in (("tiny40", leg_tiny40), ("diff384", leg_diff384), ("scale512", leg_scale512)):
+            legs[name] = fn()
+            print(f"[bench] {name}: {legs[name]}", file=sys.stderr, flush=True)
 
     gen = None
     if not args.no_general:
@@ -627,13 +799,16 @@ def main():
     line = {
         "metric": "forward+adjoint Gpt-updates/s", "value": round(value, 2), "unit": "Gpt-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(t / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "ms_per_step": round(t / args.steps * 1e3, 3), "sweeps_per_step": round(sweeps / args.steps, 2),
+        "ms_per_sweep": round(t / sweeps * 1e3, 3), "trials": trials,
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": wl.name, "grid_cells": wl.n, "fem_cells": wl.C, "nt": wl.nt,
                    "dt_over_h": round(dt / wl.h, 4), "omega": wl.omega, "noise": wl.noise,
-                   "step": "one CG iteration (forward + adjoint + gradient + update)",
+                   "step": "one CG iteration (adjoint + gradient + direction + one forward per trial step)",
                    "parallelism": "single GPU"},
-        "roofline": rl, "cpu_baseline": cpu, "f32_form": f32, "general_mesh": gen, "model_forms": forms,
+        "roofline": rl, "cpu_baseline": cpu, "f32_form": f32, "legs": legs, "general_mesh": gen,
+        "model_forms": forms,
         "p50_ms": srv["batched"]["p50_ms"] if srv else None,
         "p99_ms": srv["batched"]["p99_ms"] if srv else None,
         "serving": srv,

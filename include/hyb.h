@@ -111,7 +111,11 @@ typedef struct {
                              0: FEM-box history of every level;
                              1: sqrt(nt) checkpoints of the full state (field
                                 precision) with segment recompute;
-                             2: as 1, checkpoint increments in BF16             */
+                             2: as 1, checkpoint increments in BF16;
+                             3: as 1, checkpoint increments in 16-bit integers
+                                with one FP32 scale per 64 values (kept to
+                                1/65534 of each group's largest value).
+                             2 and 3 need field_f32 = 1 (HYB_E_UNSUPPORTED) */
     double gamma;         /* Tikhonov regularisation parameter (eq. (functional))*/
     double alpha_rel;     /* CG: first trial step alpha_rel / max|d^m|          */
     void *hip_stream;     /* hipStream_t for all work; NULL = default stream      */
@@ -136,7 +140,9 @@ typedef struct {
     double gnorm2_prev;   /* |g^{m-1}|^2_{L2} (host copy, informational)         */
     /* outputs of the last hyb_cg_step */
     double beta;          /* beta^m as computed (0 when m = 0)                   */
-    double dmax;          /* max|d^m| of the direction searched                  */
+    double dmax;          /* max|d^m| of the direction searched (also read: the
+                             next call starts its step search from twice
+                             alpha * dmax)                                       */
     double alpha;         /* step taken (0 when no trial lowered J)              */
     double J_next;        /* J at the returned sigma                             */
     int32_t trials;       /* trial points evaluated, one forward sweep each      */
@@ -290,7 +296,10 @@ hyb_status hyb_gradient_noalloc(hyb_ctx *ctx, double *grad_dev, double *J_dev);
  *      held by a bound: sigma = 0 moving down, sigma = 4 moving up) is >= 0,
  *      d^m = -g^m (restart);
  *   3. step length (the paper refers to another work for it): trial steps
- *      alpha_t = 2^-t alpha_rel / max|d^m|, t = 0 .. opts.cg_max_trials - 1;
+ *      alpha_t = 2^-t rho / max|d^m|, t = 0 .. opts.cg_max_trials - 1, with
+ *      the first relative step (largest change of sigma) rho = alpha_rel at
+ *      m = 0 and min(alpha_rel, 2 state->alpha state->dmax), twice the
+ *      previous call's accepted one, afterwards;
  *      each trial point clip(sigma^m + alpha_t d^m, 0, 4) (free cells,
  *      eq. (admpar)) costs one forward sweep; the first with J < J^m becomes
  *      sigma^{m+1}.  When none lowers J, sigma stays, state->stalled = 1 and

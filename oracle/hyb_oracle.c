@@ -1125,8 +1125,11 @@ static int functional_at(const orc_geom *g, const orc_mesh *m, const double *sig
  *   bound: sigma_c = 0 with d_c < 0, or sigma_c = 4 with d_c > 0) is >= 0,
  *   the projected direction does not descend and it restarts as d^m = -g^m;
  *   step length (the paper refers to another work for it; reading R9):
- *   trial steps alpha_t = 2^{-t} alpha_rel / max|d^m| for t = 0, 1, ...,
- *   max_trials - 1; the first trial whose projected point
+ *   trial steps alpha_t = 2^{-t} rho^m / max|d^m| for t = 0, 1, ...,
+ *   max_trials - 1, where the first relative step (largest change of sigma)
+ *   is rho^0 = alpha_rel and rho^m = min(alpha_rel, 2 alpha^{m-1}
+ *   max|d^{m-1}|), twice the previous accepted one; the first trial whose
+ *   projected point
  *   sigma_t = clip(sigma^m + alpha_t d^m, 0, 4) on eligible cells (a in
  *   [1, 5], eq. (admpar)) has J(sigma_t) < J^m becomes sigma^{m+1}.  When
  *   no trial lowers J, sigma stays and the iteration ends the run (the norms
@@ -1147,7 +1150,7 @@ int orc_cg_x(const orc_geom *g, const orc_mesh *msh, double *sigma, const double
     double *gr = (double *)calloc((size_t)nc, sizeof(double));
     double *d = (double *)calloc((size_t)nc, sizeof(double));
     double *trial = (double *)calloc((size_t)nc, sizeof(double));
-    double gn2_prev = 0.0;
+    double gn2_prev = 0.0, rho_prev = 0.0;
     int m = 0, rc = 0;
     if (!gr || !d || !trial) rc = -2;
     for (; m < iters && rc == 0; ++m) {
@@ -1174,9 +1177,10 @@ int orc_cg_x(const orc_geom *g, const orc_mesh *msh, double *sigma, const double
         for (int64_t c = 0; c < nc; ++c)
             if (fabs(d[c]) > dmax) dmax = fabs(d[c]);
         double alpha = 0.0, Jnext = J;
+        double rho = m == 0 ? alpha_rel : fmin(alpha_rel, 2.0 * rho_prev);
         int t = 0, taken = 0;
         while (dmax > 0.0 && t < max_trials && !taken) {
-            double at = ldexp(alpha_rel / dmax, -t);
+            double at = ldexp(rho / dmax, -t);
             for (int64_t c = 0; c < nc; ++c) {
                 if (!P.eligible[c]) { trial[c] = sigma[c]; continue; }
                 double s = sigma[c] + at * d[c];
@@ -1196,6 +1200,7 @@ int orc_cg_x(const orc_geom *g, const orc_mesh *msh, double *sigma, const double
             }
         }
         gn2_prev = gn2;
+        rho_prev = alpha * dmax;
         if (log) {
             double *r = log + ORC_CG_LOGW * m;
             r[0] = J; r[1] = sqrt(gn2); r[2] = beta; r[3] = alpha;

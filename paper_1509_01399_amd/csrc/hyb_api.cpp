@@ -543,15 +543,26 @@ T *hist_ptr(hyb_ctx *c, int L)
     return (T *)c->hist + (long long)(L - lo) * c->g.hlevel;
 }
 
+// Bytes of the 16-bit block-scaled form of n FP32 values: int16 values and
+// one FP32 scale per 64, each part rounded up to 256 bytes.
+size_t q16_values_bytes(size_t n) { return (2 * n + 255) / 256 * 256; }
+size_t q16_bytes(size_t n) { return q16_values_bytes(n) + (4 * ((n + 63) / 64) + 255) / 256 * 256; }
+
+// One checkpoint: u^L in field precision plus the second level (mode 1:
+// u^{L-1}, or the FP32 increment d^L, in field precision; mode 2: d^L in
+// BF16; mode 3: d^L in the 16-bit block-scaled form), grid then FEM part.
 size_t ckpt_slot_bytes(const Geo &g, size_t esz, int mode)
 {
     const size_t fb = field_bytes(g, esz), vb = fem_bytes(g, esz);
-    return mode == 2 ? (fb + vb) + (fb + vb) / 2 : 2 * (fb + vb);
+    if (mode == 2) return (fb + vb) + (fb + vb) / 2;
+    if (mode == 3) return (fb + vb) + q16_bytes(fb / 4) + q16_bytes(vb / 4);
+    return 2 * (fb + vb);
 }
 
 // Save the state at level L (u^L in buffer ib; u^{L-1} in ia, or in FP32 the
 // increment d^L in slot L & 1) as checkpoint number q.  Store mode 1 copies
-// both parts in field precision; mode 2 (FP32 only) keeps d^L in BF16.
+// both parts in field precision; mode 2 (FP32 only) keeps d^L in BF16, mode 3
+// (FP32 only) in the 16-bit block-scaled form.
 template <typename T>
 hyb_status save_ckpt(hyb_ctx *c, int q, int L, int ia, int ib)
 {
@@ -566,6 +577,12 @@ hyb_status save_ckpt(hyb_ctx *c, int q, int L, int ia, int ib)
     if (c->store_mode == 1) {
         HIPCHK(c, hipMemcpyAsync(base + fb + vb, u1, fb, hipMemcpyDeviceToDevice, st));
         if (vb) HIPCHK(c, hipMemcpyAsync(base + 2 * fb + vb, v1, vb, hipMemcpyDeviceToDevice, st));
+    } else if (c->store_mode == 3) {
+        char *p = base + fb + vb;
+        const size_t nf = fb / 4, nv = vb / 4;
+        launch_pack_q16(u1, (int16_t *)p, (float *)(p + q16_values_bytes(nf)), (long long)nf, st);
+        p += q16_bytes(nf);
+        if (vb) launch_pack_q16(v1, (int16_t *)p, (float *)(p + q16_values_bytes(nv)), (long long)nv, st);
     } else {
         uint16_t *half = (uint16_t *)(base + fb + vb);
         launch_pack_bf16(u1, half, (long long)(fb / sizeof(float)), st);
@@ -591,6 +608,13 @@ hyb_status load_ckpt(hyb_ctx *c, int q)
     if (c->store_mode == 1) {
         HIPCHK(c, hipMemcpyAsync(u1, base + fb + vb, fb, hipMemcpyDeviceToDevice, st));
         if (vb) HIPCHK(c, hipMemcpyAsync(v1, base + 2 * fb + vb, vb, hipMemcpyDeviceToDevice, st));
+    } else if (c->store_mode == 3) {
+        const char *p = base + fb + vb;
+        const size_t nf = fb / 4, nv = vb / 4;
+        launch_unpack_q16((const int16_t *)p, (const float *)(p + q16_values_bytes(nf)), u1, (long long)nf, st);
+        p += q16_bytes(nf);
+        if (vb)
+            launch_unpack_q16((const int16_t *)p, (const float *)(p + q16_values_bytes(nv)), v1, (long long)nv, st);
     } else {
         const uint16_t *half = (const uint16_t *)(base + fb + vb);
         launch_unpack_bf16(half, u1, (long long)(fb / sizeof(float)), st);
@@ -934,14 +958,14 @@ hyb_status hyb_create(const hyb_fd_grid *grid, const hyb_fem_mesh *fem, const hy
     c->h = grid->h;
     for (int f = 0; f < 6; ++f) c->bc[f] = grid->face[f];
     if (opts) {
-        if (opts->field_f32 < 0 || opts->field_f32 > 1 || opts->store_mode < 0 || opts->store_mode > 2 ||
+        if (opts->field_f32 < 0 || opts->field_f32 > 1 || opts->store_mode < 0 || opts->store_mode > 3 ||
             !std::isfinite(opts->gamma) || opts->gamma < 0 || !(opts->alpha_rel > 0)) {
             delete c;
             return fail(nullptr, HYB_E_ARG, "opts: invalid options");
         }
-        if (opts->store_mode == 2 && !opts->field_f32) {
+        if (opts->store_mode >= 2 && !opts->field_f32) {
             delete c;
-            return fail(nullptr, HYB_E_UNSUPPORTED, "opts: BF16 checkpoints need FP32 wavefields");
+            return fail(nullptr, HYB_E_UNSUPPORTED, "opts: 16-bit checkpoint increments need FP32 wavefields");
         }
         c->f32 = opts->field_f32;
         c->store_mode = opts->store_mode;
@@ -1427,15 +1451,17 @@ hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_
     s = read_scal(c, hs);
     if (s) return s;
     const double Jm = hs[S_JMIS] + hs[S_JREG], gn2 = hs[S_GN2], dmax = hs[S_DMAX];
-    state->beta = hs[S_BETA];
-    state->dmax = dmax;
-    state->restart = hs[S_RESTART] != 0.0;
-    // 3. trial steps 2^-t alpha_rel / max|d| until J falls below J^m
+    const double beta = hs[S_BETA];
+    const bool restart = hs[S_RESTART] != 0.0;
+    // 3. trial steps 2^-t rho / max|d| until J falls below J^m; rho is the
+    // first relative step (largest change of sigma): alpha_rel, and after the
+    // first iteration twice the previous accepted one, at most alpha_rel
+    const double rho = first ? c->alpha_rel : std::fmin(c->alpha_rel, 2.0 * (state->alpha * state->dmax));
     bool taken = false;
     int t = 0;
     double alpha = 0.0, Jn = Jm;
     while (dmax > 0.0 && t < c->max_trials && !taken) {
-        launch_cg_trial(p, c->dir, sigma, c->trial, c->alpha_rel, t, c->gamma, c->partials, c->scal, st);
+        launch_cg_trial(p, c->dir, sigma, c->trial, rho, t, c->gamma, c->partials, c->scal, st);
         HIPCHK(c, hipGetLastError());
         s = cg_forward(c, c->trial, src, nt, dt, data, S_JMIST);
         if (s) return s;
@@ -1461,6 +1487,9 @@ hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_
     }
     state->iter += 1;
     state->gnorm2_prev = gn2;
+    state->beta = beta;
+    state->dmax = dmax;
+    state->restart = restart ? 1 : 0;
     state->alpha = alpha;
     state->J_next = Jn;
     state->trials = t;

@@ -132,10 +132,15 @@ template <typename T>
 void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, double *u, double *v,
                          hipStream_t st);
 
-// BF16 checkpoint increments: half[i] = bf16(a[i] - b[i]) (round to nearest
-// even); unpack: b[i] = a[i] - float(half[i]).  a, b are FP32 arrays.
+// BF16 checkpoint increments: half[i] = bf16(a[i]) (round to nearest even);
+// unpack: b[i] = float(half[i]).  a, b are FP32 arrays.
 void launch_pack_bf16(const void *a, uint16_t *half, long long n, hipStream_t st);
 void launch_unpack_bf16(const uint16_t *half, void *b, long long n, hipStream_t st);
+// 16-bit block-scaled checkpoint increments: per group of 64 values
+// scale[g] = max|a| / 32767 and q[i] = round(a[i] / scale); unpack b[i] =
+// q[i] * scale[i / 64].  a, b are FP32 arrays of n values.
+void launch_pack_q16(const void *a, int16_t *q, float *scale, long long n, hipStream_t st);
+void launch_unpack_q16(const int16_t *q, const float *scale, void *b, long long n, hipStream_t st);
 
 // J_misfit = 1/2 sum_{k=1..nt} dt sum_i w_i res^2 -> scal[slot]
 void launch_misfit(const Geo &g, const double *res, int nt, double dt, double h, double *partials,

@@ -1418,6 +1418,45 @@ void launch_unpack_bf16(const uint16_t *half, void *b, long long n, hipStream_t 
     hipLaunchKernelGGL(k_unpack_bf16, dim3(4096), dim3(BLOCK), 0, st, half, (float *)b, n);
 }
 
+// 16-bit block-scaled checkpoint increments: each group of 64 consecutive
+// values (one wavefront) shares the scale m / 32767, m the group's largest
+// magnitude, and stores round(a / scale) as int16, so every value is kept to
+// m / 65534 -- 128 times finer than BF16's relative 2^-9 for the group's
+// large values, which set the state's perturbation.
+__global__ __launch_bounds__(BLOCK) void k_pack_q16(const float *a, int16_t *q, float *scale, long long n)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const long long ng = (n + 63) / 64;
+    const long long w0 = ((long long)blockIdx.x * BLOCK + threadIdx.x) >> 6, nw = (long long)gridDim.x * BLOCK / 64;
+    for (long long grp = w0; grp < ng; grp += nw) {
+        const long long i = grp * 64 + lane;
+        const float v = i < n ? a[i] : 0.0f;
+        float m = fabsf(v);
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        const float sc = m / 32767.0f;
+        int qv = 0;
+        if (sc > 0.0f) qv = max(-32767, min(32767, (int)rintf(v / sc)));
+        if (i < n) q[i] = (int16_t)qv;
+        if (lane == 0) scale[grp] = sc;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_unpack_q16(const int16_t *q, const float *scale, float *b, long long n)
+{
+    for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n; i += (long long)gridDim.x * BLOCK)
+        b[i] = (float)q[i] * scale[i >> 6];
+}
+
+void launch_pack_q16(const void *a, int16_t *q, float *scale, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_q16, dim3(4096), dim3(BLOCK), 0, st, (const float *)a, q, scale, n);
+}
+
+void launch_unpack_q16(const int16_t *q, const float *scale, void *b, long long n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unpack_q16, dim3(4096), dim3(BLOCK), 0, st, q, scale, (float *)b, n);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_misfit(Geo g, const double *res, int nt, double wscale,
                                                   double *part)
 {

@@ -175,7 +175,7 @@ def test_general_checkpoint_modes(env):
     o, h, xyz, tet, st = _case(n, C, seed=13)
     dt, nt, om = 0.18 * h, 150, 30.0
     grads = {}
-    for f32, mode in ((False, 0), (False, 1), (True, 0), (True, 1), (True, 2)):
+    for f32, mode in ((False, 0), (False, 1), (True, 0), (True, 1), (True, 2), (True, 3)):
         s = Solver(n, C=C, o=o, mesh=(xyz, tet), f32=f32, store_mode=mode)
         obs = s.forward(_t(torch, st), nt, dt, omega=om)
         s.adjoint(0.3 * obs, mode=0)
@@ -186,6 +186,7 @@ def test_general_checkpoint_modes(env):
     from tests.fpcheck import err32
     assert err32(grads[(True, 0)], grads[(False, 0)]) <= 1e-4
     assert rel(grads[(True, 2)], grads[(True, 0)]) <= 2e-2
+    assert err32(grads[(True, 3)], grads[(True, 0)]) <= 1e-4
 
 
 def test_general_refusals(env):

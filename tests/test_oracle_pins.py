@@ -386,11 +386,13 @@ def _rebuild_cg(orc, g, C, h, dt, nt, om, data, s0, iters, max_trials=8, alpha_r
     """Algorithm 3 (Sec. 8, Step 2) rebuilt from independent gradient
     evaluations: beta^m = |g^m|^2/|g^{m-1}|^2, d^m = -g^m + beta^m d^{m-1},
     restart to -g^m when the slope over the cells free to move is >= 0,
-    trial steps 2^{-t} alpha_rel / max|d^m| until the projected point lowers
-    J.  Returns the iterates and the per-iteration log."""
+    trial steps 2^{-t} rho / max|d^m| until the projected point lowers J,
+    rho = alpha_rel at m = 0 and min(alpha_rel, twice the previous accepted
+    largest change of sigma) afterwards.  Returns the iterates and the
+    per-iteration log."""
     el = _eligible(C)
     h3 = h ** 3
-    sig, d, gn2p = s0.copy(), np.zeros(C ** 3), None
+    sig, d, gn2p, rho_prev = s0.copy(), np.zeros(C ** 3), None, 0.0
     sigs, rows = [], []
     for m in range(iters):
         gm, Jm = orc.gradient(g, sig, nt, dt, data, omega=om)
@@ -402,15 +404,17 @@ def _rebuild_cg(orc, g, C, h, dt, nt, om, data, s0, iters, max_trials=8, alpha_r
         if restart:
             d = np.where(el, -gm, 0.0)
         dmax = np.max(np.abs(d))
+        rho = alpha_rel if m == 0 else min(alpha_rel, 2.0 * rho_prev)
         taken, t, alpha, Jn = False, 0, 0.0, Jm
         while dmax > 0 and t < max_trials and not taken:
-            a = alpha_rel / dmax * 2.0 ** -t
+            a = rho / dmax * 2.0 ** -t
             trial = np.where(el, np.clip(sig + a * d, 0.0, 4.0), sig)
             Jt = _functional(orc, g, trial, nt, dt, om, data, el, h)
             t += 1
             if Jt < Jm:
                 taken, alpha, Jn, sig = True, a, Jt, trial
         gn2p = gn2
+        rho_prev = alpha * dmax
         rows.append([Jm, np.sqrt(gn2), beta, alpha, dmax, t, float(restart), Jn])
         sigs.append(sig.copy())
         if not taken:
