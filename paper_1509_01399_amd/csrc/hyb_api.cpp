@@ -521,6 +521,7 @@ Step<T> make_step(const hyb_ctx *c)
     s.g = c->g;
     s.acube = (const T *)c->acube;
     s.c2 = (T)((c->dt / c->h) * (c->dt / c->h));
+    s.ic2 = (T)1 / s.c2;
     s.w2 = 1.0;
     s.minv = c->vm ? (const T *)c->minv : nullptr;
     s.r = (T)((c->h - c->dt) / (c->h + c->dt));
@@ -641,6 +642,7 @@ Step<T> fwd_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, double *obs)
     // rows do not contain dt^2 and are unchanged
     s.w2 = (c->sweep_taylor && k == 0) ? 0.5 : 1.0;
     s.c2 = (T)(s.w2 * (c->dt / c->h) * (c->dt / c->h));
+    s.ic2 = (T)1 / s.c2;
     const double fluxscale = s.w2 * 2.0 * c->dt * c->dt / c->h;
     if (c->src.kind == 0) {
         s.flux = nullptr;
@@ -680,6 +682,7 @@ Step<T> adj_step_args(hyb_ctx *c, int k, int ia, int ib, int ic, const double *r
     // dt^2 weight 1/2 enters the transposed rows and the gradient term
     s.w2 = (c->sweep_taylor && k == 0) ? 0.5 : 1.0;
     s.c2 = (T)(s.w2 * (c->dt / c->h) * (c->dt / c->h));
+    s.ic2 = (T)1 / s.c2;
     s.res = (mode == 0 && k == 0) ? nullptr : res + (long long)k * nface;
     s.hist = hist_ptr<T>(c, k);
     if (c->vm && c->store_mode == 0 && c->g.has_fem) {
@@ -1582,12 +1585,14 @@ hyb_status hyb_get_wavefield(hyb_ctx *c, int32_t which, double *u, double *v)
     const int q = which == 0 ? c->last_u : c->last_p;
     const void *Fq = which == 1 ? c->F[q] : nullptr;  // true boundary multipliers
     double *vs = c->gen ? nullptr : v;  // a general mesh exports in the caller's node numbering
+    // x faces never change condition during a sweep (only z+ carries the source)
+    const int types = face_types(c, 0);
     if (c->f32)
         launch_export_level<float>(c->g, (const float *)A[q], (const float *)B[q], (const float *)Fq, u, vs,
-                                   c->stream);
+                                   c->stream, types);
     else
         launch_export_level<double>(c->g, (const double *)A[q], (const double *)B[q], (const double *)Fq, u,
-                                    vs, c->stream);
+                                    vs, c->stream, types);
     if (c->gen && v) {
         if (c->f32) launch_gen_export<float>(c->gd, (const float *)B[q], v, c->stream);
         else launch_gen_export<double>(c->gd, (const double *)B[q], v, c->stream);

@@ -65,6 +65,7 @@ struct Step {
     T *Dc, *VDc;
     const T *acube;          // conductivity a per FEM cube [C^3]
     T c2;                    // (dt/h)^2 (times w2)
+    T ic2;                   // 1 / c2 (adjoint x-face proxies in the interior tile)
     double w2;               // weight of dt^2 in the leapfrog rows of this step: 1, or
                              // 1/2 in the first step of the Taylor start (Model
                              // Problem 1); the adjoint's gradient term of that step
@@ -128,9 +129,11 @@ void launch_hist_level(const Geo &g, const T *V, T *hist, hipStream_t st);
 template <typename T>
 void launch_record_face(const Geo &g, const T *U, double *obs_row, hipStream_t st);
 
+// types: the face conditions of the level's adjoint rows (which multipliers
+// of absorbing x faces the grid array holds); unused when F is null
 template <typename T>
 void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, double *u, double *v,
-                         hipStream_t st);
+                         hipStream_t st, int types = 0);
 
 // BF16 checkpoint increments: half[i] = bf16(a[i]) (round to nearest even);
 // unpack: b[i] = float(half[i]).  a, b are FP32 arrays.

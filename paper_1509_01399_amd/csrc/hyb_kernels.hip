@@ -119,6 +119,70 @@ __device__ __forceinline__ void face_node(const Geo &g, long long t, int &x, int
     z = d == 2 ? (hi ? g.nz - 1 : 0) : q;
 }
 
+// Absorbing x faces: their adjoint rows away from the face's edges (y in
+// [2, ny-3], z in [2, nz-3]) run in the adjoint interior launch (fdm_tile),
+// whose x = 0 lane and x = nx-2 lane already hold the inward neighbour's
+// multiplier; the face launch covers the ring next to the edges (it reads
+// the edge multipliers of the same level) and every row of a reflecting x
+// face.  A face qualifies when it is absorbing in the rows of steps k and
+// k+1 (types1, types2), the two rows its level-k multiplier enters, and, for
+// x = nx-1, when that column lies inside the last tile rather than in its
+// halo (a halo column would need a store instruction of its own per row:
+// measured +2 us per FP64 adjoint step at 257^3, more than the face launch
+// saves on that face).
+__host__ __device__ __forceinline__ long long x_fast_rows(const Geo &g)
+{
+    return (g.ny >= 5 && g.nz >= 5) ? (long long)(g.ny - 4) * (g.nz - 4) : 0;
+}
+__host__ __device__ __forceinline__ bool x_face_in_tile(const Geo &g, int types1, int types2, int f)
+{
+    return x_fast_rows(g) > 0 && ((types1 >> (2 * f)) & 3) == F_ABC && ((types2 >> (2 * f)) & 3) == F_ABC &&
+           (f == 0 || (g.nx - 2) % TX_FDM != TX_FDM - 1);
+}
+// face-launch rows of x face f
+__host__ __device__ __forceinline__ long long x_face_launch_rows(const Geo &g, int types1, int types2, int f)
+{
+    const long long A01 = (long long)(g.ny - 2) * (g.nz - 2);
+    return x_face_in_tile(g, types1, types2, f) ? A01 - x_fast_rows(g) : A01;
+}
+__host__ __device__ __forceinline__ long long adj_face_rows(const Geo &g, int types1, int types2)
+{
+    const long long A01 = (long long)(g.ny - 2) * (g.nz - 2);
+    return g.n_fi - 2 * A01 + x_face_launch_rows(g, types1, types2, 0) + x_face_launch_rows(g, types1, types2, 1);
+}
+
+// Face-interior node t of the adjoint face launch: the z and y faces as in
+// face_node, then per x face all its rows, or only its ring next to the
+// edges (the rows z = 1 and z = nz-2, then the columns y = 1 and y = ny-2)
+// when its other rows run in the interior launch.
+__device__ __forceinline__ void adj_face_node(const Geo &g, int types1, int types2, long long t, int &x, int &y,
+                                              int &z, int &f)
+{
+    const long long A01 = (long long)(g.ny - 2) * (g.nz - 2);
+    const long long zy = g.n_fi - 2 * A01;
+    if (t < zy) {
+        face_node(g, t, x, y, z, f);
+        return;
+    }
+    t -= zy;
+    const long long c0 = x_face_launch_rows(g, types1, types2, 0);
+    f = t < c0 ? 0 : 1;
+    const long long r = f ? t - c0 : t;
+    x = f ? g.nx - 1 : 0;
+    const long long a = g.ny - 2;
+    if (!x_face_in_tile(g, types1, types2, f)) {
+        y = 1 + (int)(r % a);
+        z = 1 + (int)(r / a);
+    } else if (r < 2 * a) {
+        y = 1 + (int)(r % a);
+        z = r < a ? 1 : g.nz - 2;
+    } else {
+        const long long r2 = r - 2 * a, b = g.nz - 4;
+        y = r2 < b ? 1 : g.ny - 2;
+        z = 2 + (int)(r2 % b);
+    }
+}
+
 __device__ __forceinline__ void edge_corner_node(const Geo &g, long long t, int &x, int &y, int &z)
 {
     const long long ex = g.nx - 2, ey = g.ny - 2, ez = g.nz - 2;
@@ -484,9 +548,9 @@ __device__ __forceinline__ void bnd_adj_face_body(const Step<T> &s, int bid)
 {
     const Geo &g = s.g;
     const long long t = (long long)bid * BLOCK + threadIdx.x;
-    if (t >= g.n_fi) return;
+    if (t >= adj_face_rows(g, s.types1, s.types2)) return;
     int x, y, z, f;
-    face_node(g, t, x, y, z, f);
+    adj_face_node(g, s.types1, s.types2, t, x, y, z, f);
     const int d = f >> 1, dir = (f & 1) ? -1 : 1;
     const long long sd = d == 0 ? 1 : (d == 1 ? g.px : g.plane);
     const long long id = gidx(g, x, y, z), in = id + dir * sd;
@@ -515,7 +579,7 @@ __device__ __forceinline__ void bnd_adj_face_body(const Step<T> &s, int bid)
     const T w1 = ftype(s.types1, f) == F_ABC ? (T)1 : (T)2 * s.c2;
     const T w0 = (s.level_rows && ftype(s.types0, f) == F_ABC) ? -s.r : (T)0;
     s.Fc[cb] = mu;
-    s.Pw[id] = (w1 * fb + w0 * mu) / s.c2;  // what the interior stencil reads
+    s.Pw[id] = (w1 * fb + w0 * mu) * s.ic2;  // what the interior stencil reads
 }
 
 template <typename T>
@@ -722,6 +786,25 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
 #pragma unroll
     for (int r = 0; r < R; ++r)
         if (xin && y + r >= g.hlo[1] && y + r <= g.hhi[1]) hmask |= 1u << r;
+    // Absorbing x faces of the adjoint, away from the face's edges (rows y
+    // in [2, ny-3] of planes z in [2, nz-3]; the face launch takes the
+    // ring next to the edges, which reads the edge multipliers of the same
+    // level, the rows of reflecting x faces and those of x = nx-1 when that
+    // column is the last tile's halo, see x_face_in_tile): the face node's
+    // multiplier is kept in the grid array itself, so the staged plane holds
+    // mu^{k+1} of the face node beside its inward neighbour's.  The face
+    // node's lane writes mu^k = r mu^{k+1} + c2 mu^{k+1}_in with the row's
+    // store, and the inward neighbour's stencil reads the face row's proxy
+    // (mu^{k+1} + w0 mu^k) / c2 in its place, w0 = -r when level k has
+    // rows and the face absorbed in step k-1.  In the face launch these rows
+    // read and wrote one value per 128-byte line.
+    const bool xq0 = ADJ && x0 == 0 && x_face_in_tile(g, s.types1, s.types2, 0);                        // uniform
+    const bool xq1 = ADJ && x0 <= g.nx - 2 && g.nx - 1 <= x0 + TX - 1 && x_face_in_tile(g, s.types1, s.types2, 1);
+    const T xw0 = (ADJ && s.level_rows) ? -s.r : (T)0;  // the x faces absorb in every step here
+    unsigned xfy = 0;  // rows y + r in [2, ny-3]
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (y + r >= 2 && y + r <= g.ny - 3) xfy |= 1u << r;
     // prologue: plane z0 into buffer 0, plane z0-1 of the own rows in registers
     T cm[R], c0[R];
     long long id = gidx(g, min(x, g.nx - 1), y, z0);
@@ -741,6 +824,7 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
         T cp[R], ua[R], w[R];
         bool dor[R];
         const bool inh = z >= g.hlo[2] && z <= g.hhi[2];
+        const bool xfz = ADJ && z >= 2 && z <= g.nz - 3;  // plane of absorbing x-face rows (see xq0)
         const int kz = z - g.o[2];
         const bool zs = kz >= 0 && kz <= C2, zt = kz == 0 || kz == C2;
 #pragma unroll
@@ -758,9 +842,15 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
             const long long ir = id + r * py;
             const int ly = 1 + R * ty + r;
             const T xp = buf[cur][ly][lx + 2];
+            const bool xfr = xfz && ((xfy >> r) & 1u);  // an absorbing x-face row at this (y, z)
             T d = (T)0, v = (T)0;
             if (dor[r]) {
-                const T xm = buf[cur][ly][lx];
+                T xm = buf[cur][ly][lx], xpr = xp;
+                if constexpr (ADJ) {
+                    // the face row's proxy in place of the face node's mu^{k+1}
+                    if (xq0 && x == 1 && xfr) xm = (xm + xw0 * (s.r * xm + c2 * c0[r])) * s.ic2;
+                    if (xq1 && x == g.nx - 2 && xfr) xpr = (xp + xw0 * (s.r * xp + c2 * c0[r])) * s.ic2;
+                }
                 const T ym = buf[cur][ly - 1][1 + lx], yp = buf[cur][ly + 1][1 + lx];
                 // FP32 (increment form): the Laplacian as a sum of neighbour
                 // differences, each exact in FP32 while the neighbours are
@@ -771,10 +861,10 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
                 // 4.6e-7 (FP64 reference, x-y uniform field).
                 T L;
                 if constexpr (INC)
-                    L = ((xm - c0[r]) + (xp - c0[r])) + ((ym - c0[r]) + (yp - c0[r])) +
+                    L = ((xm - c0[r]) + (xpr - c0[r])) + ((ym - c0[r]) + (yp - c0[r])) +
                         ((cm[r] - c0[r]) + (cp[r] - c0[r]));
                 else
-                    L = ((xm + xp) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
+                    L = ((xm + xpr) + (ym + yp)) + (cm[r] + cp[r]) - (T)6 * c0[r];
                 if constexpr (INC) {
                     d = ua[r] + c2 * L + w[r];
                     v = c0[r] + d;
@@ -794,6 +884,19 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
                     const T vf = c0[r] + s.r * (xp - v);
                     if constexpr (INC) st_once<T, NT>(Dc + ir + 1, vf - xp);
                     st_once<T, NT>(Uc + ir + 1, vf);
+                }
+            }
+            if constexpr (ADJ) {
+                // mu^k of the face node into the grid array (see xq0), with
+                // the row's own store (the increment array gets 0 there, which
+                // no row reads)
+                if (xq0 && x == 0 && xfr) {
+                    v = s.r * c0[r] + c2 * xp;
+                    st = true;
+                }
+                if (xq1 && xfr && x == g.nx - 1) {
+                    v = s.r * c0[r] + c2 * buf[cur][ly][lx];
+                    st = true;
                 }
             }
             if (st) {
@@ -1059,7 +1162,7 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
     const dim3 na((unsigned)ecf_blocks(s.g));
     if (s.minv) hipLaunchKernelGGL((k_bnd_adj_ecf<T, true>), na, dim3(BLOCK), 0, st, s);
     else hipLaunchKernelGGL((k_bnd_adj_ecf<T, false>), na, dim3(BLOCK), 0, st, s);
-    const long long nf = (s.g.n_fi + BLOCK - 1) / BLOCK;
+    const long long nf = (adj_face_rows(s.g, s.types1, s.types2) + BLOCK - 1) / BLOCK;
     if (nf > 0) hipLaunchKernelGGL((k_bnd_adj_face<T>), dim3((unsigned)nf), dim3(BLOCK), 0, st, s);
 }
 // ---------------------------------------------------------------- batches
@@ -1113,6 +1216,8 @@ template <typename T>
 void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st)
 {
     hipLaunchKernelGGL((k_bnd_adj_ecf_b<T>), dim3((unsigned)ecf_blocks(g), n), dim3(BLOCK), 0, st, steps_dev);
+    // every slot's own face rows (its face conditions decide which x-face
+    // rows its interior launch takes); the largest count is that of n_fi
     const long long nfb = (g.n_fi + BLOCK - 1) / BLOCK;
     if (nfb > 0) hipLaunchKernelGGL((k_bnd_adj_face_b<T>), dim3((unsigned)nfb, n), dim3(BLOCK), 0, st, steps_dev);
     const int nf = (g.n_fdm_blocks[1] + 7) / 8 * 8;
@@ -1363,7 +1468,7 @@ void launch_record_face(const Geo &g, const T *U, double *obs_row, hipStream_t s
 
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const T *V, const T *F, double *u,
-                                                       double *v)
+                                                       double *v, int types)
 {
     const long long n = (long long)g.nx * g.ny * g.nz;
     for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (long long)gridDim.x * BLOCK) {
@@ -1371,9 +1476,13 @@ __global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const
         // nodes strictly inside the hole belong to no grid row: no value
         const bool hole = g.has_fem && x > g.hlo[0] && x < g.hhi[0] && y > g.hlo[1] && y < g.hhi[1] &&
                           z > g.hlo[2] && z < g.hhi[2];
+        // boundary multipliers live in the face arrays, except the rows of
+        // absorbing x faces away from the edges (kept in the grid array)
+        const bool xin = (x == 0 || x == g.nx - 1) && x_face_in_tile(g, types, types, x == 0 ? 0 : 1) &&
+                         y >= 2 && y <= g.ny - 3 && z >= 2 && z <= g.nz - 3;
         if (u)
             u[t] = hole ? 0.0
-                        : (double)((F && on_bnd(g, x, y, z)) ? F[cidx(g, x, y, z)] : U[gidx(g, x, y, z)]);
+                        : (double)((F && on_bnd(g, x, y, z) && !xin) ? F[cidx(g, x, y, z)] : U[gidx(g, x, y, z)]);
     }
     if (!v || !g.has_fem) return;
     const long long nf = (long long)(g.C[0] + 1) * (g.C[1] + 1) * (g.C[2] + 1);
@@ -1383,9 +1492,9 @@ __global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const
 
 template <typename T>
 void launch_export_level(const Geo &g, const T *U, const T *V, const T *F, double *u, double *v,
-                         hipStream_t st)
+                         hipStream_t st, int types)
 {
-    hipLaunchKernelGGL((k_export_level<T>), dim3(1024), dim3(BLOCK), 0, st, g, U, V, F, u, v);
+    hipLaunchKernelGGL((k_export_level<T>), dim3(1024), dim3(BLOCK), 0, st, g, U, V, F, u, v, types);
 }
 
 __device__ __forceinline__ uint16_t f32_to_bf16(float x)
@@ -1757,7 +1866,7 @@ void launch_sum_J(const double *jmis, const double *jreg, int mode, double *J, h
     template void launch_hist_level<T>(const Geo &, const T *, T *, hipStream_t);                  \
     template void launch_record_face<T>(const Geo &, const T *, double *, hipStream_t);            \
     template void launch_export_level<T>(const Geo &, const T *, const T *, const T *, double *, double *,     \
-                                         hipStream_t);
+                                         hipStream_t, int);
 HYB_INST(double)
 HYB_INST(float)
 
