@@ -278,14 +278,18 @@ def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
     del obs
     sig = torch.zeros(len(tet), dtype=torch.float64, device="cuda")
     state = hyb.hyb_cg_state()
+    warm = []
     for _ in range(warmup):
         solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+        warm.append((state.trials, state.stalled, state.J_next))
     torch.cuda.synchronize()
-    sweeps = 0
+    sweeps, trials, stalls = 0, [], []
     t1 = time.perf_counter()
     for _ in range(steps):
         gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
         sweeps += state.forwards + 1
+        trials.append(state.trials)
+        stalls.append(state.stalled)
     torch.cuda.synchronize()
     t = time.perf_counter() - t1
     nfdm, nfem = solver.counts()
@@ -296,6 +300,7 @@ def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
            "node_shift": "U(-0.15 h, 0.15 h) per axis inside the inner box", "dt_over_h": round(dt / wl.h, 4),
            "dtype": "f32" if f32 else "f64", "value": round(value, 2), "unit": "Gpt-updates/s",
            "ms_per_step": round(t / steps * 1e3, 3), "sweeps_per_step": round(sweeps / steps, 2),
+           "trials": trials, "stalled": stalls, "warmup_trials_stalled_Jnext": warm,
            "host_setup_s": round(t_setup, 2), "last_J": J, "last_gnorm": gn}
     for which, b, name in ((0, bf, "forward"), (1, ba, "adjoint")):
         # each timing call overwrites the sweeps it needs: a forward sweep
@@ -357,26 +362,33 @@ def model_forms(wl_name, steps, warmup, seed=0):
             solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        te = 0.0
-        sweeps = 0
+        sweeps, trials, stalls = 0, [], []
         for _ in range(steps):
             gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
             sweeps += state.forwards + 1
-            if geps is not None:
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                solver.gradient_eps(geps)
-                torch.cuda.synchronize()
-                te += time.perf_counter() - t1
+            trials.append(state.trials)
+            stalls.append(state.stalled)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
+        te = 0.0
+        if geps is not None:
+            # dJ/d(1/c^2) of the last adjoint: a sweep pair at the final
+            # iterate, then the derivative alone timed
+            obs = solver.forward(sig, wl.nt, dt, omega=wl.omega)
+            solver.adjoint(obs - data, mode=0)
+            del obs
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            solver.gradient_eps(geps)
+            torch.cuda.synchronize()
+            te = time.perf_counter() - t1
         nfdm, nfem = solver.counts()
         res = {"value": round(sweeps * (nfdm + nfem) * wl.nt / t / 1e9, 2),
                "unit": "Gpt-updates/s", "ms_per_step": round(t / steps * 1e3, 3),
-               "sweeps_per_step": round(sweeps / steps, 2), "dt_over_h": round(dt / wl.h, 4), "dtype": "f64",
-               "last_J": J, "last_gnorm": gn}
+               "sweeps_per_step": round(sweeps / steps, 2), "trials": trials, "stalled": stalls,
+               "dt_over_h": round(dt / wl.h, 4), "dtype": "f64", "last_J": J, "last_gnorm": gn}
         if geps is not None:
-            res["eps_gradient_ms"] = round(te / steps * 1e3, 3)
+            res["eps_gradient_ms"] = round(te * 1e3, 3)
             res["min_inv_c2"] = round(float(eps.min()), 4)
             res["eps_gradient_norm"] = float(geps.norm())
         out[form] = res

@@ -299,7 +299,8 @@ hyb_status hyb_gradient_noalloc(hyb_ctx *ctx, double *grad_dev, double *J_dev);
  *      alpha_t = 2^-t rho / max|d^m|, t = 0 .. opts.cg_max_trials - 1, with
  *      the first relative step (largest change of sigma) rho = alpha_rel at
  *      m = 0 and min(alpha_rel, 2 state->alpha state->dmax), twice the
- *      previous call's accepted one, afterwards;
+ *      previous call's accepted one, afterwards (alpha_rel again after a
+ *      stalled call);
  *      each trial point clip(sigma^m + alpha_t d^m, 0, 4) (free cells,
  *      eq. (admpar)) costs one forward sweep; the first with J < J^m becomes
  *      sigma^{m+1}.  When none lowers J, sigma stays, state->stalled = 1 and

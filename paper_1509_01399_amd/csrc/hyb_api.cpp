@@ -1458,8 +1458,10 @@ hyb_status hyb_cg_step(hyb_ctx *c, const double *data, double *sigma, const hyb_
     const bool restart = hs[S_RESTART] != 0.0;
     // 3. trial steps 2^-t rho / max|d| until J falls below J^m; rho is the
     // first relative step (largest change of sigma): alpha_rel, and after the
-    // first iteration twice the previous accepted one, at most alpha_rel
-    const double rho = first ? c->alpha_rel : std::fmin(c->alpha_rel, 2.0 * (state->alpha * state->dmax));
+    // first iteration twice the previous accepted one, at most alpha_rel (a
+    // call after a stalled one, which took no step, starts from alpha_rel)
+    const double prev = state->alpha * state->dmax;
+    const double rho = (first || !(prev > 0.0)) ? c->alpha_rel : std::fmin(c->alpha_rel, 2.0 * prev);
     bool taken = false;
     int t = 0;
     double alpha = 0.0, Jn = Jm;
