@@ -146,8 +146,9 @@ def cpu_baseline(wl, dt, window):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    # kernels and the host code that fixes their launch geometry
-    for f in ("hyb_kernels.hip", "hyb_internal.h", "hyb_api.cpp"):
+    # the kernels, their launchers (grid, tiles, cache hints) and the
+    # parameter blocks they read
+    for f in ("hyb_kernels.hip", "hyb_internal.h"):
         with open(os.path.join(ROOT, "paper_1509_01399_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -196,6 +197,18 @@ def roofline(wl, dt, solver, f32, reps=50):
         out["increment_form"] = {"bytes_per_launch": b4, "achieved": round(b4 / (ms * 1e-3) / 1e9, 1),
                                  "frac": round(b4 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
     return out
+
+
+def same_horizon(wl, dt):
+    """Steps that reach the workload's own final time nt * dt_rule with the
+    step dt: a smaller step (a general mesh's or a faster medium's CFL bound)
+    keeps the time the scattered wave needs to cross the FEM box and return
+    to the observed face."""
+    import numpy as np
+
+    from paper_1509_01399_amd import synth
+    T = wl.nt * synth.dt_rule(wl.h, synth.sigma_for(wl, 0).max())
+    return int(np.ceil(T / dt - 1e-9))
 
 
 def general_mesh_setup(wl, seed=0, amp=0.15):
@@ -260,19 +273,21 @@ def general_fem_bytes(xyz, tet, wl, s):
 
 def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
     """The CG iteration of the benchmark on a general mesh of the FEM box (the
-    general-mesh path of the library), and the roofline of its FEM row
-    kernels (forward, adjoint) timed with HIP events on the solver's stream."""
+    general-mesh path of the library) over the workload's final time (more
+    steps of the mesh's smaller dt), and the roofline of its FEM row kernels
+    (forward, adjoint) timed with HIP events on the solver's stream."""
     import torch
 
     from paper_1509_01399_amd import hyb, synth
     wl = synth.WORKLOADS[wl_name]
     t0 = time.perf_counter()
     xyz, tet, st, dt = general_mesh_setup(wl, seed)
+    nt = same_horizon(wl, dt)
     solver = hyb.Solver(wl.n, C=wl.C, mesh=(xyz, tet), f32=f32)
     t_setup = time.perf_counter() - t0
     assert solver.general
     sig_true = torch.as_tensor(st, dtype=torch.float64, device="cuda")
-    obs = solver.forward(sig_true, wl.nt, dt, omega=wl.omega)
+    obs = solver.forward(sig_true, nt, dt, omega=wl.omega)
     data = torch.as_tensor(synth.add_noise(obs.cpu().numpy(), wl.noise, seed + 1), dtype=torch.float64,
                            device="cuda")
     del obs
@@ -280,24 +295,24 @@ def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
     state = hyb.hyb_cg_state()
     warm = []
     for _ in range(warmup):
-        solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+        solver.cg_step(data, sig, nt, dt, state, omega=wl.omega)
         warm.append((state.trials, state.stalled, state.J_next))
     torch.cuda.synchronize()
     sweeps, trials, stalls = 0, [], []
     t1 = time.perf_counter()
     for _ in range(steps):
-        gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+        gn, J = solver.cg_step(data, sig, nt, dt, state, omega=wl.omega)
         sweeps += state.forwards + 1
         trials.append(state.trials)
         stalls.append(state.stalled)
     torch.cuda.synchronize()
     t = time.perf_counter() - t1
     nfdm, nfem = solver.counts()
-    value = sweeps * (nfdm + nfem) * wl.nt / t / 1e9
+    value = sweeps * (nfdm + nfem) * nt / t / 1e9
     s = 4 if f32 else 8
     bf, ba = general_fem_bytes(xyz, tet, wl, s)
     out = {"workload": f"{wl.name} grid, general FEM mesh", "tets": int(len(tet)), "fem_nodes": int(len(xyz)),
-           "node_shift": "U(-0.15 h, 0.15 h) per axis inside the inner box", "dt_over_h": round(dt / wl.h, 4),
+           "node_shift": "U(-0.15 h, 0.15 h) per axis inside the inner box", "dt_over_h": round(dt / wl.h, 4), "nt": nt,
            "dtype": "f32" if f32 else "f64", "value": round(value, 2), "unit": "Gpt-updates/s",
            "ms_per_step": round(t / steps * 1e3, 3), "sweeps_per_step": round(sweeps / steps, 2),
            "trials": trials, "stalled": stalls, "warmup_trials_stalled_Jnext": warm,
@@ -307,7 +322,7 @@ def general_mesh(wl_name, steps, warmup, f32=False, seed=0):
         # (and for the adjoint rows an adjoint sweep) before the warm-up
         # launches and again before the timed ones
         for reps in (5, 50):
-            obs = solver.forward(sig, wl.nt, dt, omega=wl.omega)
+            obs = solver.forward(sig, nt, dt, omega=wl.omega)
             if which == 1:
                 solver.adjoint(obs - data, mode=0)
             del obs
@@ -331,8 +346,9 @@ def model_forms(wl_name, steps, warmup, seed=0):
       Test 1 initial condition exp(-|x|^2) at rest (Taylor start);
     - variable wave speed: 1-4 regions with c ~ U(1, 2) in the free cubes
       (synth.wave_speed), dt = 0.95 h sqrt(min(1/c^2) / 15) (the CFL bound
-      for a <= 5), plus the derivative with respect to 1/c^2 after each
-      iteration (hyb_gradient_eps)."""
+      for a <= 5), plus the derivative with respect to 1/c^2 at the final
+      iterate (hyb_gradient_eps), timed alone.
+    Both run to the workload's final time (more steps for the smaller dt)."""
     import numpy as np
     import torch
 
@@ -352,19 +368,20 @@ def model_forms(wl_name, steps, warmup, seed=0):
             eps = synth.wave_speed(wl.C, seed + 5)
             dt = 0.95 * wl.h * math.sqrt(float(eps.min()) / 15.0)
             solver.set_wave_speed(torch.as_tensor(eps, dtype=torch.float64, device="cuda"))
-        obs = solver.forward(st, wl.nt, dt, omega=wl.omega)
+        nt = same_horizon(wl, dt)
+        obs = solver.forward(st, nt, dt, omega=wl.omega)
         data = torch.as_tensor(synth.add_noise(obs.cpu().numpy(), wl.noise, seed + 1), device="cuda")
         del obs
         sig = torch.zeros_like(st)
         state = hyb.hyb_cg_state()
         geps = torch.zeros_like(st) if form == "wave_speed" else None
         for _ in range(warmup):
-            solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+            solver.cg_step(data, sig, nt, dt, state, omega=wl.omega)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sweeps, trials, stalls = 0, [], []
         for _ in range(steps):
-            gn, J = solver.cg_step(data, sig, wl.nt, dt, state, omega=wl.omega)
+            gn, J = solver.cg_step(data, sig, nt, dt, state, omega=wl.omega)
             sweeps += state.forwards + 1
             trials.append(state.trials)
             stalls.append(state.stalled)
@@ -374,7 +391,7 @@ def model_forms(wl_name, steps, warmup, seed=0):
         if geps is not None:
             # dJ/d(1/c^2) of the last adjoint: a sweep pair at the final
             # iterate, then the derivative alone timed
-            obs = solver.forward(sig, wl.nt, dt, omega=wl.omega)
+            obs = solver.forward(sig, nt, dt, omega=wl.omega)
             solver.adjoint(obs - data, mode=0)
             del obs
             torch.cuda.synchronize()
@@ -383,10 +400,10 @@ def model_forms(wl_name, steps, warmup, seed=0):
             torch.cuda.synchronize()
             te = time.perf_counter() - t1
         nfdm, nfem = solver.counts()
-        res = {"value": round(sweeps * (nfdm + nfem) * wl.nt / t / 1e9, 2),
+        res = {"value": round(sweeps * (nfdm + nfem) * nt / t / 1e9, 2),
                "unit": "Gpt-updates/s", "ms_per_step": round(t / steps * 1e3, 3),
                "sweeps_per_step": round(sweeps / steps, 2), "trials": trials, "stalled": stalls,
-               "dt_over_h": round(dt / wl.h, 4), "dtype": "f64", "last_J": J, "last_gnorm": gn}
+               "dt_over_h": round(dt / wl.h, 4), "nt": nt, "dtype": "f64", "last_J": J, "last_gnorm": gn}
         if geps is not None:
             res["eps_gradient_ms"] = round(te * 1e3, 3)
             res["min_inv_c2"] = round(float(eps.min()), 4)
