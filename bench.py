@@ -174,6 +174,35 @@ def measured_traffic(wl_name, f32):
         return None
 
 
+def stream_reference(n, s, reps=20):
+    """What plain streaming reaches on this GPU for arrays of n elements of s
+    bytes (sized like the interior launch's streams, beyond the last-level
+    cache): a copy (read 1, write 1) and an add c = a + b (read 2, write 1,
+    the leapfrog's pattern), torch's elementwise kernels, HIP events on the
+    current stream.  Context for the roofline fraction, not the peak."""
+    import torch
+    dt = torch.float32 if s == 4 else torch.float64
+    a = torch.rand(n, dtype=dt, device="cuda")
+    b = torch.rand(n, dtype=dt, device="cuda")
+    c = torch.empty_like(a)
+    out = {}
+    for name, fn, streams in (("copy", lambda: c.copy_(a), 2), ("add", lambda: torch.add(a, b, out=c), 3)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{name}_GBs"] = round(streams * n * s / (ms * 1e-3) / 1e9, 1)
+    del a, b, c
+    torch.cuda.empty_cache()
+    out["elements"] = n
+    return out
+
+
 def roofline(wl, dt, solver, f32, reps=50):
     """Roofline of the forward interior launch: algorithmic bytes (three
     streams per node, the leapfrog's minimum) over the average launch time
@@ -192,6 +221,9 @@ def roofline(wl, dt, solver, f32, reps=50):
            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(wl.name, f32),
            "kernel": "k_interior<%s,false,*> (forward FDM+FEM interior)" % ("float" if f32 else "double"),
            "bytes_per_launch": b, "avg_launch_ms": round(ms, 5)}
+    ref = stream_reference((wl.n + 1) ** 3, s)
+    out["stream_reference"] = ref
+    out["frac_of_add"] = round(achieved / ref["add_GBs"], 4)
     if f32:
         b4 = interior_bytes(wl.n, wl.C, s, streams=4)
         out["increment_form"] = {"bytes_per_launch": b4, "achieved": round(b4 / (ms * 1e-3) / 1e9, 1),

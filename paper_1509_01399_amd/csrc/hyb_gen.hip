@@ -97,15 +97,18 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
     const T nu0 = nu[n];
     const bool hrow = n < s.nH;
     const T *__restrict__ H = s.hist;
-    int eb = 0;
+    // the slice's first we entries carry the E slots (upper inner edges
+    // first in each row of [0, nH)); the rest only the stencil
+    int eb = 0, we = 0;
     double u0 = 0.0;
-    if (hrow) {
+    if ((long long)sl * 64 < s.nH) {
         eb = s.eoff[sl];
-        u0 = (double)H[n];
+        we = (s.eoff[sl + 1] - eb) >> 6;
     }
+    if (hrow) u0 = (double)H[n];
     T acc = 0;
-#pragma unroll 2
-    for (int j = 0; j < w; ++j) {
+#pragma unroll 4
+    for (int j = 0; j < we; ++j) {
         const int p = b + 64 * j + ln;
         const int m = col[p];
         const T num = nu[m];
@@ -114,6 +117,11 @@ __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
             double *e = s.E + eb + 64 * j + ln;
             *e += ((double)nu0 - (double)num) * (u0 - (double)H[m]);
         }
+    }
+#pragma unroll 2
+    for (int j = we; j < w; ++j) {
+        const int p = b + 64 * j + ln;
+        acc += kap[p] * (nu0 - nu[col[p]]);
     }
     T cw = 0;
     if (n < s.nA) {
