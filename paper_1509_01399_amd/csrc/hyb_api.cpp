@@ -838,17 +838,35 @@ template <typename T>
 hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, double *obs, bool save)
 {
     const hipStream_t st = c->stream;
+    // The edge and corner rows of step k run as extra blocks of the interior
+    // launch of step k+1 (nothing in that launch reads them), so the
+    // boundary launch of a step remains only while some face has reflecting
+    // rows.  They run in a launch of their own before a checkpoint, at the
+    // end, and when the face conditions of the two steps differ (the edge
+    // rows recompute reflecting face rows from the levels of their own step,
+    // which the next launch overwrites on faces that absorb there).
+    Step<T> prev{};
+    bool lag = false;
     for (int k = k0; k < k1; ++k) {
         const Step<T> s = fwd_step_args<T>(c, k, ia, ib, ic, obs);
-        launch_interior<T>(s, false, st);
+        if (lag && prev.types1 != s.types1) {
+            launch_bnd_fwd_edges<T>(prev, st);
+            lag = false;
+        }
+        launch_interior<T>(s, false, st, lag ? &prev : nullptr);
         if (c->gen) launch_gen_fwd<T>(gen_args<T>(c, s), st);
-        launch_bnd_fwd<T>(s, st);
+        launch_bnd_fwd_faces<T>(s, st);
+        prev = s;
+        lag = true;
         const int t = ia; ia = ib; ib = ic; ic = t;
         if (save && (k + 1) % c->ckK == 0) {
+            launch_bnd_fwd_edges<T>(prev, st);
+            lag = false;
             hyb_status r = save_ckpt<T>(c, (k + 1) / c->ckK, k + 1, ia, ib);
             if (r) return r;
         }
     }
+    if (lag) launch_bnd_fwd_edges<T>(prev, st);
     return HYB_OK;
 }
 

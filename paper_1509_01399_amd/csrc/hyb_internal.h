@@ -100,9 +100,31 @@ struct Step {
 // velocity u^{k+1} - u^k, so FP32 errors grow like sqrt(nt) instead of nt^1.5.
 template <typename T> constexpr bool incr_form() { return sizeof(T) == 4; }
 
+// The edge and corner rows of one forward step (its levels, source term,
+// face conditions and dt^2 weight), run as extra blocks of the next step's
+// interior launch: no interior or absorbing-face row reads an edge value.
+template <typename T>
+struct EdgeArgs {
+    const T *Ua, *Ub, *Da;
+    T *Uc, *Dc;
+    double *obs;
+    const double *flux;
+    double fluxscale;
+    T srcterm, c2;
+    int types1;
+};
+
 // ---- launchers (hyb_kernels.hip) ----
-template <typename T> void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st);
+// edges: the step whose edge and corner rows the forward launch also runs
+// (null: none)
+template <typename T>
+void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const Step<T> *edges = nullptr);
+// boundary launch of a forward step: reflecting face rows, edges and corners
 template <typename T> void launch_bnd_fwd(const Step<T> &s, hipStream_t st);
+// the same split in two: the reflecting face rows (no launch when every face
+// absorbs), and the edge and corner rows
+template <typename T> void launch_bnd_fwd_faces(const Step<T> &s, hipStream_t st);
+template <typename T> void launch_bnd_fwd_edges(const Step<T> &s, hipStream_t st);
 template <typename T> void launch_bnd_adj(const Step<T> &s, hipStream_t st);
 
 // batched steps: steps_dev[n] device array, all of geometry g

@@ -11,13 +11,15 @@
 //     element gather over the 8 cubes around a node reduces to six edge
 //     conductances kappa_e = sum over the 4 cubes of the edge of a_c * w_{c,e}
 //     (w from the element matrices computed on the host); no atomics.  The
-//     rows of absorbing x faces, eq. (eq:abs2), are computed here too.
-//   k_bnd_fwd: the other outer boundary rows (absorbing eq. (eq:abs2) or the
-//     ghost-node Neumann/source rows of eq. (f)), the two overlap copies of
-//     Algorithm 2 steps 3-4, the trace of the z+ face and nothing else.  Each
-//     boundary thread recomputes the values of lower-codimension boundary
-//     neighbours it depends on, so faces, edges and corners need no ordering
-//     between threads (three rotating buffers keep level k-1 intact).
+//     rows of absorbing faces, eq. (eq:abs2), away from the edges, the two
+//     overlap copies of Algorithm 2 steps 3-4 and the trace on an absorbing
+//     z+ face are computed here too.
+//   k_bnd_fwd: the rows of reflecting faces (the ghost-node Neumann/source
+//     rows of eq. (f)), the edges and the corners, with their part of the
+//     trace.  An edge or corner thread recomputes the values of the boundary
+//     neighbours it depends on that this launch computes (a corner's edges,
+//     a reflecting face node), so its threads need no ordering (three
+//     rotating buffers keep level k-1 intact).
 // Per adjoint step (computing the multipliers of level k) the reverse:
 //   k_bnd_adj_ecf: multipliers of the corner and edge rows, and beside them
 //     the FEM rows of the adjoint with the FP64 gradient time-integral of
@@ -213,13 +215,25 @@ __device__ __forceinline__ T src_flux(const Step<T> &s, int x, int y)
     return s.flux ? (T)(s.fluxscale * s.flux[x + (long long)s.g.nx * y]) : s.srcterm;
 }
 
+// A face-interior node whose face is absorbing at this step: its new value
+// comes from the interior launch.
+__device__ __forceinline__ bool fwd_face_in_tile(const Geo &g, int types, int x, int y, int z)
+{
+    const bool bx = x == 0 || x == g.nx - 1, by = y == 0 || y == g.ny - 1, bz = z == 0 || z == g.nz - 1;
+    if ((int)bx + (int)by + (int)bz != 1) return false;
+    const int f = bx ? (x == 0 ? 0 : 1) : (by ? (y == 0 ? 2 : 3) : (z == 0 ? 4 : 5));
+    return ftype(types, f) == F_ABC;
+}
+
 // Level k+1 value of boundary node (x,y,z), any codimension.  Ghost-node
 // leapfrog when every boundary axis reflects (Neumann, or the source face
 // while the pulse is on: each such axis contributes 2(u_in - u)/h^2, the
 // source adds 2 p/h); otherwise the absorbing row of eq. (eq:abs2) averaged
 // over the absorbing axes.  The absorbing row needs the new value of the
-// inward neighbour, recomputed here when that neighbour is itself a boundary
-// node (D bounds the depth: corner -> edge -> face -> interior).
+// inward neighbour: read from the level, unless that neighbour is itself a
+// boundary node the interior launch does not compute (an edge of a corner, or
+// a ghost-row face node), which is then recomputed here (D bounds the depth:
+// corner -> edge -> face).
 template <typename T, int D>
 __device__ __forceinline__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
 {
@@ -255,7 +269,9 @@ __device__ __forceinline__ T bnd_fwd(const Step<T> &s, int x, int y, int z)
                   cz = z + (d == 2 ? B.dir[d] : 0);
         const long long in = gidx(g, cx, cy, cz);
         T up;
-        if constexpr (D > 1) up = on_bnd(g, cx, cy, cz) ? bnd_fwd<T, D - 1>(s, cx, cy, cz) : s.Uc[in];
+        if constexpr (D > 1)
+            up = (on_bnd(g, cx, cy, cz) && !fwd_face_in_tile(g, s.types1, cx, cy, cz)) ? bnd_fwd<T, D - 1>(s, cx, cy, cz)
+                                                                                   : s.Uc[in];
         else up = s.Uc[in];
         acc += s.Ub[in] + s.r * (u - up);
     }
@@ -290,26 +306,92 @@ __device__ __forceinline__ void box_surface(long long t, int L, int &a, int &b, 
     c = 1 + (int)(r / (L - 1));
 }
 
-// The x-face-interior rows of an absorbing x face are computed by the
-// forward interior launch (fdm_tile).  They are the last of the face range:
-// when both x faces are absorbing the launch skips them (thread t maps past
-// them; a batch launch over the full count leaves its last threads idle).
-__host__ __device__ __forceinline__ long long x_face_rows(const Geo &g) { return 2LL * (g.ny - 2) * (g.nz - 2); }
-__host__ __device__ __forceinline__ bool x_faces_absorbing(int types)
+// Face-interior rows of the forward step on an absorbing face are computed
+// by the interior launch (fdm_tile_pairs), as are the two overlap copies; the
+// boundary launch takes the faces whose rows are not absorbing at this step
+// (ghost-node Neumann or source rows), then the edges and corners.
+__host__ __device__ __forceinline__ long long face_area(const Geo &g, int f)
 {
-    return (types & 3) == F_ABC && ((types >> 2) & 3) == F_ABC;
+    const int d = f >> 1;
+    return d == 2 ? (long long)(g.nx - 2) * (g.ny - 2)
+                  : (d == 1 ? (long long)(g.nx - 2) * (g.nz - 2) : (long long)(g.ny - 2) * (g.nz - 2));
+}
+__host__ __device__ __forceinline__ long long fwd_face_rows(const Geo &g, int types)
+{
+    long long n = 0;
+    for (int f = 0; f < 6; ++f)
+        if (((types >> (2 * f)) & 3) != F_ABC) n += face_area(g, f);
+    return n;
+}
+
+// Node t of the forward launch's face rows: the non-absorbing faces in the
+// order z, y, x (low side first), tangential positions as in face_node.
+__device__ __forceinline__ void fwd_face_node(const Geo &g, int types, long long t, int &x, int &y, int &z, int &f)
+{
+    f = 5;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+        const int ff = q < 2 ? 4 + q : (q < 4 ? q : q - 4);
+        if (ftype(types, ff) == F_ABC) continue;
+        const long long A = face_area(g, ff);
+        if (t < A) {
+            f = ff;
+            break;
+        }
+        t -= A;
+    }
+    const int d = f >> 1;
+    const bool hi = f & 1;
+    const long long a1 = d == 0 ? g.ny - 2 : g.nx - 2;
+    const int p = 1 + (int)(t % a1), q2 = 1 + (int)(t / a1);
+    x = d == 0 ? (hi ? g.nx - 1 : 0) : p;
+    y = d == 1 ? (hi ? g.ny - 1 : 0) : (d == 0 ? p : q2);
+    z = d == 2 ? (hi ? g.nz - 1 : 0) : q2;
+}
+
+// Edge or corner node t of the forward step s (t >= n_ec: nothing).
+template <typename T>
+__device__ __forceinline__ void edge_row(const Step<T> &s, long long t)
+{
+    const Geo &g = s.g;
+    if (t < 0 || t >= g.n_ec) return;
+    int x, y, z;
+    edge_corner_node(g, t, x, y, z);
+    const T v = bnd_fwd<T, 3>(s, x, y, z);
+    const long long id = gidx(g, x, y, z);
+    s.Uc[id] = v;
+    if constexpr (incr_form<T>()) s.Dc[id] = v - s.Ub[id];
+    if (s.obs && z == g.nz - 1) s.obs[x + (long long)g.nx * y] = (double)v;
+}
+
+// The edge rows of the step described by ea, with the invariant arguments
+// (geometry, r) of the step s that carries them.
+template <typename T>
+__device__ __forceinline__ void edge_row_of(const Step<T> &s, const EdgeArgs<T> &ea, long long t)
+{
+    Step<T> e = s;
+    e.Ua = ea.Ua; e.Ub = ea.Ub; e.Da = ea.Da; e.Uc = ea.Uc; e.Dc = ea.Dc;
+    e.obs = ea.obs; e.flux = ea.flux; e.fluxscale = ea.fluxscale;
+    e.srcterm = ea.srcterm; e.c2 = ea.c2; e.types1 = ea.types1;
+    edge_row<T>(e, t);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_fwd_edges(Step<T> s)
+{
+    edge_row<T>(s, (long long)blockIdx.x * BLOCK + threadIdx.x);
 }
 
 template <typename T>
 __device__ __forceinline__ void bnd_fwd_body(const Step<T> &s, long long t)
 {
     const Geo &g = s.g;
-    if (x_faces_absorbing(s.types1) && t >= g.n_fi - x_face_rows(g)) t += x_face_rows(g);
-    if (t < g.n_fi) {
-        // face-interior node: one boundary axis, never needs recursion
+    const long long nfr = fwd_face_rows(g, s.types1);
+    if (t < nfr) {
+        // ghost-node row of a reflecting face (Neumann, or the source face
+        // while the source is on), eq. (f)
         int x, y, z, f;
-        face_node(g, t, x, y, z, f);
-        if (f < 2 && ftype(s.types1, f) == F_ABC) return;  // done by the interior launch
+        fwd_face_node(g, s.types1, t, x, y, z, f);
         const int d = f >> 1, dir = (f & 1) ? -1 : 1;
         const long long sd = d == 0 ? 1 : (d == 1 ? g.px : g.plane);     // inward axis stride
         const long long sa = d == 0 ? g.px : 1, sb = d == 2 ? g.px : g.plane;  // tangential strides
@@ -317,50 +399,22 @@ __device__ __forceinline__ void bnd_fwd_body(const Step<T> &s, long long t)
         const int kind = ftype(s.types1, f);
         const T u = s.Ub[id];
         T v;
-        if (kind == F_ABC) {
-            v = s.Ub[in] + s.r * (u - s.Uc[in]);
-            if constexpr (incr_form<T>()) s.Dc[id] = v - u;
+        const T lap = (T)2 * (s.Ub[in] - u) + ((s.Ub[id + sa] - u) + (s.Ub[id - sa] - u)) +
+                      ((s.Ub[id + sb] - u) + (s.Ub[id - sb] - u));
+        if constexpr (incr_form<T>()) {
+            T dd = s.Da[id] + s.c2 * lap;
+            if (kind == F_SOURCE) dd += src_flux(s, x, y);
+            s.Dc[id] = dd;
+            v = u + dd;
         } else {
-            const T lap = (T)2 * (s.Ub[in] - u) + ((s.Ub[id + sa] - u) + (s.Ub[id - sa] - u)) +
-                          ((s.Ub[id + sb] - u) + (s.Ub[id - sb] - u));
-            if constexpr (incr_form<T>()) {
-                T d = s.Da[id] + s.c2 * lap;
-                if (kind == F_SOURCE) d += src_flux(s, x, y);
-                s.Dc[id] = d;
-                v = u + d;
-            } else {
-                v = (T)2 * u - s.Ua[id] + s.c2 * lap;
-                if (kind == F_SOURCE) v += src_flux(s, x, y);
-            }
+            v = (T)2 * u - s.Ua[id] + s.c2 * lap;
+            if (kind == F_SOURCE) v += src_flux(s, x, y);
         }
         s.Uc[id] = v;
         if (s.obs && f == 5) s.obs[x + (long long)g.nx * y] = (double)v;
         return;
     }
-    t -= g.n_fi;
-    if (t < g.n_ec) {
-        int x, y, z;
-        edge_corner_node(g, t, x, y, z);
-        const T v = bnd_fwd<T, 3>(s, x, y, z);
-        const long long id = gidx(g, x, y, z);
-        s.Uc[id] = v;
-        if constexpr (incr_form<T>()) s.Dc[id] = v - s.Ub[id];
-        if (s.obs && z == g.nz - 1) s.obs[x + (long long)g.nx * y] = (double)v;
-        return;
-    }
-    t -= g.n_ec;
-    if (t < g.nwd) {  // Algorithm 2 step 3: FEM values to the FDM inner boundary
-        int a, b, c;
-        box_surface(t, g.C[0] - 4, a, b, c);
-        s.Uc[gidx(g, g.o[0] + 2 + a, g.o[1] + 2 + b, g.o[2] + 2 + c)] = s.Vc[fidx(g, 2 + a, 2 + b, 2 + c)];
-        return;
-    }
-    t -= g.nwd;
-    if (t < g.nwo) {  // Algorithm 2 step 4: FDM values to the FEM boundary
-        int a, b, c;
-        box_surface(t, g.C[0], a, b, c);
-        s.Vc[fidx(g, a, b, c)] = s.Uc[gidx(g, g.o[0] + a, g.o[1] + b, g.o[2] + c)];
-    }
+    edge_row<T>(s, t - nfr);
 }
 
 template <typename T>
@@ -688,9 +742,9 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk)
     return (b % 8) * per + b / 8;
 }
 
-// FDM tile: the seven-point leapfrog, eq. (fdmschemeforward), on 64 x-lanes
-// starting at a multiple of 64 (rows of the padded field start on a
-// 128-byte line, so a wave's row access covers whole cache lines; the lane
+// Adjoint FDM tile: the seven-point stencil of eq. (fdmschemeadjoint) on
+// 64 x-lanes starting at a multiple of 64 (rows of the padded field start on
+// a 128-byte line, so a wave's row access covers whole cache lines; the lane
 // on the x = 0 boundary has no stencil row) by 4 thread rows of 2 grid rows each,
 // streaming z over the block's chunk.  Each plane of the tile and its
 // one-node halo (66 x 10 values) is loaded once from memory into one of two
@@ -709,6 +763,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk)
 template <typename T, bool ADJ, bool NT>
 __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
 {
+    static_assert(ADJ, "the forward step runs on fdm_tile_pairs");
     constexpr int R = RY_FDM, TX = TX_FDM, TY = TY_FDM, LX = TX + 2, LY = TY + 2;
     constexpr bool INC = incr_form<T>();
     __shared__ T buf[2][LY][LX];
@@ -761,25 +816,6 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
         rcmp[r] = xcmp && yr <= g.ny - 2;
         side[r] = ib && j >= 0 && j <= C1 && !(ii && j > 0 && j < C1);
         top[r] = ib && ii && j > 0 && j < C1;
-    }
-    // Absorbing x faces of the forward step, eq. (eq:abs2): a face row needs
-    // the old values of the face node and of its inward neighbour, both in
-    // the staged plane, and the new value of the neighbour, computed in this
-    // wave.  The x = 0 lane (no stencil row of its own) takes the row of x = 0 with
-    // the new value of lane x = 1, stored by the wave's own store
-    // instruction; the lane at x = nx-2 adds the row of x = nx-1.  The
-    // boundary launch then skips those rows, which touched a cache line per
-    // node there: forward step at 257^3 93.1 -> 90.2 us (FP64), 81.6 ->
-    // 76.8 us (FP32); the x = 0 face alone gained as much in FP32 and less
-    // in FP64.
-    bool fx0[R], fx1[R];
-    {
-        const bool a0 = !ADJ && ftype(s.types1, 0) == F_ABC, a1 = !ADJ && ftype(s.types1, 1) == F_ABC;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            fx0[r] = a0 && x == 0 && y + r <= g.ny - 2;
-            fx1[r] = a1 && x == g.nx - 2 && rcmp[r];
-        }
     }
     // rows inside the hole's x-y range skip the planes of the hole
     unsigned hmask = 0;
@@ -873,20 +909,7 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
                 }
             }
             bool st = dor[r];
-            if constexpr (!ADJ) {
-                const T v1 = __shfl_down(v, 1, 64);  // every lane: the new value of lane x+1
-                if (fx0[r]) {
-                    v = xp + s.r * (c0[r] - v1);
-                    if constexpr (INC) d = v - c0[r];
-                    st = true;
-                }
-                if (fx1[r]) {
-                    const T vf = c0[r] + s.r * (xp - v);
-                    if constexpr (INC) st_once<T, NT>(Dc + ir + 1, vf - xp);
-                    st_once<T, NT>(Uc + ir + 1, vf);
-                }
-            }
-            if constexpr (ADJ) {
+            {
                 // mu^k of the face node into the grid array (see xq0), with
                 // the row's own store (the increment array gets 0 there, which
                 // no row reads)
@@ -939,6 +962,35 @@ __device__ __forceinline__ void st_pair(T *p, typename Pair2<T>::type v)
     using P = typename Pair2<T>::type;
     if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<P *>(p));
     else *reinterpret_cast<P *>(p) = v;
+}
+
+// Absorbing face rows, eq. (eq:abs2), beside a pair of interior rows:
+// u^{k+1}_b = u^k_in + r (u^k_b - u^{k+1}_in) for the columns with a row
+// (ok), stored at `at` (the face node of the first column), with the
+// increment in FP32 and the trace when obs is given.
+template <typename T, bool NT>
+__device__ __forceinline__ void face_pair(T *Uc, T *Dc, long long at, const T ub[2], const T uin[2], const T vin[2],
+                                          const bool ok[2], double *obs, T r)
+{
+    using P = typename Pair2<T>::type;
+    T vf[2], df[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        vf[e] = uin[e] + r * (ub[e] - vin[e]);
+        df[e] = vf[e] - ub[e];
+        if (obs && ok[e]) obs[e] = (double)vf[e];
+    }
+    if (ok[0] && ok[1]) {
+        if constexpr (incr_form<T>()) st_pair<T, NT>(Dc + at, P{df[0], df[1]});
+        st_pair<T, NT>(Uc + at, P{vf[0], vf[1]});
+    } else {
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+            if (ok[e]) {
+                if constexpr (incr_form<T>()) st_once<T, NT>(Dc + at + e, df[e]);
+                st_once<T, NT>(Uc + at + e, vf[e]);
+            }
+    }
 }
 
 // FDM tile with column pairs: the same 64 x 8 tile, rows, halos, hole,
@@ -1002,7 +1054,7 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const int xe = x + e, i = xe - g.o[0];
-        const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
+        const bool ib = g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
         rcmp[e] = xe >= 1 && xe <= g.nx - 2 && y <= g.ny - 2;
         side[e] = ib && j >= 0 && j <= C1 && !(ii && j > 0 && j < C1);
         top[e] = ib && ii && j > 0 && j < C1;
@@ -1014,6 +1066,18 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
     // joins the pair store when nx-2 is the lane's first column, else it is a
     // store of its own
     const bool fx0 = a0 && x == 0 && y <= g.ny - 2;
+    // absorbing y and z faces of the forward step: the row of a node next to
+    // the face has the face node's old value (staged row, or the z neighbour
+    // in registers) and its own old and new values, so it adds the face row,
+    // eq. (eq:abs2), with a store of its own (rows y = 1 and y = ny-2, planes
+    // z = 1 and z = nz-2; the trace takes the z+ face)
+    const bool fy0 = !ADJ && y == 1 && ftype(s.types1, 2) == F_ABC;
+    const bool fy1 = !ADJ && y == g.ny - 2 && ftype(s.types1, 3) == F_ABC;
+    const bool az0 = !ADJ && ftype(s.types1, 4) == F_ABC, az1 = !ADJ && ftype(s.types1, 5) == F_ABC;
+    // Algorithm 2 step 4: new grid values on omega_o (the FEM box surface,
+    // FDM rows) go to the FEM level as well (structured box only: a general
+    // mesh copies them in its own launch)
+    const bool wo = !ADJ && g.has_fem && !g.gen;
     // absorbing x faces of the adjoint (as in fdm_tile)
     const bool xq0 = ADJ && x0 == 0 && x_face_in_tile(g, s.types1, s.types2, 0);
     const bool xq1 = ADJ && x0 <= g.nx - 2 && g.nx - 1 <= x0 + TX - 1 && x_face_in_tile(g, s.types1, s.types2, 1);
@@ -1094,6 +1158,17 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
             } else {
                 v[e] = (T)2 * cc[e] - uav[e] + c2 * L + w[e];
             }
+            if constexpr (!ADJ)
+                if (wo && ((side[e] && zs) || (top[e] && zt))) s.Vc[fidx(g, x + e - g.o[0], j, kz)] = v[e];
+        }
+        if constexpr (!ADJ) {
+            // face rows next to this row (see fy0)
+            if (fy0) face_pair<T, NT>(Uc, Dc, id - g.px, ymv, cc, v, dor, nullptr, s.r);
+            if (fy1) face_pair<T, NT>(Uc, Dc, id + g.px, ypv, cc, v, dor, nullptr, s.r);
+            if (az0 && z == 1) face_pair<T, NT>(Uc, Dc, id - pz, cmv, cc, v, dor, nullptr, s.r);
+            if (az1 && z == g.nz - 2)
+                face_pair<T, NT>(Uc, Dc, id + pz, cpv, cc, v, dor,
+                                 s.obs ? s.obs + x + (long long)g.nx * y : nullptr, s.r);
         }
         if constexpr (!ADJ) {
             if (fx0) {
@@ -1312,6 +1387,11 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
             s.VDc[id] = dv;
             v = v0 + dv;
         }
+        // Algorithm 2 step 3: the new FEM values on omega_diamond (surface of
+        // the inner box) into the grid level
+        if constexpr (!ADJ)
+            if (hin && (i == 2 || i == Cx - 2 || j == 2 || j == Cy - 2 || k == 2 || k == Cz - 2))
+                s.Uc[gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k)] = v;
         if constexpr (!ADJ)
             if (hin && s.hist)
                 st_once<T, true>(s.hist + (i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz, v);
@@ -1331,24 +1411,39 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 // remap), then, in the forward sweep, the FEM blocks.  The FEM rows of the
 // adjoint run in the boundary launch.
 //
-// FP32: at most 64 VGPRs (8 waves per SIMD), measured 77.4 -> 76.7 us per
-// forward step at 257^3.  FP64 runs unbounded (72 VGPRs, 7 waves): bounded,
-// its forward kernel spills and measured 79.1 us against 77.5 us per launch.
-template <typename T>
-constexpr int interior_waves() { return sizeof(T) == 4 ? 8 : 1; }
-
-// FDM tiles with column pairs (fdm_tile_pairs) or one column per lane
-// (fdm_tile).  Per step at 257^3, pairs against single columns (same run,
-// same box): FP64 forward 85.3 / 86.7 us, adjoint 101.1 / 97.4 us; FP32
-// forward 77.1 / 76.4 us, adjoint 86.0 / 81.5 us.  Halving the vector memory
-// instructions per node pays only in the FP64 forward.
+// FP32: at most 64 VGPRs (8 waves per SIMD) in the adjoint, 72 (7 waves) in
+// the forward, whose tile also takes the face rows: under 64 it spilled and
+// its step measured 83.2 us against 74.9 us (1200 steps at 257^3).  FP64 runs
+// unbounded (77 VGPRs forward, 72 adjoint): bounded to 7 waves the forward
+// spills, 87.8 us against 83.1 us per step.
 template <typename T, bool ADJ>
-constexpr bool pair_tile() { return sizeof(T) == 8 && !ADJ; }
+constexpr int interior_waves() { return sizeof(T) == 4 ? (ADJ ? 8 : 7) : 1; }
+
+// Forward FDM tiles take column pairs (fdm_tile_pairs), adjoint tiles one
+// column per lane (fdm_tile).  Per step at 257^3, pairs against single
+// columns (same run, same box, before the forward tile took the y and z
+// faces): FP64 forward 85.3 / 86.7 us, adjoint 101.1 / 97.4 us; FP32 forward
+// 77.1 / 76.4 us, adjoint 86.0 / 81.5 us.  With the face rows in the tile and
+// the edge rows one launch later, the forward step over 1200 steps went from
+// 85.3 to 83.1 us (FP64) and from 75.9 to 74.9 us (FP32): the interior launch
+// grew by ~4 us, the boundary launch (9 us, the latency of the edge rows) is
+// gone while every face absorbs.
+template <typename T, bool ADJ>
+constexpr bool pair_tile() { return !ADJ; }
 
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK, interior_waves<T>()) void k_interior(Step<T> s)
+__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(Step<T> s, EdgeArgs<T> ea, int ne)
 {
-    const int b = blockIdx.x;
+    int b = blockIdx.x;
+    if constexpr (!ADJ) {
+        // the previous step's edge and corner rows first (ne: a multiple of
+        // 8, so the tile numbering below keeps its XCD mapping)
+        if (b < ne) {
+            edge_row_of<T>(s, ea, (long long)b * BLOCK + threadIdx.x);
+            return;
+        }
+        b -= ne;
+    }
     const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
     if (b < nf) {
         if constexpr (pair_tile<T, ADJ>()) fdm_tile_pairs<T, ADJ, NT>(s, b);
@@ -1369,25 +1464,47 @@ static bool stream_nt(const Geo &g, size_t esz, int slots)
 }
 
 template <typename T>
-void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st)
+void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const Step<T> *edges)
 {
     const int nf = (s.g.n_fdm_blocks[adjoint ? 1 : 0] + 7) / 8 * 8;
     const bool nt = stream_nt(s.g, sizeof(T), 1);
+    EdgeArgs<T> ea{};
+    int ne = 0;
+    if (edges && !adjoint) {
+        ea.Ua = edges->Ua; ea.Ub = edges->Ub; ea.Da = edges->Da; ea.Uc = edges->Uc; ea.Dc = edges->Dc;
+        ea.obs = edges->obs; ea.flux = edges->flux; ea.fluxscale = edges->fluxscale;
+        ea.srcterm = edges->srcterm; ea.c2 = edges->c2; ea.types1 = edges->types1;
+        ne = (int)((s.g.n_ec + 8 * BLOCK - 1) / (8 * BLOCK) * 8);
+    }
     if (adjoint) {
-        if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), dim3(nf), dim3(BLOCK), 0, st, s);
-        else hipLaunchKernelGGL((k_interior<T, true, false>), dim3(nf), dim3(BLOCK), 0, st, s);
+        if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), dim3(nf), dim3(BLOCK), 0, st, s, ea, 0);
+        else hipLaunchKernelGGL((k_interior<T, true, false>), dim3(nf), dim3(BLOCK), 0, st, s, ea, 0);
     } else {
-        const dim3 grid(nf + s.g.n_fem_blocks);
-        if (nt) hipLaunchKernelGGL((k_interior<T, false, true>), grid, dim3(BLOCK), 0, st, s);
-        else hipLaunchKernelGGL((k_interior<T, false, false>), grid, dim3(BLOCK), 0, st, s);
+        const dim3 grid(ne + nf + s.g.n_fem_blocks);
+        if (nt) hipLaunchKernelGGL((k_interior<T, false, true>), grid, dim3(BLOCK), 0, st, s, ea, ne);
+        else hipLaunchKernelGGL((k_interior<T, false, false>), grid, dim3(BLOCK), 0, st, s, ea, ne);
     }
 }
 
 template <typename T>
 void launch_bnd_fwd(const Step<T> &s, hipStream_t st)
 {
-    const long long n = s.g.n_fi + s.g.n_ec + s.g.nwd + s.g.nwo - (x_faces_absorbing(s.types1) ? x_face_rows(s.g) : 0);
+    const long long n = fwd_face_rows(s.g, s.types1) + s.g.n_ec;
     hipLaunchKernelGGL((k_bnd_fwd<T>), dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
+}
+
+template <typename T>
+void launch_bnd_fwd_faces(const Step<T> &s, hipStream_t st)
+{
+    const long long n = fwd_face_rows(s.g, s.types1);
+    if (n > 0) hipLaunchKernelGGL((k_bnd_fwd<T>), dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
+}
+
+template <typename T>
+void launch_bnd_fwd_edges(const Step<T> &s, hipStream_t st)
+{
+    if (s.g.n_ec > 0)
+        hipLaunchKernelGGL((k_bnd_fwd_edges<T>), dim3((unsigned)((s.g.n_ec + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, st, s);
 }
 
 static long long ecf_blocks(const Geo &g)
@@ -1412,7 +1529,7 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 // phase; the per-slot work is exactly that of the single-context kernels.
 
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK, interior_waves<T>()) void k_interior_b(const Step<T> *__restrict__ steps)
+__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior_b(const Step<T> *__restrict__ steps)
 {
     const Step<T> &s = steps[blockIdx.y];
     const int b = blockIdx.x;
@@ -1450,7 +1567,8 @@ void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t
         hipLaunchKernelGGL((k_interior_b<T, false, true>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
     else
         hipLaunchKernelGGL((k_interior_b<T, false, false>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
-    const long long m = g.n_fi + g.n_ec + g.nwd + g.nwo;
+    // every slot's own rows; the largest count is that of n_fi + n_ec
+    const long long m = g.n_fi + g.n_ec;
     hipLaunchKernelGGL((k_bnd_fwd_b<T>), dim3((unsigned)((m + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0, st, steps_dev);
 }
 
@@ -2093,8 +2211,10 @@ void launch_sum_J(const double *jmis, const double *jreg, int mode, double *J, h
 
 // explicit instantiations
 #define HYB_INST(T)                                                                               \
-    template void launch_interior<T>(const Step<T> &, bool, hipStream_t);                          \
+    template void launch_interior<T>(const Step<T> &, bool, hipStream_t, const Step<T> *);         \
     template void launch_bnd_fwd<T>(const Step<T> &, hipStream_t);                                \
+    template void launch_bnd_fwd_faces<T>(const Step<T> &, hipStream_t);                          \
+    template void launch_bnd_fwd_edges<T>(const Step<T> &, hipStream_t);                          \
     template void launch_bnd_adj<T>(const Step<T> &, hipStream_t);                                \
     template void launch_batch_fwd<T>(const Geo &, const Step<T> *, int, hipStream_t);            \
     template void launch_batch_adj<T>(const Geo &, const Step<T> *, int, hipStream_t);                                \
