@@ -38,17 +38,20 @@ def interior_bytes(n, C, s, streams=3):
     the minimum the leapfrog must move with perfect neighbour reuse: per FDM
     node read u^k, read u^{k-1}, write u^{k+1} (3 s, s the field element
     size).  FEM nodes: the same plus one coefficient per cube (s) and one
-    history write per stored node (s).  Rows of the two absorbing x faces
-    (the launch computes them): read u^k, write u^{k+1}.  streams=4 counts
+    history write per stored node (s).  Rows of the six absorbing faces
+    away from the edges (the launch computes them): read u^k, write
+    u^{k+1}.  The overlap copy: one write per node of omega_diamond (into the
+    grid level; the FEM rows read omega_o from the grid).  streams=4 counts
     what the FP32 increment form moves: read u^k, d^k, write d^{k+1}, u^{k+1}
-    (4 s per node, d^{k+1} also on the x faces)."""
+    (4 s per node, d^{k+1} also on the faces)."""
     m = streams
     fdm_int = (n - 1) ** 3 - (C - 3) ** 3 if C else (n - 1) ** 3
     fem = (C - 1) ** 3 if C else 0
-    xface = 2 * (n - 1) ** 2 * (m - 1) * s
+    faces = 6 * (n - 1) ** 2 * (m - 1) * s
     if not C:
-        return m * s * fdm_int + xface
-    return m * s * fdm_int + m * s * fem + s * C ** 3 + s * (C - 3) ** 3 + xface
+        return m * s * fdm_int + faces
+    copies = s * ((C - 3) ** 3 - (C - 5) ** 3)
+    return m * s * fdm_int + m * s * fem + s * C ** 3 + s * (C - 3) ** 3 + faces + copies
 
 
 def setup(wl_name, f32, seed=0):
@@ -560,9 +563,10 @@ def study_diff384(seed=0, n_dir=16):
 def study_scale512(seed=0):
     """Precision form at scale: 512^3 cells, FEM 160^3, nt = 2500.  Data from
     an FP64 sweep at the true conductivity plus 3% noise; the misfit gradient
-    at sigma = 0 (first CG iteration) with FP32 fields and BF16 increment
-    checkpoints, and with FP32 checkpoints, against the FP64 sweep with the
-    full FP64 FEM history."""
+    at sigma = 0 (first CG iteration) with FP32 fields and checkpoints of
+    each kind (BF16 increments, FP32 copies, 16-bit block-scaled increments),
+    against the FP64 sweep with the full FP64 FEM history: relative L2 and
+    element max-abs errors relative to the largest entry."""
     import torch
 
     from paper_1509_01399_amd import hyb, synth
@@ -589,7 +593,10 @@ def study_scale512(seed=0):
     out["f64_footprint_gb"] = round(hyb.hyb_footprint(ref.grid, ref.mesh, 2, ref.opts, wl.nt) / 1e9, 2)
     ref.close()
     torch.cuda.empty_cache()
-    for mode, name in ((2, "f32_bf16ckpt"), (1, "f32_f32ckpt")):
+    def mx(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+
+    for mode, name in ((2, "f32_bf16ckpt"), (1, "f32_f32ckpt"), (3, "f32_q16ckpt")):
         s = hyb.Solver(wl.n, C=wl.C, f32=True, store_mode=mode)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -602,6 +609,7 @@ def study_scale512(seed=0):
                      "trace_rel_l2": float((obs - obs64).norm() / obs64.norm()),
                      "residual_rel_l2": float((obs - obs64).norm() / res64.norm()),
                      "grad_rel_l2": float((g - g64).norm() / g64.norm()),
+                     "trace_max_abs": mx(obs, obs64), "grad_max_abs": mx(g, g64),
                      "J_rel": abs(J - J64) / abs(J64)}
         s.close()
         del obs, g

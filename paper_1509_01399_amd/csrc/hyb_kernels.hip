@@ -11,9 +11,11 @@
 //     element gather over the 8 cubes around a node reduces to six edge
 //     conductances kappa_e = sum over the 4 cubes of the edge of a_c * w_{c,e}
 //     (w from the element matrices computed on the host); no atomics.  The
-//     rows of absorbing faces, eq. (eq:abs2), away from the edges, the two
-//     overlap copies of Algorithm 2 steps 3-4 and the trace on an absorbing
-//     z+ face are computed here too.
+//     rows of absorbing faces, eq. (eq:abs2), away from the edges, the copy
+//     of Algorithm 2 step 3 (FEM values into the grid on omega_diamond) and
+//     the trace on an absorbing z+ face are computed here too.  Step 4 (grid
+//     values into the FEM level on omega_o) needs no copy: the FEM rows read
+//     those neighbours from the grid level.
 //   k_bnd_fwd: the rows of reflecting faces (the ghost-node Neumann/source
 //     rows of eq. (f)), the edges and the corners, with their part of the
 //     trace.  An edge or corner thread recomputes the values of the boundary
@@ -307,7 +309,7 @@ __device__ __forceinline__ void box_surface(long long t, int L, int &a, int &b, 
 }
 
 // Face-interior rows of the forward step on an absorbing face are computed
-// by the interior launch (fdm_tile_pairs), as are the two overlap copies; the
+// by the interior launch (fdm_tile_pairs), as is the overlap copy; the
 // boundary launch takes the faces whose rows are not absorbing at this step
 // (ghost-node Neumann or source rows), then the edges and corners.
 __host__ __device__ __forceinline__ long long face_area(const Geo &g, int f)
@@ -1054,7 +1056,7 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
         const int xe = x + e, i = xe - g.o[0];
-        const bool ib = g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
+        const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
         rcmp[e] = xe >= 1 && xe <= g.nx - 2 && y <= g.ny - 2;
         side[e] = ib && j >= 0 && j <= C1 && !(ii && j > 0 && j < C1);
         top[e] = ib && ii && j > 0 && j < C1;
@@ -1074,10 +1076,6 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
     const bool fy0 = !ADJ && y == 1 && ftype(s.types1, 2) == F_ABC;
     const bool fy1 = !ADJ && y == g.ny - 2 && ftype(s.types1, 3) == F_ABC;
     const bool az0 = !ADJ && ftype(s.types1, 4) == F_ABC, az1 = !ADJ && ftype(s.types1, 5) == F_ABC;
-    // Algorithm 2 step 4: new grid values on omega_o (the FEM box surface,
-    // FDM rows) go to the FEM level as well (structured box only: a general
-    // mesh copies them in its own launch)
-    const bool wo = !ADJ && g.has_fem && !g.gen;
     // absorbing x faces of the adjoint (as in fdm_tile)
     const bool xq0 = ADJ && x0 == 0 && x_face_in_tile(g, s.types1, s.types2, 0);
     const bool xq1 = ADJ && x0 <= g.nx - 2 && g.nx - 1 <= x0 + TX - 1 && x_face_in_tile(g, s.types1, s.types2, 1);
@@ -1158,8 +1156,6 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
             } else {
                 v[e] = (T)2 * cc[e] - uav[e] + c2 * L + w[e];
             }
-            if constexpr (!ADJ)
-                if (wo && ((side[e] && zs) || (top[e] && zt))) s.Vc[fidx(g, x + e - g.o[0], j, kz)] = v[e];
         }
         if constexpr (!ADJ) {
             // face rows next to this row (see fy0)
@@ -1255,7 +1251,14 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
     const T c2 = s.c2;
     const long long fy = g.fpx, fz = g.fplane;
     long long id = fidx(g, i, j, k0);
-    T vm = s.Vb[id - fz], v0 = s.Vb[id];
+    // Forward: the neighbours on omega_o (the box surface, FDM rows) are read
+    // from the grid level, which holds them (Algorithm 2 step 4 makes the
+    // FEM copy equal to it); the adjoint multipliers of the FEM level are 0
+    // there.  gq: grid index of the node.
+    const T *__restrict__ Gb = s.Ub;
+    long long gq = gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k0);
+    const bool sxm = !ADJ && i == 1, sxp = !ADJ && i == Cx - 1, sym = !ADJ && j == 1, syp = !ADJ && j == Cy - 1;
+    T vm = (!ADJ && k0 == 1) ? Gb[gq - g.plane] : s.Vb[id - fz], v0 = s.Vb[id];
     constexpr bool AV = ADJ && VM;
     const T *__restrict__ Mi = s.minv;
     T mm = 1, m0 = 1;  // minv of the planes k-1, k (AV)
@@ -1270,11 +1273,12 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
     const long long hpz = (long long)hn0 * hn1;
     bool qfull = false;  // ql, hl hold plane k of the gradient corners
     double ql[4] = {0, 0, 0, 0}, hl[4] = {0, 0, 0, 0};
-    for (int k = k0; k < k1; ++k, id += fz) {
+    for (int k = k0; k < k1; ++k, id += fz, gq += g.plane) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) ahi[q] = A[cb + (q & 1) + (q >> 1) * cpy + (long long)k * cpz];
-        const T vp = s.Vb[id + fz];
-        const T xm = s.Vb[id - 1], xp = s.Vb[id + 1], ym = s.Vb[id - fy], yp = s.Vb[id + fy];
+        const T vp = (!ADJ && k + 1 == Cz) ? Gb[gq + g.plane] : s.Vb[id + fz];
+        const T xm = sxm ? Gb[gq - 1] : s.Vb[id - 1], xp = sxp ? Gb[gq + 1] : s.Vb[id + 1];
+        const T ym = sym ? Gb[gq - g.px] : s.Vb[id - fy], yp = syp ? Gb[gq + g.px] : s.Vb[id + fy];
         // operand of the stencil: the level itself, or nu = minv * mu (AV)
         T mp = 1, nxm = xm, nxp = xp, nym = ym, nyp = yp;
         if constexpr (AV) {
@@ -1846,8 +1850,13 @@ __global__ __launch_bounds__(BLOCK) void k_export_level(Geo g, const T *U, const
     }
     if (!v || !g.has_fem) return;
     const long long nf = (long long)(g.C[0] + 1) * (g.C[1] + 1) * (g.C[2] + 1);
-    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nf; t += (long long)gridDim.x * BLOCK)
-        v[t] = (double)V[t];
+    for (long long t = (long long)blockIdx.x * BLOCK + threadIdx.x; t < nf; t += (long long)gridDim.x * BLOCK) {
+        // the forward level's box surface (omega_o) is the grid's
+        const int i = (int)(t % (g.C[0] + 1)), j = (int)((t / (g.C[0] + 1)) % (g.C[1] + 1));
+        const int k = (int)(t / ((long long)(g.C[0] + 1) * (g.C[1] + 1)));
+        const bool surf = i == 0 || i == g.C[0] || j == 0 || j == g.C[1] || k == 0 || k == g.C[2];
+        v[t] = (double)((!F && surf) ? U[gidx(g, g.o[0] + i, g.o[1] + j, g.o[2] + k)] : V[t]);
+    }
 }
 
 template <typename T>

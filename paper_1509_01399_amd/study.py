@@ -80,8 +80,8 @@ def refined_data(n, C, sig_true, nt, dt, omega, test, noise, seed, torch):
 def reconstruct(n, C, sig_true, nt, dt, omega, test, noise, seed=0, theta=1e-6, stab=0.05, max_iter=20,
                 gamma=0.01, given=None):
     """One row of Tables 1-2: returns max a of the post-processed image, its
-    error against the exact value in percent, the final iteration number and
-    the histories of J and ||g||.  Stops at ||g|| <= theta, when the norms
+    error against the exact value in percent, the final iteration number,
+    the histories of J and ||g|| and J at the true coefficient.  Stops at ||g|| <= theta, when the norms
     stabilise (relative change <= stab) or when no trial step lowers J.
     given: (clean, data) traces to use instead of the refined-grid solve."""
     import torch
@@ -97,9 +97,14 @@ def reconstruct(n, C, sig_true, nt, dt, omega, test, noise, seed=0, theta=1e-6, 
         # the coarse trace at the true coefficient: its distance to the
         # refined-grid data is the discretisation gap the inversion sees
         st = torch.as_tensor(sig_true, dtype=torch.float64, device="cuda")
-        gap = float(np.linalg.norm(s.forward(st, nt, dt, omega=omega).cpu().numpy() - clean) /
-                    np.linalg.norm(clean))
+        obs_true = s.forward(st, nt, dt, omega=omega)
+        gap = float(np.linalg.norm(obs_true.cpu().numpy() - clean) / np.linalg.norm(clean))
         d = torch.as_tensor(data, dtype=torch.float64, device="cuda")
+        # J at the true coefficient (eq. (functional) with its Tikhonov term):
+        # how far below J at a = 1 the data let the minimisation go
+        s.adjoint(obs_true - d, mode=0)
+        _, J_true = s.gradient()
+        del obs_true
         sig = torch.zeros((C,) * 3, dtype=torch.float64, device="cuda")
         state = hyb.hyb_cg_state()
         gn, Js, iterates = [], [], []
@@ -133,6 +138,7 @@ def reconstruct(n, C, sig_true, nt, dt, omega, test, noise, seed=0, theta=1e-6, 
     row.update(summary(a))
     row["at_min_J"] = dict(iteration=best, **summary(1.0 + iterates[best]))
     row.update({"J": [float(x) for x in Js], "J_final": float(state.J_next), "gnorm": [float(x) for x in gn],
+                "J_true": float(J_true), "J_true_over_J0": round(float(J_true) / float(Js[0]), 4),
                 "refined_vs_coarse_trace": round(gap, 4), "seconds": round(time.perf_counter() - t0, 2)})
     return row
 
