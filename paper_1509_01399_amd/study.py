@@ -139,6 +139,8 @@ def reconstruct(n, C, sig_true, nt, dt, omega, test, noise, seed=0, theta=1e-6, 
     row["at_min_J"] = dict(iteration=best, **summary(1.0 + iterates[best]))
     row.update({"J": [float(x) for x in Js], "J_final": float(state.J_next), "gnorm": [float(x) for x in gn],
                 "J_true": float(J_true), "J_true_over_J0": round(float(J_true) / float(Js[0]), 4),
+                # its Tikhonov part, 0.5 gamma |sigma_true|^2 (h^3 cell weight)
+                "J_true_tikhonov": float(0.5 * gamma * np.sum(np.asarray(sig_true, dtype=np.float64) ** 2) / n ** 3),
                 "refined_vs_coarse_trace": round(gap, 4), "seconds": round(time.perf_counter() - t0, 2)})
     return row
 
@@ -160,4 +162,4 @@ def tables(n=96, omegas=(20.0, 30.0, 40.0, 50.0, 60.0), noises=(0.03, 0.10), tes
             for om in omegas:
                 rows.append(reconstruct(n, C, sig_true, nt, dt, om, test, noise, seed=seed + 1, **kw))
     return {"n": n, "C": C, "nt": nt, "dt": dt, "T": T, "scatterers": f"two {edge}^3-cell cubes of a = 4",
-            "rows": rows}
+            "gamma": kw.get("gamma", 0.01), "rows": rows}
