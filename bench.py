@@ -785,6 +785,8 @@ def main():
                     help="full-size check of a form instead of the benchmark line")
     ap.add_argument("--gamma", type=float, default=None,
                     help="Tikhonov weight of the reconstruction study (default: the paper's 0.01)")
+    ap.add_argument("--noise-kind", choices=["additive", "relative"], default="additive",
+                    help="noise of the reconstruction study's data (default: additive, max-scaled)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus must be 1 (a multi-GPU split of the "
@@ -806,7 +808,8 @@ def main():
             res = general_mesh(args.workload, args.steps, args.warmup, f32=args.probe_f32)
         elif args.study == "recon":
             from paper_1509_01399_amd import study
-            res = study.tables(**({} if args.gamma is None else {"gamma": args.gamma}))
+            kw = {} if args.gamma is None else {"gamma": args.gamma}
+            res = study.tables(noise_kind=args.noise_kind, **kw)
         else:
             res = study_diff384() if args.study == "diff384" else study_scale512()
         print(json.dumps(res), flush=True)

@@ -62,9 +62,10 @@ def stabilised(gnorms, stab):
     return len(gnorms) >= 2 and abs(gnorms[-1] - gnorms[-2]) <= stab * gnorms[-2]
 
 
-def refined_data(n, C, sig_true, nt, dt, omega, test, noise, seed, torch):
+def refined_data(n, C, sig_true, nt, dt, omega, test, noise, seed, torch, noise_kind="additive"):
     """Data of one test: forward solve on the refined grid (2n cells, FEM box
-    2C, 2nt steps of dt/2), restricted to the coarse grid, plus noise."""
+    2C, 2nt steps of dt/2), restricted to the coarse grid, plus noise
+    (synth.add_noise of the given kind)."""
     fine = hyb.Solver(2 * n, C=2 * C)
     try:
         if test == 1:
@@ -74,11 +75,11 @@ def refined_data(n, C, sig_true, nt, dt, omega, test, noise, seed, torch):
         clean = restrict_trace(obs).cpu().numpy().copy()
     finally:
         fine.close()
-    return clean, synth.add_noise(clean, noise, seed)
+    return clean, synth.add_noise(clean, noise, seed, noise_kind)
 
 
 def reconstruct(n, C, sig_true, nt, dt, omega, test, noise, seed=0, theta=1e-6, stab=0.05, max_iter=20,
-                gamma=0.01, given=None):
+                gamma=0.01, given=None, noise_kind="additive"):
     """One row of Tables 1-2: returns max a of the post-processed image, its
     error against the exact value in percent, the final iteration number,
     the histories of J and ||g|| and J at the true coefficient.  Stops at ||g|| <= theta, when the norms
@@ -87,7 +88,7 @@ def reconstruct(n, C, sig_true, nt, dt, omega, test, noise, seed=0, theta=1e-6, 
     import torch
     t0 = time.perf_counter()
     if given is None:
-        clean, data = refined_data(n, C, sig_true, nt, dt, omega, test, noise, seed, torch)
+        clean, data = refined_data(n, C, sig_true, nt, dt, omega, test, noise, seed, torch, noise_kind)
     else:
         clean, data = given
     s = hyb.Solver(n, C=C, gamma=gamma)
@@ -162,4 +163,4 @@ def tables(n=96, omegas=(20.0, 30.0, 40.0, 50.0, 60.0), noises=(0.03, 0.10), tes
             for om in omegas:
                 rows.append(reconstruct(n, C, sig_true, nt, dt, om, test, noise, seed=seed + 1, **kw))
     return {"n": n, "C": C, "nt": nt, "dt": dt, "T": T, "scatterers": f"two {edge}^3-cell cubes of a = 4",
-            "gamma": kw.get("gamma", 0.01), "rows": rows}
+            "gamma": kw.get("gamma", 0.01), "noise_kind": kw.get("noise_kind", "additive"), "rows": rows}

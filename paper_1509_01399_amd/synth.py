@@ -172,13 +172,18 @@ def sigma_for(wl: Workload, seed=0):
     raise ValueError(wl.inclusions)
 
 
-def add_noise(obs, level, seed):
-    """Additive Gaussian noise scaled by the largest absolute datum:
-    data = obs + level * max|obs| * xi, xi ~ N(0,1) i.i.d."""
+def add_noise(obs, level, seed, kind="additive"):
+    """Gaussian noise, xi ~ N(0,1) i.i.d.: additive and scaled by the largest
+    absolute datum, data = obs + level * max|obs| * xi (the workloads), or
+    relative to each datum, data = obs * (1 + level * xi)."""
     if level == 0:
         return np.array(obs, dtype=np.float64, copy=True)
     rng = np.random.default_rng(seed)
     obs = np.asarray(obs, dtype=np.float64)
+    if kind == "relative":
+        return obs * (1.0 + level * rng.standard_normal(obs.shape))
+    if kind != "additive":
+        raise ValueError(f"noise kind {kind!r}")
     return obs + level * np.max(np.abs(obs)) * rng.standard_normal(obs.shape)
 
 

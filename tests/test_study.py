@@ -36,3 +36,22 @@ def test_stopping_rule():
     assert not study.stabilised([1.0, 0.9], 0.05)
     assert study.stabilised([1.0, 0.96], 0.05)
     assert study.stabilised([1.0, 1.04], 0.05)
+
+
+def test_add_noise_kinds():
+    """Both noise readings: additive noise has standard deviation level *
+    max|obs| everywhere; relative noise scales each datum (zero data stay
+    zero) with standard deviation level of the ratio."""
+    import numpy as np
+
+    from paper_1509_01399_amd import synth
+    rng = np.random.default_rng(3)
+    obs = rng.standard_normal((40, 50, 50))
+    obs[:5] = 0.0
+    add = synth.add_noise(obs, 0.03, 1)
+    assert abs(np.std(add - obs) / (0.03 * np.max(np.abs(obs))) - 1.0) < 0.02
+    rel = synth.add_noise(obs, 0.03, 1, kind="relative")
+    assert np.all(rel[:5] == 0.0)
+    ratio = rel[5:] / obs[5:]
+    assert abs(np.std(ratio - 1.0) / 0.03 - 1.0) < 0.02
+    assert np.array_equal(synth.add_noise(obs, 0.0, 1, kind="relative"), obs)
