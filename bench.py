@@ -149,11 +149,17 @@ def cpu_baseline(wl, dt, window):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1509_01399_amd", "csrc")
     # the kernels, their launchers (grid, tiles, cache hints) and the
     # parameter blocks they read
     for f in ("hyb_kernels.hip", "hyb_internal.h"):
-        with open(os.path.join(ROOT, "paper_1509_01399_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    # and the host function that fixes the tiles and z chunks
+    with open(os.path.join(csrc, "hyb_api.cpp"), "rb") as fh:
+        api = fh.read()
+    a = api.find(b"void setup_geo(")
+    h.update(api[a:api.find(b"\n}\n", a)] if a >= 0 else api)
     return h.hexdigest()[:16]
 
 

@@ -375,14 +375,15 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     g.fdm_tiles[1] = (int)ceil_div(g.ny - 2, TY_FDM);
     const long long txy = (long long)g.fdm_tiles[0] * g.fdm_tiles[1];
     // Planes per z chunk, measured per precision and sweep on 257^3 grids
-    // (us per step, forward / adjoint, chunks of 4 / 6 / 8 / 12 / 16):
-    // FP64 forward 94.3 / 96.2 / 95.7 / 96.9 / 107.8, adjoint 110.9 / 112.7 /
-    // 106.5 / 119.3 / 106.1; FP32 (chunks of 6 / 8 / 12) forward 81.9 / 81.9
-    // / 88.7, adjoint 94.3 / 95.8 / 100.6.  Chunk counts that
-    // divide into whole rounds of resident blocks balance best; small grids
-    // keep 4 planes for parallelism.
+    // (us per step).  Adjoint, chunks of 4 / 6 / 8 / 12 / 16: FP64 110.9 /
+    // 112.7 / 106.5 / 119.3 / 106.1; FP32 (6 / 8 / 12) 94.3 / 95.8 / 100.6.
+    // Forward with the column-pair tile and its face rows, chunks of 3 / 4 /
+    // 6 / 8 / 10 / 12 / 16: FP64 82.9 / 79.9 / 80.8 / 78.3 / 85.0 / 79.9 /
+    // 87.9; FP32 (4 / 6 / 8) 75.0 / 73.6 / 80.3.  Chunk counts that divide
+    // into whole rounds of resident blocks balance best; small grids keep 4
+    // planes for parallelism.
     const bool big = g.nz > 200;
-    const int zc[2] = {esz == 4 && big ? 6 : 4, big ? (esz == 4 ? 6 : 8) : 4};
+    const int zc[2] = {big ? (esz == 4 ? 6 : 8) : 4, big ? (esz == 4 ? 6 : 8) : 4};
     for (int a = 0; a < 2; ++a) {
         g.zc_fdm[a] = zc[a];
         g.fdm_zt[a] = (int)ceil_div(g.nz - 2, zc[a]);
