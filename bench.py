@@ -147,19 +147,25 @@ def cpu_baseline(wl, dt, window):
 
 
 def kernel_source_hash():
+    """Hash of the code (comments and blank space left out) of the kernels,
+    their launchers (grid, tiles, cache hints), the parameter blocks they
+    read and the host function that fixes the tiles and z chunks."""
     import hashlib
+    import re
+
+    def code(text):
+        text = re.sub(r"//[^\n]*", "", text)
+        return re.sub(r"\s+", " ", text).strip().encode()
+
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1509_01399_amd", "csrc")
-    # the kernels, their launchers (grid, tiles, cache hints) and the
-    # parameter blocks they read
     for f in ("hyb_kernels.hip", "hyb_internal.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    # and the host function that fixes the tiles and z chunks
-    with open(os.path.join(csrc, "hyb_api.cpp"), "rb") as fh:
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(code(fh.read()))
+    with open(os.path.join(csrc, "hyb_api.cpp")) as fh:
         api = fh.read()
-    a = api.find(b"void setup_geo(")
-    h.update(api[a:api.find(b"\n}\n", a)] if a >= 0 else api)
+    a = api.find("void setup_geo(")
+    h.update(code(api[a:api.find("\n}\n", a)] if a >= 0 else api))
     return h.hexdigest()[:16]
 
 

@@ -1411,9 +1411,10 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
     }
 }
 
-// FDM blocks first (their count rounded up to a multiple of 8 for the XCD
-// remap), then, in the forward sweep, the FEM blocks.  The FEM rows of the
-// adjoint run in the boundary launch.
+// Block order of the interior launch: in the forward sweep the previous
+// step's edge and corner rows (when given), then the FDM tiles, then the FEM
+// tiles; each range is rounded up to a multiple of 8 for the XCD remap.  The
+// FEM rows of the adjoint run in the boundary launch.
 //
 // FP32: at most 64 VGPRs (8 waves per SIMD) in the adjoint, 72 (7 waves) in
 // the forward, whose tile also takes the face rows: under 64 it spilled and
