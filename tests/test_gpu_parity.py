@@ -66,7 +66,7 @@ def test_forward_shapes_and_bcs(env, orc, case):
     elif case == "fdm_waveguide":
         n, C, o, bc = (3, 2, 70), 0, None, (N, N, N, N, A, S)
     elif case == "fdm_thin_abc":
-        # one interior column: both absorbing x-face rows from one wave
+        # one interior column: both absorbing x-face rows from one lane's column pair
         n, C, o, bc = (2, 9, 40), 0, None, (A, A, N, A, A, S)
     elif case == "hyb_ragged":
         n, C, o, bc = (67, 45, 29), 9, (40, 17, 11), (A, A, A, A, A, S)

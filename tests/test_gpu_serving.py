@@ -120,8 +120,8 @@ def test_batch_slot_errors():
 
 @pytest.mark.parametrize("f32", [False, True])
 def test_batch_mixed_face_kinds(f32, orc):
-    """Slots of one grid whose x faces differ share the batched launches: the
-    absorbing x-face rows are computed by the interior launch, Neumann rows
+    """Slots of one grid whose faces differ share the batched launches: the
+    rows of absorbing faces are computed by the interior launch, Neumann rows
     by the boundary launch, each slot by its own face conditions.  Every
     slot's trace, misfit and gradient against the oracle with the same face
     conditions (bars as in test_batched_equals_alone_and_oracle)."""
