@@ -854,7 +854,8 @@ hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, doub
             launch_bnd_fwd_edges<T>(prev, st);
             lag = false;
         }
-        launch_interior<T>(s, false, st, lag ? &prev : nullptr);
+        const EdgeArgs<T> pe = edge_args(prev);
+        launch_interior<T>(s, false, st, lag ? &pe : nullptr);
         if (c->gen) launch_gen_fwd<T>(gen_args<T>(c, s), st);
         launch_bnd_fwd_faces<T>(s, st);
         prev = s;
@@ -1735,6 +1736,11 @@ struct hyb_batch {
                                    // regularisation
         double sigma_max = 0.0;    // the caller's max sigma, used for the CFL check
         int lane = 0;
+        // the slot's last planned forward step, whose edge and corner rows
+        // its next forward launch runs (lag set) or a launch of their own
+        Step<float> prevf{};
+        Step<double> prevd{};
+        bool lag = false;
     };
     // one lane per stream: slots of different lanes run concurrently on the
     // device; each lane has its own ring of step-argument staging buffers
@@ -1844,13 +1850,85 @@ void finish_adjoint(hyb_batch::Slot &sl)
     (void)hipEventRecord(sl.done, c->stream);
 }
 
-// One planned launch group or slot transition, in stream order.
+// One planned launch group, edge launch or slot transition, in stream order.
 struct Action {
-    int kind;        // 0 launch group, 1 forward ended, 2 adjoint ended
+    int kind;        // 0 launch group, 1 forward ended, 2 adjoint ended, 3 edge rows of a step
     int lane, slot;  // lane of the work; slot for transitions / first slot of a group
     int adjoint, n, f32;
-    size_t offset;   // byte offset of the group's step array in the lane buffer
+    size_t offset;   // byte offset of the group's step array in the lane buffer (kind 3: of the
+                     // step in the host-only buffer)
+    int edges = 0;   // forward group: the lane buffer holds its edge arguments at eoff
+    size_t eoff = 0;
+    long long face_rows = 0;  // forward group: largest count of reflecting face rows
 };
+
+template <typename T> Step<T> &slot_prev(hyb_batch::Slot &sl);
+template <> Step<float> &slot_prev<float>(hyb_batch::Slot &sl) { return sl.prevf; }
+template <> Step<double> &slot_prev<double>(hyb_batch::Slot &sl) { return sl.prevd; }
+
+// append n objects to a staging buffer at a 256-byte boundary; returns their offset
+size_t stage_put(std::vector<char> &B, const void *p, size_t bytes)
+{
+    const size_t off = (B.size() + 255) / 256 * 256;
+    B.resize(off + bytes);
+    std::memcpy(B.data() + off, p, bytes);
+    return off;
+}
+
+// Plan one launch group of slots ids (one phase, one geometry, lane `lane`).
+// A forward group carries the edge and corner rows of each slot's previous
+// step in its interior launch (as the single-context sweep does); a slot
+// whose face conditions change between the two steps gets them in a launch
+// of their own first (they recompute reflecting face rows from their own
+// step's levels, which the interior launch overwrites on faces that absorb).
+template <typename T>
+void plan_group(hyb_batch *b, const std::vector<int> &ids, bool adj, int lane, std::vector<char> &B,
+                std::vector<char> &H, std::vector<Action> &acts)
+{
+    const size_t n = ids.size();
+    const int f32 = sizeof(T) == 4 ? 1 : 0;
+    std::vector<Step<T>> steps(n);
+    std::vector<EdgeArgs<T>> edges(n, EdgeArgs<T>{});
+    bool any = false;
+    long long frows = 0;
+    for (size_t j = 0; j < n; ++j) {
+        hyb_batch::Slot &sl = b->slots[ids[j]];
+        if (adj) {
+            steps[j] = adj_step_args<T>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.c->resbuf, 0);
+            continue;
+        }
+        steps[j] = fwd_step_args<T>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.obs);
+        Step<T> &prev = slot_prev<T>(sl);
+        if (sl.lag && prev.types1 != steps[j].types1) {
+            acts.push_back(Action{3, lane, ids[j], 0, 1, f32, stage_put(H, &prev, sizeof prev)});
+            sl.lag = false;
+        }
+        if (sl.lag) {
+            edges[j] = edge_args(prev);
+            any = true;
+        }
+        frows = std::max(frows, fwd_face_row_count(sl.c->g, steps[j].types1));
+        prev = steps[j];
+        sl.lag = true;
+    }
+    Action a{0, lane, ids[0], adj ? 1 : 0, (int)n, f32, stage_put(B, steps.data(), n * sizeof(Step<T>))};
+    if (any) {
+        a.edges = 1;
+        a.eoff = stage_put(B, edges.data(), n * sizeof(EdgeArgs<T>));
+    }
+    a.face_rows = frows;
+    acts.push_back(a);
+}
+
+// the edge and corner rows of a slot's last forward step, once its sweep ends
+template <typename T>
+void plan_flush(hyb_batch::Slot &sl, int id, std::vector<char> &H, std::vector<Action> &acts)
+{
+    if (!sl.lag) return;
+    const Step<T> &prev = slot_prev<T>(sl);
+    acts.push_back(Action{3, sl.lane, id, 0, 1, sizeof(T) == 4 ? 1 : 0, stage_put(H, &prev, sizeof prev)});
+    sl.lag = false;
+}
 
 bool same_geometry(const hyb_ctx *a, const hyb_ctx *b)
 {
@@ -1869,6 +1947,7 @@ namespace {
 hyb_status batch_plan_run(hyb_batch *b, int ticks, int32_t *n_first)
 {
     std::vector<std::vector<char>> buf(b->lanes.size());
+    std::vector<char> hbuf;  // steps of the edge launches, read on the host only
     std::vector<Action> acts;
     int first = -1;
     for (int t = 0; t < ticks; ++t) {
@@ -1893,27 +1972,16 @@ hyb_status batch_plan_run(hyb_batch *b, int ticks, int32_t *n_first)
             const auto &ids = groups[q];
             const hyb_batch::Slot &s0 = b->slots[ids[0]];
             const bool adj = gphase[q] == 2, f32 = s0.c->f32;
-            std::vector<char> &B = buf[s0.lane];
-            const size_t off = (B.size() + 255) / 256 * 256;
-            const size_t one = f32 ? sizeof(Step<float>) : sizeof(Step<double>);
-            B.resize(off + ids.size() * one);
-            for (size_t j = 0; j < ids.size(); ++j) {
-                hyb_batch::Slot &sl = b->slots[ids[j]];
-                char *dst = B.data() + off + j * one;
-                if (f32) {
-                    const Step<float> st = adj ? adj_step_args<float>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.c->resbuf, 0)
-                                               : fwd_step_args<float>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.obs);
-                    std::memcpy(dst, &st, one);
-                } else {
-                    const Step<double> st = adj ? adj_step_args<double>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.c->resbuf, 0)
-                                                : fwd_step_args<double>(sl.c, sl.k, sl.ia, sl.ib, sl.ic, sl.obs);
-                    std::memcpy(dst, &st, one);
-                }
-            }
-            acts.push_back(Action{0, s0.lane, ids[0], adj ? 1 : 0, (int)ids.size(), f32 ? 1 : 0, off});
+            if (f32) plan_group<float>(b, ids, adj, s0.lane, buf[s0.lane], hbuf, acts);
+            else plan_group<double>(b, ids, adj, s0.lane, buf[s0.lane], hbuf, acts);
             for (int id : ids) {
-                const int ev = advance_slot(b->slots[id]);
-                if (ev) trans.push_back(Action{ev, b->slots[id].lane, id, 0, 0, b->slots[id].c->f32 ? 1 : 0, 0});
+                hyb_batch::Slot &sl = b->slots[id];
+                const int ev = advance_slot(sl);
+                if (ev == 1) {
+                    if (sl.c->f32) plan_flush<float>(sl, id, hbuf, trans);
+                    else plan_flush<double>(sl, id, hbuf, trans);
+                }
+                if (ev) trans.push_back(Action{ev, sl.lane, id, 0, 0, sl.c->f32 ? 1 : 0, 0});
             }
         }
         acts.insert(acts.end(), trans.begin(), trans.end());
@@ -1950,8 +2018,10 @@ hyb_status batch_plan_run(hyb_batch *b, int ticks, int32_t *n_first)
                     launch_bnd_adj<T>(s1, st);
                     launch_interior<T>(s1, true, st);
                 } else {
-                    launch_interior<T>(s1, false, st);
-                    launch_bnd_fwd<T>(s1, st);
+                    EdgeArgs<T> e1{};
+                    if (a.edges) std::memcpy(&e1, buf[a.lane].data() + a.eoff, sizeof e1);
+                    launch_interior<T>(s1, false, st, a.edges ? &e1 : nullptr);
+                    launch_bnd_fwd_faces<T>(s1, st);
                 }
             };
             if (a.f32) one(0.0f);
@@ -1959,13 +2029,26 @@ hyb_status batch_plan_run(hyb_batch *b, int ticks, int32_t *n_first)
         } else if (a.kind == 0) {
             const Geo &g = sl.c->g;
             const hipStream_t st = b->lanes[a.lane].st;
-            if (a.f32) {
-                const Step<float> *d = (const Step<float> *)(dbase[a.lane] + a.offset);
-                if (a.adjoint) launch_batch_adj<float>(g, d, a.n, st); else launch_batch_fwd<float>(g, d, a.n, st);
-            } else {
-                const Step<double> *d = (const Step<double> *)(dbase[a.lane] + a.offset);
-                if (a.adjoint) launch_batch_adj<double>(g, d, a.n, st); else launch_batch_fwd<double>(g, d, a.n, st);
-            }
+            auto group = [&](auto tag) {
+                using T = decltype(tag);
+                const Step<T> *d = (const Step<T> *)(dbase[a.lane] + a.offset);
+                if (a.adjoint) launch_batch_adj<T>(g, d, a.n, st);
+                else
+                    launch_batch_fwd<T>(g, d, a.edges ? (const EdgeArgs<T> *)(dbase[a.lane] + a.eoff) : nullptr,
+                                        a.n, a.face_rows, st);
+            };
+            if (a.f32) group(0.0f);
+            else group(0.0);
+        } else if (a.kind == 3) {
+            const hipStream_t st = b->lanes[a.lane].st;
+            auto flush = [&](auto tag) {
+                using T = decltype(tag);
+                Step<T> p;
+                std::memcpy(&p, hbuf.data() + a.offset, sizeof p);
+                launch_bnd_fwd_edges<T>(p, st);
+            };
+            if (a.f32) flush(0.0f);
+            else flush(0.0);
         } else if (a.kind == 1) {
             if (a.f32) finish_forward<float>(sl); else finish_forward<double>(sl);
         } else {
@@ -1994,7 +2077,9 @@ hyb_status hyb_batch_create(int32_t max_slots, void *hip_stream, hyb_batch **out
     b->ring = STAGE_RING;
     // per plan and lane: TICKS_PER_PLAN ticks of at most max_slots step
     // structs in at most max_slots groups, each group aligned to 256 bytes
-    b->entry = (size_t)TICKS_PER_PLAN * (size_t)max_slots * (sizeof(Step<double>) + 256);
+    // per slot and tick: its step and its edge arguments, each group's two
+    // arrays at 256-byte boundaries
+    b->entry = (size_t)TICKS_PER_PLAN * (size_t)max_slots * (sizeof(Step<double>) + sizeof(EdgeArgs<double>) + 512);
     bool ok = hipHostMalloc((void **)&b->h_J, 4 * sizeof(double) * max_slots) == hipSuccess &&
               lane_of(b, (hipStream_t)hip_stream) == 0;
     for (int q = 0; ok && q < max_slots; ++q) {
@@ -2053,6 +2138,7 @@ hyb_status hyb_batch_submit(hyb_batch *b, hyb_ctx *c, const double *sigma, doubl
     sl.data = data; sl.obs = obs; sl.grad = grad;
     sl.sigma_max = sigma_max;
     sl.lane = lane;
+    sl.lag = false;
     c->in_batch = true;
     *slot = q;
     return HYB_OK;

@@ -114,11 +114,21 @@ struct EdgeArgs {
     int types1;
 };
 
+template <typename T>
+inline EdgeArgs<T> edge_args(const Step<T> &s)
+{
+    EdgeArgs<T> e;
+    e.Ua = s.Ua; e.Ub = s.Ub; e.Da = s.Da; e.Uc = s.Uc; e.Dc = s.Dc;
+    e.obs = s.obs; e.flux = s.flux; e.fluxscale = s.fluxscale;
+    e.srcterm = s.srcterm; e.c2 = s.c2; e.types1 = s.types1;
+    return e;
+}
+
 // ---- launchers (hyb_kernels.hip) ----
 // edges: the step whose edge and corner rows the forward launch also runs
 // (null: none)
 template <typename T>
-void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const Step<T> *edges = nullptr);
+void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeArgs<T> *edges = nullptr);
 // boundary launch of a forward step: reflecting face rows, edges and corners
 template <typename T> void launch_bnd_fwd(const Step<T> &s, hipStream_t st);
 // the same split in two: the reflecting face rows (no launch when every face
@@ -127,8 +137,16 @@ template <typename T> void launch_bnd_fwd_faces(const Step<T> &s, hipStream_t st
 template <typename T> void launch_bnd_fwd_edges(const Step<T> &s, hipStream_t st);
 template <typename T> void launch_bnd_adj(const Step<T> &s, hipStream_t st);
 
-// batched steps: steps_dev[n] device array, all of geometry g
-template <typename T> void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st);
+// rows of the forward boundary launch that face conditions `types` give
+long long fwd_face_row_count(const Geo &g, int types);
+
+// batched steps: steps_dev[n] device array, all of geometry g.  Forward:
+// edges_dev[n] (or null) holds, per slot, the step whose edge and corner rows
+// the interior launch also runs (Uc null: none); face_rows is the largest
+// count of reflecting face rows over the slots (0: no boundary launch).
+template <typename T>
+void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, const EdgeArgs<T> *edges_dev, int n,
+                      long long face_rows, hipStream_t st);
 template <typename T> void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st);
 
 // a = 1 + sigma on free cubes (1 elsewhere); scal[0] = max sigma over free

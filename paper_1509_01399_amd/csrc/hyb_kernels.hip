@@ -1441,8 +1441,7 @@ __global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(
 {
     int b = blockIdx.x;
     if constexpr (!ADJ) {
-        // the previous step's edge and corner rows first (ne: a multiple of
-        // 8, so the tile numbering below keeps its XCD mapping)
+        // the previous step's edge and corner rows first
         if (b < ne) {
             edge_row_of<T>(s, ea, (long long)b * BLOCK + threadIdx.x);
             return;
@@ -1468,18 +1467,20 @@ static bool stream_nt(const Geo &g, size_t esz, int slots)
     return arrays * (double)g.plane * g.nz * esz * slots > 224.0 * (1 << 20);
 }
 
+// blocks of the edge and corner rows carried by a forward interior launch, a
+// multiple of 8 so that the tile numbering after them keeps its XCD mapping
+static int edge_blocks8(const Geo &g) { return (int)((g.n_ec + 8 * BLOCK - 1) / (8 * BLOCK) * 8); }
+
 template <typename T>
-void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const Step<T> *edges)
+void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeArgs<T> *edges)
 {
     const int nf = (s.g.n_fdm_blocks[adjoint ? 1 : 0] + 7) / 8 * 8;
     const bool nt = stream_nt(s.g, sizeof(T), 1);
     EdgeArgs<T> ea{};
     int ne = 0;
     if (edges && !adjoint) {
-        ea.Ua = edges->Ua; ea.Ub = edges->Ub; ea.Da = edges->Da; ea.Uc = edges->Uc; ea.Dc = edges->Dc;
-        ea.obs = edges->obs; ea.flux = edges->flux; ea.fluxscale = edges->fluxscale;
-        ea.srcterm = edges->srcterm; ea.c2 = edges->c2; ea.types1 = edges->types1;
-        ne = (int)((s.g.n_ec + 8 * BLOCK - 1) / (8 * BLOCK) * 8);
+        ea = *edges;
+        ne = edge_blocks8(s.g);
     }
     if (adjoint) {
         if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), dim3(nf), dim3(BLOCK), 0, st, s, ea, 0);
@@ -1534,10 +1535,19 @@ void launch_bnd_adj(const Step<T> &s, hipStream_t st)
 // phase; the per-slot work is exactly that of the single-context kernels.
 
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior_b(const Step<T> *__restrict__ steps)
+__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior_b(
+    const Step<T> *__restrict__ steps, const EdgeArgs<T> *__restrict__ edges, int ne)
 {
     const Step<T> &s = steps[blockIdx.y];
-    const int b = blockIdx.x;
+    int b = blockIdx.x;
+    if constexpr (!ADJ) {
+        // the slot's previous step's edge and corner rows first
+        if (b < ne) {
+            if (edges[blockIdx.y].Uc) edge_row_of<T>(s, edges[blockIdx.y], (long long)b * BLOCK + threadIdx.x);
+            return;
+        }
+        b -= ne;
+    }
     const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
     if (b < nf) {
         if constexpr (pair_tile<T, ADJ>()) fdm_tile_pairs<T, ADJ, NT>(s, b);
@@ -1546,10 +1556,15 @@ __global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior_
     else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
 }
 
+// faces_only: the slot's reflecting face rows (its edge rows run lagged in
+// the next interior launch), else those and its edge and corner rows
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_bnd_fwd_b(const Step<T> *__restrict__ steps)
+__global__ __launch_bounds__(BLOCK) void k_bnd_fwd_b(const Step<T> *__restrict__ steps, int faces_only)
 {
-    bnd_fwd_body<T>(steps[blockIdx.y], (long long)blockIdx.x * BLOCK + threadIdx.x);
+    const Step<T> &s = steps[blockIdx.y];
+    const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (faces_only && t >= fwd_face_rows(s.g, s.types1)) return;
+    bnd_fwd_body<T>(s, t);
 }
 
 template <typename T>
@@ -1564,17 +1579,27 @@ __global__ __launch_bounds__(BLOCK) void k_bnd_adj_face_b(const Step<T> *__restr
     bnd_adj_face_body<T>(steps[blockIdx.y], blockIdx.x);
 }
 
+long long fwd_face_row_count(const Geo &g, int types) { return fwd_face_rows(g, types); }
+
+// With edges_dev the edge rows of each slot's previous step ride in the
+// interior launch and the boundary launch takes the reflecting face rows
+// alone; without it the boundary launch takes every slot's face, edge and
+// corner rows.
 template <typename T>
-void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t st)
+void launch_batch_fwd(const Geo &g, const Step<T> *steps_dev, const EdgeArgs<T> *edges_dev, int n,
+                      long long face_rows, hipStream_t st)
 {
     const int nf = (g.n_fdm_blocks[0] + 7) / 8 * 8;
+    const int ne = edges_dev ? edge_blocks8(g) : 0;
+    const dim3 grid(ne + nf + g.n_fem_blocks, n);
     if (stream_nt(g, sizeof(T), n))
-        hipLaunchKernelGGL((k_interior_b<T, false, true>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
+        hipLaunchKernelGGL((k_interior_b<T, false, true>), grid, dim3(BLOCK), 0, st, steps_dev, edges_dev, ne);
     else
-        hipLaunchKernelGGL((k_interior_b<T, false, false>), dim3(nf + g.n_fem_blocks, n), dim3(BLOCK), 0, st, steps_dev);
-    // every slot's own rows; the largest count is that of n_fi + n_ec
-    const long long m = g.n_fi + g.n_ec;
-    hipLaunchKernelGGL((k_bnd_fwd_b<T>), dim3((unsigned)((m + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0, st, steps_dev);
+        hipLaunchKernelGGL((k_interior_b<T, false, false>), grid, dim3(BLOCK), 0, st, steps_dev, edges_dev, ne);
+    const long long m = edges_dev ? face_rows : face_rows + g.n_ec;
+    if (m > 0)
+        hipLaunchKernelGGL((k_bnd_fwd_b<T>), dim3((unsigned)((m + BLOCK - 1) / BLOCK), n), dim3(BLOCK), 0, st,
+                           steps_dev, edges_dev ? 1 : 0);
 }
 
 template <typename T>
@@ -1587,9 +1612,11 @@ void launch_batch_adj(const Geo &g, const Step<T> *steps_dev, int n, hipStream_t
     if (nfb > 0) hipLaunchKernelGGL((k_bnd_adj_face_b<T>), dim3((unsigned)nfb, n), dim3(BLOCK), 0, st, steps_dev);
     const int nf = (g.n_fdm_blocks[1] + 7) / 8 * 8;
     if (stream_nt(g, sizeof(T), n))
-        hipLaunchKernelGGL((k_interior_b<T, true, true>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev);
+        hipLaunchKernelGGL((k_interior_b<T, true, true>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev,
+                           (const EdgeArgs<T> *)nullptr, 0);
     else
-        hipLaunchKernelGGL((k_interior_b<T, true, false>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev);
+        hipLaunchKernelGGL((k_interior_b<T, true, false>), dim3(nf, n), dim3(BLOCK), 0, st, steps_dev,
+                           (const EdgeArgs<T> *)nullptr, 0);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -2221,12 +2248,13 @@ void launch_sum_J(const double *jmis, const double *jreg, int mode, double *J, h
 
 // explicit instantiations
 #define HYB_INST(T)                                                                               \
-    template void launch_interior<T>(const Step<T> &, bool, hipStream_t, const Step<T> *);         \
+    template void launch_interior<T>(const Step<T> &, bool, hipStream_t, const EdgeArgs<T> *);      \
     template void launch_bnd_fwd<T>(const Step<T> &, hipStream_t);                                \
     template void launch_bnd_fwd_faces<T>(const Step<T> &, hipStream_t);                          \
     template void launch_bnd_fwd_edges<T>(const Step<T> &, hipStream_t);                          \
     template void launch_bnd_adj<T>(const Step<T> &, hipStream_t);                                \
-    template void launch_batch_fwd<T>(const Geo &, const Step<T> *, int, hipStream_t);            \
+    template void launch_batch_fwd<T>(const Geo &, const Step<T> *, const EdgeArgs<T> *, int,     \
+                                       long long, hipStream_t);                                 \
     template void launch_batch_adj<T>(const Geo &, const Step<T> *, int, hipStream_t);                                \
     template void launch_acube<T>(const Geo &, const double *, T *, double *, double *, hipStream_t); \
     template void launch_load_level<T>(const Geo &, const double *, T *, T *, hipStream_t);        \
