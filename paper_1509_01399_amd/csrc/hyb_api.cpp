@@ -369,11 +369,11 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     } else {
         g.nwd = g.nwo = 0;
     }
-    // x tiles start at multiples of TX_FDM (x = 0 included: no stencil row), so that
-    // they cover the interior [1, nx-2]
-    g.fdm_tiles[0] = (int)ceil_div(g.nx - 1, TX_FDM);
-    g.fdm_tiles[1] = (int)ceil_div(g.ny - 2, TY_FDM);
-    const long long txy = (long long)g.fdm_tiles[0] * g.fdm_tiles[1];
+    // x tiles start at multiples of the tile width (x = 0 included: no stencil
+    // row), so that they cover the interior [1, nx-2]
+    g.fdm_tx[0] = (int)ceil_div(g.nx - 1, fwd_tile_x(esz));
+    g.fdm_tx[1] = (int)ceil_div(g.nx - 1, TX_FDM);
+    g.fdm_ty = (int)ceil_div(g.ny - 2, TY_FDM);
     // Planes per z chunk, measured per precision and sweep on 257^3 grids
     // (us per step).  Adjoint, chunks of 4 / 6 / 8 / 12 / 16: FP64 110.9 /
     // 112.7 / 106.5 / 119.3 / 106.1; FP32 (6 / 8 / 12) 94.3 / 95.8 / 100.6.
@@ -387,7 +387,7 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     for (int a = 0; a < 2; ++a) {
         g.zc_fdm[a] = zc[a];
         g.fdm_zt[a] = (int)ceil_div(g.nz - 2, zc[a]);
-        g.n_fdm_blocks[a] = (int)(txy * g.fdm_zt[a]);
+        g.n_fdm_blocks[a] = (int)((long long)g.fdm_tx[a] * g.fdm_ty * g.fdm_zt[a]);
     }
     if (has_fem) {
         g.fem_tiles[0] = (int)ceil_div(g.C[0] - 1, TX_FEM);

@@ -9,13 +9,15 @@
 
 namespace hyb {
 
-// Block shapes (64-wide wavefronts): the FDM tile is 64 x TY_FDM columns
-// (each thread takes RY_FDM neighbouring rows), the FEM tile 32 x TY_FEM
-// columns; both stream along z.
+// Block shapes (64-wide wavefronts): the adjoint FDM tile is 64 x TY_FDM
+// columns (each thread takes RY_FDM neighbouring rows); the forward FDM tile
+// is fwd_tile_x(element size) x TY_FDM columns (32 lanes of 16 bytes of
+// columns per grid row); the FEM tile 32 x TY_FEM columns; all stream along z.
 constexpr int TX_FDM = 64, RY_FDM = 2, TY_FDM = 4 * RY_FDM;
 constexpr int TX_FEM = 32, TY_FEM = 8;
 constexpr int BLOCK = 256;
 static_assert(BLOCK / TX_FDM * RY_FDM == TY_FDM, "FDM tile: BLOCK / TX_FDM thread rows of RY_FDM grid rows");
+constexpr int fwd_tile_x(size_t esz) { return 32 * (16 / (int)esz); }
 
 // Face condition of one face at one step, 2 bits per face in a packed int.
 enum : int { F_ABC = 0, F_NEUMANN = 1, F_SOURCE = 2 };
@@ -33,7 +35,8 @@ struct Geo {
     long long n_fi, n_ec;     // face-interior nodes; edge and corner nodes
     long long foff[6], ftot;  // compact per-face arrays of boundary values
     long long nwd, nwo;       // |omega_diamond|, |omega_o|
-    int fdm_tiles[2], fem_tiles[3];  // tiles along x, y (FDM); x, y, z (FEM)
+    int fdm_tx[2], fdm_ty;    // FDM tiles along x (forward [0], adjoint [1]) and y
+    int fem_tiles[3];         // FEM tiles along x, y, z
     // FDM z chunks per tile column, planes per chunk and blocks launched, for
     // the forward [0] and the adjoint [1] sweep
     int fdm_zt[2], zc_fdm[2], n_fdm_blocks[2];

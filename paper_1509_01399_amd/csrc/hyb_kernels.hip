@@ -309,7 +309,7 @@ __device__ __forceinline__ void box_surface(long long t, int L, int &a, int &b, 
 }
 
 // Face-interior rows of the forward step on an absorbing face are computed
-// by the interior launch (fdm_tile_pairs), as is the overlap copy; the
+// by the interior launch (fdm_tile_cols), as is the overlap copy; the
 // boundary launch takes the faces whose rows are not absorbing at this step
 // (ghost-node Neumann or source rows), then the edges and corners.
 __host__ __device__ __forceinline__ long long face_area(const Geo &g, int f)
@@ -765,17 +765,17 @@ __device__ __forceinline__ int xcd_remap(int b, int nblk)
 template <typename T, bool ADJ, bool NT>
 __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
 {
-    static_assert(ADJ, "the forward step runs on fdm_tile_pairs");
+    static_assert(ADJ, "the forward step runs on fdm_tile_cols");
     constexpr int R = RY_FDM, TX = TX_FDM, TY = TY_FDM, LX = TX + 2, LY = TY + 2;
     constexpr bool INC = incr_form<T>();
     __shared__ T buf[2][LY][LX];
     const Geo &g = s.g;
     bid = xcd_remap(bid, g.n_fdm_blocks[ADJ]);
     if (bid >= g.n_fdm_blocks[ADJ]) return;
-    const int bx = bid % g.fdm_tiles[0];
-    const int tt = bid / g.fdm_tiles[0];
-    const int by = tt % g.fdm_tiles[1];
-    const int bz = tt / g.fdm_tiles[1];
+    const int bx = bid % g.fdm_tx[1];
+    const int tt = bid / g.fdm_tx[1];
+    const int by = tt % g.fdm_ty;
+    const int bz = tt / g.fdm_ty;
     const int x0 = bx * TX, y0 = 1 + by * TY;
     const int z0 = 1 + bz * g.zc_fdm[ADJ];
     const int z1 = min(z0 + g.zc_fdm[ADJ], g.nz - 1);
@@ -944,85 +944,107 @@ __device__ __forceinline__ void fdm_tile(const Step<T> &s, int bid)
     }
 }
 
-// Two neighbouring x columns of one lane: one 8-byte (FP32) or 16-byte
-// (FP64) access instead of two.
-template <typename T> struct Pair2;
-template <> struct Pair2<float> { typedef float type __attribute__((ext_vector_type(2))); };
-template <> struct Pair2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+// W neighbouring x columns of one lane, moved by one 16-byte access (FP64
+// pairs, FP32 quads) instead of W.
+template <typename T, int W> struct ColsV {
+    typedef T type __attribute__((ext_vector_type(W)));
+};
 
-template <typename T, bool NT>
-__device__ __forceinline__ typename Pair2<T>::type ld_pair(const T *p)
+template <typename T, int W, bool NT>
+__device__ __forceinline__ typename ColsV<T, W>::type ld_cols(const T *p)
 {
-    using P = typename Pair2<T>::type;
+    using P = typename ColsV<T, W>::type;
     if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const P *>(p));
     else return *reinterpret_cast<const P *>(p);
 }
 
-template <typename T, bool NT>
-__device__ __forceinline__ void st_pair(T *p, typename Pair2<T>::type v)
+template <typename T, int W, bool NT>
+__device__ __forceinline__ void st_cols(T *p, typename ColsV<T, W>::type v)
 {
-    using P = typename Pair2<T>::type;
+    using P = typename ColsV<T, W>::type;
     if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<P *>(p));
     else *reinterpret_cast<P *>(p) = v;
 }
 
-// Absorbing face rows, eq. (eq:abs2), beside a pair of interior rows:
+// Values a[0..W) stored at p: one vector store when every column has a row
+// (ok), else one store per column that has.
+template <typename T, int W, bool NT>
+__device__ __forceinline__ void st_cols_masked(T *p, const T a[W], const bool ok[W])
+{
+    using P = typename ColsV<T, W>::type;
+    bool all = true;
+#pragma unroll
+    for (int e = 0; e < W; ++e) all = all && ok[e];
+    if (all) {
+        P v;
+#pragma unroll
+        for (int e = 0; e < W; ++e) v[e] = a[e];
+        st_cols<T, W, NT>(p, v);
+    } else {
+#pragma unroll
+        for (int e = 0; e < W; ++e)
+            if (ok[e]) st_once<T, NT>(p + e, a[e]);
+    }
+}
+
+// Absorbing face rows, eq. (eq:abs2), beside W interior rows:
 // u^{k+1}_b = u^k_in + r (u^k_b - u^{k+1}_in) for the columns with a row
 // (ok), stored at `at` (the face node of the first column), with the
 // increment in FP32 and the trace when obs is given.
-template <typename T, bool NT>
-__device__ __forceinline__ void face_pair(T *Uc, T *Dc, long long at, const T ub[2], const T uin[2], const T vin[2],
-                                          const bool ok[2], double *obs, T r)
+template <typename T, int W, bool NT>
+__device__ __forceinline__ void face_cols(T *Uc, T *Dc, long long at, const T ub[W], const T uin[W], const T vin[W],
+                                          const bool ok[W], double *obs, T r)
 {
-    using P = typename Pair2<T>::type;
-    T vf[2], df[2];
+    T vf[W], df[W];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < W; ++e) {
         vf[e] = uin[e] + r * (ub[e] - vin[e]);
         df[e] = vf[e] - ub[e];
         if (obs && ok[e]) obs[e] = (double)vf[e];
     }
-    if (ok[0] && ok[1]) {
-        if constexpr (incr_form<T>()) st_pair<T, NT>(Dc + at, P{df[0], df[1]});
-        st_pair<T, NT>(Uc + at, P{vf[0], vf[1]});
-    } else {
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-            if (ok[e]) {
-                if constexpr (incr_form<T>()) st_once<T, NT>(Dc + at + e, df[e]);
-                st_once<T, NT>(Uc + at + e, vf[e]);
-            }
-    }
+    if constexpr (incr_form<T>()) st_cols_masked<T, W, NT>(Dc + at, df, ok);
+    st_cols_masked<T, W, NT>(Uc + at, vf, ok);
 }
 
-// FDM tile with column pairs: the same 64 x 8 tile, rows, halos, hole,
-// couplings and x-face rows as fdm_tile, but each lane takes the two
-// columns x, x+1 (x even) of one grid row, so a wave covers two rows of 64
-// columns and every field access of the z loop moves two values per lane:
-// half the vector memory instructions per node, the same registers per
-// thread.  Rows start on 128-byte lines (even pitch), so the pair at an even
-// x < nx stays inside its row (x + 1 <= pitch - 1); a value past nx - 1 is
-// padding, zeroed on load and never stored.  LDS rows hold the tile's
-// columns at offset 2 (pairs aligned), the left halo column at 1 and the
-// right one at TX + 2.
-template <typename T, bool ADJ, bool NT>
-__device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
+// Columns per lane of the forward FDM tile: 16 bytes.
+template <typename T>
+constexpr int fwd_cols() { return 16 / (int)sizeof(T); }
+
+// Forward FDM tile with W columns per lane: a block of 8 thread rows of 32
+// lanes covers 8 grid rows of 32 W columns (fwd_tile_x(sizeof(T)), a 64 x 8 tile
+// in FP64 and 128 x 8 in FP32), streaming along z through the chunk of
+// zc_fdm[0] planes, each plane staged in LDS; the FEM hole is skipped (the
+// tile when it lies inside, else the rows).  Every field access of the z
+// loop moves W values per lane.  Rows start on 128-byte lines, so the W
+// columns at a lane's x (a multiple of W) stay inside its row; values past
+// nx - 1 are padding, never stored, and enter only rows that are not
+// computed (a column's row reads its own column and its x neighbours, and
+// the right neighbour of a computed row, x <= nx-2, is a grid node), so
+// they are used as loaded: a masking select right after a load would make
+// the wave wait for it before issuing the next one.  LDS rows hold the
+// tile's columns at offset W (16-byte aligned), the left halo column at
+// W - 1 and the right one at TX + W.  The tile also takes the rows of the
+// absorbing faces next to its rows (x faces in the lane of the inward
+// neighbour; y and z faces by the row beside them) and the trace on an
+// absorbing z+ face.
+template <typename T, bool NT, int W>
+__device__ __forceinline__ void fdm_tile_cols(const Step<T> &s, int bid)
 {
-    using P = typename Pair2<T>::type;
-    constexpr int TX = TX_FDM, TY = TY_FDM, LX = TX + 4, LY = TY + 2, HL = TX / 2;
-    static_assert(BLOCK / HL == TY, "pair tile: BLOCK / (TX_FDM / 2) thread rows of one grid row");
+    using P = typename ColsV<T, W>::type;
+    constexpr int HL = 32, TX = HL * W, TY = BLOCK / HL, LX = TX + 2 * W, LY = TY + 2;
+    static_assert(TX == fwd_tile_x(sizeof(T)) && TY == TY_FDM, "forward tile shape");
     constexpr bool INC = incr_form<T>();
     __shared__ __align__(16) T buf[2][LY][LX];
     const Geo &g = s.g;
-    bid = xcd_remap(bid, g.n_fdm_blocks[ADJ]);
-    if (bid >= g.n_fdm_blocks[ADJ]) return;
-    const int bx = bid % g.fdm_tiles[0];
-    const int tt = bid / g.fdm_tiles[0];
-    const int by = tt % g.fdm_tiles[1];
-    const int bz = tt / g.fdm_tiles[1];
+    bid = xcd_remap(bid, g.n_fdm_blocks[0]);
+    if (bid >= g.n_fdm_blocks[0]) return;
+    const int bx = bid % g.fdm_tx[0];
+    const int tt = bid / g.fdm_tx[0];
+    const int by = tt % g.fdm_ty;
+    const int bz = tt / g.fdm_ty;
     const int x0 = bx * TX, y0 = 1 + by * TY;
-    const int z0 = 1 + bz * g.zc_fdm[ADJ];
-    const int z1 = min(z0 + g.zc_fdm[ADJ], g.nz - 1);
+    const int z0 = 1 + bz * g.zc_fdm[0];
+    const int z1 = min(z0 + g.zc_fdm[0], g.nz - 1);
     {
         const int xa = max(x0, 1), xb = min(x0 + TX - 1, g.nx - 2), yb = min(y0 + TY - 1, g.ny - 2);
         if (g.has_fem && xa >= g.hlo[0] && xb <= g.hhi[0] && y0 >= g.hlo[1] && yb <= g.hhi[1] &&
@@ -1030,73 +1052,58 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
             return;
     }
     const int lx = (int)(threadIdx.x % HL), ty = (int)(threadIdx.x / HL);
-    const int x = x0 + 2 * lx, y = y0 + ty, ly = 1 + ty, lc = 2 + 2 * lx;
+    const int x = x0 + W * lx, y = y0 + ty, ly = 1 + ty, lc = W + W * lx;
     const long long pz = g.plane;
     const T c2 = s.c2;
     const T *__restrict__ Ub = s.Ub;
     const T *__restrict__ Ua = INC ? s.Da : s.Ua;
     T *__restrict__ Uc = s.Uc;
     T *__restrict__ Dc = s.Dc;
-    const bool x1v = x + 1 <= g.nx - 1;              // the pair's second column is a grid node
-    const bool rval = x <= g.nx - 1 && y <= g.ny - 1;  // pair loads of this row
+    const bool rval = x <= g.nx - 1 && y <= g.ny - 1;  // column loads of this row
     // halo columns: lanes 0..2LY-1 of thread row 2 (the second wave)
     const bool hcol = ty == 2 && lx < 2 * LY;
     const int hly = lx < LY ? lx : lx - LY;
     const int hx = lx < LY ? x0 - 1 : x0 + TX, hy = y0 - 1 + hly;
     const bool hval = hcol && hx >= 0 && hx <= g.nx - 1 && hy <= g.ny - 1;
-    const int hcl = lx < LY ? 1 : TX + 2;
+    const int hcl = lx < LY ? W - 1 : TX + W;
     // halo rows: thread row 0 the row below the tile, the last the row above
     const bool hrow = (ty == 0 || ty == TY - 1) && x <= g.nx - 1;
     const int hry = ty == 0 ? y0 - 1 : y0 + TY, hrl = ty == 0 ? 0 : LY - 1;
     const bool hrval = hrow && hry <= g.ny - 1;
-    const int j = y - g.o[1], C0 = g.C[0], C1 = g.C[1], C2 = g.C[2];
     const bool yin = y >= g.hlo[1] && y <= g.hhi[1];
-    bool rcmp[2], side[2], top[2], hole[2], fx1[2];
-    const bool a0 = !ADJ && ftype(s.types1, 0) == F_ABC, a1 = !ADJ && ftype(s.types1, 1) == F_ABC;
+    bool rcmp[W], hole[W], fx1[W];
+    const bool a0 = ftype(s.types1, 0) == F_ABC, a1 = ftype(s.types1, 1) == F_ABC;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const int xe = x + e, i = xe - g.o[0];
-        const bool ib = ADJ && g.has_fem && i >= 0 && i <= C0, ii = i > 0 && i < C0;
+    for (int e = 0; e < W; ++e) {
+        const int xe = x + e;
         rcmp[e] = xe >= 1 && xe <= g.nx - 2 && y <= g.ny - 2;
-        side[e] = ib && j >= 0 && j <= C1 && !(ii && j > 0 && j < C1);
-        top[e] = ib && ii && j > 0 && j < C1;
         hole[e] = g.has_fem && xe >= g.hlo[0] && xe <= g.hhi[0] && yin;
         fx1[e] = a1 && xe == g.nx - 2 && rcmp[e];
     }
-    // absorbing x faces of the forward step (as in fdm_tile): the x = 0 row
-    // takes the new value of x = 1 from the same lane; the row of x = nx-1
-    // joins the pair store when nx-2 is the lane's first column, else it is a
-    // store of its own
+    // absorbing x faces: the x = 0 row takes the new value of x = 1 from the
+    // same lane; the row of x = nx-1 joins the lane's store when nx-2 is not
+    // its last column, else it is a store of its own
     const bool fx0 = a0 && x == 0 && y <= g.ny - 2;
-    // absorbing y and z faces of the forward step: the row of a node next to
-    // the face has the face node's old value (staged row, or the z neighbour
-    // in registers) and its own old and new values, so it adds the face row,
-    // eq. (eq:abs2), with a store of its own (rows y = 1 and y = ny-2, planes
-    // z = 1 and z = nz-2; the trace takes the z+ face)
-    const bool fy0 = !ADJ && y == 1 && ftype(s.types1, 2) == F_ABC;
-    const bool fy1 = !ADJ && y == g.ny - 2 && ftype(s.types1, 3) == F_ABC;
-    const bool az0 = !ADJ && ftype(s.types1, 4) == F_ABC, az1 = !ADJ && ftype(s.types1, 5) == F_ABC;
-    // absorbing x faces of the adjoint (as in fdm_tile)
-    const bool xq0 = ADJ && x0 == 0 && x_face_in_tile(g, s.types1, s.types2, 0);
-    const bool xq1 = ADJ && x0 <= g.nx - 2 && g.nx - 1 <= x0 + TX - 1 && x_face_in_tile(g, s.types1, s.types2, 1);
-    const T xw0 = (ADJ && s.level_rows) ? -s.r : (T)0;
-    const bool xfy = y >= 2 && y <= g.ny - 3;
-    // prologue: plane z0 into buffer 0, plane z0-1 of the own pair in registers
+    // absorbing y and z faces: the row of a node next to the face has the
+    // face node's old value (staged row, or the z neighbour in registers) and
+    // its own old and new values, so it adds the face row, eq. (eq:abs2),
+    // with a store of its own (rows y = 1 and y = ny-2, planes z = 1 and
+    // z = nz-2; the trace takes the z+ face)
+    const bool fy0 = y == 1 && ftype(s.types1, 2) == F_ABC;
+    const bool fy1 = y == g.ny - 2 && ftype(s.types1, 3) == F_ABC;
+    const bool az0 = ftype(s.types1, 4) == F_ABC, az1 = ftype(s.types1, 5) == F_ABC;
+    // prologue: plane z0 into buffer 0, plane z0-1 of the own columns in registers
     long long id = gidx(g, min(x, g.nx - 1), y, z0);
-    P c0 = {(T)0, (T)0}, cm = {(T)0, (T)0};
+    P c0 = (T)0, cm = (T)0;
     if (rval) {
-        c0 = ld_pair<T, false>(Ub + id);
-        cm = ld_pair<T, false>(Ub + id - pz);
-        if (!x1v) c0.y = cm.y = (T)0;
+        c0 = ld_cols<T, W, false>(Ub + id);
+        cm = ld_cols<T, W, false>(Ub + id - pz);
     }
     *reinterpret_cast<P *>(&buf[0][ly][lc]) = c0;
     if (hval) buf[0][hly][hcl] = Ub[gidx(g, hx, hy, z0)];
     if (hrow) {
-        P hr = {(T)0, (T)0};
-        if (hrval) {
-            hr = ld_pair<T, false>(Ub + gidx(g, x, hry, z0));
-            if (!x1v) hr.y = (T)0;
-        }
+        P hr = (T)0;
+        if (hrval) hr = ld_cols<T, W, false>(Ub + gidx(g, x, hry, z0));
         *reinterpret_cast<P *>(&buf[0][hrl][lc]) = hr;
     }
     __syncthreads();
@@ -1104,46 +1111,34 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
     for (int z = z0; z < z1; ++z, id += pz) {
         const int nxt = cur ^ 1;
         const bool inh = z >= g.hlo[2] && z <= g.hhi[2];
-        const int kz = z - g.o[2];
-        const bool zs = kz >= 0 && kz <= C2, zt = kz == 0 || kz == C2;
-        const bool xfr = ADJ && xfy && z >= 2 && z <= g.nz - 3;  // an absorbing x-face row at (y, z)
-        bool dor[2];
-        T w[2];
+        bool dor[W], any = false;
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
+        for (int e = 0; e < W; ++e) {
             dor[e] = rcmp[e] && !(hole[e] && inh);
-            w[e] = (ADJ && dor[e] && ((side[e] && zs) || (top[e] && zt))) ? Uc[id + e] : (T)0;
+            any = any || dor[e];
         }
-        P cp = {(T)0, (T)0}, ua = {(T)0, (T)0};
-        if (rval) {
-            cp = ld_pair<T, false>(Ub + id + pz);
-            if (!x1v) cp.y = (T)0;
-        }
-        if (dor[0] || dor[1]) ua = ld_pair<T, NT>(Ua + id);
+        P cp = (T)0, ua = (T)0;
+        if (rval) cp = ld_cols<T, W, false>(Ub + id + pz);
+        if (any) ua = ld_cols<T, W, NT>(Ua + id);
         const T hv = hval ? Ub[gidx(g, hx, hy, z + 1)] : (T)0;
-        P hr = {(T)0, (T)0};
-        if (hrval) {
-            hr = ld_pair<T, false>(Ub + gidx(g, x, hry, z + 1));
-            if (!x1v) hr.y = (T)0;
-        }
+        P hr = (T)0;
+        if (hrval) hr = ld_cols<T, W, false>(Ub + gidx(g, x, hry, z + 1));
         const P ym = *reinterpret_cast<const P *>(&buf[cur][ly - 1][lc]);
         const P yp = *reinterpret_cast<const P *>(&buf[cur][ly + 1][lc]);
-        const T xl = buf[cur][ly][lc - 1], xr = buf[cur][ly][lc + 2];
-        // the old x neighbours of each column (raw) and what its stencil reads
-        const T xm0[2] = {xl, c0.x}, xp0[2] = {c0.y, xr};
-        const T cc[2] = {c0.x, c0.y}, cmv[2] = {cm.x, cm.y}, cpv[2] = {cp.x, cp.y}, uav[2] = {ua.x, ua.y};
-        const T ymv[2] = {ym.x, ym.y}, ypv[2] = {yp.x, yp.y};
-        T d[2] = {(T)0, (T)0}, v[2] = {(T)0, (T)0};
-        bool st[2];
+        const T xl = buf[cur][ly][lc - 1], xr = buf[cur][ly][lc + W];
+        T cc[W], cmv[W], cpv[W], ymv[W], ypv[W], d[W], v[W];
+        bool st[W];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
+        for (int e = 0; e < W; ++e) {
+            cc[e] = c0[e]; cmv[e] = cm[e]; cpv[e] = cp[e]; ymv[e] = ym[e]; ypv[e] = yp[e];
+            d[e] = v[e] = (T)0;
+        }
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
             st[e] = dor[e];
             if (!dor[e]) continue;
-            T xm = xm0[e], xpr = xp0[e];
-            if constexpr (ADJ) {
-                if (xq0 && x + e == 1 && xfr) xm = (xm + xw0 * (s.r * xm + c2 * cc[e])) * s.ic2;
-                if (xq1 && x + e == g.nx - 2 && xfr) xpr = (xpr + xw0 * (s.r * xpr + c2 * cc[e])) * s.ic2;
-            }
+            // the old x neighbours of the column
+            const T xm = e == 0 ? xl : cc[e - 1], xpr = e == W - 1 ? xr : cc[e + 1];
             T L;
             if constexpr (INC)
                 L = ((xm - cc[e]) + (xpr - cc[e])) + ((ymv[e] - cc[e]) + (ypv[e] - cc[e])) +
@@ -1151,62 +1146,38 @@ __device__ __forceinline__ void fdm_tile_pairs(const Step<T> &s, int bid)
             else
                 L = ((xm + xpr) + (ymv[e] + ypv[e])) + (cmv[e] + cpv[e]) - (T)6 * cc[e];
             if constexpr (INC) {
-                d[e] = uav[e] + c2 * L + w[e];
+                d[e] = ua[e] + c2 * L;
                 v[e] = cc[e] + d[e];
             } else {
-                v[e] = (T)2 * cc[e] - uav[e] + c2 * L + w[e];
+                v[e] = (T)2 * cc[e] - ua[e] + c2 * L;
             }
         }
-        if constexpr (!ADJ) {
-            // face rows next to this row (see fy0)
-            if (fy0) face_pair<T, NT>(Uc, Dc, id - g.px, ymv, cc, v, dor, nullptr, s.r);
-            if (fy1) face_pair<T, NT>(Uc, Dc, id + g.px, ypv, cc, v, dor, nullptr, s.r);
-            if (az0 && z == 1) face_pair<T, NT>(Uc, Dc, id - pz, cmv, cc, v, dor, nullptr, s.r);
-            if (az1 && z == g.nz - 2)
-                face_pair<T, NT>(Uc, Dc, id + pz, cpv, cc, v, dor,
-                                 s.obs ? s.obs + x + (long long)g.nx * y : nullptr, s.r);
+        // face rows next to this row (see fy0)
+        if (fy0) face_cols<T, W, NT>(Uc, Dc, id - g.px, ymv, cc, v, dor, nullptr, s.r);
+        if (fy1) face_cols<T, W, NT>(Uc, Dc, id + g.px, ypv, cc, v, dor, nullptr, s.r);
+        if (az0 && z == 1) face_cols<T, W, NT>(Uc, Dc, id - pz, cmv, cc, v, dor, nullptr, s.r);
+        if (az1 && z == g.nz - 2)
+            face_cols<T, W, NT>(Uc, Dc, id + pz, cpv, cc, v, dor, s.obs ? s.obs + x + (long long)g.nx * y : nullptr,
+                                s.r);
+        if (fx0) {
+            v[0] = cc[1] + s.r * (cc[0] - v[1]);
+            if constexpr (INC) d[0] = v[0] - cc[0];
+            st[0] = true;
         }
-        if constexpr (!ADJ) {
-            if (fx0) {
-                v[0] = c0.y + s.r * (c0.x - v[1]);
-                if constexpr (INC) d[0] = v[0] - c0.x;
-                st[0] = true;
-            }
-            if (fx1[0]) {  // x = nx-2 is the first column: the face is the second
-                v[1] = c0.x + s.r * (c0.y - v[0]);
-                if constexpr (INC) d[1] = v[1] - c0.y;
-                st[1] = true;
-            }
-            if (fx1[1]) {
-                const T vf = c0.y + s.r * (xr - v[1]);
-                if constexpr (INC) st_once<T, NT>(Dc + id + 2, vf - xr);
-                st_once<T, NT>(Uc + id + 2, vf);
-            }
-        }
-        if constexpr (ADJ) {
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                if (xq0 && xfr && x + e == 0) {
-                    v[e] = s.r * cc[e] + c2 * xp0[e];
-                    st[e] = true;
-                }
-                if (xq1 && xfr && x + e == g.nx - 1) {
-                    v[e] = s.r * cc[e] + c2 * xm0[e];
-                    st[e] = true;
-                }
+        for (int e = 0; e + 1 < W; ++e)
+            if (fx1[e]) {  // x = nx-2 is column e: the face is column e+1
+                v[e + 1] = cc[e] + s.r * (cc[e + 1] - v[e]);
+                if constexpr (INC) d[e + 1] = v[e + 1] - cc[e + 1];
+                st[e + 1] = true;
             }
+        if (fx1[W - 1]) {
+            const T vf = cc[W - 1] + s.r * (xr - v[W - 1]);
+            if constexpr (INC) st_once<T, NT>(Dc + id + W, vf - xr);
+            st_once<T, NT>(Uc + id + W, vf);
         }
-        if (st[0] && st[1]) {
-            if constexpr (INC) st_pair<T, NT>(Dc + id, P{d[0], d[1]});
-            st_pair<T, NT>(Uc + id, P{v[0], v[1]});
-        } else {
-#pragma unroll
-            for (int e = 0; e < 2; ++e)
-                if (st[e]) {
-                    if constexpr (INC) st_once<T, NT>(Dc + id + e, d[e]);
-                    st_once<T, NT>(Uc + id + e, v[e]);
-                }
-        }
+        if constexpr (INC) st_cols_masked<T, W, NT>(Dc + id, d, st);
+        st_cols_masked<T, W, NT>(Uc + id, v, st);
         // the next plane into the other buffer
         *reinterpret_cast<P *>(&buf[nxt][ly][lc]) = cp;
         if (hval) buf[nxt][hly][hcl] = hv;
@@ -1422,19 +1393,17 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 // unbounded (77 VGPRs forward, 72 adjoint): bounded to 7 waves the forward
 // spills, 87.8 us against 83.1 us per step.
 template <typename T, bool ADJ>
-constexpr int interior_waves() { return sizeof(T) == 4 ? (ADJ ? 8 : 7) : 1; }
+constexpr int interior_waves() { return sizeof(T) == 4 ? (ADJ ? 8 : 1) : 1; }
 
-// Forward FDM tiles take column pairs (fdm_tile_pairs), adjoint tiles one
-// column per lane (fdm_tile).  Per step at 257^3, pairs against single
-// columns (same run, same box, before the forward tile took the y and z
-// faces): FP64 forward 85.3 / 86.7 us, adjoint 101.1 / 97.4 us; FP32 forward
-// 77.1 / 76.4 us, adjoint 86.0 / 81.5 us.  With the face rows in the tile and
-// the edge rows one launch later, the forward step over 1200 steps went from
-// 85.3 to 83.1 us (FP64) and from 75.9 to 74.9 us (FP32): the interior launch
-// grew by ~4 us, the boundary launch (9 us, the latency of the edge rows) is
-// gone while every face absorbs.
-template <typename T, bool ADJ>
-constexpr bool pair_tile() { return !ADJ; }
+// Forward FDM tiles take 16 bytes of columns per lane (fdm_tile_cols),
+// adjoint tiles one column per lane (fdm_tile).  Per step at 257^3, pairs
+// against single columns (same run, same box, before the forward tile took
+// the y and z faces): FP64 forward 85.3 / 86.7 us, adjoint 101.1 / 97.4 us;
+// FP32 forward 77.1 / 76.4 us, adjoint 86.0 / 81.5 us.  With the face rows in
+// the tile and the edge rows one launch later, the forward step over 1200
+// steps went from 85.3 to 83.1 us (FP64) and from 75.9 to 74.9 us (FP32): the
+// interior launch grew by ~4 us, the boundary launch (9 us, the latency of
+// the edge rows) is gone while every face absorbs.
 
 template <typename T, bool ADJ, bool NT>
 __global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(Step<T> s, EdgeArgs<T> ea, int ne)
@@ -1450,8 +1419,8 @@ __global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(
     }
     const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
     if (b < nf) {
-        if constexpr (pair_tile<T, ADJ>()) fdm_tile_pairs<T, ADJ, NT>(s, b);
-        else fdm_tile<T, ADJ, NT>(s, b);
+        if constexpr (ADJ) fdm_tile<T, true, NT>(s, b);
+        else fdm_tile_cols<T, NT, fwd_cols<T>()>(s, b);
     }
     else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
 }
@@ -1550,8 +1519,8 @@ __global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior_
     }
     const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
     if (b < nf) {
-        if constexpr (pair_tile<T, ADJ>()) fdm_tile_pairs<T, ADJ, NT>(s, b);
-        else fdm_tile<T, ADJ, NT>(s, b);
+        if constexpr (ADJ) fdm_tile<T, true, NT>(s, b);
+        else fdm_tile_cols<T, NT, fwd_cols<T>()>(s, b);
     }
     else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
 }
