@@ -855,8 +855,12 @@ hyb_status fwd_steps(hyb_ctx *c, int k0, int k1, int &ia, int &ib, int &ic, doub
             lag = false;
         }
         const EdgeArgs<T> pe = edge_args(prev);
-        launch_interior<T>(s, false, st, lag ? &pe : nullptr);
-        if (c->gen) launch_gen_fwd<T>(gen_args<T>(c, s), st);
+        if (c->gen) {
+            const GenStep<T> gs = gen_args<T>(c, s);
+            launch_interior<T>(s, false, st, lag ? &pe : nullptr, &gs);
+        } else {
+            launch_interior<T>(s, false, st, lag ? &pe : nullptr);
+        }
         launch_bnd_fwd_faces<T>(s, st);
         prev = s;
         lag = true;
@@ -930,9 +934,14 @@ hyb_status run_adjoint(hyb_ctx *c, const double *res, int mode)
             if (r) return r;
         }
         const Step<T> s = adj_step_args<T>(c, k, ia, ib, ic, res, mode);
-        launch_bnd_adj<T>(s, st);
-        if (c->gen) launch_gen_adj<T>(gen_adj_args<T>(c, s, k), st);
-        launch_interior<T>(s, true, st);
+        if (c->gen) {
+            const GenStep<T> gs = gen_adj_args<T>(c, s, k);
+            launch_bnd_adj<T>(s, st, &gs);
+            launch_interior<T>(s, true, st, nullptr, &gs);
+        } else {
+            launch_bnd_adj<T>(s, st);
+            launch_interior<T>(s, true, st);
+        }
         const int t = ia; ia = ib; ib = ic; ic = t;
     }
     c->last_p = ib;
@@ -1616,8 +1625,10 @@ hyb_status hyb_get_wavefield(hyb_ctx *c, int32_t which, double *u, double *v)
         launch_export_level<double>(c->g, (const double *)A[q], (const double *)B[q], (const double *)Fq, u,
                                     vs, c->stream, types);
     if (c->gen && v) {
-        if (c->f32) launch_gen_export<float>(c->gd, (const float *)B[q], v, c->stream);
-        else launch_gen_export<double>(c->gd, (const double *)B[q], v, c->stream);
+        // the forward level's omega_o nodes hold grid values, read from the grid level
+        const void *Ug = which == 0 ? A[q] : nullptr;
+        if (c->f32) launch_gen_export<float>(c->gd, (const float *)B[q], (const float *)Ug, v, c->stream);
+        else launch_gen_export<double>(c->gd, (const double *)B[q], (const double *)Ug, v, c->stream);
     }
     HIPCHK(c, hipGetLastError());
     return HYB_OK;

@@ -74,9 +74,9 @@ struct GenDev {
 };
 
 // Arguments of one general FEM step.  Forward: V levels k-1, k, k+1 (or the
-// increments VDa = d^k, VDc = d^{k+1}), Uc the grid level k+1 (omega_diamond
-// receives the new FEM values, omega_o gives its values to Vc), hist the
-// history level k+1 (nodes [0, nH)).  Adjoint (computing level k): V levels
+// increments VDa = d^k, VDc = d^{k+1}), Ub the grid level k (the rows read
+// their omega_o neighbours there), Uc the grid level k+1 (omega_diamond
+// receives the new FEM values), hist the history level k+1 (nodes [0, nH)).  Adjoint (computing level k): V levels
 // k+2, k+1, k of the FEM multipliers, Ub the grid multipliers of level k+1
 // (read by the omega_diamond rows), Uc the grid level k (receives the
 // omega_o couplings), hist the history level k, E the gradient accumulators.
@@ -106,6 +106,9 @@ struct GenStep {
     T cs_prev;
 };
 
+// The rows in launches of their own (timing; the sweeps run them inside the
+// grid's launches, launch_interior and launch_bnd_adj): forward rows, and
+// adjoint rows with the omega_o couplings.
 template <typename T> void launch_gen_fwd(const GenStep<T> &s, hipStream_t st);
 template <typename T> void launch_gen_adj(const GenStep<T> &s, hipStream_t st);
 
@@ -128,9 +131,11 @@ template <typename T>
 void launch_gen_load_combo(const GenDev &d, const double *a, const double *b, double cb, T *V, hipStream_t st);
 template <typename T>
 void launch_gen_load_incr(const GenDev &d, const double *u0, const double *um1, T *VD, hipStream_t st);
-// v[orig_of_dev[n]] = V[n] (FP64, caller's numbering)
+// v[orig_of_dev[n]] = V[n] (FP64, caller's numbering); with U (the grid
+// level of a forward sweep) the omega_o nodes take their grid values, which
+// the time steps do not copy into the FEM level
 template <typename T>
-void launch_gen_export(const GenDev &d, const T *V, double *v, hipStream_t st);
+void launch_gen_export(const GenDev &d, const T *V, const T *U, double *v, hipStream_t st);
 
 // Gradient from the edge accumulators: dJ/da_t = sum over the 6 vertex pairs
 // of K^t_pair E_pair (free t).  mode 0: g_t = dJ/da_t / |t| + gamma sigma_t,

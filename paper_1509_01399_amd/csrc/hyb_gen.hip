@@ -1,145 +1,31 @@
 // HIP kernels (gfx950) of the FEM box on a general tetrahedral mesh: the
-// lumped-mass P1 update of eq. (fem) and its exact adjoint with the FP64
-// gradient integral of eq. (gradient1), on the sliced ELL tables described
-// in hyb_gen.h.  One thread per row; a wavefront owns one 64-row slice, so
-// its column and kappa loads are contiguous, and the neighbour values are
-// gathered (the node numbering follows the grid order of the cells, so the
-// gathers stay within a few z planes of the box and hit the caches).
+// coefficient preparation, loads and exports of FEM levels, the gradient
+// from the edge accumulators, and the rows of hyb_gen_rows.h in launches of
+// their own (the time steps run them inside the grid's launches).
 #include <algorithm>
 
 #include "hyb_gen.h"
+#include "hyb_gen_rows.h"
 #include "hyb_internal.h"
 
 namespace hyb {
 
 namespace {
 
-// Blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-// range of rows so that the rows of a neighbourhood share an L2.
-__device__ __forceinline__ long long gen_row(int nblk)
-{
-    const int per = (nblk + 7) / 8;
-    const int b = ((int)blockIdx.x % 8) * per + (int)blockIdx.x / 8;
-    return (long long)b * BLOCK + threadIdx.x;
-}
-
-// Forward row n (level k -> k+1):
-//   v^{k+1}_n = 2 v^k_n - v^{k-1}_n - (dt^2 / m_n) sum_m kappa_nm (v^k_n - v^k_m),
-// or in increment form d^{k+1}_n = d^k_n - (dt^2/m_n) (...), v^{k+1} = v^k + d^{k+1}.
-// Rows on omega_diamond also write their new value into the grid level
-// (Algorithm 2, step 3); the omega_o nodes take the new grid values (step 4).
+// The forward rows alone.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gen_fwd(GenStep<T> s, int nblk)
 {
-    const long long n = gen_row(nblk);
-    if (n >= s.fn) return;
-    if (n >= s.nR) {
-        s.Vc[n] = s.Uc[s.wog[n - s.nR]];
-        return;
-    }
-    const int sl = (int)(n >> 6), ln = (int)(n & 63);
-    const int b = s.soff[sl], w = (s.soff[sl + 1] - b) >> 6;
-    const T *__restrict__ Vb = s.Vb;
-    const T *__restrict__ kap = s.kap;
-    const int32_t *__restrict__ col = s.col;
-    const T v0 = Vb[n];
-    T acc = 0;
-#pragma unroll 2
-    for (int j = 0; j < w; ++j) {
-        const int p = b + 64 * j + ln;
-        acc += kap[p] * (v0 - Vb[col[p]]);
-    }
-    const T c = s.cs * s.cn[n];
-    T v;
-    if constexpr (incr_form<T>()) {
-        const T d = s.VDa[n] - c * acc;
-        s.VDc[n] = d;
-        v = v0 + d;
-    } else {
-        v = (T)2 * v0 - s.Va[n] - c * acc;
-    }
-    s.Vc[n] = v;
-    if (n < s.nA) s.Uc[s.wdg[n]] = v;
-    if (n < s.nH && s.hist) __builtin_nontemporal_store(v, s.hist + n);
+    gen_fwd_row<T>(s, gen_row((int)blockIdx.x, nblk));
 }
 
-// Adjoint row n, computing the multipliers of level k from those of levels
-// k+1 and k+2 (the transpose of the forward rows):
-//   mu^k_n = 2 mu^{k+1}_n - mu^{k+2}_n - sum_m kappa_nm (nu_n - nu_m)
-//            [+ (dt/h)^2 sum of the 6 grid multipliers around n, on omega_diamond]
-// with nu_m = (dt^2 / m_m) mu^{k+1}_m (0 off the rows).  The gradient
-// integral pairs u^k with nu: every edge (n, m), n < m, of the inner box
-// accumulates (nu_n - nu_m)(u^k_n - u^k_m) in FP64.  On omega_o (not a row)
-// the thread leaves sum_m kappa_nm nu_m, the coupling of the FEM rows that
-// read the node, in the grid level k for the grid row of the node to add.
+// The adjoint rows and the omega_o couplings alone.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_gen_adj(GenStep<T> s, int nblk)
 {
-    const long long n = gen_row(nblk);
-    if (n >= s.fn) return;
-    const int sl = (int)(n >> 6), ln = (int)(n & 63);
-    const int b = s.soff[sl], w = (s.soff[sl + 1] - b) >> 6;
-    const T *__restrict__ Vb = s.Vb;
-    const T *__restrict__ nu = s.nu_in;
-    const T *__restrict__ kap = s.kap;
-    const int32_t *__restrict__ col = s.col;
-    if (n >= s.nR) {
-        T acc = 0;
-#pragma unroll 2
-        for (int j = 0; j < w; ++j) {
-            const int p = b + 64 * j + ln;
-            acc += kap[p] * nu[col[p]];
-        }
-        s.Uc[s.wog[n - s.nR]] = acc;
-        return;
-    }
-    const T mu1 = Vb[n];
-    const T nu0 = nu[n];
-    const bool hrow = n < s.nH;
-    const T *__restrict__ H = s.hist;
-    // the slice's first we entries carry the E slots (upper inner edges
-    // first in each row of [0, nH)); the rest only the stencil
-    int eb = 0, we = 0;
-    double u0 = 0.0;
-    if ((long long)sl * 64 < s.nH) {
-        eb = s.eoff[sl];
-        we = (s.eoff[sl + 1] - eb) >> 6;
-    }
-    if (hrow) u0 = (double)H[n];
-    T acc = 0;
-#pragma unroll 4
-    for (int j = 0; j < we; ++j) {
-        const int p = b + 64 * j + ln;
-        const int m = col[p];
-        const T num = nu[m];
-        acc += kap[p] * (nu0 - num);
-        if (hrow && m > n && m < s.nH) {
-            double *e = s.E + eb + 64 * j + ln;
-            *e += ((double)nu0 - (double)num) * (u0 - (double)H[m]);
-        }
-    }
-#pragma unroll 2
-    for (int j = we; j < w; ++j) {
-        const int p = b + 64 * j + ln;
-        acc += kap[p] * (nu0 - nu[col[p]]);
-    }
-    T cw = 0;
-    if (n < s.nA) {
-        const long long gg = s.wdg[n];
-        const T *Ub = s.Ub;
-        cw = s.c2 * (((Ub[gg - 1] + Ub[gg + 1]) + (Ub[gg - s.px] + Ub[gg + s.px])) +
-                     (Ub[gg - s.plane] + Ub[gg + s.plane]));
-    }
-    T mu0;
-    if constexpr (incr_form<T>()) {
-        const T d = s.VDa[n] - acc + cw;
-        s.VDc[n] = d;
-        mu0 = mu1 + d;
-    } else {
-        mu0 = (T)2 * mu1 - s.Va[n] - acc + cw;
-    }
-    s.Vc[n] = mu0;
-    s.nu_out[n] = (s.cs_prev * s.cn[n]) * mu0;
+    const long long n = gen_row((int)blockIdx.x, nblk);
+    if (n < s.nR) gen_adj_row<T>(s, n);
+    else gen_wo_row<T>(s, n);
 }
 
 __device__ double block_reduce_g(double v, bool is_max)
@@ -247,10 +133,11 @@ __global__ __launch_bounds__(BLOCK) void k_gen_load_incr(long long fn, const int
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLOCK) void k_gen_export(long long fn, const int32_t *orig, const T *V, double *v)
+__global__ __launch_bounds__(BLOCK) void k_gen_export(long long fn, long long nR, const int32_t *orig, const T *V,
+                                                      const T *U, const int64_t *wog, double *v)
 {
     for (long long n = (long long)blockIdx.x * BLOCK + threadIdx.x; n < fn; n += (long long)gridDim.x * BLOCK)
-        v[orig[n]] = (double)V[n];
+        v[orig[n]] = (double)((U && n >= nR) ? U[wog[n - nR]] : V[n]);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_gen_grad_final(long long nt, const int32_t *tetE, const double *ke6,
@@ -280,26 +167,20 @@ __global__ __launch_bounds__(BLOCK) void k_gen_grad_final(long long nt, const in
     if (threadIdx.x == 0) part[blockIdx.x] = reg;
 }
 
-int row_blocks(long long fn)
-{
-    const long long nb = (fn + BLOCK - 1) / BLOCK;
-    return (int)((nb + 7) / 8 * 8);
-}
-
 }  // namespace
 
 template <typename T>
 void launch_gen_fwd(const GenStep<T> &s, hipStream_t st)
 {
-    const int nb = (int)((s.fn + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL((k_gen_fwd<T>), dim3(row_blocks(s.fn)), dim3(BLOCK), 0, st, s, nb);
+    const int nb = gen_row_blocks(s.nR);
+    hipLaunchKernelGGL((k_gen_fwd<T>), dim3(nb), dim3(BLOCK), 0, st, s, nb);
 }
 
 template <typename T>
 void launch_gen_adj(const GenStep<T> &s, hipStream_t st)
 {
-    const int nb = (int)((s.fn + BLOCK - 1) / BLOCK);
-    hipLaunchKernelGGL((k_gen_adj<T>), dim3(row_blocks(s.fn)), dim3(BLOCK), 0, st, s, nb);
+    const int nb = gen_row_blocks(s.fn);
+    hipLaunchKernelGGL((k_gen_adj<T>), dim3(nb), dim3(BLOCK), 0, st, s, nb);
 }
 
 template <typename T>
@@ -338,9 +219,10 @@ void launch_gen_load_incr(const GenDev &d, const double *u0, const double *um1, 
 }
 
 template <typename T>
-void launch_gen_export(const GenDev &d, const T *V, double *v, hipStream_t st)
+void launch_gen_export(const GenDev &d, const T *V, const T *U, double *v, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_gen_export<T>), dim3(nparts_g(d.fn)), dim3(BLOCK), 0, st, d.fn, d.orig_of_dev, V, v);
+    hipLaunchKernelGGL((k_gen_export<T>), dim3(nparts_g(d.fn)), dim3(BLOCK), 0, st, d.fn, d.nR, d.orig_of_dev, V,
+                       U, d.wog, v);
 }
 
 void launch_gen_grad_final(const GenDev &d, const double *sigma, double gamma, int mode, double *grad,
@@ -362,7 +244,7 @@ void launch_gen_grad_final(const GenDev &d, const double *sigma, double gamma, i
                                            hipStream_t);                                           \
     template void launch_gen_load_incr<T>(const GenDev &, const double *, const double *, T *,     \
                                           hipStream_t);                                            \
-    template void launch_gen_export<T>(const GenDev &, const T *, double *, hipStream_t);
+    template void launch_gen_export<T>(const GenDev &, const T *, const T *, double *, hipStream_t);
 HYB_GEN_INST(double)
 HYB_GEN_INST(float)
 

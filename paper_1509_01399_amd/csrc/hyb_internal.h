@@ -127,18 +127,23 @@ inline EdgeArgs<T> edge_args(const Step<T> &s)
     return e;
 }
 
+template <typename T> struct GenStep;
+
 // ---- launchers (hyb_kernels.hip) ----
 // edges: the step whose edge and corner rows the forward launch also runs
+// (null: none); gen: the FEM rows of a general mesh that go with the step
 // (null: none)
 template <typename T>
-void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeArgs<T> *edges = nullptr);
+void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeArgs<T> *edges = nullptr,
+                     const GenStep<T> *gen = nullptr);
 // boundary launch of a forward step: reflecting face rows, edges and corners
 template <typename T> void launch_bnd_fwd(const Step<T> &s, hipStream_t st);
 // the same split in two: the reflecting face rows (no launch when every face
 // absorbs), and the edge and corner rows
 template <typename T> void launch_bnd_fwd_faces(const Step<T> &s, hipStream_t st);
 template <typename T> void launch_bnd_fwd_edges(const Step<T> &s, hipStream_t st);
-template <typename T> void launch_bnd_adj(const Step<T> &s, hipStream_t st);
+// gen: the omega_o couplings of a general mesh's FEM rows (null: none)
+template <typename T> void launch_bnd_adj(const Step<T> &s, hipStream_t st, const GenStep<T> *gen = nullptr);
 
 // rows of the forward boundary launch that face conditions `types` give
 long long fwd_face_row_count(const Geo &g, int types);

@@ -29,6 +29,7 @@
 //   k_bnd_adj_face: multipliers of the face rows, including the trace seed;
 //   k_interior<T,true>: the FDM stencil applied to the multipliers plus the
 //     transposed boundary and exchange couplings.
+#include "hyb_gen_rows.h"
 #include "hyb_internal.h"
 
 #include <cmath>
@@ -591,10 +592,14 @@ __device__ __forceinline__ void bnd_adj_ecf_body(const Step<T> &s, int bid)
     if (t < g.nwo) omega_o_fill(s, t);
 }
 
+// gs, nw: on a general mesh, the omega_o couplings of its FEM rows (nw
+// blocks after the others; they need only the nu of level k+1)
 template <typename T, bool VM>
-__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ecf(Step<T> s)
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ecf(Step<T> s, GenStep<T> gs, int nw)
 {
-    bnd_adj_ecf_body<T, VM>(s, blockIdx.x);
+    const int nb = (int)gridDim.x - nw;
+    if ((int)blockIdx.x < nb) bnd_adj_ecf_body<T, VM>(s, blockIdx.x);
+    else gen_wo_row<T>(gs, gs.nR + (long long)((int)blockIdx.x - nb) * BLOCK + threadIdx.x);
 }
 
 // Second adjoint launch: the face-interior nodes (they read the corner and
@@ -1405,8 +1410,12 @@ constexpr int interior_waves() { return sizeof(T) == 4 ? (ADJ ? 8 : 1) : 1; }
 // interior launch grew by ~4 us, the boundary launch (9 us, the latency of
 // the edge rows) is gone while every face absorbs.
 
+// gs, ngb: on a general mesh, its FEM rows in ngb blocks after the tiles
+// (forward: the rows of step k; adjoint: the rows of level k, which read
+// only levels k+1 and k+2, as the grid tiles do)
 template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(Step<T> s, EdgeArgs<T> ea, int ne)
+__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(Step<T> s, EdgeArgs<T> ea, int ne,
+                                                                               GenStep<T> gs, int ngb)
 {
     int b = blockIdx.x;
     if constexpr (!ADJ) {
@@ -1421,8 +1430,21 @@ __global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(
     if (b < nf) {
         if constexpr (ADJ) fdm_tile<T, true, NT>(s, b);
         else fdm_tile_cols<T, NT, fwd_cols<T>()>(s, b);
+        return;
     }
-    else if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
+    b -= nf;
+    if constexpr (!ADJ) {
+        if (b < s.g.n_fem_blocks) {
+            fem_tile<T, false, false>(s, b);
+            return;
+        }
+        b -= s.g.n_fem_blocks;
+    }
+    if (b < ngb) {
+        const long long n = gen_row(b, ngb);
+        if constexpr (ADJ) gen_adj_row<T>(gs, n);
+        else gen_fwd_row<T>(gs, n);
+    }
 }
 
 // Non-temporal hints pay when the field arrays a step streams (three levels,
@@ -1441,7 +1463,8 @@ static bool stream_nt(const Geo &g, size_t esz, int slots)
 static int edge_blocks8(const Geo &g) { return (int)((g.n_ec + 8 * BLOCK - 1) / (8 * BLOCK) * 8); }
 
 template <typename T>
-void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeArgs<T> *edges)
+void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeArgs<T> *edges,
+                     const GenStep<T> *gen)
 {
     const int nf = (s.g.n_fdm_blocks[adjoint ? 1 : 0] + 7) / 8 * 8;
     const bool nt = stream_nt(s.g, sizeof(T), 1);
@@ -1451,13 +1474,20 @@ void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeA
         ea = *edges;
         ne = edge_blocks8(s.g);
     }
+    GenStep<T> gs{};
+    int ngb = 0;
+    if (gen) {
+        gs = *gen;
+        ngb = gen_row_blocks(gen->nR);
+    }
     if (adjoint) {
-        if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), dim3(nf), dim3(BLOCK), 0, st, s, ea, 0);
-        else hipLaunchKernelGGL((k_interior<T, true, false>), dim3(nf), dim3(BLOCK), 0, st, s, ea, 0);
+        const dim3 grid(nf + ngb);
+        if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), grid, dim3(BLOCK), 0, st, s, ea, 0, gs, ngb);
+        else hipLaunchKernelGGL((k_interior<T, true, false>), grid, dim3(BLOCK), 0, st, s, ea, 0, gs, ngb);
     } else {
-        const dim3 grid(ne + nf + s.g.n_fem_blocks);
-        if (nt) hipLaunchKernelGGL((k_interior<T, false, true>), grid, dim3(BLOCK), 0, st, s, ea, ne);
-        else hipLaunchKernelGGL((k_interior<T, false, false>), grid, dim3(BLOCK), 0, st, s, ea, ne);
+        const dim3 grid(ne + nf + s.g.n_fem_blocks + ngb);
+        if (nt) hipLaunchKernelGGL((k_interior<T, false, true>), grid, dim3(BLOCK), 0, st, s, ea, ne, gs, ngb);
+        else hipLaunchKernelGGL((k_interior<T, false, false>), grid, dim3(BLOCK), 0, st, s, ea, ne, gs, ngb);
     }
 }
 
@@ -1488,11 +1518,17 @@ static long long ecf_blocks(const Geo &g)
 }
 
 template <typename T>
-void launch_bnd_adj(const Step<T> &s, hipStream_t st)
+void launch_bnd_adj(const Step<T> &s, hipStream_t st, const GenStep<T> *gen)
 {
-    const dim3 na((unsigned)ecf_blocks(s.g));
-    if (s.minv) hipLaunchKernelGGL((k_bnd_adj_ecf<T, true>), na, dim3(BLOCK), 0, st, s);
-    else hipLaunchKernelGGL((k_bnd_adj_ecf<T, false>), na, dim3(BLOCK), 0, st, s);
+    GenStep<T> gs{};
+    int nw = 0;
+    if (gen) {
+        gs = *gen;
+        nw = (int)((gen->fn - gen->nR + BLOCK - 1) / BLOCK);
+    }
+    const dim3 na((unsigned)(ecf_blocks(s.g) + nw));
+    if (s.minv) hipLaunchKernelGGL((k_bnd_adj_ecf<T, true>), na, dim3(BLOCK), 0, st, s, gs, nw);
+    else hipLaunchKernelGGL((k_bnd_adj_ecf<T, false>), na, dim3(BLOCK), 0, st, s, gs, nw);
     const long long nf = (adj_face_rows(s.g, s.types1, s.types2) + BLOCK - 1) / BLOCK;
     if (nf > 0) hipLaunchKernelGGL((k_bnd_adj_face<T>), dim3((unsigned)nf), dim3(BLOCK), 0, st, s);
 }
@@ -2217,11 +2253,12 @@ void launch_sum_J(const double *jmis, const double *jreg, int mode, double *J, h
 
 // explicit instantiations
 #define HYB_INST(T)                                                                               \
-    template void launch_interior<T>(const Step<T> &, bool, hipStream_t, const EdgeArgs<T> *);      \
+    template void launch_interior<T>(const Step<T> &, bool, hipStream_t, const EdgeArgs<T> *,       \
+                                     const GenStep<T> *);                                         \
     template void launch_bnd_fwd<T>(const Step<T> &, hipStream_t);                                \
     template void launch_bnd_fwd_faces<T>(const Step<T> &, hipStream_t);                          \
     template void launch_bnd_fwd_edges<T>(const Step<T> &, hipStream_t);                          \
-    template void launch_bnd_adj<T>(const Step<T> &, hipStream_t);                                \
+    template void launch_bnd_adj<T>(const Step<T> &, hipStream_t, const GenStep<T> *);            \
     template void launch_batch_fwd<T>(const Geo &, const Step<T> *, const EdgeArgs<T> *, int,     \
                                        long long, hipStream_t);                                 \
     template void launch_batch_adj<T>(const Geo &, const Step<T> *, int, hipStream_t);                                \
