@@ -592,13 +592,19 @@ __device__ __forceinline__ void bnd_adj_ecf_body(const Step<T> &s, int bid)
     if (t < g.nwo) omega_o_fill(s, t);
 }
 
-// gs, nw: on a general mesh, the omega_o couplings of its FEM rows (nw
-// blocks after the others; they need only the nu of level k+1)
 template <typename T, bool VM>
-__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ecf(Step<T> s, GenStep<T> gs, int nw)
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ecf(Step<T> s)
+{
+    bnd_adj_ecf_body<T, VM>(s, blockIdx.x);
+}
+
+// On a general mesh, the same launch with the omega_o couplings of its FEM
+// rows in the last blocks (they need only the nu of level k+1).
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_bnd_adj_ecf_gen(Step<T> s, GenStep<T> gs, int nw)
 {
     const int nb = (int)gridDim.x - nw;
-    if ((int)blockIdx.x < nb) bnd_adj_ecf_body<T, VM>(s, blockIdx.x);
+    if ((int)blockIdx.x < nb) bnd_adj_ecf_body<T, false>(s, blockIdx.x);
     else gen_wo_row<T>(gs, gs.nR + (long long)((int)blockIdx.x - nb) * BLOCK + threadIdx.x);
 }
 
@@ -1388,9 +1394,11 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 }
 
 // Block order of the interior launch: in the forward sweep the previous
-// step's edge and corner rows (when given), then the FDM tiles, then the FEM
-// tiles; each range is rounded up to a multiple of 8 for the XCD remap.  The
-// FEM rows of the adjoint run in the boundary launch.
+// step's edge and corner rows (when given), then the rows of a general FEM
+// mesh (when given, in both sweeps), then the FDM tiles, then the FEM tiles
+// of the structured box; each range is rounded up to a multiple of 8 for the
+// XCD remap.  The structured FEM rows of the adjoint run in the boundary
+// launch.
 //
 // FP32: at most 64 VGPRs (8 waves per SIMD) in the adjoint, 72 (7 waves) in
 // the forward, whose tile also takes the face rows: under 64 it spilled and
@@ -1410,12 +1418,13 @@ constexpr int interior_waves() { return sizeof(T) == 4 ? (ADJ ? 8 : 1) : 1; }
 // interior launch grew by ~4 us, the boundary launch (9 us, the latency of
 // the edge rows) is gone while every face absorbs.
 
-// gs, ngb: on a general mesh, its FEM rows in ngb blocks after the tiles
-// (forward: the rows of step k; adjoint: the rows of level k, which read
-// only levels k+1 and k+2, as the grid tiles do)
-template <typename T, bool ADJ, bool NT>
-__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(Step<T> s, EdgeArgs<T> ea, int ne,
-                                                                               GenStep<T> gs, int ngb)
+// Blocks of the interior launch (kernels k_interior and, on a general FEM
+// mesh, k_interior_gen); with GEN, gs and ngb give the mesh's FEM rows in ngb
+// blocks (forward: the rows of step k; adjoint: the rows of level k, which
+// read only levels k+1 and k+2, as the grid tiles do).
+template <typename T, bool ADJ, bool NT, bool GEN>
+__device__ __forceinline__ void interior_block(const Step<T> &s, const EdgeArgs<T> &ea, int ne,
+                                               const GenStep<T> &gs, int ngb)
 {
     int b = blockIdx.x;
     if constexpr (!ADJ) {
@@ -1426,25 +1435,41 @@ __global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(
         }
         b -= ne;
     }
+    if constexpr (GEN) {
+        // the rows of a general FEM mesh next: their gathers take longer per
+        // block than a tile, so they start before the tiles (adjoint step
+        // 197.1 -> 189.1 us at cg256 against placing them last)
+        if (b < ngb) {
+            const long long n = gen_row(b, ngb);
+            if constexpr (ADJ) gen_adj_row<T>(gs, n);
+            else gen_fwd_row<T>(gs, n);
+            return;
+        }
+        b -= ngb;
+    }
     const int nf = (s.g.n_fdm_blocks[ADJ] + 7) / 8 * 8;
     if (b < nf) {
         if constexpr (ADJ) fdm_tile<T, true, NT>(s, b);
         else fdm_tile_cols<T, NT, fwd_cols<T>()>(s, b);
         return;
     }
-    b -= nf;
-    if constexpr (!ADJ) {
-        if (b < s.g.n_fem_blocks) {
-            fem_tile<T, false, false>(s, b);
-            return;
-        }
-        b -= s.g.n_fem_blocks;
-    }
-    if (b < ngb) {
-        const long long n = gen_row(b, ngb);
-        if constexpr (ADJ) gen_adj_row<T>(gs, n);
-        else gen_fwd_row<T>(gs, n);
-    }
+    if constexpr (!ADJ) fem_tile<T, false, false>(s, b - nf);
+}
+
+template <typename T, bool ADJ, bool NT>
+__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior(Step<T> s, EdgeArgs<T> ea, int ne)
+{
+    interior_block<T, ADJ, NT, false>(s, ea, ne, GenStep<T>{}, 0);
+}
+
+// A separate kernel, so that the structured launch carries neither the
+// general rows' code nor their arguments (both cost the structured steps
+// ~0.6 us in FP64 and ~0.8 us in FP32).
+template <typename T, bool ADJ, bool NT>
+__global__ __launch_bounds__(BLOCK, (interior_waves<T, ADJ>())) void k_interior_gen(Step<T> s, EdgeArgs<T> ea,
+                                                                                   int ne, GenStep<T> gs, int ngb)
+{
+    interior_block<T, ADJ, NT, true>(s, ea, ne, gs, ngb);
 }
 
 // Non-temporal hints pay when the field arrays a step streams (three levels,
@@ -1474,20 +1499,25 @@ void launch_interior(const Step<T> &s, bool adjoint, hipStream_t st, const EdgeA
         ea = *edges;
         ne = edge_blocks8(s.g);
     }
-    GenStep<T> gs{};
-    int ngb = 0;
     if (gen) {
-        gs = *gen;
-        ngb = gen_row_blocks(gen->nR);
+        const int ngb = gen_row_blocks(gen->nR);
+        const dim3 grid((adjoint ? 0 : ne) + ngb + nf + (adjoint ? 0 : s.g.n_fem_blocks));
+        if (adjoint) {
+            if (nt) hipLaunchKernelGGL((k_interior_gen<T, true, true>), grid, dim3(BLOCK), 0, st, s, ea, 0, *gen, ngb);
+            else hipLaunchKernelGGL((k_interior_gen<T, true, false>), grid, dim3(BLOCK), 0, st, s, ea, 0, *gen, ngb);
+        } else {
+            if (nt) hipLaunchKernelGGL((k_interior_gen<T, false, true>), grid, dim3(BLOCK), 0, st, s, ea, ne, *gen, ngb);
+            else hipLaunchKernelGGL((k_interior_gen<T, false, false>), grid, dim3(BLOCK), 0, st, s, ea, ne, *gen, ngb);
+        }
+        return;
     }
     if (adjoint) {
-        const dim3 grid(nf + ngb);
-        if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), grid, dim3(BLOCK), 0, st, s, ea, 0, gs, ngb);
-        else hipLaunchKernelGGL((k_interior<T, true, false>), grid, dim3(BLOCK), 0, st, s, ea, 0, gs, ngb);
+        if (nt) hipLaunchKernelGGL((k_interior<T, true, true>), dim3(nf), dim3(BLOCK), 0, st, s, ea, 0);
+        else hipLaunchKernelGGL((k_interior<T, true, false>), dim3(nf), dim3(BLOCK), 0, st, s, ea, 0);
     } else {
-        const dim3 grid(ne + nf + s.g.n_fem_blocks + ngb);
-        if (nt) hipLaunchKernelGGL((k_interior<T, false, true>), grid, dim3(BLOCK), 0, st, s, ea, ne, gs, ngb);
-        else hipLaunchKernelGGL((k_interior<T, false, false>), grid, dim3(BLOCK), 0, st, s, ea, ne, gs, ngb);
+        const dim3 grid(ne + nf + s.g.n_fem_blocks);
+        if (nt) hipLaunchKernelGGL((k_interior<T, false, true>), grid, dim3(BLOCK), 0, st, s, ea, ne);
+        else hipLaunchKernelGGL((k_interior<T, false, false>), grid, dim3(BLOCK), 0, st, s, ea, ne);
     }
 }
 
@@ -1520,15 +1550,16 @@ static long long ecf_blocks(const Geo &g)
 template <typename T>
 void launch_bnd_adj(const Step<T> &s, hipStream_t st, const GenStep<T> *gen)
 {
-    GenStep<T> gs{};
-    int nw = 0;
     if (gen) {
-        gs = *gen;
-        nw = (int)((gen->fn - gen->nR + BLOCK - 1) / BLOCK);
+        // a variable wave speed (minv) is not carried by general meshes
+        const int nw = (int)((gen->fn - gen->nR + BLOCK - 1) / BLOCK);
+        hipLaunchKernelGGL((k_bnd_adj_ecf_gen<T>), dim3((unsigned)(ecf_blocks(s.g) + nw)), dim3(BLOCK), 0, st, s,
+                           *gen, nw);
+    } else {
+        const dim3 na((unsigned)ecf_blocks(s.g));
+        if (s.minv) hipLaunchKernelGGL((k_bnd_adj_ecf<T, true>), na, dim3(BLOCK), 0, st, s);
+        else hipLaunchKernelGGL((k_bnd_adj_ecf<T, false>), na, dim3(BLOCK), 0, st, s);
     }
-    const dim3 na((unsigned)(ecf_blocks(s.g) + nw));
-    if (s.minv) hipLaunchKernelGGL((k_bnd_adj_ecf<T, true>), na, dim3(BLOCK), 0, st, s, gs, nw);
-    else hipLaunchKernelGGL((k_bnd_adj_ecf<T, false>), na, dim3(BLOCK), 0, st, s, gs, nw);
     const long long nf = (adj_face_rows(s.g, s.types1, s.types2) + BLOCK - 1) / BLOCK;
     if (nf > 0) hipLaunchKernelGGL((k_bnd_adj_face<T>), dim3((unsigned)nf), dim3(BLOCK), 0, st, s);
 }
