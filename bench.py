@@ -289,12 +289,14 @@ def general_fem_bytes(xyz, tet, wl, s):
     element size s).  Per row: its column ids and kappa values (4 + s per mesh
     neighbour), the row's own levels (FP64: read v^k, v^{k-1}, write v^{k+1};
     FP32 increment form: read v^k, d^k, write d^{k+1}, v^{k+1}) and dt^2/m;
-    the history level of the inner-box nodes; the overlap copies (an 8-byte
-    grid index and the copied value).  The adjoint also reads the neighbour
-    lists of the box surface (its omega_o couplings), the six grid multipliers
-    around each omega_diamond node, and read-modify-writes one FP64
-    accumulator per edge of the inner box.  Neighbour values gathered by
-    several rows are counted once."""
+    the history level of the inner-box nodes; the omega_diamond copy (an
+    8-byte grid index and the value written into the grid); the omega_o
+    neighbours, read from the grid level (an 8-byte grid index and the
+    value).  The adjoint also reads the neighbour lists of the box surface
+    (its omega_o couplings, an index and a value written into the grid),
+    the six grid multipliers around each omega_diamond node, and
+    read-modify-writes one FP64 accumulator per edge of the inner box.
+    Neighbour values gathered by several rows are counted once."""
     import numpy as np
     h, o, C = wl.h, wl.o, wl.C
     q = xyz / h - o
@@ -313,7 +315,7 @@ def general_fem_bytes(xyz, tet, wl, s):
     nR, nH, nA, nS = int(rows.sum()), int(inner.sum()), int(onD.sum()), int(surf.sum())
     ent_rows, ent_all = int(deg[rows].sum()), int(deg.sum())
     up_inner = int((inner[ea] & inner[eb]).sum())
-    fwd = ent_rows * (4 + s) + nR * (m * s + s) + nH * s + nS * (8 + 2 * s) + nA * (8 + s)
+    fwd = ent_rows * (4 + s) + nR * (m * s + s) + nH * s + nS * (8 + s) + nA * (8 + s)
     adj = ent_all * (4 + s) + nR * (m * s + s) + nH * s + up_inner * 16 + nS * (8 + s) + nA * (8 + 6 * s)
     return fwd, adj
 

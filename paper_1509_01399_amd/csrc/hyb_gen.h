@@ -7,7 +7,8 @@
 //             [o+2, o+C-2]^3, whose values the grid reads (Sec. 3);
 //   [nA, nH)  the other nodes of the closed inner box;
 //   [nH, nR)  the other FEM rows (the two-element overlap layer);
-//   [nR, fn)  omega_o: the box surface, grid nodes that take the grid values.
+//   [nR, fn)  omega_o: the box surface, grid nodes whose values are the grid
+//             values (the rows read them from the grid level).
 // [0, nR) are the rows of the lumped-mass scheme eq. (fem); [0, nH) are the
 // nodes of the free tetrahedra (those with every vertex in the closed inner
 // box), whose history the gradient integral reads.  Within a range the nodes
