@@ -379,9 +379,10 @@ void setup_geo(Geo &g, const int n[3], const Mesh &m, bool has_fem, size_t esz)
     // 112.7 / 106.5 / 119.3 / 106.1; FP32 (6 / 8 / 12) 94.3 / 95.8 / 100.6.
     // Forward with the column-pair tile and its face rows, chunks of 3 / 4 /
     // 6 / 8 / 10 / 12 / 16: FP64 82.9 / 79.9 / 80.8 / 78.3 / 85.0 / 79.9 /
-    // 87.9; FP32 (4 / 6 / 8) 75.0 / 73.6 / 80.3.  Chunk counts that divide
-    // into whole rounds of resident blocks balance best; small grids keep 4
-    // planes for parallelism.
+    // 87.9; FP32 (4 / 6 / 8) 75.0 / 73.6 / 80.3, with the tile of four FP32
+    // columns per lane 73.1 / 69.7 / 75.0.  Chunk counts that divide into
+    // whole rounds of resident blocks balance best; small grids keep 4 planes
+    // for parallelism.
     const bool big = g.nz > 200;
     const int zc[2] = {big ? (esz == 4 ? 6 : 8) : 4, big ? (esz == 4 ? 6 : 8) : 4};
     for (int a = 0; a < 2; ++a) {
