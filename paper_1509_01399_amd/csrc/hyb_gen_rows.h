@@ -92,21 +92,47 @@ __device__ __forceinline__ void gen_adj_row(const GenStep<T> &s, long long n)
         eb = s.eoff[sl];
         we = (s.eoff[sl + 1] - eb) >> 6;
     }
-    if (hrow) u0 = (double)H[n];
     T acc = 0;
+    int j0 = 0;
+    if constexpr (sizeof(T) == 4) {
+        // FP32 fields: every access of the E loop is unconditional, so the
+        // loads of several slots are in flight together; a slot that is not
+        // an upper inner edge pairs the row's history with itself (factor
+        // u0 - u0 = 0) and writes its E entry, which no tetrahedron reads,
+        // back.  Adjoint step at cg256 141.8 -> 137.3 us; with FP64 fields
+        // the extra E writes cost more than the wait they save (189.4 ->
+        // 194.5 us), so those keep the conditional update.
+        if (hrow) {
+            u0 = (double)H[n];
 #pragma unroll 4
-    for (int j = 0; j < we; ++j) {
-        const int p = b + 64 * j + ln;
-        const int m = col[p];
-        const T num = nu[m];
-        acc += kap[p] * (nu0 - num);
-        if (hrow && m > n && m < s.nH) {
-            double *e = s.E + eb + 64 * j + ln;
-            *e += ((double)nu0 - (double)num) * (u0 - (double)H[m]);
+            for (int j = 0; j < we; ++j) {
+                const int p = b + 64 * j + ln;
+                const int m = col[p];
+                const T num = nu[m];
+                acc += kap[p] * (nu0 - num);
+                const bool up = m > n && m < s.nH;
+                double *e = s.E + eb + 64 * j + ln;
+                *e += ((double)nu0 - (double)num) * (u0 - (double)H[up ? m : n]);
+            }
+            j0 = we;
         }
+    } else {
+        if (hrow) u0 = (double)H[n];
+#pragma unroll 4
+        for (int j = 0; j < we; ++j) {
+            const int p = b + 64 * j + ln;
+            const int m = col[p];
+            const T num = nu[m];
+            acc += kap[p] * (nu0 - num);
+            if (hrow && m > n && m < s.nH) {
+                double *e = s.E + eb + 64 * j + ln;
+                *e += ((double)nu0 - (double)num) * (u0 - (double)H[m]);
+            }
+        }
+        j0 = we;
     }
 #pragma unroll 2
-    for (int j = we; j < w; ++j) {
+    for (int j = j0; j < w; ++j) {
         const int p = b + 64 * j + ln;
         acc += kap[p] * (nu0 - nu[col[p]]);
     }
