@@ -466,31 +466,56 @@ __device__ __forceinline__ T bnd_adj(const Step<T> &s, int x, int y, int z)
     const long long cb = cidx(g, x, y, z);
     const BInfo B1 = classify(g, x, y, z, s.types1);
     const BInfo B2 = classify(g, x, y, z, s.types2);
-    T mu = (B1.nabc == 0 ? ((T)2 - (T)6 * c2) : s.r) * s.Fb[cb];
-    if (B2.nabc == 0) mu -= s.Fa[cb];
+    // Every term's operand address and weight first (a term that does not
+    // apply reads the node's own entry with weight 0), then all the loads,
+    // then the sum in the order of the terms: the loads are in flight
+    // together instead of one dependent round trip per neighbour.
+    const T *p1[6], *p0[6];
+    T w1[6], w0[6];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int sg = 2 * q - 1;
+            const int i = 2 * d + q, sg = 2 * q - 1;
             const int cx = x + (d == 0 ? sg : 0), cy = y + (d == 1 ? sg : 0), cz = z + (d == 2 ? sg : 0);
             const int cd = d == 0 ? cx : (d == 1 ? cy : cz);
             const int md = d == 0 ? g.nx : (d == 1 ? g.ny : g.nz);
+            p1[i] = p0[i] = s.Fb + cb;
+            w1[i] = w0[i] = (T)0;
             if (cd >= 0 && cd < md) {
                 if (!on_bnd(g, cx, cy, cz)) {
-                    mu += c2 * s.Ub[gidx(g, cx, cy, cz)];
+                    p1[i] = s.Ub + gidx(g, cx, cy, cz);
+                    w1[i] = c2;
                 } else {
                     const long long cn = cidx(g, cx, cy, cz);
                     const BInfo N1 = classify(g, cx, cy, cz, s.types1);
-                    if (N1.nabc == 0) mu += (N1.kind[d] >= 0 ? (T)2 * c2 : c2) * s.Fb[cn];
-                    else if (N1.kind[d] == F_ABC) mu += s.Fb[cn] / (T)N1.nabc;
+                    p1[i] = s.Fb + cn;
+                    if (N1.nabc == 0) w1[i] = N1.kind[d] >= 0 ? (T)2 * c2 : c2;
+                    else if (N1.kind[d] == F_ABC) w1[i] = (T)1 / (T)N1.nabc;
                     if (s.level_rows) {
                         const BInfo N0 = classify(g, cx, cy, cz, s.types0);
-                        if (N0.nabc > 0 && N0.kind[d] == F_ABC) mu -= s.r * s.Fc[cn] / (T)N0.nabc;
+                        if (N0.nabc > 0 && N0.kind[d] == F_ABC) {
+                            p0[i] = s.Fc + cn;
+                            w0[i] = s.r / (T)N0.nabc;
+                        }
                     }
                 }
             }
         }
+    }
+    const T fb = s.Fb[cb], fa = s.Fa[cb];
+    T v1[6], v0[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        v1[i] = *p1[i];
+        v0[i] = *p0[i];
+    }
+    T mu = (B1.nabc == 0 ? ((T)2 - (T)6 * c2) : s.r) * fb;
+    if (B2.nabc == 0) mu -= fa;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        mu += w1[i] * v1[i];
+        mu -= w0[i] * v0[i];
     }
     if (s.res && z == g.nz - 1) mu += seed_at(s, x, y);
     return mu;
