@@ -1278,8 +1278,7 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
     const bool hcol = i >= 2 && i <= Cx - 2 && j >= 2 && j <= Cy - 2;
     const int hn0 = g.hn[0], hn1 = g.hn[1];
     const long long hpz = (long long)hn0 * hn1;
-    bool qfull = false;  // ql, hl hold plane k of the gradient corners
-    double ql[4] = {0, 0, 0, 0}, hl[4] = {0, 0, 0, 0};
+    double ql[4] = {0, 0, 0, 0}, hl[4] = {0, 0, 0, 0};  // plane k of the gradient corners
     for (int k = k0; k < k1; ++k, id += fz, gq += g.plane) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) ahi[q] = A[cb + (q & 1) + (q >> 1) * cpy + (long long)k * cpz];
@@ -1296,6 +1295,71 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
             nyp = Mi[id + fy] * yp;
         }
         const T n0 = AV ? m0 * v0 : v0, nzm = AV ? mm * vm : vm, nzp = AV ? mp * vp : vp;
+        if constexpr (ADJ) {
+            // gradient of eq. (gradient1): cube with lower corner (i,j,k),
+            // sum over its 12 edges of w_e (D_e lambda^{k+1}) (D_e u^k) in
+            // FP64.  The corners of plane k come from the previous
+            // iteration's plane k+1 (register queue), so each plane's
+            // multipliers and history values are loaded once per column.
+            // Every thread runs it on every plane, with history addresses
+            // clamped into the history box and weight 0 where the cube has
+            // no gradient (gcol, k in [2, Cz-3]; it then adds an exact zero to
+            // its own cube, which no other thread touches), so these loads
+            // are issued with the stencil's instead of after them.  Plain
+            // loads for the history: the four columns around a corner re-read
+            // it from L2.
+            const bool gq = gcol && k >= 2 && k <= Cz - 3;
+            const T *H = s.hist;
+            const int hi0 = min(max(i - 2, 0), hn0 - 2), hj0 = min(max(j - 2, 0), hn1 - 2);
+            const long long hcol0 = hi0 + (long long)hj0 * hn0;
+            const int hn2 = Cz - 3;
+            const long long hk = min(max(k - 2, 0), hn2 - 1), hk1 = min(max(k - 1, 0), hn2 - 1);
+            if (k == k0) {
+                ql[0] = (double)n0;
+                ql[1] = (double)nxp;
+                ql[2] = (double)nyp;
+                ql[3] = AV ? (double)(Mi[id + 1 + fy] * s.Vb[id + 1 + fy]) : (double)s.Vb[id + 1 + fy];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) hl[c] = (double)H[hcol0 + hk * hpz + (c & 1) + (c >> 1) * hn0];
+            }
+            double q[8], hv[8], qh[4], hh[4];
+            qh[0] = (double)nzp;
+            if constexpr (AV) {
+                qh[1] = (double)(Mi[id + fz + 1] * s.Vb[id + fz + 1]);
+                qh[2] = (double)(Mi[id + fz + fy] * s.Vb[id + fz + fy]);
+                qh[3] = (double)(Mi[id + fz + fy + 1] * s.Vb[id + fz + fy + 1]);
+            } else {
+                qh[1] = (double)s.Vb[id + fz + 1];
+                qh[2] = (double)s.Vb[id + fz + fy];
+                qh[3] = (double)s.Vb[id + fz + fy + 1];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) hh[c] = (double)H[hcol0 + hk1 * hpz + (c & 1) + (c >> 1) * hn0];
+            double *gp = s.G + (i + cpy * j + cpz * k);
+            const double gv = *gp;
+            // corner c = dx + 2 dy + 4 dz
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                q[c] = ql[c];
+                q[c + 4] = qh[c];
+                hv[c] = hl[c];
+                hv[c + 4] = hh[c];
+                ql[c] = qh[c];
+                hl[c] = hh[c];
+            }
+            double acc = 0.0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int s0 = e & 1, s1 = e >> 1;
+                const int ax0 = 0 + 2 * s0 + 4 * s1, ax1 = ax0 + 1;          // x-edge (y=s0,z=s1)
+                const int ay0 = s0 + 4 * s1, ay1 = ay0 + 2;                  // y-edge (x=s0,z=s1)
+                const int az0 = s0 + 2 * s1, az1 = az0 + 4;                  // z-edge (x=s0,y=s1)
+                acc += (double)w[e] * (q[ax1] - q[ax0]) * (hv[ax1] - hv[ax0]);
+                acc += (double)w[4 + e] * (q[ay1] - q[ay0]) * (hv[ay1] - hv[ay0]);
+                acc += (double)w[8 + e] * (q[az1] - q[az0]) * (hv[az1] - hv[az0]);
+            }
+            *gp = __builtin_fma(gq ? s.w2 : 0.0, acc, gv);
+        }
         // a(dx,dy,dz): dz = 0 -> alo, 1 -> ahi
 #define AC(dx, dy, dz) ((dz) ? ahi[(dx) + 2 * (dy)] : alo[(dx) + 2 * (dy)])
         const T kxp = w[0] * AC(1, 1, 1) + w[1] * AC(1, 0, 1) + w[2] * AC(1, 1, 0) + w[3] * AC(1, 0, 0);
@@ -1325,63 +1389,6 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
                                    (s.Ub[gg - g.plane] + s.Ub[gg + g.plane]));
                 if constexpr (incr_form<T>()) dv += cw;
                 else v += cw;
-            }
-            // gradient of eq. (gradient1): cube with lower corner (i,j,k),
-            // sum over its 12 edges of w_e (D_e lambda^{k+1}) (D_e u^k) in FP64
-            // The corners of plane k come from the previous iteration's plane
-            // k+1 (register queue), so each plane's multipliers and history
-            // values are loaded once per column.  Plain loads for the
-            // history: the four columns around a corner re-read it from L2.
-            if (gcol && k >= 2 && k <= Cz - 3) {
-                double q[8], hv[8];
-                const T *H = s.hist;
-                const long long hb = (i - 2) + (long long)(j - 2) * hn0 + (long long)(k - 2) * hpz;
-                if (!qfull) {
-                    ql[0] = (double)n0;
-                    ql[1] = (double)nxp;
-                    ql[2] = (double)nyp;
-                    ql[3] = AV ? (double)(Mi[id + 1 + fy] * s.Vb[id + 1 + fy]) : (double)s.Vb[id + 1 + fy];
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) hl[c] = (double)H[hb + (c & 1) + (c >> 1) * hn0];
-                }
-                double qh[4], hh[4];
-                qh[0] = (double)nzp;
-                if constexpr (AV) {
-                    qh[1] = (double)(Mi[id + fz + 1] * s.Vb[id + fz + 1]);
-                    qh[2] = (double)(Mi[id + fz + fy] * s.Vb[id + fz + fy]);
-                    qh[3] = (double)(Mi[id + fz + fy + 1] * s.Vb[id + fz + fy + 1]);
-                } else {
-                    qh[1] = (double)s.Vb[id + fz + 1];
-                    qh[2] = (double)s.Vb[id + fz + fy];
-                    qh[3] = (double)s.Vb[id + fz + fy + 1];
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) hh[c] = (double)H[hb + hpz + (c & 1) + (c >> 1) * hn0];
-                // corner c = dx + 2 dy + 4 dz
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    q[c] = ql[c];
-                    q[c + 4] = qh[c];
-                    hv[c] = hl[c];
-                    hv[c + 4] = hh[c];
-                    ql[c] = qh[c];
-                    hl[c] = hh[c];
-                }
-                qfull = true;
-                double acc = 0.0;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int s0 = e & 1, s1 = e >> 1;
-                    const int ax0 = 0 + 2 * s0 + 4 * s1, ax1 = ax0 + 1;          // x-edge (y=s0,z=s1)
-                    const int ay0 = s0 + 4 * s1, ay1 = ay0 + 2;                  // y-edge (x=s0,z=s1)
-                    const int az0 = s0 + 2 * s1, az1 = az0 + 4;                  // z-edge (x=s0,y=s1)
-                    acc += (double)w[e] * (q[ax1] - q[ax0]) * (hv[ax1] - hv[ax0]);
-                    acc += (double)w[4 + e] * (q[ay1] - q[ay0]) * (hv[ay1] - hv[ay0]);
-                    acc += (double)w[8 + e] * (q[az1] - q[az0]) * (hv[az1] - hv[az0]);
-                }
-                s.G[i + cpy * j + cpz * k] += s.w2 * acc;
-            } else {
-                qfull = false;
             }
             // wave speed: row n reads u^{k+1}_n = ... - c2 (K u^k)_n / m_n, so
             // d u^{k+1}_n / d m_n = -(u^{k+1} - 2 u^k + u^{k-1})_n / m_n and
