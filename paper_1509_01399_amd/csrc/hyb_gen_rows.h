@@ -99,9 +99,10 @@ __device__ __forceinline__ void gen_adj_row(const GenStep<T> &s, long long n)
         // loads of several slots are in flight together; a slot that is not
         // an upper inner edge pairs the row's history with itself (factor
         // u0 - u0 = 0) and writes its E entry, which no tetrahedron reads,
-        // back.  Adjoint step at cg256 141.8 -> 137.3 us; with FP64 fields
-        // the extra E writes cost more than the wait they save (189.4 ->
-        // 194.5 us), so those keep the conditional update.
+        // back.  Adjoint step on a 256^3-cell grid with a 96^3-cell general
+        // box 141.8 -> 137.3 us; with FP64 fields the extra E writes cost
+        // more than the wait they save (189.4 -> 194.5 us), so those keep
+        // the conditional update.
         if (hrow) {
             u0 = (double)H[n];
 #pragma unroll 4

@@ -1470,7 +1470,8 @@ __device__ __forceinline__ void interior_block(const Step<T> &s, const EdgeArgs<
     if constexpr (GEN) {
         // the rows of a general FEM mesh next: their gathers take longer per
         // block than a tile, so they start before the tiles (adjoint step
-        // 197.1 -> 189.1 us at cg256 against placing them last)
+        // 197.1 -> 189.1 us on a 256^3-cell grid with a 96^3-cell general
+        // box, against placing them last)
         if (b < ngb) {
             const long long n = gen_row(b, ngb);
             if constexpr (ADJ) gen_adj_row<T>(gs, n);
