@@ -1432,11 +1432,12 @@ __device__ __forceinline__ void fem_tile(const Step<T> &s, int bid)
 // XCD remap.  The structured FEM rows of the adjoint run in the boundary
 // launch.
 //
-// FP32: at most 64 VGPRs (8 waves per SIMD) in the adjoint, 72 (7 waves) in
-// the forward, whose tile also takes the face rows: under 64 it spilled and
-// its step measured 83.2 us against 74.9 us (1200 steps at 257^3).  FP64 runs
-// unbounded (77 VGPRs forward, 72 adjoint): bounded to 7 waves the forward
-// spills, 87.8 us against 83.1 us per step.
+// Occupancy bounds: the FP32 adjoint at most 64 VGPRs (8 waves per SIMD);
+// the forward kernels unbounded (FP64 79 VGPRs, set by the FEM tile; FP32
+// 100, set by the four-column tile, which bounded to 6 waves spills 16 VGPRs
+// and measured 83.4 against 69.7 us per step at 257^3; FP64 bounded to 7
+// waves spills 2 in the FEM tile, 78.2 against 75.8 us); the FP64 adjoint
+// unbounded (56 VGPRs).
 template <typename T, bool ADJ>
 constexpr int interior_waves() { return sizeof(T) == 4 ? (ADJ ? 8 : 1) : 1; }
 
