@@ -1,10 +1,12 @@
 // HIP kernels (gfx950) of the domain-decomposition FEM/FDM time stepping of
 // arXiv 1509.01399 (Algorithm 2, Sec. 7.5) and its exact discrete adjoint.
 //
-// Per forward step k -> k+1 two launches:
+// Per forward step k -> k+1 one launch, and a second one while a face has
+// reflecting rows:
 //   k_interior<T,false>: the seven-point leapfrog of eq. (fdmschemeforward)
-//     on every FDM-owned interior node (blocks of 64 x 8 columns streaming
-//     along z, each plane staged in LDS; the hole [o+2, o+C-2]^3 is skipped) and,
+//     on every FDM-owned interior node (blocks of 8 grid rows of 16 bytes of
+//     columns per lane, 64 x 8 in FP64 and 128 x 8 in FP32, streaming along
+//     z, each plane staged in LDS; the hole [o+2, o+C-2]^3 is skipped) and,
 //     in the same launch, the lumped-mass P1 update of eq. (fem) on the open
 //     FEM box (32 x 8 columns).  On the 6-tetrahedra cube split the P1
 //     stiffness couples only along the 12 axis edges of each cube, so the
@@ -15,13 +17,16 @@
 //     of Algorithm 2 step 3 (FEM values into the grid on omega_diamond) and
 //     the trace on an absorbing z+ face are computed here too.  Step 4 (grid
 //     values into the FEM level on omega_o) needs no copy: the FEM rows read
-//     those neighbours from the grid level.
+//     those neighbours from the grid level.  Its first blocks compute the
+//     edge and corner rows of the previous step (no row of this step reads
+//     them).
 //   k_bnd_fwd: the rows of reflecting faces (the ghost-node Neumann/source
-//     rows of eq. (f)), the edges and the corners, with their part of the
-//     trace.  An edge or corner thread recomputes the values of the boundary
-//     neighbours it depends on that this launch computes (a corner's edges,
-//     a reflecting face node), so its threads need no ordering (three
-//     rotating buffers keep level k-1 intact).
+//     rows of eq. (f)), with their part of the trace; the edges and corners
+//     run there too when they are not carried by the next interior launch.
+//     An edge or corner thread recomputes the values of the boundary
+//     neighbours it depends on (a corner's edges, a reflecting face node),
+//     so its threads need no ordering (three rotating buffers keep level
+//     k-1 intact).
 // Per adjoint step (computing the multipliers of level k) the reverse:
 //   k_bnd_adj_ecf: multipliers of the corner and edge rows, and beside them
 //     the FEM rows of the adjoint with the FP64 gradient time-integral of
